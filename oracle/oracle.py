@@ -1,0 +1,193 @@
+"""ctypes wrapper of the plain C++ CPU oracle (``grf_oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark load this module; the GPU library never does, and this module
+imports nothing from the GPU package.
+
+States are numpy float64 arrays of shape (27, nz+6, ny+6, nx+6).  Parameters
+are the 14-double vector (lambda_gb, g2, a, b, kappa1, kappa2, kappa3,
+lapse_coeff, lapse_power, lapse_advec, shift_gamma_coeff, shift_advec, eta,
+ko_sigma).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "grf_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+NF = 27
+NG = 3
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (plain -O2, no fused multiply-add contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+               "-o", _LIB + ".tmp", _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.oracle_rhs.argtypes = [_dp, _ip, _dp, _dp, _dp]
+        L.oracle_rhs_cells.argtypes = [_dp, _ip, _dp, _dp, ctypes.c_int, _ip, _dp]
+        L.oracle_rhs_cs.argtypes = [_dp, _dp, _ip, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_constraints.argtypes = [_dp, _ip, _dp, _dp, _dp, _dp]
+        L.oracle_fill_periodic.argtypes = [_ip, _dp]
+        L.oracle_rk4.argtypes = [_dp, _ip, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp]
+        L.oracle_rk4_cs.argtypes = [_dp, _dp, _ip, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp, _dp]
+        L.oracle_rhs_point.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_gepp.argtypes = [ctypes.c_int, _dp, _dp, _dp]
+        L.oracle_gepp.restype = ctypes.c_double
+        L.oracle_stencils.argtypes = [_ip, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _c(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def _dims(u):
+    nz, ny, nx = (s - 2 * NG for s in u.shape[1:])
+    return np.array([nx, ny, nz], dtype=np.int32)
+
+
+def _spacing(dx):
+    if np.isscalar(dx):
+        dx = (dx, dx, dx)
+    return np.array(dx, dtype=np.float64)
+
+
+def rhs(params, u, dx):
+    """Right-hand side (incl. Kreiss-Oliger) on interior cells; ghosts of the result are 0."""
+    u = _c(u)
+    out = np.zeros_like(u)
+    p = _c(params)
+    dims = _dims(u)
+    flags = lib().oracle_rhs(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(u), _d(out))
+    return out, flags
+
+
+def rhs_cells(params, u, dx, cells):
+    """Right-hand side at interior cells given as an (n, 3) array of (i, j, k)."""
+    u = _c(u)
+    cells = np.ascontiguousarray(cells, dtype=np.int32)
+    out = np.zeros((cells.shape[0], NF))
+    p = _c(params)
+    dims = _dims(u)
+    flags = lib().oracle_rhs_cells(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(u), cells.shape[0],
+                                   cells.ctypes.data_as(_ip), _d(out))
+    return out, flags
+
+
+def rhs_cs(params, theta_im, u_re, u_im, dx):
+    """Complex-step right-hand side. Returns (real part, imaginary part)."""
+    u_re = _c(u_re)
+    u_im = _c(u_im) if u_im is not None else np.zeros_like(u_re)
+    r_re = np.zeros_like(u_re)
+    r_im = np.zeros_like(u_re)
+    p = _c(params)
+    ti = _c(theta_im)
+    dims = _dims(u_re)
+    lib().oracle_rhs_cs(_d(p), _d(ti), dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(u_re), _d(u_im),
+                        _d(r_re), _d(r_im))
+    return r_re, r_im
+
+
+def constraints(params, u, dx):
+    """Hamiltonian (nz,ny,nx) and momentum (3,nz,ny,nx) constraints on the interior."""
+    u = _c(u)
+    ham = np.zeros(u.shape[1:])
+    mom = np.zeros((NF,) + u.shape[1:])  # only the first 3 fields are written
+    p = _c(params)
+    dims = _dims(u)
+    lib().oracle_constraints(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(u), _d(ham), _d(mom))
+    s = (slice(NG, -NG),) * 3
+    return ham[s], mom[(slice(0, 3),) + s]
+
+
+def fill_periodic(u):
+    u = _c(u).copy()
+    dims = _dims(u)
+    lib().oracle_fill_periodic(dims.ctypes.data_as(_ip), _d(u))
+    return u
+
+
+def rk4(params, u, dx, dt, nsteps, periodic):
+    """nsteps classic RK4 steps; returns (new state, flags)."""
+    u = _c(u).copy()
+    p = _c(params)
+    dims = _dims(u)
+    flags = lib().oracle_rk4(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), 1 if periodic else 0,
+                             float(dt), int(nsteps), _d(u))
+    return u, flags
+
+
+def rk4_cs(params, theta_im, u_re, u_im, dx, dt, nsteps, periodic):
+    """Complex-step RK4: returns (real state, imaginary state)."""
+    u_re = _c(u_re).copy()
+    u_im = _c(u_im).copy()
+    p = _c(params)
+    ti = _c(theta_im)
+    dims = _dims(u_re)
+    lib().oracle_rk4_cs(_d(p), _d(ti), dims.ctypes.data_as(_ip), _d(_spacing(dx)), 1 if periodic else 0,
+                        float(dt), int(nsteps), _d(u_re), _d(u_im))
+    return u_re, u_im
+
+
+def rhs_point(params, u, d1, d2, adv):
+    """Pointwise right-hand side from values u[27], d1[27,3], d2[27,6], adv[27,3].
+    Returns (rhs[27], extra dict, flags)."""
+    p = _c(params)
+    u = _c(u)
+    d1 = _c(d1)
+    d2 = _c(d2)
+    adv = _c(adv)
+    out = np.zeros(NF)
+    extra = np.zeros(68)
+    flags = lib().oracle_rhs_point(_d(p), _d(u), _d(d1), _d(d2), _d(adv), _d(out), _d(extra))
+    ex = dict(ham=extra[0], mom=extra[1:4], C=extra[4:10], p=extra[10],
+              A=extra[11:60].reshape(7, 7), b=extra[60:67], pivot_ratio=extra[67])
+    return out, ex, flags
+
+
+def gepp(A, b):
+    A = _c(A)
+    b = _c(b)
+    x = np.zeros(b.shape[0])
+    ratio = lib().oracle_gepp(int(b.shape[0]), _d(A), _d(b), _d(x))
+    return x, ratio
+
+
+def stencils(f, dx, i, j, k):
+    """Stencils of a scalar field f (shape (nz+6, ny+6, nx+6)) at interior cell (i,j,k):
+    dict with d1[3], d2[6], adv_plus[3], adv_minus[3], ko."""
+    f = _c(f)
+    nz, ny, nx = (s - 2 * NG for s in f.shape)
+    dims = np.array([nx, ny, nz], dtype=np.int32)
+    out = np.zeros(16)
+    lib().oracle_stencils(dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(f), i, j, k, _d(out))
+    return dict(d1=out[0:3], d2=out[3:9], adv_plus=out[9:12], adv_minus=out[12:15], ko=out[15])

@@ -1,0 +1,433 @@
+"""Pins of the CPU oracle against what mathematics fixes (no GPU needed).
+
+Each test ties the oracle to something other than itself:
+  * stencils: exactness on polynomials (closed form);
+  * flat space: every right-hand side exactly 0.0 (special case);
+  * covariant pin: random spacetimes solved to satisfy the covariant field
+    equations at a point, differentiated by autograd (brute-force symbolic);
+  * static Schwarzschild: RHS -> 0 at 4th order (closed form);
+  * Gauss-Bonnet source on Schwarzschild: d p / d lambda_gb -> lambda' 48 M^2/R^6;
+  * FLRW: homogeneous data reproduce the Euler-Lagrange equations of the
+    minisuperspace Lagrangian (sympy);
+  * the 7x7 solve against numpy.linalg.solve;
+  * complex-step tangent against central differences;
+  * periodic ghost fill against numpy's wrap padding;
+  * 4th-order self-convergence of the Hamiltonian constraint;
+  * bounded growth on the robust-stability noise test.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2309_06225_amd import inputs as I
+
+IDX = I.IDX
+NONGAUGE = [i for i in range(27) if not (18 <= i <= 24)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _build():
+    O.build(force=False)
+
+
+# ------------------------------------------------------------------ stencils
+def _poly_field(n, dx, coeffs, degree):
+    """sum c_{abc} x^a y^b z^c over a+b+c <= degree on the grid (incl. ghosts)."""
+    X, Y, Z = I.coords((n, n, n), dx)
+    f = np.zeros_like(X)
+    derivs = {}
+    for (a, b, c), cf in coeffs.items():
+        f += cf * X ** a * Y ** b * Z ** c
+    return f, X, Y, Z
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3, 4])
+def test_stencils_exact_on_polynomials(degree):
+    rng = np.random.default_rng(degree)
+    n, dx = 8, 2.0 ** -2
+    terms = [(a, b, c) for a in range(degree + 1) for b in range(degree + 1) for c in range(degree + 1)
+             if a + b + c <= degree]
+    coeffs = {t: float(rng.integers(-3, 4)) for t in terms}
+    f, X, Y, Z = _poly_field(n, dx, coeffs, degree)
+    for (i, j, k) in [(0, 0, 0), (3, 4, 5), (7, 7, 7)]:
+        s = O.stencils(f, dx, i, j, k)
+        x, y, z = X[k + 3, j + 3, i + 3], Y[k + 3, j + 3, i + 3], Z[k + 3, j + 3, i + 3]
+
+        def d(px, py, pz):
+            tot = 0.0
+            for (a, b, c), cf in coeffs.items():
+                if a < px or b < py or c < pz:
+                    continue
+                fa = np.prod(range(a - px + 1, a + 1)) if px else 1
+                fb = np.prod(range(b - py + 1, b + 1)) if py else 1
+                fc = np.prod(range(c - pz + 1, c + 1)) if pz else 1
+                tot += cf * fa * fb * fc * x ** (a - px) * y ** (b - py) * z ** (c - pz)
+            return tot
+
+        exact_d1 = [d(1, 0, 0), d(0, 1, 0), d(0, 0, 1)]
+        exact_d2 = [d(2, 0, 0), d(1, 1, 0), d(1, 0, 1), d(0, 2, 0), d(0, 1, 1), d(0, 0, 2)]
+        scale = max(1.0, np.abs(f).max())
+        np.testing.assert_allclose(s["d1"], exact_d1, rtol=0, atol=1e-12 * scale / dx)
+        np.testing.assert_allclose(s["d2"], exact_d2, rtol=0, atol=1e-12 * scale / dx ** 2)
+        np.testing.assert_allclose(s["adv_plus"], exact_d1, rtol=0, atol=1e-12 * scale / dx)
+        np.testing.assert_allclose(s["adv_minus"], exact_d1, rtol=0, atol=1e-12 * scale / dx)
+        assert abs(s["ko"]) <= 1e-12 * scale / dx
+
+
+def test_stencils_order_five_upwind_is_not_exact_but_ko_is():
+    """Degree 5: Kreiss-Oliger (a 6th difference) still annihilates it; the
+    4th-order first-derivative stencils do not (guards against a test that
+    cannot fail)."""
+    n, dx = 8, 0.25
+    X, Y, Z = I.coords((n, n, n), dx)
+    f = X ** 5
+    s = O.stencils(f, dx, 3, 3, 3)
+    assert abs(s["ko"]) < 1e-10
+    x = X[6, 6, 6]
+    assert abs(s["d1"][0] - 5 * x ** 4) > 1e-6
+    # the 6th difference of x^6 is 720 h^6, so KO = 720 h^6 / (64 h)
+    s6 = O.stencils(X ** 6, dx, 3, 3, 3)
+    assert s6["ko"] == pytest.approx(720 * dx ** 6 / (64 * dx), rel=1e-9)
+
+
+# ------------------------------------------------------------------ flat space
+@pytest.mark.parametrize("lam,g2,a,b", [(0.1, 0.01, 0.2, 0.4), (0.0, 0.0, 0.0, 0.0), (2.0, 1.0, 0.5, 1.0)])
+def test_flat_space_exactly_zero(lam, g2, a, b):
+    p = I.params_vector(I.default_params(lambda_gb=lam, g2=g2, a_gauge=a, b_gauge=b, kappa2=0.3))
+    u = I.set_flat(I.empty_state((6, 5, 7)))
+    r, flags = O.rhs(p, u, (0.25, 0.5, 0.125))
+    assert flags == 0
+    assert np.all(r == 0.0)
+
+
+# ------------------------------------------------------------------ covariant pin
+COV_PARAMS = [
+    dict(lambda_gb=0.3, g2=0.2, b_gauge=0.4, kappa1=0.1, kappa2=-0.3),
+    dict(lambda_gb=0.0, g2=0.0, b_gauge=0.0, kappa1=0.1, kappa2=0.0),   # pure CCZ4 + free scalar
+    dict(lambda_gb=0.0, g2=0.0, b_gauge=0.7, kappa1=0.2, kappa2=0.5),   # b-terms, no coupling
+    dict(lambda_gb=0.5, g2=0.0, b_gauge=0.0, kappa1=0.0, kappa2=0.0),   # Gauss-Bonnet only
+    dict(lambda_gb=0.0, g2=0.4, b_gauge=0.2, kappa1=0.1, kappa2=0.1),   # X^2 only
+]
+
+
+@pytest.mark.parametrize("case", range(len(COV_PARAMS)))
+@pytest.mark.parametrize("seed", [11, 12])
+def test_covariant_pointwise_pin(case, seed):
+    import covariant_ref as C
+    params = I.default_params(kappa3=1.0, a_gauge=0.0, **COV_PARAMS[case])
+    ref = C.reference_point(seed + 7 * case, params)
+    assert ref["residual"] < 1e-12
+    rhs, ex, flags = O.rhs_point(I.params_vector(params), ref["u"], ref["d1"], ref["d2"], ref["d1"])
+    assert flags == 0
+    scale = np.abs(ref["dt"][NONGAUGE]).max()
+    np.testing.assert_allclose(rhs[NONGAUGE], ref["dt"][NONGAUGE], rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(ex["C"], ref["C"], rtol=0, atol=1e-12 * np.abs(ref["C"]).max())
+    assert ex["p"] == pytest.approx(ref["p"], abs=1e-12 * max(1.0, abs(ref["p"])))
+
+
+def test_standard_gauge_when_a_is_zero():
+    """a = 0 gives back the 1+log lapse and the B-form Gamma-driver."""
+    rng = np.random.default_rng(5)
+    u = np.zeros(27)
+    u[IDX["chi"]] = 0.8
+    for f in ("h11", "h22", "h33"):
+        u[IDX[f]] = 1.0
+    u[IDX["K"]] = 0.3
+    u[IDX["Theta"]] = 0.1
+    u[IDX["lapse"]] = 0.7
+    u[19:25] = rng.uniform(-0.3, 0.3, 6)
+    d1 = rng.uniform(-0.2, 0.2, (27, 3))
+    d2 = np.zeros((27, 6))
+    adv = rng.uniform(-0.2, 0.2, (27, 3))
+    p = I.default_params(a_gauge=0.0)
+    rhs, _, _ = O.rhs_point(I.params_vector(p), u, d1, d2, adv)
+    beta = u[19:22]
+    assert rhs[IDX["lapse"]] == pytest.approx(beta @ adv[IDX["lapse"]] - 2.0 * 0.7 * (0.3 - 0.2), rel=1e-14)
+    np.testing.assert_allclose(rhs[19:22], 0.75 * u[22:25], rtol=1e-15)
+
+
+# ------------------------------------------------------------------ Schwarzschild
+def _schwarzschild(n, dx, centre, phi0=0.0):
+    u = I.puncture((n, n, n), dx, centre=centre)
+    X, Y, Z = I.coords((n, n, n), dx, centre)
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    u[IDX["lapse"]] = (1 - 1 / (2 * r)) / (1 + 1 / (2 * r))
+    u[IDX["phi"]] = phi0
+    return u, r
+
+
+def test_schwarzschild_static_fourth_order():
+    p = I.params_vector(I.default_params(a_gauge=0.0))
+    errs = []
+    for n in (8, 16, 32):
+        u, _ = _schwarzschild(n, 1.0 / n, (2.0, 0.5, 0.25))
+        r, flags = O.rhs(p, u, 1.0 / n)
+        assert flags == 0
+        errs.append(np.abs(I.interior(r)).max(axis=(1, 2, 3)))
+    errs = np.array(errs)
+    for f in (IDX["K"], IDX["A11"], IDX["A12"], IDX["Theta"]):
+        order = np.log2(errs[:-1, f] / errs[1:, f])
+        assert order[-1] > 3.7, (I.FIELDS[f], order)
+    # fields whose exact and discrete right-hand sides both vanish identically
+    for f in ("h11", "h12", "Gam1", "shift1", "B1", "phi", "Pi"):
+        assert errs[:, IDX[f]].max() == 0.0
+
+
+def test_gauss_bonnet_source_on_schwarzschild():
+    """With phi = phi0 constant and Pi = 0 the scalar source is lambda' L_GB,
+    and L_GB on Schwarzschild is the Kretschmann scalar 48 M^2 / R^6 (R the
+    areal radius).  d p / d lambda_gb at lambda_gb = 0 by complex step."""
+    phi0, h = 0.7, 1e-20
+    errs = []
+    for n in (8, 16, 32):
+        dx = 1.0 / n
+        u, r = _schwarzschild(n, dx, (2.0, 0.5, 0.25), phi0=phi0)
+        pp = I.params_vector(I.default_params(a_gauge=0.0, lambda_gb=0.0))
+        _, rim = O.rhs_cs(pp, np.array([h, 0.0]), u, None, dx)
+        dp = I.interior(rim[IDX["Pi"]]) / h / I.interior(u[IDX["lapse"]])
+        ri = I.interior(r)
+        R = ri * (1 + 1 / (2 * ri)) ** 2
+        exact = 0.5 * phi0 * 48.0 / R ** 6
+        errs.append(np.abs(dp - exact).max() / np.abs(exact).max())
+    assert errs[-1] < 1e-6
+    assert np.log2(errs[-2] / errs[-1]) > 3.7
+
+
+# ------------------------------------------------------------------ FLRW
+def _flrw_equations():
+    import sympy as sp
+    t = sp.symbols("t")
+    lgb, g2 = sp.symbols("lambda_gb g2")
+    a = sp.Function("a")(t)
+    N = sp.Function("N")(t)
+    ph = sp.Function("phi")(t)
+    ad, pd = a.diff(t), ph.diff(t)
+    lam = lgb * ph ** 2 / 4
+    # minisuperspace Lagrangian of (1/16pi) sqrt(-g)[R + X + lambda L_GB + g2 X^2]
+    # for ds^2 = -N^2 dt^2 + a^2 dx^2, after integrating total derivatives by parts
+    L = (-6 * a * ad ** 2 / N + a ** 3 * pd ** 2 / (2 * N) + g2 * a ** 3 * pd ** 4 / (4 * N ** 3)
+         - 8 * sp.diff(lam, ph) * pd * ad ** 3 / N ** 3)
+
+    def EL(q):
+        return sp.diff(L.diff(q.diff(t)), t) - L.diff(q)
+
+    A2, P2 = sp.symbols("A2 P2")
+    sub = {a.diff(t, 2): A2, ph.diff(t, 2): P2}
+    M, b = sp.linear_eq_to_matrix([sp.expand(EL(a).subs(sub)), sp.expand(EL(ph).subs(sub))], [A2, P2])
+    av, adv, pv, pdv, Nv, Ndv = sp.symbols("av adv pv pdv Nv Ndv")
+
+    def num(expr):
+        expr = expr.subs({a.diff(t): adv, ph.diff(t): pdv, N.diff(t): Ndv}).subs({a: av, ph: pv, N: Nv})
+        return sp.lambdify((av, adv, pv, pdv, Nv, Ndv, lgb, g2), expr, "numpy")
+
+    fM = [[num(M[i, j]) for j in range(2)] for i in range(2)]
+    fb = [num(b[i]) for i in range(2)]
+
+    def second_derivs(*args):
+        Mn = np.array([[fM[i][j](*args) for j in range(2)] for i in range(2)], dtype=float)
+        bn = np.array([fb[i](*args) for i in range(2)], dtype=float)
+        return np.linalg.solve(Mn, bn)
+
+    return second_derivs
+
+
+@pytest.mark.timeout(300)
+def test_flrw_minisuperspace():
+    second = _flrw_equations()
+    rng = np.random.default_rng(3)
+    for trial in range(6):
+        lg, gg = 0.3 * rng.uniform(0.2, 1), 0.2 * rng.uniform(0.2, 1)
+        aval, Nval, phv = rng.uniform(0.8, 1.3), rng.uniform(0.7, 1.3), rng.uniform(-1, 1)
+        Pi = rng.uniform(-0.5, 0.5)
+        dl = lg * phv / 2
+        # Friedmann constraint 3H^2 + 12 lambda' Pi H^3 = Pi^2/4 + 3/8 g2 Pi^4, root near GR
+        roots = np.roots([12 * dl * Pi, 3.0, 0.0, -(Pi ** 2 / 4 + 3 / 8 * gg * Pi ** 4)])
+        roots = roots[np.abs(roots.imag) < 1e-12].real
+        sgn = 1.0 if trial % 2 == 0 else -1.0
+        H = roots[np.argmin(np.abs(roots - sgn * abs(Pi) / (2 * np.sqrt(3))))]
+        adot, pdot = H * aval * Nval, Pi * Nval
+        u = I.empty_state((4, 4, 4))
+        u[IDX["chi"]] = aval ** -2
+        for f in ("h11", "h22", "h33"):
+            u[IDX[f]] = 1.0
+        u[IDX["K"]] = -3 * H
+        u[IDX["lapse"]] = Nval
+        u[IDX["phi"]] = phv
+        u[IDX["Pi"]] = Pi
+        p = I.params_vector(I.default_params(lambda_gb=lg, g2=gg, a_gauge=0.3, b_gauge=0.4,
+                                             kappa1=0.1, kappa2=-0.2))
+        r, flags = O.rhs(p, u, 0.5)
+        ham, _ = O.constraints(p, u, 0.5)
+        assert abs(ham[1, 1, 1]) < 1e-14
+        for Nd in (0.0, 0.37):  # the result may not depend on dN/dt
+            A2, P2 = second(aval, adot, phv, pdot, Nval, Nd, lg, gg)
+            dK = -3 * (A2 / (aval * Nval) - adot ** 2 / (aval ** 2 * Nval) - adot * Nd / (aval * Nval ** 2))
+            dPi = P2 / Nval - pdot * Nd / Nval ** 2
+            assert r[IDX["K"], 4, 4, 4] == pytest.approx(dK, rel=1e-11, abs=1e-15)
+            assert r[IDX["Pi"], 4, 4, 4] == pytest.approx(dPi, rel=1e-11, abs=1e-15)
+
+
+# ------------------------------------------------------------------ solver
+def test_gepp_matches_numpy():
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        A = np.eye(7) + 0.3 * rng.standard_normal((7, 7))
+        b = rng.standard_normal(7)
+        x, ratio = O.gepp(A, b)
+        np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=1e-12, atol=1e-13)
+        assert ratio > 0
+    # a pivoting case: zero on the diagonal
+    A = np.eye(7)[[1, 0, 2, 3, 4, 5, 6]] * 1.0
+    b = np.arange(7.0)
+    x, _ = O.gepp(A, b)
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=1e-14)
+
+
+def test_assembled_system_solution_matches_numpy():
+    import covariant_ref as C
+    params = I.default_params(kappa3=1.0, a_gauge=0.0, lambda_gb=0.8, g2=0.3)
+    ref = C.reference_point(31, params)
+    rhs, ex, _ = O.rhs_point(I.params_vector(params), ref["u"], ref["d1"], ref["d2"], ref["d1"])
+    x = np.linalg.solve(ex["A"], ex["b"])
+    np.testing.assert_allclose(x[:6], ex["C"], rtol=1e-12, atol=1e-14)
+    assert x[6] == pytest.approx(ex["p"], rel=1e-12)
+    assert ex["pivot_ratio"] > 1e-3
+
+
+def test_singular_system_is_flagged():
+    """A huge coupling makes the per-cell system lose its diagonal dominance;
+    a degenerate D_Pi (1 + 3 g2 Pi^2 - g2 |d phi|^2 = 0) makes it singular."""
+    u = np.zeros(27)
+    u[IDX["chi"]] = 1.0
+    for f in ("h11", "h22", "h33"):
+        u[IDX[f]] = 1.0
+    u[IDX["lapse"]] = 1.0
+    d1 = np.zeros((27, 3))
+    d1[IDX["phi"]] = [1.0, 0.0, 0.0]
+    p = I.default_params(lambda_gb=0.0, g2=1.0)  # D_Pi = 1 - |d phi|^2 = 0
+    _, ex, flags = O.rhs_point(I.params_vector(p), u, d1, np.zeros((27, 6)), np.zeros((27, 3)))
+    assert flags & 2
+
+
+# ------------------------------------------------------------------ tangent
+def test_complex_step_matches_central_differences():
+    rng = np.random.default_rng(7)
+    n, dx = 6, 0.5
+    u = I.puncture((n, n, n), dx, centre=(2.0, 1.0, 0.5), phi_fn=I.shell_pulse(0.3, 1.5))
+    u += 0.01 * rng.standard_normal(u.shape)
+    v = rng.standard_normal(u.shape)
+    p = I.params_vector(I.default_params(lambda_gb=0.3, g2=0.1))
+    h = 1e-30
+    _, t_cs = O.rhs_cs(p, np.zeros(2), u, h * v, dx)
+    t_cs = t_cs / h
+    eps = 1e-6
+    rp, _ = O.rhs(p, u + eps * v, dx)
+    rm, _ = O.rhs(p, u - eps * v, dx)
+    t_fd = (rp - rm) / (2 * eps)
+    assert np.abs(t_cs - t_fd).max() < 1e-7 * np.abs(t_cs).max()
+    # tangent in the couplings
+    for q in range(2):
+        th = np.zeros(2)
+        th[q] = h
+        _, t_cs = O.rhs_cs(p, th, u, None, dx)
+        pp, pm = p.copy(), p.copy()
+        pp[q] += eps
+        pm[q] -= eps
+        t_fd = (O.rhs(pp, u, dx)[0] - O.rhs(pm, u, dx)[0]) / (2 * eps)
+        assert np.abs(t_cs / h - t_fd).max() < 1e-7 * max(np.abs(t_fd).max(), 1e-30)
+
+
+# ------------------------------------------------------------------ boundaries
+def test_periodic_fill_matches_numpy_wrap():
+    rng = np.random.default_rng(1)
+    u = rng.standard_normal((27, 5 + 6, 4 + 6, 6 + 6))
+    got = O.fill_periodic(u)
+    want = I.wrap_ghosts(u)
+    assert np.array_equal(got, want)
+
+
+# ------------------------------------------------------------------ convergence
+def _smooth_periodic(n, L, ny=4):
+    dims = (n, ny, ny)
+    dx = L / n
+    u = I.set_flat(I.empty_state(dims))
+    X, Y, Z = I.coords(dims, dx)
+    k = 2 * np.pi / L
+    s = (slice(None),) * 3
+    u[IDX["phi"]] = 0.2 * np.sin(k * X)
+    u[IDX["Pi"]] = 0.1 * np.cos(k * X)
+    u[IDX["lapse"]] = 1.0 + 0.1 * np.sin(k * X + 0.3)
+    u[IDX["h11"]] = 1.0 + 0.05 * np.sin(k * X)
+    u[IDX["h22"]] = 1.0 / (1.0 + 0.05 * np.sin(k * X))
+    u[IDX["shift1"]] = 0.05 * np.cos(k * X)
+    u[IDX["K"]] = 0.05 * np.sin(k * X + 1.0)
+    del s
+    return I.wrap_ghosts(u), dx
+
+
+def test_hamiltonian_self_convergence_fourth_order():
+    """Self-convergence of the Hamiltonian constraint at a fixed time on smooth
+    periodic data (varying along x), compared through its lowest Fourier modes
+    (midpoint quadrature is spectrally accurate for periodic data)."""
+    L, T = 8.0, 1.0
+    p = I.params_vector(I.default_params())
+    coefs = []
+    for n in (16, 32, 64):
+        u, dx = _smooth_periodic(n, L)
+        dt = 0.25 * dx
+        steps = int(round(T / dt))
+        u, flags = O.rk4(p, u, dx, dt, steps, periodic=True)
+        assert flags == 0
+        ham, _ = O.constraints(p, u, dx)
+        X, _, _ = I.coords((n, 4, 4), dx)
+        x = I.interior(X[None])[0]
+        c = [np.mean(ham * np.exp(-1j * m * 2 * np.pi * x / L)) for m in (0, 1, 2)]
+        coefs.append(np.array(c))
+    coefs = np.array(coefs)
+    d1 = np.abs(coefs[0] - coefs[1])
+    d2 = np.abs(coefs[1] - coefs[2])
+    order = np.log2(d1 / d2)
+    assert np.all(np.abs(order - 4.0) < 0.3), order
+
+
+def _flat_noise(n, amp, seed):
+    dims = (n, n, n)
+    u = I.set_flat(I.empty_state(dims))
+    rng = np.random.default_rng(seed)
+    inner = (slice(3, -3),) * 3
+    for f in range(27):
+        u[(f,) + inner] += rng.uniform(-amp, amp, (n, n, n))
+    return I.wrap_ghosts(u)
+
+
+def _growth_run(n, steps, seed):
+    """Run flat space + 1e-6 noise; return (max|Ham|, max|u - flat|) at t=0, T/2, T."""
+    p = I.params_vector(I.default_params())
+    dx = 0.25 * 32 / n
+    u = _flat_noise(n, 1e-6, seed)
+    flat = I.set_flat(I.empty_state((n, n, n)))
+    hist = [(np.abs(O.constraints(p, u, dx)[0]).max(), np.abs(u - flat).max())]
+    for _ in range(2):
+        u, flags = O.rk4(p, u, dx, 0.25 * dx, steps // 2, periodic=True)
+        assert flags == 0
+        hist.append((np.abs(O.constraints(p, u, dx)[0]).max(), np.abs(u - flat).max()))
+    return np.array(hist)
+
+
+@pytest.mark.parametrize("n,steps", [(8, 400), (12, 200)])
+def test_robust_stability_noise(n, steps):
+    """Flat space with 1e-6 noise: the Hamiltonian constraint stays bounded and
+    the deviation from flat space grows at most linearly in time (a drift of the
+    unenforced algebraic constraints), never exponentially."""
+    h = _growth_run(n, steps, n)
+    assert h[1:, 0].max() < 10 * h[0, 0]
+    assert h[2, 1] < 2.5 * h[1, 1]
+    assert h[2, 1] < 100 * h[0, 1]
+
+
+@pytest.mark.slow
+def test_robust_stability_noise_long():
+    for n in (8, 16):
+        h = _growth_run(n, 1000, 100 + n)
+        assert h[1:, 0].max() < 10 * h[0, 0]
+        assert h[2, 1] < 2.5 * h[1, 1]
