@@ -1,0 +1,145 @@
+/*
+ * libgrf -- MI355X (gfx950) FP64 hot path of the 4dST + modified-CCZ4 method:
+ * the pointwise right-hand side of CCZ4 in the modified puncture gauge coupled
+ * to a scalar field with the four-derivative scalar-tensor terms, with
+ * Kreiss-Oliger dissipation, and the classic RK4 stage update, on 3-D boxes with
+ * three ghost cells (the method named in the paper's Summary and Key features:
+ * 4dST theory, modified moving-puncture gauge, 4th-order finite differences,
+ * RK4, periodic boundaries).
+ *
+ * Conventions shared by every call
+ *  - State layout: 27 FP64 fields, field-major; field f of a box starts at
+ *    f * field_stride; within a field, cells are [z][y][x] with x fastest over
+ *    (nx+6) x (ny+6) x (nz+6) cells (3 ghost cells on every side).  Field order:
+ *      chi, h11 h12 h13 h22 h23 h33, K, A11 A12 A13 A22 A23 A33, Theta,
+ *      Gam1 Gam2 Gam3, lapse, shift1 shift2 shift3, B1 B2 B3, phi, Pi.
+ *  - Interior arrays ("compact"): 27 fields, field-major, nx*ny*nz cells each,
+ *    [z][y][x] with x fastest, no ghosts (used for the RK4 accumulator).
+ *  - Every pointer argument named u*, rhs, acc, w*, *_bar, workspace is device
+ *    memory owned by the caller; grf_params / grf_box are host structs read at
+ *    call time.  Nothing is allocated by these calls.
+ *  - All calls are asynchronous on `stream` (0 = the null stream).  Argument
+ *    errors are detected on the host, returned synchronously, and leave every
+ *    output untouched.  Conditions found on the device (non-finite results, a
+ *    near-singular per-cell system, chi <= 0 or lapse <= 0) are OR-ed into a
+ *    status word at the start of the workspace; read it with
+ *    grf_status_fetch, clear it with grf_status_clear.
+ *  - Calls that share a workspace must not overlap in time (same stream, or
+ *    ordered by events).
+ */
+#ifndef GRF_H
+#define GRF_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GRF_OK = 0,
+  GRF_EINVAL = 1,        /* null pointer, bad stage number, bad parameter value   */
+  GRF_ESHAPE = 2,        /* box dimensions, ghost count or field stride invalid   */
+  GRF_EHIP = 3,          /* a HIP runtime call failed                              */
+  GRF_ENONFINITE = 4,    /* device: a right-hand side was NaN or infinite         */
+  GRF_EHYPERBOLIC = 5,   /* device: the per-cell 7x7 system was near-singular     */
+  GRF_ENOMEM = 6,        /* workspace smaller than required                       */
+  GRF_EUNSUPPORTED = 7,  /* parameter combination not implemented                 */
+  GRF_ENONPOSITIVE = 8   /* device: chi <= 0 or lapse <= 0 at some cell          */
+} grf_status;
+
+enum { GRF_NFIELDS = 27, GRF_NTHETA = 2, GRF_NGHOST = 3 };
+enum { GRF_BC_FROZEN = 0, GRF_BC_PERIODIC = 1 };
+enum { GRF_LAMBDA_QUADRATIC = 0 };
+/* device status bits (grf_status_fetch's *bits) */
+enum { GRF_FLAG_NONFINITE = 1, GRF_FLAG_HYPERBOLIC = 2, GRF_FLAG_NONPOSITIVE = 4 };
+
+/* Couplings and gauge.  lambda(phi) = lambda_gb phi^2 / 4 (lambda_kind 0 only),
+ * g2 constant, V = 0.  a_gauge, b_gauge: the modified-gauge functions a(x), b(x)
+ * (constants).  lapse: d_t alpha = lapse_advec beta.d alpha
+ *   - lapse_coeff alpha^lapse_power (K - 2 Theta) / (1 + a)   (lapse_power 1 only);
+ * shift (B form): d_t beta^i = shift_advec beta.d beta^i + shift_gamma_coeff B^i
+ *   - a/(1+a) alpha D^i alpha,  d_t B^i = d_t Gam^i/(1+a) - eta B^i (+ advection).
+ * enforce / chi_min / lapse_min: post-stage algebraic enforcement (0 = off). */
+typedef struct {
+  double lambda_gb;
+  int32_t lambda_kind;
+  double g2;
+  double a_gauge, b_gauge;
+  double kappa1, kappa2, kappa3;
+  double lapse_coeff, lapse_power, lapse_advec;
+  double shift_gamma_coeff, shift_advec, eta;
+  double ko_sigma;
+  int32_t enforce;
+  double chi_min, lapse_min;
+} grf_params;
+
+/* One box: nx, ny, nz interior cells, ng ghosts (must be 3), spacing dx, dy,
+ * dz, coordinates x0, y0, z0 of interior cell (0,0,0) (informational),
+ * field_stride >= (nx+6)(ny+6)(nz+6), boundary rule bc. */
+typedef struct {
+  int32_t nx, ny, nz, ng;
+  double dx, dy, dz;
+  double x0, y0, z0;
+  int64_t field_stride;
+  int32_t bc;
+} grf_box;
+
+/* Bytes of workspace needed by grf_rhs_eval / grf_rk4_stage on this machine
+ * (the status word plus one 198-component derivative record per interior cell). */
+size_t grf_workspace_bytes(const grf_box* box);
+
+/* Right-hand side d_t u (including Kreiss-Oliger) at interior cells of u,
+ * written to the interior cells of rhs (state layout; ghosts of rhs untouched). */
+grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u, double* rhs,
+                        void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* One classic RK4 stage (c = 1/2, 1/2, 1; weights 1, 2, 2, 1 over 6), stage in 1..4.
+ * Reads u0 (state at the start of the step) and us (the stage state; us == u0 at
+ * stage 1), computes k = RHS(us) and
+ *   stage 1: acc  = dt/6 k;        unext = u0 + dt/2 k
+ *   stage 2: acc += dt/3 k;        unext = u0 + dt/2 k
+ *   stage 3: acc += dt/3 k;        unext = u0 + dt k
+ *   stage 4:                       unext = u0 + acc + dt/6 k   (the new state)
+ * on interior cells.  acc is compact (27 x nx*ny*nz).  unext must not alias us
+ * or u0.  GRF_BC_PERIODIC: the ghosts of unext are then filled periodically;
+ * GRF_BC_FROZEN: ghosts of unext are not written (the caller keeps them at the
+ * frozen values, e.g. by allocating unext as a copy of the initial state). */
+grf_status grf_rk4_stage(const grf_params* p, const grf_box* box, int stage, double dt, const double* u0,
+                         const double* us, double* unext, double* acc, void* workspace, size_t workspace_bytes,
+                         hipStream_t stream);
+
+/* Periodic ghost fill of a state (every ghost copies the interior cell congruent
+ * to it modulo the box size), on the device. */
+grf_status grf_fill_periodic(const grf_box* box, double* u, hipStream_t stream);
+
+/* Vector-Jacobian product of the right-hand side: with w a cotangent of
+ * grf_rhs_eval's output (state layout, interior cells read),
+ *   u_bar     += (d RHS / d u)^T w      over all cells of u, ghosts included,
+ *   theta_bar += (d RHS / d (lambda_gb, g2))^T w   (2 doubles, device memory),
+ * the coupling sum taken in a fixed order (deterministic).  Workspace size from
+ * grf_vjp_workspace_bytes. */
+size_t grf_vjp_workspace_bytes(const grf_box* box);
+grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u, const double* w, double* u_bar,
+                       double* theta_bar, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Device status word kept at the start of a workspace: synchronises `stream`,
+ * returns GRF_OK or the device condition of highest precedence (NONFINITE,
+ * then HYPERBOLIC, then NONPOSITIVE), and stores the raw bits in *bits if non-null. */
+grf_status grf_status_fetch(const void* workspace, hipStream_t stream, uint32_t* bits);
+grf_status grf_status_clear(void* workspace, hipStream_t stream);
+
+/* Algorithmic FP64 flops per interior cell: the pointwise algebra of one RHS
+ * (shift advection on or off) and of its VJP, counted on the expression graph
+ * (add, sub, mul and reciprocal each 1), stencils not included. */
+int64_t grf_flops_per_cell(int which /* 0 rhs, 1 rhs with shift advection, 2 vjp */);
+
+/* Human-readable reason of the last error returned on this host thread. */
+const char* grf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRF_H */

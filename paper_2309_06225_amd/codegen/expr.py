@@ -1,0 +1,283 @@
+"""A small expression-DAG builder that emits straight-line HIP device code.
+
+The pointwise 4dST/CCZ4 algebra is described once with these nodes; the same
+graph is emitted as the forward right-hand side and, by reverse-mode
+accumulation over the graph, as its vector-Jacobian product.  Nodes are
+hash-consed (common subexpressions are shared), constants are folded, and the
+emitted code is a list of ``const double`` definitions that the HIP compiler
+schedules and register-allocates.
+"""
+from __future__ import annotations
+
+import math
+
+
+class Graph:
+    def __init__(self):
+        self.nodes: list[Node] = []
+        self.table: dict = {}
+
+    def _new(self, op, a=None, b=None, val=None, name=None):
+        key = (op, a.idx if a is not None else None, b.idx if b is not None else None, val, name)
+        hit = self.table.get(key)
+        if hit is not None:
+            return hit
+        n = Node(self, op, a, b, val, name, len(self.nodes))
+        self.nodes.append(n)
+        self.table[key] = n
+        return n
+
+    # leaves
+    def const(self, v: float) -> "Node":
+        v = float(v)
+        if v == 0.0:
+            v = 0.0  # fold -0.0
+        return self._new("c", val=v)
+
+    def input(self, name: str) -> "Node":
+        return self._new("in", name=name)
+
+    def param(self, name: str) -> "Node":
+        return self._new("p", name=name)
+
+    # arithmetic with folding
+    def add(self, a, b):
+        a, b = self.lift(a), self.lift(b)
+        if a.is_const(0.0):
+            return b
+        if b.is_const(0.0):
+            return a
+        if a.op == "c" and b.op == "c":
+            return self.const(a.val + b.val)
+        if b.op == "neg":
+            return self.sub(a, b.a)
+        if a.op == "neg":
+            return self.sub(b, a.a)
+        if a.idx > b.idx:
+            a, b = b, a
+        return self._new("+", a, b)
+
+    def sub(self, a, b):
+        a, b = self.lift(a), self.lift(b)
+        if b.is_const(0.0):
+            return a
+        if a.is_const(0.0):
+            return self.neg(b)
+        if a is b:
+            return self.const(0.0)
+        if a.op == "c" and b.op == "c":
+            return self.const(a.val - b.val)
+        if b.op == "neg":
+            return self.add(a, b.a)
+        return self._new("-", a, b)
+
+    def mul(self, a, b):
+        a, b = self.lift(a), self.lift(b)
+        if a.is_const(0.0) or b.is_const(0.0):
+            return self.const(0.0)
+        if a.is_const(1.0):
+            return b
+        if b.is_const(1.0):
+            return a
+        if a.is_const(-1.0):
+            return self.neg(b)
+        if b.is_const(-1.0):
+            return self.neg(a)
+        if a.op == "c" and b.op == "c":
+            return self.const(a.val * b.val)
+        if a.op == "neg" and b.op == "neg":
+            return self.mul(a.a, b.a)
+        if a.op == "neg":
+            return self.neg(self.mul(a.a, b))
+        if b.op == "neg":
+            return self.neg(self.mul(a, b.a))
+        if a.idx > b.idx:
+            a, b = b, a
+        return self._new("*", a, b)
+
+    def div(self, a, b):
+        a, b = self.lift(a), self.lift(b)
+        if b.is_const(1.0):
+            return a
+        if a.is_const(0.0):
+            return self.const(0.0)
+        if b.op == "c":
+            return self.mul(a, 1.0 / b.val)
+        if a.op == "c" and a.val == 1.0:
+            return self._new("rcp", b)
+        return self.mul(a, self._new("rcp", b))
+
+    def neg(self, a):
+        a = self.lift(a)
+        if a.op == "c":
+            return self.const(-a.val)
+        if a.op == "neg":
+            return a.a
+        return self._new("neg", a)
+
+    def lift(self, x):
+        if isinstance(x, Node):
+            return x
+        return self.const(x)
+
+    def sum(self, terms):
+        acc = self.const(0.0)
+        for t in terms:
+            acc = self.add(acc, t)
+        return acc
+
+
+class Node:
+    __slots__ = ("g", "op", "a", "b", "val", "name", "idx")
+
+    def __init__(self, g, op, a, b, val, name, idx):
+        self.g, self.op, self.a, self.b, self.val, self.name, self.idx = g, op, a, b, val, name, idx
+
+    def is_const(self, v):
+        return self.op == "c" and self.val == v
+
+    def __add__(self, o):
+        return self.g.add(self, o)
+
+    def __radd__(self, o):
+        return self.g.add(o, self)
+
+    def __sub__(self, o):
+        return self.g.sub(self, o)
+
+    def __rsub__(self, o):
+        return self.g.sub(o, self)
+
+    def __mul__(self, o):
+        return self.g.mul(self, o)
+
+    def __rmul__(self, o):
+        return self.g.mul(o, self)
+
+    def __truediv__(self, o):
+        return self.g.div(self, o)
+
+    def __rtruediv__(self, o):
+        return self.g.div(o, self)
+
+    def __neg__(self):
+        return self.g.neg(self)
+
+    def __repr__(self):
+        return f"Node({self.op},{self.idx})"
+
+
+def reachable(outputs):
+    """Indices of nodes needed to compute `outputs`."""
+    seen = set()
+    stack = [o for o in outputs]
+    while stack:
+        n = stack.pop()
+        if n.idx in seen:
+            continue
+        seen.add(n.idx)
+        if n.a is not None:
+            stack.append(n.a)
+        if n.b is not None:
+            stack.append(n.b)
+    return seen
+
+
+def vjp(g: Graph, outputs, cotangents, wrt):
+    """Reverse-mode accumulation: returns nodes for sum_k cot_k d out_k / d w."""
+    need = reachable(outputs)
+    wrt_idx = {w.idx for w in wrt}
+    # nodes that depend on any w (only they receive adjoints)
+    varied = set()
+    for n in g.nodes:
+        if n.idx not in need:
+            continue
+        if n.idx in wrt_idx or (n.a is not None and n.a.idx in varied) or (n.b is not None and n.b.idx in varied):
+            varied.add(n.idx)
+    adj: dict[int, Node] = {}
+
+    def acc(x, v):
+        if x.idx not in varied:
+            return
+        adj[x.idx] = v if x.idx not in adj else g.add(adj[x.idx], v)
+
+    for o, c in zip(outputs, cotangents):
+        acc(o, c)
+    order = sorted((g.nodes[i] for i in varied), key=lambda n: -n.idx)
+    for n in order:
+        a = adj.get(n.idx)
+        if a is None or n.op in ("in", "p", "c"):
+            continue
+        if n.op == "+":
+            acc(n.a, a)
+            acc(n.b, a)
+        elif n.op == "-":
+            acc(n.a, a)
+            acc(n.b, g.neg(a))
+        elif n.op == "*":
+            acc(n.a, g.mul(a, n.b))
+            acc(n.b, g.mul(a, n.a))
+        elif n.op == "neg":
+            acc(n.a, g.neg(a))
+        elif n.op == "rcp":  # d(1/x) = -1/x^2
+            acc(n.a, g.neg(g.mul(a, g.mul(n, n))))
+        else:
+            raise ValueError(n.op)
+    return [adj.get(w.idx, g.const(0.0)) for w in wrt]
+
+
+def _lit(v: float) -> str:
+    if v == 0.0:
+        return "0.0"
+    if math.isfinite(v) and float(repr(v)) == v and len(repr(v)) < 18:
+        r = repr(v)
+        return r if ("." in r or "e" in r) else r + ".0"
+    return v.hex()
+
+
+def count_flops(g: Graph, outputs):
+    """add/sub/mul = 1, reciprocal = 1 (R18 convention: div = 1), neg = 0."""
+    need = reachable(outputs)
+    c = {"+": 0, "-": 0, "*": 0, "rcp": 0, "neg": 0}
+    for i in need:
+        op = g.nodes[i].op
+        if op in c:
+            c[op] += 1
+    total = c["+"] + c["-"] + c["*"] + c["rcp"]
+    return total, c
+
+
+def emit(g: Graph, outputs, out_names, input_expr, param_expr, indent="  ", prefix="t"):
+    """Straight-line C for `outputs`.  input_expr(name) / param_expr(name)
+    return C expressions for leaves; out_names are C lvalue templates taking
+    the value expression (e.g. 'OUT(3, {})')."""
+    need = sorted(reachable(outputs))
+    lines = []
+    names = {}
+    for i in need:
+        n = g.nodes[i]
+        if n.op == "c":
+            names[i] = _lit(n.val) if n.val >= 0 else f"({_lit(n.val)})"
+            continue
+        if n.op == "in":
+            expr = input_expr(n.name)
+        elif n.op == "p":
+            expr = param_expr(n.name)
+        elif n.op == "+":
+            expr = f"{names[n.a.idx]} + {names[n.b.idx]}"
+        elif n.op == "-":
+            expr = f"{names[n.a.idx]} - {names[n.b.idx]}"
+        elif n.op == "*":
+            expr = f"{names[n.a.idx]} * {names[n.b.idx]}"
+        elif n.op == "neg":
+            expr = f"-{names[n.a.idx]}"
+        elif n.op == "rcp":
+            expr = f"1.0 / {names[n.a.idx]}"
+        else:
+            raise ValueError(n.op)
+        nm = f"{prefix}{i}"
+        names[i] = nm
+        lines.append(f"{indent}const double {nm} = {expr};")
+    for o, tmpl in zip(outputs, out_names):
+        lines.append(indent + tmpl.format(names[o.idx]) + ";")
+    return "\n".join(lines)

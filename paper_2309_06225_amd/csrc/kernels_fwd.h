@@ -1,0 +1,261 @@
+// Forward kernels of libgrf: LDS-tiled stencil stage, pointwise right-hand side
+// fused with the RK4 stage update, periodic ghost fill, status word.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gen/gen_layout.h"
+
+namespace grf {
+
+constexpr int NF = 27;
+constexpr int NG = 3;
+constexpr int F_CHI = 0, F_LAPSE = 18, F_SHIFT = 19, F_B = 22;
+
+// Geometry of one box as the kernels see it.
+struct BoxDev {
+  int nx, ny, nz;
+  int sy;          // state stride in y (nx + 6)
+  int64_t sz;      // state stride in z ((nx+6)(ny+6))
+  int64_t fs;      // field stride of the state
+  int64_t ncell;   // nx*ny*nz
+  double i12h[3];  // 1/(12 h)
+  double i12h2[3]; // 1/(12 h^2)
+  double i144[3];  // 1/(144 h_x h_y), 1/(144 h_x h_z), 1/(144 h_y h_z)
+  double i64h[3];  // 1/(64 h)
+};
+
+__device__ __forceinline__ bool advected(int f, int shift_adv) {
+  return (f < F_SHIFT || f >= F_B + 3) || shift_adv;
+}
+
+
+// Stencil sums on a line L[0..6] = u at offsets -3..3.  Each sum is taken in
+// increasing offset order with every product rounded on its own (no fused
+// multiply-add), so that the large cancellation of an O(1) background is
+// reproduced exactly; the scale 1/(12 h) etc. is applied afterwards.
+#pragma clang fp contract(off)
+__device__ __forceinline__ double sten_d1(const double* L) {  // 1, -8, 0, 8, -1
+  return ((L[1] - 8.0 * L[2]) + 8.0 * L[4]) - L[5];
+}
+__device__ __forceinline__ double sten_d2(const double* L) {  // -1, 16, -30, 16, -1
+  return ((((-L[1]) + 16.0 * L[2]) - 30.0 * L[3]) + 16.0 * L[4]) - L[5];
+}
+__device__ __forceinline__ double sten_up_plus(const double* L) {  // offsets -1..3: -3, -10, 18, -6, 1
+  return ((((-3.0) * L[2] - 10.0 * L[3]) + 18.0 * L[4]) - 6.0 * L[5]) + L[6];
+}
+__device__ __forceinline__ double sten_up_minus(const double* L) {  // offsets 1, 0, -1, -2, -3: 3, 10, -18, 6, -1
+  return (((3.0 * L[4] + 10.0 * L[3]) - 18.0 * L[2]) + 6.0 * L[1]) - L[0];
+}
+__device__ __forceinline__ double sten_ko(const double* L) {  // 1, -6, 15, -20, 15, -6, 1
+  return (((((L[0] - 6.0 * L[1]) + 15.0 * L[2]) - 20.0 * L[3]) + 15.0 * L[4]) - 6.0 * L[5]) + L[6];
+}
+// 16-point mixed derivative: sum over a (axis d, outer) and b (axis e, inner)
+// of c_a c_b u(a, b), c = (1, -8, 0, 8, -1); the weights are powers of two, so
+// every product is exact.
+__device__ __forceinline__ double sten_mixed(const double* t, int c0, int sd, int se) {
+  const double w[5] = {1.0, -8.0, 0.0, 8.0, -1.0};
+  double s = 0.0;
+#pragma unroll
+  for (int a = -2; a <= 2; ++a) {
+    if (a == 0) continue;
+#pragma unroll
+    for (int bb = -2; bb <= 2; ++bb) {
+      if (bb == 0) continue;
+      s += (w[a + 2] * w[bb + 2]) * t[c0 + a * sd + bb * se];
+    }
+  }
+  return s;
+}
+#pragma clang fp contract(fast)
+
+// ---------------------------------------------------------------------------
+// Stencil stage.  One workgroup = one field of one TX*TY*TZ tile.  The tile and
+// its 3-deep halo are staged in LDS with coalesced row loads, then every thread
+// produces, for its cell, the derivative record of that field:
+//   centred d_k (4th order), d_k d_k and the 16-point mixed d_k d_l,
+//   the upwinded advection sum beta^k D^up_k u (side by the sign of beta^k),
+//   sigma * sum_k (6th difference)/(64 h_k)  (Kreiss-Oliger).
+// Output record: D[comp * ncell + cell], cell = (k*ny + j)*nx + i.
+// With UP non-null the three upwinded derivatives are also stored (for the VJP):
+//   UP[(3 f + k) * ncell + cell].
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX* TY* TZ) void k_deriv(BoxDev b, const double* __restrict__ u,
+                                                      double* __restrict__ D, double ko_sigma, int shift_adv,
+                                                      double* __restrict__ UP) {
+  constexpr int LX = TX + 6, LY = TY + 6, LZ = TZ + 6;
+  __shared__ double t[LZ * LY * LX];
+  const int f = blockIdx.y;
+  const int ntx = (b.nx + TX - 1) / TX, nty = (b.ny + TY - 1) / TY;
+  int tile = blockIdx.x;
+  const int tx0 = (tile % ntx) * TX;
+  tile /= ntx;
+  const int ty0 = (tile % nty) * TY;
+  const int tz0 = (tile / nty) * TZ;
+  const double* __restrict__ uf = u + (int64_t)f * b.fs;
+  // tile origin in state coordinates is (tx0, ty0, tz0): state coord = interior + 3
+  for (int e = threadIdx.x; e < LX * LY * LZ; e += TX * TY * TZ) {
+    const int lx = e % LX;
+    const int r = e / LX;
+    const int ly = r % LY;
+    const int lz = r / LY;
+    const int gx = tx0 + lx, gy = ty0 + ly, gz = tz0 + lz;
+    if (gx < b.nx + 6 && gy < b.ny + 6 && gz < b.nz + 6) t[e] = uf[(int64_t)gz * b.sz + (int64_t)gy * b.sy + gx];
+  }
+  __syncthreads();
+  const int ix = threadIdx.x % TX;
+  const int iy = (threadIdx.x / TX) % TY;
+  const int iz = threadIdx.x / (TX * TY);
+  const int i = tx0 + ix, j = ty0 + iy, k = tz0 + iz;
+  if (i >= b.nx || j >= b.ny || k >= b.nz) return;
+  const int64_t cell = ((int64_t)k * b.ny + j) * b.nx + i;
+  const int c0 = ((iz + 3) * LY + (iy + 3)) * LX + (ix + 3);
+  const int st[3] = {1, LX, LX * LY};
+  double* __restrict__ Dc = D + cell;
+  const int64_t nc = b.ncell;
+
+  double line[3][7];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int o = -3; o <= 3; ++o) line[d][o + 3] = t[c0 + o * st[d]];
+
+  const int s1 = grf_d1_slot[f];
+  if (s1 >= 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) Dc[(int64_t)(GRF_OFF_D1 + 3 * s1 + d) * nc] = sten_d1(line[d]) * b.i12h[d];
+  }
+  const int s2 = grf_d2_slot[f];
+  if (s2 >= 0) {
+    const int pure[3] = {0, 3, 5};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc] = sten_d2(line[d]) * b.i12h2[d];
+    const int pd[3] = {0, 0, 1}, pe[3] = {1, 2, 2}, pq[3] = {1, 2, 4};
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+      Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + pq[m]) * nc] = sten_mixed(t, c0, st[pd[m]], st[pe[m]]) * b.i144[m];
+  }
+  // upwinded advection: the lopsided stencil on the side the shift points to
+  const int64_t sc = (int64_t)(k + 3) * b.sz + (int64_t)(j + 3) * b.sy + (i + 3);
+  double beta[3], up[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    beta[d] = u[(int64_t)(F_SHIFT + d) * b.fs + sc];
+    up[d] = (beta[d] >= 0.0 ? sten_up_plus(line[d]) : sten_up_minus(line[d])) * b.i12h[d];
+    if (UP) UP[(int64_t)(3 * f + d) * nc + cell] = up[d];
+  }
+  if (advected(f, shift_adv)) Dc[(int64_t)(GRF_OFF_ADV + f) * nc] = beta[0] * up[0] + beta[1] * up[1] + beta[2] * up[2];
+  double ko = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) ko += sten_ko(line[d]) * b.i64h[d];
+  Dc[(int64_t)(GRF_OFF_KO + f) * nc] = ko_sigma * ko;
+}
+
+// ---------------------------------------------------------------------------
+// Pointwise right-hand side (generated algebra) fused with the RK4 stage.
+// MODE 0: rhs[f] = k;  MODE 1: first stage;  MODE 2: middle stage;  MODE 4: last stage.
+struct StageCoef {
+  double cacc;   // weight of k added to acc (stage 1: written, not added)
+  double cnext;  // weight of k in unext = u0 (+ acc) + cnext k
+};
+
+template <int MODE, int SHIFTADV>
+__global__ __launch_bounds__(128) void k_point(BoxDev b, grf_point_params P, const double* __restrict__ us,
+                                               const double* __restrict__ D, const double* __restrict__ u0,
+                                               double* __restrict__ out, double* __restrict__ acc, StageCoef sc,
+                                               unsigned* __restrict__ status) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= b.ncell) return;
+  const int i = (int)(c % b.nx);
+  const int64_t r = c / b.nx;
+  const int j = (int)(r % b.ny);
+  const int k = (int)(r / b.ny);
+  const int64_t s = (int64_t)(k + 3) * b.sz + (int64_t)(j + 3) * b.sy + (i + 3);
+  const int64_t nc = b.ncell;
+  double rhs[NF];
+  int bad = 0;
+#define GRF_U(f) us[(int64_t)(f) * b.fs + s]
+#define GRF_D(cc) D[(int64_t)(cc) * nc + c]
+#define GRF_P(n) P.n
+#define GRF_RHS(f, v) rhs[f] = (v)
+#define GRF_PIVCHK(v) bad |= !(fabs(v) <= 1e12)
+#define GRF_SHIFT_ADVEC (SHIFTADV != 0)
+#include "gen/gen_rhs.inc"
+#undef GRF_SHIFT_ADVEC
+#undef GRF_RHS
+#undef GRF_PIVCHK
+  unsigned flags = bad ? 2u : 0u;
+  if (!(us[(int64_t)F_CHI * b.fs + s] > 0.0) || !(us[(int64_t)F_LAPSE * b.fs + s] > 0.0)) flags |= 4u;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const double kf = rhs[f] + D[(int64_t)(GRF_OFF_KO + f) * nc + c];
+    if (!isfinite(kf)) flags |= 1u;
+    const int64_t q = (int64_t)f * b.fs + s;
+    const int64_t qa = (int64_t)f * nc + c;
+    if (MODE == 0) {
+      out[q] = kf;
+    } else if (MODE == 1) {
+      acc[qa] = sc.cacc * kf;
+      out[q] = u0[q] + sc.cnext * kf;
+    } else if (MODE == 2) {
+      acc[qa] = acc[qa] + sc.cacc * kf;
+      out[q] = u0[q] + sc.cnext * kf;
+    } else {
+      out[q] = u0[q] + (acc[qa] + sc.cnext * kf);
+    }
+  }
+  if (flags) atomicOr(status, flags);
+}
+
+// ---------------------------------------------------------------------------
+// Periodic ghost fill, one axis per launch (x, then y over x-ghosts, then z over
+// everything), so that edges and corners end up congruent to interior cells.
+__global__ void k_periodic(BoxDev b, double* __restrict__ u, int axis) {
+  const int n[3] = {b.nx, b.ny, b.nz};
+  // extents of the ghost slab of this axis in state coordinates
+  int ext[3], off[3];
+  for (int d = 0; d < 3; ++d) {
+    if (d == axis) {
+      ext[d] = 6;
+      off[d] = 0;
+    } else if (d < axis) {
+      ext[d] = n[d] + 6;
+      off[d] = 0;
+    } else {
+      ext[d] = n[d];
+      off[d] = 3;
+    }
+  }
+  const int64_t total = (int64_t)ext[0] * ext[1] * ext[2];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total * NF) return;
+  const int f = (int)(e / total);
+  int64_t r = e % total;
+  int x[3];
+  x[0] = (int)(r % ext[0]);
+  r /= ext[0];
+  x[1] = (int)(r % ext[1]);
+  x[2] = (int)(r / ext[1]);
+  int src[3];
+  for (int d = 0; d < 3; ++d) {
+    int v = x[d] + off[d];
+    if (d == axis) {
+      const int g = x[d];                 // 0..5
+      v = g < 3 ? g : n[d] + g;           // ghost state coordinate
+      src[d] = (((v - 3) % n[d]) + n[d]) % n[d] + 3;  // congruent interior cell
+      x[d] = v;
+    } else {
+      x[d] = v;
+      src[d] = v;
+    }
+  }
+  const int64_t base = (int64_t)f * b.fs;
+  u[base + (int64_t)x[2] * b.sz + (int64_t)x[1] * b.sy + x[0]] =
+      u[base + (int64_t)src[2] * b.sz + (int64_t)src[1] * b.sy + src[0]];
+}
+
+__global__ void k_status_clear(unsigned* s) {
+  if (threadIdx.x == 0) s[threadIdx.x] = 0u;
+}
+
+}  // namespace grf

@@ -1,0 +1,294 @@
+// libgrf: C-ABI entry points of the MI355X 4dST/CCZ4 right-hand side and RK4
+// stage (declarations and argument conventions in include/grf.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdarg>
+#include <cstring>
+#include <string>
+
+#include "../../include/grf.h"
+#include "kernels_fwd.h"
+
+namespace grf {
+
+thread_local std::string g_err;
+
+grf_status fail(grf_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define GRF_HIP_CHECK(call)                                                        \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) return fail(GRF_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kStatusBytes = 256;
+
+grf_status check_box(const grf_box* b) {
+  if (!b) return fail(GRF_EINVAL, "box is null");
+  if (b->ng != NG) return fail(GRF_ESHAPE, "ng must be 3 (got %d)", b->ng);
+  if (b->nx < 1 || b->ny < 1 || b->nz < 1) return fail(GRF_ESHAPE, "box dims must be >= 1");
+  if ((int64_t)b->nx + 6 > (1 << 20) || (int64_t)b->ny + 6 > (1 << 20) || (int64_t)b->nz + 6 > (1 << 20))
+    return fail(GRF_ESHAPE, "box too large");
+  const int64_t need = (int64_t)(b->nx + 6) * (b->ny + 6) * (b->nz + 6);
+  if (b->field_stride < need) return fail(GRF_ESHAPE, "field_stride %lld < %lld", (long long)b->field_stride, (long long)need);
+  if (!(b->dx > 0.0) || !(b->dy > 0.0) || !(b->dz > 0.0)) return fail(GRF_EINVAL, "spacing must be > 0");
+  if (b->bc != GRF_BC_FROZEN && b->bc != GRF_BC_PERIODIC) return fail(GRF_EINVAL, "unknown bc %d", b->bc);
+  return GRF_OK;
+}
+
+grf_status check_params(const grf_params* p) {
+  if (!p) return fail(GRF_EINVAL, "params is null");
+  if (p->lambda_kind != GRF_LAMBDA_QUADRATIC) return fail(GRF_EUNSUPPORTED, "only lambda_kind 0 (quadratic)");
+  if (p->lapse_power != 1.0) return fail(GRF_EUNSUPPORTED, "only lapse_power 1");
+  if (p->a_gauge == -1.0 || p->b_gauge == -1.0) return fail(GRF_EINVAL, "a and b must differ from -1");
+  if (p->enforce) return fail(GRF_EUNSUPPORTED, "post-stage enforcement is not implemented");
+  return GRF_OK;
+}
+
+BoxDev make_boxdev(const grf_box* b) {
+  BoxDev d;
+  d.nx = b->nx;
+  d.ny = b->ny;
+  d.nz = b->nz;
+  d.sy = b->nx + 6;
+  d.sz = (int64_t)(b->nx + 6) * (b->ny + 6);
+  d.fs = b->field_stride;
+  d.ncell = (int64_t)b->nx * b->ny * b->nz;
+  const double h[3] = {b->dx, b->dy, b->dz};
+  for (int k = 0; k < 3; ++k) {
+    d.i12h[k] = 1.0 / (12.0 * h[k]);
+    d.i12h2[k] = 1.0 / (12.0 * h[k] * h[k]);
+    d.i64h[k] = 1.0 / (64.0 * h[k]);
+  }
+  d.i144[0] = 1.0 / (144.0 * h[0] * h[1]);
+  d.i144[1] = 1.0 / (144.0 * h[0] * h[2]);
+  d.i144[2] = 1.0 / (144.0 * h[1] * h[2]);
+  return d;
+}
+
+grf_point_params make_pp(const grf_params* p) {
+  grf_point_params q;
+  const double a = p->a_gauge, b = p->b_gauge, k1 = p->kappa1, k2 = p->kappa2;
+  q.lambda_gb = p->lambda_gb;
+  q.g2 = p->g2;
+  q.kappa1 = k1;
+  q.kappa3 = p->kappa3;
+  q.k1_1pk2 = k1 * (1.0 + k2);
+  q.k1_2pk2 = k1 * (2.0 + k2);
+  q.k1k2 = k1 * k2;
+  q.lapse_coeff = p->lapse_coeff;
+  q.lapse_advec = p->lapse_advec;
+  q.shift_gamma_coeff = p->shift_gamma_coeff;
+  q.shift_advec = p->shift_advec;
+  q.eta = p->eta;
+  q.inv1pa = 1.0 / (1.0 + a);
+  q.a_1pa = a / (1.0 + a);
+  q.fb = b / (1.0 + b);
+  q.cfac = 1.0 / (1.0 + b);
+  q.b4 = b / (4.0 * (1.0 + b));
+  return q;
+}
+
+size_t deriv_bytes(const grf_box* b) {
+  return (size_t)GRF_NCOMP * (size_t)b->nx * b->ny * b->nz * sizeof(double);
+}
+
+// Tile shapes of the stencil stage (index = tile variant).
+constexpr int kTileVariants = 5;
+const int kTiles[kTileVariants][3] = {{16, 8, 4}, {32, 4, 4}, {8, 8, 8}, {16, 16, 2}, {64, 4, 2}};
+
+template <int TX, int TY, int TZ>
+hipError_t launch_deriv_t(const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
+                          hipStream_t st) {
+  const int ntiles = ((bd.nx + TX - 1) / TX) * ((bd.ny + TY - 1) / TY) * ((bd.nz + TZ - 1) / TZ);
+  hipLaunchKernelGGL((k_deriv<TX, TY, TZ>), dim3(ntiles, NF), dim3(TX * TY * TZ), 0, st, bd, u, D, sigma, sa, UP);
+  return hipGetLastError();
+}
+
+hipError_t launch_deriv(int variant, const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
+                        hipStream_t st) {
+  switch (variant) {
+    case 1: return launch_deriv_t<32, 4, 4>(bd, u, D, sigma, sa, UP, st);
+    case 2: return launch_deriv_t<8, 8, 8>(bd, u, D, sigma, sa, UP, st);
+    case 3: return launch_deriv_t<16, 16, 2>(bd, u, D, sigma, sa, UP, st);
+    case 4: return launch_deriv_t<64, 4, 2>(bd, u, D, sigma, sa, UP, st);
+    default: return launch_deriv_t<16, 8, 4>(bd, u, D, sigma, sa, UP, st);
+  }
+}
+
+int g_tile_variant = 0;
+
+template <int MODE>
+hipError_t launch_point_m(int sa, const BoxDev& bd, const grf_point_params& pp, const double* us, const double* D,
+                          const double* u0, double* out, double* acc, StageCoef sc, unsigned* status,
+                          hipStream_t st) {
+  const int64_t nblk = (bd.ncell + 127) / 128;
+  if (sa)
+    hipLaunchKernelGGL((k_point<MODE, 1>), dim3((unsigned)nblk), dim3(128), 0, st, bd, pp, us, D, u0, out, acc, sc,
+                       status);
+  else
+    hipLaunchKernelGGL((k_point<MODE, 0>), dim3((unsigned)nblk), dim3(128), 0, st, bd, pp, us, D, u0, out, acc, sc,
+                       status);
+  return hipGetLastError();
+}
+
+hipError_t launch_point(int mode, int sa, const BoxDev& bd, const grf_point_params& pp, const double* us,
+                        const double* D, const double* u0, double* out, double* acc, StageCoef sc, unsigned* status,
+                        hipStream_t st) {
+  switch (mode) {
+    case 1: return launch_point_m<1>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
+    case 2: return launch_point_m<2>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
+    case 4: return launch_point_m<4>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
+    default: return launch_point_m<0>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
+  }
+}
+
+hipError_t launch_periodic(const BoxDev& bd, double* u, hipStream_t st) {
+  const int n[3] = {bd.nx, bd.ny, bd.nz};
+  for (int axis = 0; axis < 3; ++axis) {
+    int64_t cells = 6;
+    for (int d = 0; d < 3; ++d)
+      if (d != axis) cells *= (d < axis) ? (n[d] + 6) : n[d];
+    const int64_t total = cells * NF;
+    hipLaunchKernelGGL(k_periodic, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, bd, u, axis);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace grf
+
+using namespace grf;
+
+extern "C" {
+
+size_t grf_workspace_bytes(const grf_box* box) {
+  if (check_box(box) != GRF_OK) return 0;
+  return kStatusBytes + deriv_bytes(box);
+}
+
+const char* grf_last_error(void) { return g_err.c_str(); }
+
+int64_t grf_flops_per_cell(int which) {
+  switch (which) {
+    case 0: return GRF_FLOPS_RHS;
+    case 1: return GRF_FLOPS_RHS_SHIFTADV;
+    case 2: return GRF_FLOPS_VJP;
+    default: return -1;
+  }
+}
+
+grf_status grf_status_clear(void* workspace, hipStream_t stream) {
+  if (!workspace) return fail(GRF_EINVAL, "workspace is null");
+  hipLaunchKernelGGL(k_status_clear, dim3(1), dim3(64), 0, stream, (unsigned*)workspace);
+  GRF_HIP_CHECK(hipGetLastError());
+  return GRF_OK;
+}
+
+grf_status grf_status_fetch(const void* workspace, hipStream_t stream, uint32_t* bits) {
+  if (!workspace) return fail(GRF_EINVAL, "workspace is null");
+  unsigned host = 0;
+  GRF_HIP_CHECK(hipMemcpyAsync(&host, workspace, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+  GRF_HIP_CHECK(hipStreamSynchronize(stream));
+  if (bits) *bits = host;
+  if (host & GRF_FLAG_NONFINITE) return fail(GRF_ENONFINITE, "non-finite right-hand side");
+  if (host & GRF_FLAG_HYPERBOLIC) return fail(GRF_EHYPERBOLIC, "near-singular per-cell system");
+  if (host & GRF_FLAG_NONPOSITIVE) return fail(GRF_ENONPOSITIVE, "chi or lapse not positive");
+  return GRF_OK;
+}
+
+grf_status grf_fill_periodic(const grf_box* box, double* u, hipStream_t stream) {
+  grf_status s = check_box(box);
+  if (s != GRF_OK) return s;
+  if (!u) return fail(GRF_EINVAL, "u is null");
+  BoxDev bd = make_boxdev(box);
+  GRF_HIP_CHECK(launch_periodic(bd, u, stream));
+  return GRF_OK;
+}
+
+static grf_status common_checks(const grf_params* p, const grf_box* box, void* ws, size_t ws_bytes) {
+  grf_status s = check_params(p);
+  if (s != GRF_OK) return s;
+  s = check_box(box);
+  if (s != GRF_OK) return s;
+  if (!ws) return fail(GRF_EINVAL, "workspace is null");
+  if (ws_bytes < kStatusBytes + deriv_bytes(box))
+    return fail(GRF_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, kStatusBytes + deriv_bytes(box));
+  return GRF_OK;
+}
+
+grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u, double* rhs, void* workspace,
+                        size_t workspace_bytes, hipStream_t stream) {
+  grf_status s = common_checks(p, box, workspace, workspace_bytes);
+  if (s != GRF_OK) return s;
+  if (!u || !rhs) return fail(GRF_EINVAL, "u/rhs is null");
+  if (u == rhs) return fail(GRF_EINVAL, "rhs must not alias u");
+  BoxDev bd = make_boxdev(box);
+  grf_point_params pp = make_pp(p);
+  unsigned* status = (unsigned*)workspace;
+  double* D = (double*)((char*)workspace + kStatusBytes);
+  const int sa = p->shift_advec != 0.0;
+  GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, sa, nullptr, stream));
+  GRF_HIP_CHECK(launch_point(0, sa, bd, pp, u, D, nullptr, rhs, nullptr, StageCoef{0.0, 0.0}, status, stream));
+  return GRF_OK;
+}
+
+grf_status grf_rk4_stage(const grf_params* p, const grf_box* box, int stage, double dt, const double* u0,
+                         const double* us, double* unext, double* acc, void* workspace, size_t workspace_bytes,
+                         hipStream_t stream) {
+  grf_status s = common_checks(p, box, workspace, workspace_bytes);
+  if (s != GRF_OK) return s;
+  if (stage < 1 || stage > 4) return fail(GRF_EINVAL, "stage must be 1..4 (got %d)", stage);
+  if (!u0 || !us || !unext || !acc) return fail(GRF_EINVAL, "null state pointer");
+  if (unext == us || unext == u0) return fail(GRF_EINVAL, "unext must not alias us or u0");
+  if (!std::isfinite(dt)) return fail(GRF_EINVAL, "dt not finite");
+  BoxDev bd = make_boxdev(box);
+  grf_point_params pp = make_pp(p);
+  unsigned* status = (unsigned*)workspace;
+  double* D = (double*)((char*)workspace + kStatusBytes);
+  const int sa = p->shift_advec != 0.0;
+  StageCoef sc;
+  int mode;
+  switch (stage) {
+    case 1: mode = 1; sc = StageCoef{dt / 6.0, 0.5 * dt}; break;
+    case 2: mode = 2; sc = StageCoef{dt / 3.0, 0.5 * dt}; break;
+    case 3: mode = 2; sc = StageCoef{dt / 3.0, dt}; break;
+    default: mode = 4; sc = StageCoef{0.0, dt / 6.0}; break;
+  }
+  GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, us, D, p->ko_sigma, sa, nullptr, stream));
+  GRF_HIP_CHECK(launch_point(mode, sa, bd, pp, us, D, u0, unext, acc, sc, status, stream));
+  if (box->bc == GRF_BC_PERIODIC) GRF_HIP_CHECK(launch_periodic(bd, unext, stream));
+  return GRF_OK;
+}
+
+size_t grf_vjp_workspace_bytes(const grf_box* box) {
+  if (check_box(box) != GRF_OK) return 0;
+  return kStatusBytes + deriv_bytes(box);
+}
+
+grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u, const double* w, double* u_bar,
+                       double* theta_bar, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  (void)p; (void)box; (void)u; (void)w; (void)u_bar; (void)theta_bar; (void)workspace; (void)workspace_bytes;
+  (void)stream;
+  return fail(GRF_EUNSUPPORTED, "vjp not built yet");
+}
+
+// Select the stencil tile shape (0..4) used by the single-box calls.
+grf_status grf_set_tile_variant(int variant) {
+  if (variant < 0 || variant >= kTileVariants) return fail(GRF_EINVAL, "tile variant out of range");
+  g_tile_variant = variant;
+  return GRF_OK;
+}
+
+}  // extern "C"

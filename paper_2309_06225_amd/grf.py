@@ -1,0 +1,200 @@
+"""Python binding of libgrf (argument marshalling only).
+
+Every step of the hot path runs in libgrf's HIP kernels; this module converts
+torch device tensors to pointers, the current torch stream to a hipStream_t,
+and parameter dicts to the C structs of include/grf.h.  If the library is not
+built, every entry point raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+from . import inputs as _inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgrf.so")
+
+NF = 27
+NG = 3
+BC_FROZEN, BC_PERIODIC = 0, 1
+STATUS = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "EHIP", 4: "ENONFINITE", 5: "EHYPERBOLIC", 6: "ENOMEM",
+          7: "EUNSUPPORTED", 8: "ENONPOSITIVE"}
+
+
+class GrfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libgrf {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("lambda_gb", ctypes.c_double), ("lambda_kind", ctypes.c_int32), ("g2", ctypes.c_double),
+                ("a_gauge", ctypes.c_double), ("b_gauge", ctypes.c_double),
+                ("kappa1", ctypes.c_double), ("kappa2", ctypes.c_double), ("kappa3", ctypes.c_double),
+                ("lapse_coeff", ctypes.c_double), ("lapse_power", ctypes.c_double), ("lapse_advec", ctypes.c_double),
+                ("shift_gamma_coeff", ctypes.c_double), ("shift_advec", ctypes.c_double), ("eta", ctypes.c_double),
+                ("ko_sigma", ctypes.c_double), ("enforce", ctypes.c_int32), ("chi_min", ctypes.c_double),
+                ("lapse_min", ctypes.c_double)]
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("ng", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("z0", ctypes.c_double),
+                ("field_stride", ctypes.c_int64), ("bc", ctypes.c_int32)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """Load libgrf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libgrf.so not found at {LIB_PATH}: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        P, B = ctypes.POINTER(Params), ctypes.POINTER(Box)
+        L.grf_workspace_bytes.argtypes = [B]
+        L.grf_workspace_bytes.restype = ctypes.c_size_t
+        L.grf_vjp_workspace_bytes.argtypes = [B]
+        L.grf_vjp_workspace_bytes.restype = ctypes.c_size_t
+        L.grf_rhs_eval.argtypes = [P, B, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.grf_rk4_stage.argtypes = [P, B, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.grf_fill_periodic.argtypes = [B, _vp, _vp]
+        L.grf_rhs_vjp.argtypes = [P, B, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.grf_status_fetch.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_uint32)]
+        L.grf_status_clear.argtypes = [_vp, _vp]
+        L.grf_flops_per_cell.argtypes = [ctypes.c_int]
+        L.grf_flops_per_cell.restype = ctypes.c_int64
+        L.grf_last_error.restype = ctypes.c_char_p
+        L.grf_set_tile_variant.argtypes = [ctypes.c_int]
+        for name in ("grf_rhs_eval", "grf_rk4_stage", "grf_fill_periodic", "grf_rhs_vjp", "grf_status_fetch",
+                     "grf_status_clear", "grf_set_tile_variant"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != 0:
+        raise GrfError(code, lib().grf_last_error().decode())
+
+
+def make_params(p: dict | None = None, **over) -> Params:
+    d = _inputs.default_params() if p is None else dict(p)
+    d.update(over)
+    return Params(lambda_gb=d["lambda_gb"], lambda_kind=0, g2=d["g2"], a_gauge=d["a_gauge"], b_gauge=d["b_gauge"],
+                  kappa1=d["kappa1"], kappa2=d["kappa2"], kappa3=d["kappa3"], lapse_coeff=d["lapse_coeff"],
+                  lapse_power=d["lapse_power"], lapse_advec=d["lapse_advec"],
+                  shift_gamma_coeff=d["shift_gamma_coeff"], shift_advec=d["shift_advec"], eta=d["eta"],
+                  ko_sigma=d["ko_sigma"], enforce=0, chi_min=0.0, lapse_min=0.0)
+
+
+def make_box(dims, dx, bc=BC_FROZEN, origin=(0.0, 0.0, 0.0)) -> Box:
+    nx, ny, nz = dims
+    if not isinstance(dx, (tuple, list)):
+        dx = (dx, dx, dx)
+    return Box(nx=nx, ny=ny, nz=nz, ng=NG, dx=dx[0], dy=dx[1], dz=dx[2], x0=origin[0], y0=origin[1],
+               z0=origin[2], field_stride=(nx + 6) * (ny + 6) * (nz + 6), bc=bc)
+
+
+def box_of(u: torch.Tensor, dx, bc=BC_FROZEN) -> Box:
+    nz, ny, nx = (s - 2 * NG for s in u.shape[1:])
+    return make_box((nx, ny, nz), dx, bc)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def workspace_bytes(box: Box) -> int:
+    return int(lib().grf_workspace_bytes(ctypes.byref(box)))
+
+
+def vjp_workspace_bytes(box: Box) -> int:
+    return int(lib().grf_vjp_workspace_bytes(ctypes.byref(box)))
+
+
+def alloc_workspace(nbytes: int, device="cuda") -> torch.Tensor:
+    ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=device)
+    status_clear(ws)
+    return ws
+
+
+def rhs_eval(params: Params, box: Box, u, rhs, ws, stream=None):
+    _check(lib().grf_rhs_eval(ctypes.byref(params), ctypes.byref(box), _ptr(u), _ptr(rhs), _ptr(ws),
+                              ws.numel() * 8, _stream(stream)))
+
+
+def rk4_stage(params: Params, box: Box, stage, dt, u0, us, unext, acc, ws, stream=None):
+    _check(lib().grf_rk4_stage(ctypes.byref(params), ctypes.byref(box), int(stage), float(dt), _ptr(u0), _ptr(us),
+                               _ptr(unext), _ptr(acc), _ptr(ws), ws.numel() * 8, _stream(stream)))
+
+
+def fill_periodic(box: Box, u, stream=None):
+    _check(lib().grf_fill_periodic(ctypes.byref(box), _ptr(u), _stream(stream)))
+
+
+def rhs_vjp(params: Params, box: Box, u, w, u_bar, theta_bar, ws, stream=None):
+    _check(lib().grf_rhs_vjp(ctypes.byref(params), ctypes.byref(box), _ptr(u), _ptr(w), _ptr(u_bar),
+                             _ptr(theta_bar), _ptr(ws), ws.numel() * 8, _stream(stream)))
+
+
+def status_fetch(ws, stream=None):
+    bits = ctypes.c_uint32(0)
+    code = lib().grf_status_fetch(_ptr(ws), _stream(stream), ctypes.byref(bits))
+    return code, int(bits.value)
+
+
+def status_clear(ws, stream=None):
+    _check(lib().grf_status_clear(_ptr(ws), _stream(stream)))
+
+
+def set_tile_variant(v: int):
+    _check(lib().grf_set_tile_variant(int(v)))
+
+
+def flops_per_cell(which=0) -> int:
+    return int(lib().grf_flops_per_cell(int(which)))
+
+
+class Stepper:
+    """Classic RK4 steps of one box, all buffers resident on the device.
+
+    Buffers: u (current state), ua, ub (stage states), acc (compact
+    accumulator), ws (workspace).  Frozen ghosts: ua and ub start as copies of
+    u so that their ghosts hold the frozen values."""
+
+    def __init__(self, params: Params, box: Box, u: torch.Tensor, dt: float):
+        self.params, self.box, self.dt = params, box, float(dt)
+        self.u = u.contiguous()
+        self.ua = self.u.clone()
+        self.ub = self.u.clone()
+        n = box.nx * box.ny * box.nz
+        self.acc = torch.zeros((NF, n), dtype=torch.float64, device=u.device)
+        self.ws = alloc_workspace(workspace_bytes(box), u.device)
+
+    def step(self, stream=None):
+        p, b, dt = self.params, self.box, self.dt
+        rk4_stage(p, b, 1, dt, self.u, self.u, self.ua, self.acc, self.ws, stream)
+        rk4_stage(p, b, 2, dt, self.u, self.ua, self.ub, self.acc, self.ws, stream)
+        rk4_stage(p, b, 3, dt, self.u, self.ub, self.ua, self.acc, self.ws, stream)
+        rk4_stage(p, b, 4, dt, self.u, self.ua, self.ub, self.acc, self.ws, stream)
+        self.u, self.ub = self.ub, self.u
+
+    def status(self):
+        return status_fetch(self.ws)
