@@ -1,0 +1,159 @@
+"""Benchmark of the 4dST/CCZ4 RHS + RK4 hot path on one MI355X.
+
+Workload: one 128^3 box (3 frozen ghosts), dx = M/8, single non-spinning
+puncture (M = 1) with the scalar shell phi = 0.1 exp(-(r-4)^2), couplings
+lambda(phi) = 0.1 phi^2/4, g2 = 0.01, a = 0.2, b = 0.4, kappa = (0.1, 0, 1),
+eta = 1, KO sigma = 0.3, dt = dx/4.  A step is one full RK4 step (4 stencil
+stages + 4 pointwise/RK4 stages).  Inputs are resident in HBM before the timed
+region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FP64 cell-updates/s (4∂ST RHS+RK4 stage) at 1 GPU; adjoint/forward time ratio"
+PEAK_FP64 = 78.6  # TFLOP/s, MI355X FP64 vector
+PEAK_HBM = 8000.0  # GB/s
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in ("paper_2309_06225_amd/csrc/kernels_fwd.h", "paper_2309_06225_amd/csrc/gen/gen_rhs.inc",
+                "paper_2309_06225_amd/csrc/libgrf.hip"):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    if absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(params, u, dx, dt):
+    """The CPU oracle, untuned, on one full RK4 step of the same box."""
+    from oracle import oracle as O
+    from paper_2309_06225_amd import inputs as I
+    O.build(force=False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    O.rk4(I.params_vector(params), u, dx, dt, 1, periodic=False)
+    t = time.perf_counter() - t0
+    ncell = (u.shape[1] - 6) * (u.shape[2] - 6) * (u.shape[3] - 6)
+    return {"value": ncell / t, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"one full RK4 step of the same {u.shape[3] - 6}^3 box ({t:.1f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=128, help="box edge (cells)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run one plain 1 GiB device-to-device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.copy_calib:
+        import torch
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8}))
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the box-per-GPU "
+              "sharding with halo exchange is a design, not code); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2309_06225_amd import grf as G
+    from paper_2309_06225_amd import inputs as I
+
+    n = args.n
+    dx = 1.0 / 8.0
+    dt = 0.25 * dx
+    params = I.default_params()
+    u_host = I.single_puncture(n, dx)
+    u = torch.from_numpy(u_host).to("cuda")
+    box = G.box_of(u, dx, G.BC_FROZEN)
+    st = G.Stepper(G.make_params(params), box, u, dt)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        st.step()
+    torch.cuda.synchronize()
+    G.prof_begin(4 * args.steps)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        st.step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    prof = G.prof_end()
+    code, bits = st.status()
+    if code != 0:
+        print(f"device status {code} bits {bits}", file=sys.stderr)
+        sys.exit(1)
+
+    ncell = n ** 3
+    ms_step = ms_total / args.steps
+    value = ncell * args.steps / (ms_total * 1e-3)
+    # dominant kernel: the pointwise right-hand side + RK4 stage
+    point_ms, point_n = prof["point"]
+    deriv_ms, deriv_n = prof["deriv"]
+    avg_point = point_ms / max(point_n, 1)
+    # graph algebra + per field: the Kreiss-Oliger add (1) and the stage update
+    # averaged over the four stages ((2 + 4 + 4 + 3) / 4)
+    flops_cell = G.flops_per_cell(0) + 27 * (1.0 + 13.0 / 4.0)
+    achieved = flops_cell * ncell / (avg_point * 1e-3) / 1e12
+    traffic = load_traffic("k_point", f"single_puncture_{n}")
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"single_puncture_{n}", "cells": ncell, "ghosts": 3, "dx": dx, "dt": dt,
+                   "bc": "frozen", "lambda_gb": params["lambda_gb"], "g2": params["g2"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64, "traffic": traffic, "kernel": "k_point",
+                     "flops_per_cell": flops_cell, "avg_launch_ms": avg_point},
+        "kernels_ms_per_step": {"stencil": deriv_ms / args.steps, "pointwise_rk4": point_ms / args.steps},
+        "rhs_cells_per_s": ncell * 4 * args.steps / (ms_total * 1e-3),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(params, u_host, dx, dt)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -98,12 +98,12 @@ grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u
 
 /* One classic RK4 stage (c = 1/2, 1/2, 1; weights 1, 2, 2, 1 over 6), stage in 1..4.
  * Reads u0 (state at the start of the step) and us (the stage state; us == u0 at
- * stage 1), computes k = RHS(us) and
- *   stage 1: acc  = dt/6 k;        unext = u0 + dt/2 k
- *   stage 2: acc += dt/3 k;        unext = u0 + dt/2 k
- *   stage 3: acc += dt/3 k;        unext = u0 + dt k
- *   stage 4:                       unext = u0 + acc + dt/6 k   (the new state)
- * on interior cells.  acc is compact (27 x nx*ny*nz).  unext must not alias us
+ * stage 1), computes k = RHS(us) and, on interior cells,
+ *   stage 1: acc  = k;             unext = u0 + (dt/2) k
+ *   stage 2: acc  = acc + 2 k;     unext = u0 + (dt/2) k
+ *   stage 3: acc  = acc + 2 k;     unext = u0 + dt k
+ *   stage 4:                       unext = u0 + (dt/6)(acc + k)   (the new state)
+ * each product rounded on its own (no fused multiply-add).  acc is compact (27 x nx*ny*nz).  unext must not alias us
  * or u0.  GRF_BC_PERIODIC: the ghosts of unext are then filled periodically;
  * GRF_BC_FROZEN: ghosts of unext are not written (the caller keeps them at the
  * frozen values, e.g. by allocating unext as a copy of the initial state). */
@@ -135,6 +135,18 @@ grf_status grf_status_clear(void* workspace, hipStream_t stream);
  * (shift advection on or off) and of its VJP, counted on the expression graph
  * (add, sub, mul and reciprocal each 1), stencils not included. */
 int64_t grf_flops_per_cell(int which /* 0 rhs, 1 rhs with shift advection, 2 vjp */);
+
+/* Stencil-stage tile shape used by the single-box calls: 0: 16x8x4 (default),
+ * 1: 32x4x4, 2: 8x8x8, 3: 16x16x2, 4: 64x4x2.  Results do not depend on it. */
+grf_status grf_set_tile_variant(int variant);
+
+/* Kernel timing with HIP events recorded on the launch stream around each
+ * launch, for up to max_launches launches per kernel class; grf_prof_end waits
+ * for the events and returns per class (0 stencil stage, 1 pointwise + RK4,
+ * 2 VJP kernels) the summed milliseconds and launch counts (arrays of 3).
+ * Host-side state, not thread-safe; intended for benchmarks. */
+grf_status grf_prof_begin(int max_launches);
+grf_status grf_prof_end(double* ms, int* count);
 
 /* Human-readable reason of the last error returned on this host thread. */
 const char* grf_last_error(void);

@@ -236,7 +236,7 @@ def _lit(v: float) -> str:
 
 
 def count_flops(g: Graph, outputs):
-    """add/sub/mul = 1, reciprocal = 1 (R18 convention: div = 1), neg = 0."""
+    """Count of add, sub, mul and reciprocal nodes (1 flop each); negation is free."""
     need = reachable(outputs)
     c = {"+": 0, "-": 0, "*": 0, "rcp": 0, "neg": 0}
     for i in need:
@@ -247,37 +247,73 @@ def count_flops(g: Graph, outputs):
     return total, c
 
 
-def emit(g: Graph, outputs, out_names, input_expr, param_expr, indent="  ", prefix="t"):
+def dfs_order(outputs):
+    """Post-order depth-first node order: each output's dependencies are placed
+    just before it, so intermediates are computed close to their uses."""
+    order, seen = [], set()
+    for o in outputs:
+        stack = [(o, False)]
+        while stack:
+            n, done = stack.pop()
+            if n.idx in seen:
+                continue
+            if done:
+                seen.add(n.idx)
+                order.append(n.idx)
+                continue
+            stack.append((n, True))
+            for ch in (n.b, n.a):
+                if ch is not None and ch.idx not in seen:
+                    stack.append((ch, False))
+    return order
+
+
+def emit(g: Graph, outputs, out_names, input_expr, param_expr, indent="  ", prefix="t", order="dfs"):
     """Straight-line C for `outputs`.  input_expr(name) / param_expr(name)
-    return C expressions for leaves; out_names are C lvalue templates taking
-    the value expression (e.g. 'OUT(3, {})')."""
-    need = sorted(reachable(outputs))
+    return C expressions for leaves; out_names are C statement templates taking
+    the value expression (e.g. 'OUT(3, {})').  With order='dfs' each output
+    statement is placed right after the last node it needs."""
+    if order == "dfs":
+        seq = dfs_order(outputs)
+    else:
+        seq = sorted(reachable(outputs))
+    pos = {i: k for k, i in enumerate(seq)}
+    # output statements go right after their value is computed
+    after = {}
+    for o, tmpl in zip(outputs, out_names):
+        after.setdefault(pos[o.idx] if o.op != "c" else -1, []).append((o, tmpl))
     lines = []
     names = {}
-    for i in need:
+
+    def name_of(n):
+        return names[n.idx]
+
+    for o, tmpl in after.get(-1, []):
+        lines.append(indent + tmpl.format(_lit(o.val) if o.val >= 0 else f"({_lit(o.val)})") + ";")
+    for k, i in enumerate(seq):
         n = g.nodes[i]
         if n.op == "c":
             names[i] = _lit(n.val) if n.val >= 0 else f"({_lit(n.val)})"
-            continue
-        if n.op == "in":
-            expr = input_expr(n.name)
-        elif n.op == "p":
-            expr = param_expr(n.name)
-        elif n.op == "+":
-            expr = f"{names[n.a.idx]} + {names[n.b.idx]}"
-        elif n.op == "-":
-            expr = f"{names[n.a.idx]} - {names[n.b.idx]}"
-        elif n.op == "*":
-            expr = f"{names[n.a.idx]} * {names[n.b.idx]}"
-        elif n.op == "neg":
-            expr = f"-{names[n.a.idx]}"
-        elif n.op == "rcp":
-            expr = f"1.0 / {names[n.a.idx]}"
         else:
-            raise ValueError(n.op)
-        nm = f"{prefix}{i}"
-        names[i] = nm
-        lines.append(f"{indent}const double {nm} = {expr};")
-    for o, tmpl in zip(outputs, out_names):
-        lines.append(indent + tmpl.format(names[o.idx]) + ";")
+            if n.op == "in":
+                expr = input_expr(n.name)
+            elif n.op == "p":
+                expr = param_expr(n.name)
+            elif n.op == "+":
+                expr = f"{name_of(n.a)} + {name_of(n.b)}"
+            elif n.op == "-":
+                expr = f"{name_of(n.a)} - {name_of(n.b)}"
+            elif n.op == "*":
+                expr = f"{name_of(n.a)} * {name_of(n.b)}"
+            elif n.op == "neg":
+                expr = f"-{name_of(n.a)}"
+            elif n.op == "rcp":
+                expr = f"1.0 / {name_of(n.a)}"
+            else:
+                raise ValueError(n.op)
+            nm = f"{prefix}{i}"
+            names[i] = nm
+            lines.append(f"{indent}const double {nm} = {expr};")
+        for o, tmpl in after.get(k, []):
+            lines.append(indent + tmpl.format(names[o.idx]) + ";")
     return "\n".join(lines)

@@ -155,9 +155,39 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_deriv(BoxDev b, const double* __
 // Pointwise right-hand side (generated algebra) fused with the RK4 stage.
 // MODE 0: rhs[f] = k;  MODE 1: first stage;  MODE 2: middle stage;  MODE 4: last stage.
 struct StageCoef {
-  double cacc;   // weight of k added to acc (stage 1: written, not added)
-  double cnext;  // weight of k in unext = u0 (+ acc) + cnext k
+  double cnext;  // c_s dt for stages 1-3, dt/6 for stage 4
 };
+
+// RK4 stage update of one field in the textbook order: acc holds
+// k1 + 2 k2 + 2 k3 (summed in that order), stage states are u0 + (c dt) k, the
+// new state u0 + (dt/6)(acc + k4).  Products are rounded on their own (no fused
+// multiply-add) so that states carrying a tiny perturbation on an O(1)
+// background round exactly as the textbook formula does.  k includes the
+// Kreiss-Oliger term stored by the stencil stage.
+#pragma clang fp contract(off)
+template <int MODE>
+__device__ __forceinline__ void stage_one(int f, double rhs_f, const BoxDev& b, const double* __restrict__ D,
+                                          int64_t c, int64_t s, const double* __restrict__ u0,
+                                          double* __restrict__ out, double* __restrict__ acc, StageCoef sc,
+                                          unsigned& flags) {
+  const int64_t nc = b.ncell;
+  const double kf = rhs_f + D[(int64_t)(GRF_OFF_KO + f) * nc + c];
+  if (!isfinite(kf)) flags |= 1u;
+  const int64_t q = (int64_t)f * b.fs + s;
+  const int64_t qa = (int64_t)f * nc + c;
+  if (MODE == 0) {
+    out[q] = kf;
+  } else if (MODE == 1) {
+    acc[qa] = kf;
+    out[q] = u0[q] + sc.cnext * kf;
+  } else if (MODE == 2) {
+    acc[qa] = acc[qa] + 2.0 * kf;
+    out[q] = u0[q] + sc.cnext * kf;
+  } else {
+    out[q] = u0[q] + sc.cnext * (acc[qa] + kf);
+  }
+}
+#pragma clang fp contract(fast)
 
 template <int MODE, int SHIFTADV>
 __global__ __launch_bounds__(128) void k_point(BoxDev b, grf_point_params P, const double* __restrict__ us,
@@ -172,38 +202,20 @@ __global__ __launch_bounds__(128) void k_point(BoxDev b, grf_point_params P, con
   const int k = (int)(r / b.ny);
   const int64_t s = (int64_t)(k + 3) * b.sz + (int64_t)(j + 3) * b.sy + (i + 3);
   const int64_t nc = b.ncell;
-  double rhs[NF];
   int bad = 0;
+  unsigned flags = 0u;
 #define GRF_U(f) us[(int64_t)(f) * b.fs + s]
 #define GRF_D(cc) D[(int64_t)(cc) * nc + c]
 #define GRF_P(n) P.n
-#define GRF_RHS(f, v) rhs[f] = (v)
+#define GRF_RHS(f, v) stage_one<MODE>(f, (v), b, D, c, s, u0, out, acc, sc, flags)
 #define GRF_PIVCHK(v) bad |= !(fabs(v) <= 1e12)
 #define GRF_SHIFT_ADVEC (SHIFTADV != 0)
 #include "gen/gen_rhs.inc"
 #undef GRF_SHIFT_ADVEC
 #undef GRF_RHS
 #undef GRF_PIVCHK
-  unsigned flags = bad ? 2u : 0u;
+  if (bad) flags |= 2u;
   if (!(us[(int64_t)F_CHI * b.fs + s] > 0.0) || !(us[(int64_t)F_LAPSE * b.fs + s] > 0.0)) flags |= 4u;
-#pragma unroll
-  for (int f = 0; f < NF; ++f) {
-    const double kf = rhs[f] + D[(int64_t)(GRF_OFF_KO + f) * nc + c];
-    if (!isfinite(kf)) flags |= 1u;
-    const int64_t q = (int64_t)f * b.fs + s;
-    const int64_t qa = (int64_t)f * nc + c;
-    if (MODE == 0) {
-      out[q] = kf;
-    } else if (MODE == 1) {
-      acc[qa] = sc.cacc * kf;
-      out[q] = u0[q] + sc.cnext * kf;
-    } else if (MODE == 2) {
-      acc[qa] = acc[qa] + sc.cacc * kf;
-      out[q] = u0[q] + sc.cnext * kf;
-    } else {
-      out[q] = u0[q] + (acc[qa] + sc.cnext * kf);
-    }
-  }
   if (flags) atomicOr(status, flags);
 }
 

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/grf.h"
 #include "kernels_fwd.h"
@@ -128,6 +129,25 @@ hipError_t launch_deriv(int variant, const BoxDev& bd, const double* u, double* 
 
 int g_tile_variant = 0;
 
+// Optional per-kernel timing with HIP events recorded on the launch stream
+// around each stencil-stage and pointwise launch (enabled by grf_prof_begin).
+struct ProfClass {
+  std::vector<hipEvent_t> ev;  // start/end pairs
+  int used = 0;
+};
+struct Prof {
+  bool on = false;
+  int cap = 0;
+  ProfClass cls[3];  // 0 stencil stage, 1 pointwise/RK4, 2 VJP kernels
+} g_prof;
+
+void prof_mark(int which, hipStream_t st) {
+  if (!g_prof.on) return;
+  ProfClass& c = g_prof.cls[which];
+  if (c.used >= g_prof.cap * 2) return;
+  hipEventRecord(c.ev[c.used++], st);
+}
+
 template <int MODE>
 hipError_t launch_point_m(int sa, const BoxDev& bd, const grf_point_params& pp, const double* us, const double* D,
                           const double* u0, double* out, double* acc, StageCoef sc, unsigned* status,
@@ -239,8 +259,12 @@ grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u
   unsigned* status = (unsigned*)workspace;
   double* D = (double*)((char*)workspace + kStatusBytes);
   const int sa = p->shift_advec != 0.0;
+  prof_mark(0, stream);
   GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, sa, nullptr, stream));
-  GRF_HIP_CHECK(launch_point(0, sa, bd, pp, u, D, nullptr, rhs, nullptr, StageCoef{0.0, 0.0}, status, stream));
+  prof_mark(0, stream);
+  prof_mark(1, stream);
+  GRF_HIP_CHECK(launch_point(0, sa, bd, pp, u, D, nullptr, rhs, nullptr, StageCoef{0.0}, status, stream));
+  prof_mark(1, stream);
   return GRF_OK;
 }
 
@@ -261,13 +285,17 @@ grf_status grf_rk4_stage(const grf_params* p, const grf_box* box, int stage, dou
   StageCoef sc;
   int mode;
   switch (stage) {
-    case 1: mode = 1; sc = StageCoef{dt / 6.0, 0.5 * dt}; break;
-    case 2: mode = 2; sc = StageCoef{dt / 3.0, 0.5 * dt}; break;
-    case 3: mode = 2; sc = StageCoef{dt / 3.0, dt}; break;
-    default: mode = 4; sc = StageCoef{0.0, dt / 6.0}; break;
+    case 1: mode = 1; sc = StageCoef{0.5 * dt}; break;
+    case 2: mode = 2; sc = StageCoef{0.5 * dt}; break;
+    case 3: mode = 2; sc = StageCoef{1.0 * dt}; break;
+    default: mode = 4; sc = StageCoef{dt / 6.0}; break;
   }
+  prof_mark(0, stream);
   GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, us, D, p->ko_sigma, sa, nullptr, stream));
+  prof_mark(0, stream);
+  prof_mark(1, stream);
   GRF_HIP_CHECK(launch_point(mode, sa, bd, pp, us, D, u0, unext, acc, sc, status, stream));
+  prof_mark(1, stream);
   if (box->bc == GRF_BC_PERIODIC) GRF_HIP_CHECK(launch_periodic(bd, unext, stream));
   return GRF_OK;
 }
@@ -282,6 +310,42 @@ grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u,
   (void)p; (void)box; (void)u; (void)w; (void)u_bar; (void)theta_bar; (void)workspace; (void)workspace_bytes;
   (void)stream;
   return fail(GRF_EUNSUPPORTED, "vjp not built yet");
+}
+
+// Start recording up to max_launches timed launches per kernel class.
+grf_status grf_prof_begin(int max_launches) {
+  if (max_launches < 1 || max_launches > (1 << 20)) return fail(GRF_EINVAL, "max_launches out of range");
+  for (auto& c : g_prof.cls) {
+    while ((int)c.ev.size() < 2 * max_launches) {
+      hipEvent_t e;
+      GRF_HIP_CHECK(hipEventCreate(&e));
+      c.ev.push_back(e);
+    }
+    c.used = 0;
+  }
+  g_prof.cap = max_launches;
+  g_prof.on = true;
+  return GRF_OK;
+}
+
+// Stop recording; for each kernel class (0 stencil, 1 pointwise, 2 VJP) return
+// the summed kernel time in ms and the number of timed launches (waits for them).
+grf_status grf_prof_end(double* ms, int* count) {
+  g_prof.on = false;
+  for (int k = 0; k < 3; ++k) {
+    ProfClass& c = g_prof.cls[k];
+    double tot = 0.0;
+    for (int q = 0; q + 1 < c.used; q += 2) {
+      GRF_HIP_CHECK(hipEventSynchronize(c.ev[q + 1]));
+      float t = 0.f;
+      GRF_HIP_CHECK(hipEventElapsedTime(&t, c.ev[q], c.ev[q + 1]));
+      tot += t;
+    }
+    if (ms) ms[k] = tot;
+    if (count) count[k] = c.used / 2;
+    c.used = 0;
+  }
+  return GRF_OK;
 }
 
 // Select the stencil tile shape (0..4) used by the single-box calls.

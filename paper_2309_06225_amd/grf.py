@@ -73,8 +73,10 @@ def lib():
         L.grf_flops_per_cell.restype = ctypes.c_int64
         L.grf_last_error.restype = ctypes.c_char_p
         L.grf_set_tile_variant.argtypes = [ctypes.c_int]
+        L.grf_prof_begin.argtypes = [ctypes.c_int]
+        L.grf_prof_end.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         for name in ("grf_rhs_eval", "grf_rk4_stage", "grf_fill_periodic", "grf_rhs_vjp", "grf_status_fetch",
-                     "grf_status_clear", "grf_set_tile_variant"):
+                     "grf_status_clear", "grf_set_tile_variant", "grf_prof_begin", "grf_prof_end"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -166,6 +168,18 @@ def status_clear(ws, stream=None):
 
 def set_tile_variant(v: int):
     _check(lib().grf_set_tile_variant(int(v)))
+
+
+def prof_begin(max_launches: int):
+    _check(lib().grf_prof_begin(int(max_launches)))
+
+
+def prof_end():
+    """-> {'deriv': (ms, n), 'point': (ms, n), 'vjp': (ms, n)} from HIP events."""
+    ms = (ctypes.c_double * 3)()
+    cnt = (ctypes.c_int * 3)()
+    _check(lib().grf_prof_end(ms, cnt))
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(("deriv", "point", "vjp"))}
 
 
 def flops_per_cell(which=0) -> int:
