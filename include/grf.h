@@ -125,6 +125,19 @@ size_t grf_vjp_workspace_bytes(const grf_box* box);
 grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u, const double* w, double* u_bar,
                        double* theta_bar, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Adjoint of one frozen-ghost RK4 step u -> u_new (the four stages of
+ * grf_rk4_stage).  Inputs: the step's start state u and its stage states
+ * u2 = u + dt/2 k1, u3 = u + dt/2 k2, u4 = u + dt k3 (state layout, ghosts equal
+ * to u's), and ubar_new, the cotangent of u_new (all cells).  Output:
+ *   ubar       = (d u_new / d u)^T ubar_new        (all cells, overwritten),
+ *   theta_bar += (d u_new / d (lambda_gb, g2))^T ubar_new.
+ * ubar must not alias any input.  Workspace from grf_rk4_step_vjp_workspace_bytes
+ * (the RHS-VJP workspace plus two state-sized temporaries). */
+size_t grf_rk4_step_vjp_workspace_bytes(const grf_box* box);
+grf_status grf_rk4_step_vjp(const grf_params* p, const grf_box* box, double dt, const double* u, const double* u2,
+                            const double* u3, const double* u4, const double* ubar_new, double* ubar,
+                            double* theta_bar, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* Device status word kept at the start of a workspace: synchronises `stream`,
  * returns GRF_OK or the device condition of highest precedence (NONFINITE,
  * then HYPERBOLIC, then NONPOSITIVE), and stores the raw bits in *bits if non-null. */

@@ -11,6 +11,7 @@
 
 #include "../../include/grf.h"
 #include "kernels_fwd.h"
+#include "kernels_vjp.h"
 
 namespace grf {
 
@@ -300,16 +301,131 @@ grf_status grf_rk4_stage(const grf_params* p, const grf_box* box, int stage, dou
   return GRF_OK;
 }
 
+}  // extern "C"
+
+namespace grf {
+constexpr int64_t kRedChunk = 4096;
+struct VjpLayout {
+  size_t off_D, off_UP, off_Dbar, off_TH, off_part, total;
+  int nparts;
+};
+VjpLayout vjp_layout(const grf_box* b) {
+  const size_t n = (size_t)b->nx * b->ny * b->nz;
+  VjpLayout L;
+  L.nparts = (int)((n + kRedChunk - 1) / kRedChunk);
+  L.off_D = kStatusBytes;
+  L.off_UP = L.off_D + (size_t)GRF_NCOMP * n * 8;
+  L.off_Dbar = L.off_UP + (size_t)3 * NF * n * 8;
+  L.off_TH = L.off_Dbar + (size_t)NCOMP_BAR * n * 8;
+  L.off_part = L.off_TH + (size_t)NTH * n * 8;
+  L.total = L.off_part + (size_t)NTH * L.nparts * 8;
+  return L;
+}
+}  // namespace grf
+
+extern "C" {
+
 size_t grf_vjp_workspace_bytes(const grf_box* box) {
   if (check_box(box) != GRF_OK) return 0;
-  return kStatusBytes + deriv_bytes(box);
+  return vjp_layout(box).total;
 }
 
 grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u, const double* w, double* u_bar,
                        double* theta_bar, void* workspace, size_t workspace_bytes, hipStream_t stream) {
-  (void)p; (void)box; (void)u; (void)w; (void)u_bar; (void)theta_bar; (void)workspace; (void)workspace_bytes;
-  (void)stream;
-  return fail(GRF_EUNSUPPORTED, "vjp not built yet");
+  grf_status s = check_params(p);
+  if (s != GRF_OK) return s;
+  s = check_box(box);
+  if (s != GRF_OK) return s;
+  if (!u || !w || !u_bar || !theta_bar || !workspace) return fail(GRF_EINVAL, "null pointer");
+  if (u_bar == u || u_bar == w) return fail(GRF_EINVAL, "u_bar must not alias u or w");
+  const VjpLayout L = vjp_layout(box);
+  if (workspace_bytes < L.total) return fail(GRF_ENOMEM, "workspace %zu bytes < %zu", workspace_bytes, L.total);
+  BoxDev bd = make_boxdev(box);
+  grf_point_params pp = make_pp(p);
+  char* ws = (char*)workspace;
+  double* D = (double*)(ws + L.off_D);
+  double* UP = (double*)(ws + L.off_UP);
+  double* Dbar = (double*)(ws + L.off_Dbar);
+  double* TH = (double*)(ws + L.off_TH);
+  double* part = (double*)(ws + L.off_part);
+  const int sa = p->shift_advec != 0.0;
+  prof_mark(2, stream);
+  GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, sa, UP, stream));
+  const unsigned nblk = (unsigned)((bd.ncell + 63) / 64);
+  if (sa)
+    hipLaunchKernelGGL((k_vjp_point<1>), dim3(nblk), dim3(64), 0, stream, bd, pp, u, D, UP, w, u_bar, Dbar, TH);
+  else
+    hipLaunchKernelGGL((k_vjp_point<0>), dim3(nblk), dim3(64), 0, stream, bd, pp, u, D, UP, w, u_bar, Dbar, TH);
+  GRF_HIP_CHECK(hipGetLastError());
+  {
+    constexpr int TX = 16, TY = 8, TZ = 4;
+    const int ntiles = ((bd.nx + 6 + TX - 1) / TX) * ((bd.ny + 6 + TY - 1) / TY) * ((bd.nz + 6 + TZ - 1) / TZ);
+    hipLaunchKernelGGL((k_vjp_transpose<TX, TY, TZ>), dim3(ntiles, NF), dim3(TX * TY * TZ), 0, stream, bd, u, w,
+                       Dbar, p->ko_sigma, sa, u_bar);
+    GRF_HIP_CHECK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_reduce_partial, dim3(L.nparts, NTH), dim3(kRedThreads), 0, stream, TH, bd.ncell, kRedChunk,
+                     part);
+  GRF_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce_final, dim3(NTH), dim3(kRedThreads), 0, stream, part, L.nparts, theta_bar);
+  GRF_HIP_CHECK(hipGetLastError());
+  prof_mark(2, stream);
+  return GRF_OK;
+}
+
+size_t grf_rk4_step_vjp_workspace_bytes(const grf_box* box) {
+  if (check_box(box) != GRF_OK) return 0;
+  const size_t state = (size_t)NF * box->field_stride * 8;
+  return vjp_layout(box).total + 2 * ((state + 255) / 256 * 256);
+}
+
+grf_status grf_rk4_step_vjp(const grf_params* p, const grf_box* box, double dt, const double* u, const double* u2,
+                            const double* u3, const double* u4, const double* ubar_new, double* ubar,
+                            double* theta_bar, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  grf_status s = check_params(p);
+  if (s != GRF_OK) return s;
+  s = check_box(box);
+  if (s != GRF_OK) return s;
+  if (box->bc != GRF_BC_FROZEN) return fail(GRF_EUNSUPPORTED, "the step adjoint is implemented for frozen ghosts");
+  if (!u || !u2 || !u3 || !u4 || !ubar_new || !ubar || !theta_bar || !workspace) return fail(GRF_EINVAL, "null pointer");
+  if (ubar == ubar_new || ubar == u || ubar == u2 || ubar == u3 || ubar == u4)
+    return fail(GRF_EINVAL, "ubar must not alias an input");
+  if (!std::isfinite(dt)) return fail(GRF_EINVAL, "dt not finite");
+  const size_t need = grf_rk4_step_vjp_workspace_bytes(box);
+  if (workspace_bytes < need) return fail(GRF_ENOMEM, "workspace %zu bytes < %zu", workspace_bytes, need);
+  const VjpLayout L = vjp_layout(box);
+  const size_t state = (size_t)NF * box->field_stride * 8;
+  const size_t sstate = (state + 255) / 256 * 256;
+  double* kbar = (double*)((char*)workspace + L.total);
+  double* sbar = (double*)((char*)workspace + L.total + sstate);
+  const int64_t n = (int64_t)NF * box->field_stride;
+  const dim3 g((unsigned)((n + 255) / 256)), blk(256);
+  auto vjp = [&](const double* at, const double* w, double* out) {
+    return grf_rhs_vjp(p, box, at, w, out, theta_bar, workspace, L.total, stream);
+  };
+  // stage 4: k4 = f(u4), u_new = u + dt/6 (k1 + 2k2 + 2k3 + k4), u4 = u + dt k3
+  hipLaunchKernelGGL(k_axpby, g, blk, 0, stream, n, dt / 6.0, ubar_new, 0.0, (const double*)nullptr, kbar);
+  hipLaunchKernelGGL(k_fill, g, blk, 0, stream, n, 0.0, sbar);
+  GRF_HIP_CHECK(hipGetLastError());
+  if ((s = vjp(u4, kbar, sbar)) != GRF_OK) return s;
+  hipLaunchKernelGGL(k_axpby, g, blk, 0, stream, n, 1.0, ubar_new, 1.0, (const double*)sbar, ubar);
+  // stage 3: k3 = f(u3), u3 = u + dt/2 k2
+  hipLaunchKernelGGL(k_axpby, g, blk, 0, stream, n, dt / 3.0, ubar_new, dt, (const double*)sbar, kbar);
+  hipLaunchKernelGGL(k_fill, g, blk, 0, stream, n, 0.0, sbar);
+  GRF_HIP_CHECK(hipGetLastError());
+  if ((s = vjp(u3, kbar, sbar)) != GRF_OK) return s;
+  hipLaunchKernelGGL(k_axpby, g, blk, 0, stream, n, 1.0, (const double*)ubar, 1.0, (const double*)sbar, ubar);
+  // stage 2: k2 = f(u2), u2 = u + dt/2 k1
+  hipLaunchKernelGGL(k_axpby, g, blk, 0, stream, n, dt / 3.0, ubar_new, 0.5 * dt, (const double*)sbar, kbar);
+  hipLaunchKernelGGL(k_fill, g, blk, 0, stream, n, 0.0, sbar);
+  GRF_HIP_CHECK(hipGetLastError());
+  if ((s = vjp(u2, kbar, sbar)) != GRF_OK) return s;
+  hipLaunchKernelGGL(k_axpby, g, blk, 0, stream, n, 1.0, (const double*)ubar, 1.0, (const double*)sbar, ubar);
+  // stage 1: k1 = f(u)
+  hipLaunchKernelGGL(k_axpby, g, blk, 0, stream, n, dt / 6.0, ubar_new, 0.5 * dt, (const double*)sbar, kbar);
+  GRF_HIP_CHECK(hipGetLastError());
+  if ((s = vjp(u, kbar, ubar)) != GRF_OK) return s;
+  return GRF_OK;
 }
 
 // Start recording up to max_launches timed launches per kernel class.

@@ -67,6 +67,10 @@ def lib():
         L.grf_rk4_stage.argtypes = [P, B, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.grf_fill_periodic.argtypes = [B, _vp, _vp]
         L.grf_rhs_vjp.argtypes = [P, B, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.grf_rk4_step_vjp_workspace_bytes.argtypes = [B]
+        L.grf_rk4_step_vjp_workspace_bytes.restype = ctypes.c_size_t
+        L.grf_rk4_step_vjp.argtypes = [P, B, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                       _vp]
         L.grf_status_fetch.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_uint32)]
         L.grf_status_clear.argtypes = [_vp, _vp]
         L.grf_flops_per_cell.argtypes = [ctypes.c_int]
@@ -76,7 +80,8 @@ def lib():
         L.grf_prof_begin.argtypes = [ctypes.c_int]
         L.grf_prof_end.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         for name in ("grf_rhs_eval", "grf_rk4_stage", "grf_fill_periodic", "grf_rhs_vjp", "grf_status_fetch",
-                     "grf_status_clear", "grf_set_tile_variant", "grf_prof_begin", "grf_prof_end"):
+                     "grf_status_clear", "grf_set_tile_variant", "grf_prof_begin", "grf_prof_end",
+                     "grf_rk4_step_vjp"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -154,6 +159,16 @@ def fill_periodic(box: Box, u, stream=None):
 def rhs_vjp(params: Params, box: Box, u, w, u_bar, theta_bar, ws, stream=None):
     _check(lib().grf_rhs_vjp(ctypes.byref(params), ctypes.byref(box), _ptr(u), _ptr(w), _ptr(u_bar),
                              _ptr(theta_bar), _ptr(ws), ws.numel() * 8, _stream(stream)))
+
+
+def step_vjp_workspace_bytes(box: Box) -> int:
+    return int(lib().grf_rk4_step_vjp_workspace_bytes(ctypes.byref(box)))
+
+
+def rk4_step_vjp(params: Params, box: Box, dt, u, u2, u3, u4, ubar_new, ubar, theta_bar, ws, stream=None):
+    _check(lib().grf_rk4_step_vjp(ctypes.byref(params), ctypes.byref(box), float(dt), _ptr(u), _ptr(u2), _ptr(u3),
+                                  _ptr(u4), _ptr(ubar_new), _ptr(ubar), _ptr(theta_bar), _ptr(ws), ws.numel() * 8,
+                                  _stream(stream)))
 
 
 def status_fetch(ws, stream=None):
