@@ -149,6 +149,44 @@ grf_status grf_status_clear(void* workspace, hipStream_t stream);
  * (add, sub, mul and reciprocal each 1), stencils not included. */
 int64_t grf_flops_per_cell(int which /* 0 rhs, 1 rhs with shift advection, 2 vjp */);
 
+/* ---- Batched boxes (uneven sizes and refinement levels, frozen ghosts).
+ * One RK4 step of the batch is four stages; each stage is one persistent
+ * stencil launch per tile shape in use and one persistent pointwise launch,
+ * covering every box (work lists of (box, tile) and (box, 128-cell block)
+ * entries, fixed assignment to workgroups, no atomics).  Per cell the device
+ * code is the one of grf_rk4_stage, so results are bitwise identical to
+ * per-box launches (grf_batch_step_perbox runs that reference form on the same
+ * buffers).
+ *   u[b]      state of box b (device, caller-owned); after an even number of
+ *             steps the current state is back in u[b], after an odd number it
+ *             is in the batch's second buffer (grf_batch_state gives it);
+ *   dts[b]    time step of box b (host array, copied);
+ *   scratch   caller-owned device memory of grf_batch_scratch_bytes: two
+ *             stage states, the accumulator and the derivative records per box.
+ * The batch object (host) owns its device descriptor and work-list arrays
+ * (allocated by grf_batch_create / grf_batch_autotune, freed by
+ * grf_batch_destroy) and a status word (grf_batch_status_fetch). */
+typedef struct grf_batch grf_batch;
+size_t grf_batch_scratch_bytes(const grf_box* boxes, int nboxes);
+grf_status grf_batch_create(const grf_params* p, const grf_box* boxes, int nboxes, double* const* u,
+                            const double* dts, void* scratch, size_t scratch_bytes, grf_batch** out);
+grf_status grf_batch_step(grf_batch* batch, hipStream_t stream);
+grf_status grf_batch_step_perbox(grf_batch* batch, hipStream_t stream);
+/* Captures two batched RK4 steps (so that buffer roles are the same before
+ * and after every replay) on a non-null stream into an executable graph. */
+grf_status grf_batch_capture(grf_batch* batch, hipStream_t stream, hipGraphExec_t* exec);
+/* Times every stencil tile shape on one box of each box-shape class and keeps
+ * the fastest (ties: lower variant index); choices are cached per shape class
+ * for the life of the process and reused by later batches. */
+grf_status grf_batch_autotune(grf_batch* batch, hipStream_t stream);
+grf_status grf_batch_state(const grf_batch* batch, int box, double** current);
+grf_status grf_batch_tile_variant(const grf_batch* batch, int box, int* variant);
+grf_status grf_batch_status_fetch(const grf_batch* batch, hipStream_t stream, uint32_t* bits);
+void grf_batch_destroy(grf_batch* batch);
+/* Launch / destroy an executable graph made by grf_batch_capture. */
+grf_status grf_graph_launch(hipGraphExec_t exec, hipStream_t stream);
+grf_status grf_graph_destroy(hipGraphExec_t exec);
+
 /* Stencil-stage tile shape used by the single-box calls: 0: 16x8x4 (default),
  * 1: 32x4x4, 2: 8x8x8, 3: 16x16x2, 4: 64x4x2.  Results do not depend on it. */
 grf_status grf_set_tile_variant(int variant);

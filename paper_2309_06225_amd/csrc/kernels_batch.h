@@ -1,0 +1,83 @@
+// Batched persistent kernels: one launch per RK4 stage phase covers every box
+// of a batch.  Work lists are static (box, tile) and (box, cell block) entries;
+// workgroup w takes entries w, w + G, w + 2G, ... so no atomics are involved and
+// every cell is computed by exactly the same device code as in the per-box
+// launches (results are bitwise identical).
+#pragma once
+#include "kernels_fwd.h"
+
+namespace grf {
+
+struct BatchBoxDev {
+  BoxDev bd;
+  double* u;    // state buffer A (the state after an even number of steps)
+  double* ub;   // state buffer B (after an odd number of steps; stage scratch otherwise)
+  double* ua;   // stage scratch
+  double* acc;  // compact accumulator
+  double* D;    // derivative records
+  double dt;
+};
+
+struct TileEntry {
+  int box;
+  int tile;
+};
+struct CellEntry {
+  int box;
+  int pad;
+  int64_t c0;
+};
+
+// Buffer roles of RK4 stage s (1..4) for step parity p: base state, stage input,
+// stage output.  Parity 0 steps u -> ub, parity 1 steps ub -> u.
+__device__ __forceinline__ void stage_roles(const BatchBoxDev& B, int stage, int parity, const double*& base,
+                                            const double*& in, double*& out) {
+  double* b0 = parity ? B.ub : B.u;
+  double* fin = parity ? B.u : B.ub;
+  base = b0;
+  switch (stage) {
+    case 1: in = b0; out = B.ua; break;
+    case 2: in = B.ua; out = fin; break;
+    case 3: in = fin; out = B.ua; break;
+    default: in = B.ua; out = fin; break;
+  }
+}
+
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX* TY* TZ) void k_deriv_batch(const BatchBoxDev* __restrict__ boxes,
+                                                            const TileEntry* __restrict__ entries, int nentries,
+                                                            int stage, int parity, double ko_sigma, int shift_adv) {
+  __shared__ double t[(TZ + 6) * (TY + 6) * (TX + 6)];
+  const int64_t total = (int64_t)nentries * NF;
+  for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    const int e = (int)(g / NF), f = (int)(g % NF);
+    const TileEntry en = entries[e];
+    const BatchBoxDev B = boxes[en.box];
+    const double *base, *in;
+    double* out;
+    stage_roles(B, stage, parity, base, in, out);
+    deriv_tile<TX, TY, TZ>(B.bd, en.tile, f, in, B.D, ko_sigma, shift_adv, nullptr, t);
+  }
+}
+
+template <int SHIFTADV>
+__global__ __launch_bounds__(kPointThreads) void k_point_batch(const BatchBoxDev* __restrict__ boxes,
+                                                               const CellEntry* __restrict__ entries, int nentries,
+                                                               int stage, int parity, grf_point_params P,
+                                                               unsigned* __restrict__ status) {
+  const int mode = stage == 1 ? 1 : (stage == 4 ? 4 : 2);
+  for (int g = blockIdx.x; g < nentries; g += gridDim.x) {
+    const CellEntry en = entries[g];
+    const BatchBoxDev B = boxes[en.box];
+    const int64_t c = en.c0 + threadIdx.x;
+    if (c >= B.bd.ncell) continue;
+    const double *base, *in;
+    double* out;
+    stage_roles(B, stage, parity, base, in, out);
+    StageCoef sc;
+    sc.cnext = stage == 4 ? B.dt / 6.0 : (stage == 3 ? 1.0 * B.dt : 0.5 * B.dt);
+    point_cell<SHIFTADV>(B.bd, c, mode, P, in, B.D, base, out, B.acc, sc, status);
+  }
+}
+
+}  // namespace grf

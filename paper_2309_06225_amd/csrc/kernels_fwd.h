@@ -80,19 +80,17 @@ __device__ __forceinline__ double sten_mixed(const double* t, int c0, int sd, in
 // With UP non-null the three upwinded derivatives are also stored (for the VJP):
 //   UP[(3 f + k) * ncell + cell].
 template <int TX, int TY, int TZ>
-__global__ __launch_bounds__(TX* TY* TZ) void k_deriv(BoxDev b, const double* __restrict__ u,
-                                                      double* __restrict__ D, double ko_sigma, int shift_adv,
-                                                      double* __restrict__ UP) {
+__device__ __forceinline__ void deriv_tile(const BoxDev& b, int tile, int f, const double* __restrict__ u,
+                                           double* __restrict__ D, double ko_sigma, int shift_adv,
+                                           double* __restrict__ UP, double* t) {
   constexpr int LX = TX + 6, LY = TY + 6, LZ = TZ + 6;
-  __shared__ double t[LZ * LY * LX];
-  const int f = blockIdx.y;
   const int ntx = (b.nx + TX - 1) / TX, nty = (b.ny + TY - 1) / TY;
-  int tile = blockIdx.x;
   const int tx0 = (tile % ntx) * TX;
   tile /= ntx;
   const int ty0 = (tile % nty) * TY;
   const int tz0 = (tile / nty) * TZ;
   const double* __restrict__ uf = u + (int64_t)f * b.fs;
+  __syncthreads();  // the previous work item of this workgroup is done with t
   // tile origin in state coordinates is (tx0, ty0, tz0): state coord = interior + 3
   for (int e = threadIdx.x; e < LX * LY * LZ; e += TX * TY * TZ) {
     const int lx = e % LX;
@@ -107,7 +105,7 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_deriv(BoxDev b, const double* __
   const int iy = (threadIdx.x / TX) % TY;
   const int iz = threadIdx.x / (TX * TY);
   const int i = tx0 + ix, j = ty0 + iy, k = tz0 + iz;
-  if (i >= b.nx || j >= b.ny || k >= b.nz) return;
+  if (i >= b.nx || j >= b.ny || k >= b.nz) return;  // no barrier follows in this function
   const int64_t cell = ((int64_t)k * b.ny + j) * b.nx + i;
   const int c0 = ((iz + 3) * LY + (iy + 3)) * LX + (ix + 3);
   const int st[3] = {1, LX, LX * LY};
@@ -151,6 +149,14 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_deriv(BoxDev b, const double* __
   Dc[(int64_t)(GRF_OFF_KO + f) * nc] = ko_sigma * ko;
 }
 
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX* TY* TZ) void k_deriv(BoxDev b, const double* __restrict__ u,
+                                                      double* __restrict__ D, double ko_sigma, int shift_adv,
+                                                      double* __restrict__ UP) {
+  __shared__ double t[(TZ + 6) * (TY + 6) * (TX + 6)];
+  deriv_tile<TX, TY, TZ>(b, blockIdx.x, blockIdx.y, u, D, ko_sigma, shift_adv, UP, t);
+}
+
 // ---------------------------------------------------------------------------
 // Pointwise right-hand side (generated algebra) fused with the RK4 stage.
 // MODE 0: rhs[f] = k;  MODE 1: first stage;  MODE 2: middle stage;  MODE 4: last stage.
@@ -165,8 +171,7 @@ struct StageCoef {
 // background round exactly as the textbook formula does.  k includes the
 // Kreiss-Oliger term stored by the stencil stage.
 #pragma clang fp contract(off)
-template <int MODE>
-__device__ __forceinline__ void stage_one(int f, double rhs_f, const BoxDev& b, const double* __restrict__ D,
+__device__ __forceinline__ void stage_one(int mode, int f, double rhs_f, const BoxDev& b, const double* __restrict__ D,
                                           int64_t c, int64_t s, const double* __restrict__ u0,
                                           double* __restrict__ out, double* __restrict__ acc, StageCoef sc,
                                           unsigned& flags) {
@@ -175,12 +180,12 @@ __device__ __forceinline__ void stage_one(int f, double rhs_f, const BoxDev& b, 
   if (!isfinite(kf)) flags |= 1u;
   const int64_t q = (int64_t)f * b.fs + s;
   const int64_t qa = (int64_t)f * nc + c;
-  if (MODE == 0) {
+  if (mode == 0) {
     out[q] = kf;
-  } else if (MODE == 1) {
+  } else if (mode == 1) {
     acc[qa] = kf;
     out[q] = u0[q] + sc.cnext * kf;
-  } else if (MODE == 2) {
+  } else if (mode == 2) {
     acc[qa] = acc[qa] + 2.0 * kf;
     out[q] = u0[q] + sc.cnext * kf;
   } else {
@@ -189,13 +194,13 @@ __device__ __forceinline__ void stage_one(int f, double rhs_f, const BoxDev& b, 
 }
 #pragma clang fp contract(fast)
 
-template <int MODE, int SHIFTADV>
-__global__ __launch_bounds__(128) void k_point(BoxDev b, grf_point_params P, const double* __restrict__ us,
-                                               const double* __restrict__ D, const double* __restrict__ u0,
-                                               double* __restrict__ out, double* __restrict__ acc, StageCoef sc,
-                                               unsigned* __restrict__ status) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= b.ncell) return;
+// One interior cell c of box b: right-hand side and stage update (mode 0: rhs
+// only; 1: first stage; 2: middle stage; 4: last stage).
+template <int SHIFTADV>
+__device__ __forceinline__ void point_cell(const BoxDev& b, int64_t c, int mode, const grf_point_params& P,
+                                           const double* __restrict__ us, const double* __restrict__ D,
+                                           const double* __restrict__ u0, double* __restrict__ out,
+                                           double* __restrict__ acc, StageCoef sc, unsigned* __restrict__ status) {
   const int i = (int)(c % b.nx);
   const int64_t r = c / b.nx;
   const int j = (int)(r % b.ny);
@@ -207,7 +212,7 @@ __global__ __launch_bounds__(128) void k_point(BoxDev b, grf_point_params P, con
 #define GRF_U(f) us[(int64_t)(f) * b.fs + s]
 #define GRF_D(cc) D[(int64_t)(cc) * nc + c]
 #define GRF_P(n) P.n
-#define GRF_RHS(f, v) stage_one<MODE>(f, (v), b, D, c, s, u0, out, acc, sc, flags)
+#define GRF_RHS(f, v) stage_one(mode, f, (v), b, D, c, s, u0, out, acc, sc, flags)
 #define GRF_PIVCHK(v) bad |= !(fabs(v) <= 1e12)
 #define GRF_SHIFT_ADVEC (SHIFTADV != 0)
 #include "gen/gen_rhs.inc"
@@ -217,6 +222,20 @@ __global__ __launch_bounds__(128) void k_point(BoxDev b, grf_point_params P, con
   if (bad) flags |= 2u;
   if (!(us[(int64_t)F_CHI * b.fs + s] > 0.0) || !(us[(int64_t)F_LAPSE * b.fs + s] > 0.0)) flags |= 4u;
   if (flags) atomicOr(status, flags);
+}
+
+constexpr int kPointThreads = 128;
+
+template <int SHIFTADV>
+__global__ __launch_bounds__(kPointThreads) void k_point(BoxDev b, int mode, grf_point_params P,
+                                                         const double* __restrict__ us,
+                                                         const double* __restrict__ D,
+                                                         const double* __restrict__ u0, double* __restrict__ out,
+                                                         double* __restrict__ acc, StageCoef sc,
+                                                         unsigned* __restrict__ status) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= b.ncell) return;
+  point_cell<SHIFTADV>(b, c, mode, P, us, D, u0, out, acc, sc, status);
 }
 
 // ---------------------------------------------------------------------------

@@ -71,6 +71,20 @@ def lib():
         L.grf_rk4_step_vjp_workspace_bytes.restype = ctypes.c_size_t
         L.grf_rk4_step_vjp.argtypes = [P, B, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
                                        _vp]
+        L.grf_batch_scratch_bytes.argtypes = [B, ctypes.c_int]
+        L.grf_batch_scratch_bytes.restype = ctypes.c_size_t
+        L.grf_batch_create.argtypes = [P, B, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_double), _vp,
+                                       ctypes.c_size_t, ctypes.POINTER(_vp)]
+        for name in ("grf_batch_step", "grf_batch_step_perbox", "grf_batch_autotune"):
+            getattr(L, name).argtypes = [_vp, _vp]
+        L.grf_batch_capture.argtypes = [_vp, _vp, ctypes.POINTER(_vp)]
+        L.grf_batch_state.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_vp)]
+        L.grf_batch_tile_variant.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.grf_batch_status_fetch.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_uint32)]
+        L.grf_batch_destroy.argtypes = [_vp]
+        L.grf_batch_destroy.restype = None
+        L.grf_graph_launch.argtypes = [_vp, _vp]
+        L.grf_graph_destroy.argtypes = [_vp]
         L.grf_status_fetch.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_uint32)]
         L.grf_status_clear.argtypes = [_vp, _vp]
         L.grf_flops_per_cell.argtypes = [ctypes.c_int]
@@ -81,7 +95,9 @@ def lib():
         L.grf_prof_end.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         for name in ("grf_rhs_eval", "grf_rk4_stage", "grf_fill_periodic", "grf_rhs_vjp", "grf_status_fetch",
                      "grf_status_clear", "grf_set_tile_variant", "grf_prof_begin", "grf_prof_end",
-                     "grf_rk4_step_vjp"):
+                     "grf_rk4_step_vjp", "grf_batch_create", "grf_batch_step", "grf_batch_step_perbox",
+                     "grf_batch_autotune", "grf_batch_capture", "grf_batch_state", "grf_batch_tile_variant",
+                     "grf_batch_status_fetch", "grf_graph_launch", "grf_graph_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -227,3 +243,80 @@ class Stepper:
 
     def status(self):
         return status_fetch(self.ws)
+
+
+class Batch:
+    """Boxes of uneven sizes and levels advanced together (frozen ghosts).
+
+    states: list of device tensors (state layout, one per box), advanced in
+    place: after an even number of steps each box's state is back in its
+    tensor; `state(b)` returns the current state of box b at any time."""
+
+    def __init__(self, params: Params, boxes, states, dts):
+        self.params = params
+        self.nb = len(boxes)
+        self.boxes = (Box * self.nb)(*boxes)
+        self.states = [s.contiguous() for s in states]
+        self._ptrs = (_vp * self.nb)(*[s.data_ptr() for s in self.states])
+        self._dts = (ctypes.c_double * self.nb)(*[float(d) for d in dts])
+        nbytes = int(lib().grf_batch_scratch_bytes(self.boxes, self.nb))
+        if nbytes == 0:
+            raise ValueError("invalid boxes")
+        self.scratch = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=self.states[0].device)
+        h = _vp()
+        _check(lib().grf_batch_create(ctypes.byref(params), self.boxes, self.nb, self._ptrs, self._dts,
+                                      _ptr(self.scratch), nbytes, ctypes.byref(h)))
+        self.h = h
+        self.graphs = []
+
+    def step(self, stream=None):
+        _check(lib().grf_batch_step(self.h, _stream(stream)))
+
+    def step_perbox(self, stream=None):
+        _check(lib().grf_batch_step_perbox(self.h, _stream(stream)))
+
+    def autotune(self, stream=None):
+        _check(lib().grf_batch_autotune(self.h, _stream(stream)))
+
+    def tile_variant(self, b):
+        v = ctypes.c_int(0)
+        _check(lib().grf_batch_tile_variant(self.h, int(b), ctypes.byref(v)))
+        return v.value
+
+    def capture(self, stream):
+        """Executable graph of two batched steps, captured on `stream` (non-default)."""
+        g = _vp()
+        _check(lib().grf_batch_capture(self.h, _stream(stream), ctypes.byref(g)))
+        self.graphs.append(g)
+        return g
+
+    def replay(self, graph, stream=None):
+        _check(lib().grf_graph_launch(graph, _stream(stream)))
+
+    def state(self, b):
+        p = _vp()
+        _check(lib().grf_batch_state(self.h, int(b), ctypes.byref(p)))
+        if p.value == self.states[b].data_ptr():
+            return self.states[b]
+        off = (p.value - self.scratch.data_ptr()) // 8
+        n = self.states[b].numel()
+        return self.scratch[off:off + n].view(self.states[b].shape)
+
+    def status(self, stream=None):
+        bits = ctypes.c_uint32(0)
+        code = lib().grf_batch_status_fetch(self.h, _stream(stream), ctypes.byref(bits))
+        return code, int(bits.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            for g in self.graphs:
+                lib().grf_graph_destroy(g)
+            self.graphs = []
+            lib().grf_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

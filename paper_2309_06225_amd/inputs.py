@@ -176,3 +176,13 @@ def shell_mask(dims, dx, r_in=8.0, r_out=10.0, centre=(0.0, 0.0, 0.0)):
 
 def interior(u):
     return u[..., NG:-NG, NG:-NG, NG:-NG]
+
+
+def amr_states(boxes):
+    """The single-puncture data (mass 1 at the origin, phi = 0.1 exp(-(r-4)^2))
+    sampled at the cells of each box; returns (states, dts) with dt = dx/4."""
+    states, dts = [], []
+    for bx in boxes:
+        states.append(puncture(bx["dims"], bx["dx"], centre=bx["centre"], phi_fn=shell_pulse()))
+        dts.append(0.25 * bx["dx"])
+    return states, dts

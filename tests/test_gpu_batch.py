@@ -1,0 +1,132 @@
+"""Batched persistent launches against per-box launches and the oracle; graph
+replays against eager steps; the tile autotuner."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import oracle as O
+from paper_2309_06225_amd import grf as G
+from paper_2309_06225_amd import inputs as I
+from parity_util import rel_err_per_field
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    O.build(force=False)
+    G.lib()
+
+
+def _make(boxes_spec, shift_advec=0.0):
+    states, dts = I.amr_states(boxes_spec)
+    p = I.default_params(shift_advec=shift_advec)
+    boxes = [G.make_box(b["dims"], b["dx"]) for b in boxes_spec]
+    return p, boxes, states, dts
+
+
+SMALL = [dict(dims=(16, 24, 16), dx=0.5, centre=(3.0, 1.0, -2.0), level=1),
+         dict(dims=(24, 16, 32), dx=0.25, centre=(-1.0, 0.5, 0.7), level=2),
+         dict(dims=(16, 16, 16), dx=1.0, centre=(10.0, -6.0, 4.0), level=0),
+         dict(dims=(19, 13, 11), dx=0.125, centre=(0.9, 0.4, -0.3), level=3)]
+
+
+@pytest.mark.parametrize("shift_advec", [0.0, 1.0])
+def test_batched_equals_per_box_bitwise(shift_advec):
+    print("case: batch of 4 uneven boxes, shift_advec", shift_advec, flush=True)
+    p, boxes, states, dts = _make(SMALL, shift_advec)
+    A = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
+    B = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
+    for _ in range(2):
+        A.step()
+        B.step_perbox()
+    torch.cuda.synchronize()
+    for b in range(len(boxes)):
+        assert torch.equal(A.state(b), B.state(b)), b
+    assert A.status() == (0, 0)
+    # one step each more: odd count, the state lives in the second buffer
+    A.step()
+    B.step_perbox()
+    for b in range(len(boxes)):
+        assert torch.equal(A.state(b), B.state(b)), b
+    A.close()
+    B.close()
+
+
+def test_batched_matches_oracle():
+    print("case: batch vs oracle, 2 steps", flush=True)
+    p, boxes, states, dts = _make(SMALL[:3])
+    A = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
+    A.step()
+    A.step()
+    for b, s in enumerate(states):
+        o, _ = O.rk4(I.params_vector(p), s, SMALL[b]["dx"], dts[b], 2, periodic=False)
+        e = rel_err_per_field(A.state(b).cpu().numpy(), o, interior=False)
+        assert e.max() <= 1e-10, (b, dict(zip(I.FIELDS, e)))
+    A.close()
+
+
+def test_graph_replays_match_eager():
+    """Each replay is two steps; eager work and synchronisations in between;
+    every replay is checked against an eager batch."""
+    print("case: hipGraph replays", flush=True)
+    p, boxes, states, dts = _make(SMALL)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        A = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
+        E = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
+        torch.cuda.synchronize()
+        graph = A.capture(stream)
+        for rep in range(3):
+            A.replay(graph, stream)
+            E.step(stream)
+            E.step(stream)
+            stream.synchronize()
+            junk = torch.randn(1000, device=DEV).sum()  # unrelated eager work
+            torch.cuda.synchronize()
+            for b in range(len(boxes)):
+                assert torch.equal(A.state(b), E.state(b)), (rep, b)
+            del junk
+    A.close()
+    E.close()
+
+
+def test_autotune_is_cached_and_result_independent():
+    p, boxes, states, dts = _make(SMALL)
+    A = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
+    A.autotune()
+    v1 = [A.tile_variant(b) for b in range(len(boxes))]
+    assert all(0 <= v < 5 for v in v1)
+    B = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
+    assert [B.tile_variant(b) for b in range(len(boxes))] == v1  # cached per shape class
+    C = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
+    A.step()
+    A.step()
+    C.step_perbox()
+    C.step_perbox()
+    for b in range(len(boxes)):
+        assert torch.equal(A.state(b), C.state(b))
+    for x in (A, B, C):
+        x.close()
+
+
+def test_amr_workload_batched_equals_per_box():
+    """The 96-box workload: one batched step against per-box launches."""
+    print("case: 96 AMR boxes", flush=True)
+    spec = I.amr_boxes()
+    p, boxes, states, dts = _make(spec)
+    A = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
+    B = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
+    A.autotune()
+    A.step()
+    B.step_perbox()
+    torch.cuda.synchronize()
+    for b in range(len(boxes)):
+        assert torch.equal(A.state(b), B.state(b)), b
+    assert A.status()[0] == 0
+    A.close()
+    B.close()
