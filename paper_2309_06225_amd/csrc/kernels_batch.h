@@ -60,12 +60,11 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_deriv_batch(const BatchBoxDev* _
   }
 }
 
-template <int SHIFTADV>
+template <int MODE, int SHIFTADV>
 __global__ __launch_bounds__(kPointThreads) void k_point_batch(const BatchBoxDev* __restrict__ boxes,
                                                                const CellEntry* __restrict__ entries, int nentries,
                                                                int stage, int parity, grf_point_params P,
                                                                unsigned* __restrict__ status) {
-  const int mode = stage == 1 ? 1 : (stage == 4 ? 4 : 2);
   for (int g = blockIdx.x; g < nentries; g += gridDim.x) {
     const CellEntry en = entries[g];
     const BatchBoxDev B = boxes[en.box];
@@ -76,7 +75,7 @@ __global__ __launch_bounds__(kPointThreads) void k_point_batch(const BatchBoxDev
     stage_roles(B, stage, parity, base, in, out);
     StageCoef sc;
     sc.cnext = stage == 4 ? B.dt / 6.0 : (stage == 3 ? 1.0 * B.dt : 0.5 * B.dt);
-    point_cell<SHIFTADV>(B.bd, c, mode, P, in, B.D, base, out, B.acc, sc, status);
+    point_cell<MODE, SHIFTADV>(B.bd, c, P, in, B.D, base, out, B.acc, sc, status);
   }
 }
 

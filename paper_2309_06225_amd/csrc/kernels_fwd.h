@@ -171,7 +171,8 @@ struct StageCoef {
 // background round exactly as the textbook formula does.  k includes the
 // Kreiss-Oliger term stored by the stencil stage.
 #pragma clang fp contract(off)
-__device__ __forceinline__ void stage_one(int mode, int f, double rhs_f, const BoxDev& b, const double* __restrict__ D,
+template <int MODE>
+__device__ __forceinline__ void stage_one(int f, double rhs_f, const BoxDev& b, const double* __restrict__ D,
                                           int64_t c, int64_t s, const double* __restrict__ u0,
                                           double* __restrict__ out, double* __restrict__ acc, StageCoef sc,
                                           unsigned& flags) {
@@ -180,12 +181,12 @@ __device__ __forceinline__ void stage_one(int mode, int f, double rhs_f, const B
   if (!isfinite(kf)) flags |= 1u;
   const int64_t q = (int64_t)f * b.fs + s;
   const int64_t qa = (int64_t)f * nc + c;
-  if (mode == 0) {
+  if constexpr (MODE == 0) {
     out[q] = kf;
-  } else if (mode == 1) {
+  } else if constexpr (MODE == 1) {
     acc[qa] = kf;
     out[q] = u0[q] + sc.cnext * kf;
-  } else if (mode == 2) {
+  } else if constexpr (MODE == 2) {
     acc[qa] = acc[qa] + 2.0 * kf;
     out[q] = u0[q] + sc.cnext * kf;
   } else {
@@ -194,10 +195,10 @@ __device__ __forceinline__ void stage_one(int mode, int f, double rhs_f, const B
 }
 #pragma clang fp contract(fast)
 
-// One interior cell c of box b: right-hand side and stage update (mode 0: rhs
+// One interior cell c of box b: right-hand side and stage update (MODE 0: rhs
 // only; 1: first stage; 2: middle stage; 4: last stage).
-template <int SHIFTADV>
-__device__ __forceinline__ void point_cell(const BoxDev& b, int64_t c, int mode, const grf_point_params& P,
+template <int MODE, int SHIFTADV>
+__device__ __forceinline__ void point_cell(const BoxDev& b, int64_t c, const grf_point_params& P,
                                            const double* __restrict__ us, const double* __restrict__ D,
                                            const double* __restrict__ u0, double* __restrict__ out,
                                            double* __restrict__ acc, StageCoef sc, unsigned* __restrict__ status) {
@@ -212,7 +213,7 @@ __device__ __forceinline__ void point_cell(const BoxDev& b, int64_t c, int mode,
 #define GRF_U(f) us[(int64_t)(f) * b.fs + s]
 #define GRF_D(cc) D[(int64_t)(cc) * nc + c]
 #define GRF_P(n) P.n
-#define GRF_RHS(f, v) stage_one(mode, f, (v), b, D, c, s, u0, out, acc, sc, flags)
+#define GRF_RHS(f, v) stage_one<MODE>(f, (v), b, D, c, s, u0, out, acc, sc, flags)
 #define GRF_PIVCHK(v) bad |= !(fabs(v) <= 1e12)
 #define GRF_SHIFT_ADVEC (SHIFTADV != 0)
 #include "gen/gen_rhs.inc"
@@ -226,67 +227,15 @@ __device__ __forceinline__ void point_cell(const BoxDev& b, int64_t c, int mode,
 
 constexpr int kPointThreads = 128;
 
-template <int SHIFTADV>
-__global__ __launch_bounds__(kPointThreads) void k_point(BoxDev b, int mode, grf_point_params P,
-                                                         const double* __restrict__ us,
+template <int MODE, int SHIFTADV>
+__global__ __launch_bounds__(kPointThreads) void k_point(BoxDev b, grf_point_params P, const double* __restrict__ us,
                                                          const double* __restrict__ D,
                                                          const double* __restrict__ u0, double* __restrict__ out,
                                                          double* __restrict__ acc, StageCoef sc,
                                                          unsigned* __restrict__ status) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= b.ncell) return;
-  point_cell<SHIFTADV>(b, c, mode, P, us, D, u0, out, acc, sc, status);
-}
-
-// ---------------------------------------------------------------------------
-// Periodic ghost fill, one axis per launch (x, then y over x-ghosts, then z over
-// everything), so that edges and corners end up congruent to interior cells.
-__global__ void k_periodic(BoxDev b, double* __restrict__ u, int axis) {
-  const int n[3] = {b.nx, b.ny, b.nz};
-  // extents of the ghost slab of this axis in state coordinates
-  int ext[3], off[3];
-  for (int d = 0; d < 3; ++d) {
-    if (d == axis) {
-      ext[d] = 6;
-      off[d] = 0;
-    } else if (d < axis) {
-      ext[d] = n[d] + 6;
-      off[d] = 0;
-    } else {
-      ext[d] = n[d];
-      off[d] = 3;
-    }
-  }
-  const int64_t total = (int64_t)ext[0] * ext[1] * ext[2];
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= total * NF) return;
-  const int f = (int)(e / total);
-  int64_t r = e % total;
-  int x[3];
-  x[0] = (int)(r % ext[0]);
-  r /= ext[0];
-  x[1] = (int)(r % ext[1]);
-  x[2] = (int)(r / ext[1]);
-  int src[3];
-  for (int d = 0; d < 3; ++d) {
-    int v = x[d] + off[d];
-    if (d == axis) {
-      const int g = x[d];                 // 0..5
-      v = g < 3 ? g : n[d] + g;           // ghost state coordinate
-      src[d] = (((v - 3) % n[d]) + n[d]) % n[d] + 3;  // congruent interior cell
-      x[d] = v;
-    } else {
-      x[d] = v;
-      src[d] = v;
-    }
-  }
-  const int64_t base = (int64_t)f * b.fs;
-  u[base + (int64_t)x[2] * b.sz + (int64_t)x[1] * b.sy + x[0]] =
-      u[base + (int64_t)src[2] * b.sz + (int64_t)src[1] * b.sy + src[0]];
-}
-
-__global__ void k_status_clear(unsigned* s) {
-  if (threadIdx.x == 0) s[threadIdx.x] = 0u;
+  point_cell<MODE, SHIFTADV>(b, c, P, us, D, u0, out, acc, sc, status);
 }
 
 }  // namespace grf

@@ -218,52 +218,4 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_vjp_transpose(BoxDev b, const do
   if (valid) ubar[(int64_t)f * b.fs + (int64_t)Z * b.sz + (int64_t)Y * b.sy + X] += acc;
 }
 
-// Fixed-order two-level reduction of the per-cell coupling cotangents.
-constexpr int kRedThreads = 256;
-__global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const double* __restrict__ TH, int64_t n,
-                                                                int64_t chunk, double* __restrict__ part) {
-  __shared__ double sh[kRedThreads];
-  const int q = blockIdx.y;
-  const int64_t beg = (int64_t)blockIdx.x * chunk;
-  const int64_t end = beg + chunk < n ? beg + chunk : n;
-  double s = 0.0;
-  for (int64_t e = beg + threadIdx.x; e < end; e += kRedThreads) s += TH[(int64_t)q * n + e];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int h = kRedThreads / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[(int64_t)q * gridDim.x + blockIdx.x] = sh[0];
-}
-
-__global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* __restrict__ part, int nparts,
-                                                              double* __restrict__ theta_bar) {
-  __shared__ double sh[kRedThreads];
-  const int q = blockIdx.x;
-  double s = 0.0;
-  for (int e = threadIdx.x; e < nparts; e += kRedThreads) s += part[(int64_t)q * nparts + e];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int h = kRedThreads / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) theta_bar[q] += sh[0];
-}
-
-// out = a x + b y over n elements (y may be null: out = a x); n counts all
-// cells of all fields of a state.
-__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, const double* __restrict__ y,
-                        double* __restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  out[e] = y ? a * x[e] + b * y[e] : a * x[e];
-}
-
-__global__ void k_fill(int64_t n, double v, double* __restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) out[e] = v;
-}
-
 }  // namespace grf

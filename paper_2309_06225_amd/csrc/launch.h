@@ -1,0 +1,75 @@
+// Host-side launchers of libgrf's kernels.  Each is defined in the translation
+// unit that instantiates its kernel (so the large pointwise kernels compile in
+// parallel); the C-ABI entry points in libgrf.hip call them.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gen/gen_layout.h"
+
+namespace grf {
+
+struct BoxDev;
+struct StageCoef;
+struct BatchBoxDev;
+struct TileEntry;
+struct CellEntry;
+
+constexpr int kTileVariants = 5;
+extern const int kTiles[kTileVariants][3];
+
+// stencil stage (tile variant 0..4), optionally storing the upwinded derivatives
+hipError_t launch_deriv(int variant, const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
+                        hipStream_t st);
+int tiles_of_variant(int variant, const BoxDev& bd);
+hipError_t launch_deriv_batch(int variant, int grid, const BatchBoxDev* boxes, const TileEntry* tiles, int ntiles,
+                              int stage, int parity, double sigma, int sa, hipStream_t st);
+int grid_deriv_batch(int variant, int64_t work);
+hipError_t launch_periodic(const BoxDev& bd, double* u, hipStream_t st);
+hipError_t launch_status_clear(unsigned* s, hipStream_t st);
+
+// pointwise right-hand side + stage update (mode 0, 1, 2, 4)
+template <int MODE>
+hipError_t launch_point_m(int sa, const BoxDev& bd, const grf_point_params& pp, const double* us, const double* D,
+                          const double* u0, double* out, double* acc, const StageCoef& sc, unsigned* status,
+                          hipStream_t st);
+template <> hipError_t launch_point_m<0>(int, const BoxDev&, const grf_point_params&, const double*, const double*,
+                                         const double*, double*, double*, const StageCoef&, unsigned*, hipStream_t);
+template <> hipError_t launch_point_m<1>(int, const BoxDev&, const grf_point_params&, const double*, const double*,
+                                         const double*, double*, double*, const StageCoef&, unsigned*, hipStream_t);
+template <> hipError_t launch_point_m<2>(int, const BoxDev&, const grf_point_params&, const double*, const double*,
+                                         const double*, double*, double*, const StageCoef&, unsigned*, hipStream_t);
+template <> hipError_t launch_point_m<4>(int, const BoxDev&, const grf_point_params&, const double*, const double*,
+                                         const double*, double*, double*, const StageCoef&, unsigned*, hipStream_t);
+
+// batched pointwise stage (stage 1 -> mode 1, stages 2-3 -> mode 2, stage 4 -> mode 4)
+template <int MODE>
+hipError_t launch_point_batch_m(int sa, int grid, const BatchBoxDev* boxes, const CellEntry* cells, int ncells,
+                                int stage, int parity, const grf_point_params& pp, unsigned* status, hipStream_t st);
+template <> hipError_t launch_point_batch_m<1>(int, int, const BatchBoxDev*, const CellEntry*, int, int, int,
+                                               const grf_point_params&, unsigned*, hipStream_t);
+template <> hipError_t launch_point_batch_m<2>(int, int, const BatchBoxDev*, const CellEntry*, int, int, int,
+                                               const grf_point_params&, unsigned*, hipStream_t);
+template <> hipError_t launch_point_batch_m<4>(int, int, const BatchBoxDev*, const CellEntry*, int, int, int,
+                                               const grf_point_params&, unsigned*, hipStream_t);
+template <int MODE>
+int grid_point_batch_m(int sa, int64_t work);
+template <> int grid_point_batch_m<1>(int, int64_t);
+template <> int grid_point_batch_m<2>(int, int64_t);
+template <> int grid_point_batch_m<4>(int, int64_t);
+
+// VJP pieces
+hipError_t launch_vjp_point(int sa, const BoxDev& bd, const grf_point_params& pp, const double* u, const double* D,
+                            const double* UP, const double* w, double* ubar, double* Dbar, double* TH,
+                            hipStream_t st);
+hipError_t launch_vjp_transpose(const BoxDev& bd, const double* u, const double* w, const double* Dbar, double sigma,
+                                int sa, double* ubar, hipStream_t st);
+hipError_t launch_reduce(const double* TH, int64_t n, int64_t chunk, int nparts, double* part, double* theta_bar,
+                         hipStream_t st);
+hipError_t launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out,
+                        hipStream_t st);
+hipError_t launch_fill(int64_t n, double v, double* out, hipStream_t st);
+
+int persistent_grid_from(int per_cu, int64_t work);
+
+}  // namespace grf

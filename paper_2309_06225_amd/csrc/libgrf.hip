@@ -13,6 +13,7 @@
 #include "kernels_fwd.h"
 #include "kernels_vjp.h"
 #include "kernels_batch.h"
+#include "launch.h"
 
 #include <map>
 #include <tuple>
@@ -109,30 +110,7 @@ size_t deriv_bytes(const grf_box* b) {
   return (size_t)GRF_NCOMP * (size_t)b->nx * b->ny * b->nz * sizeof(double);
 }
 
-// Tile shapes of the stencil stage (index = tile variant).
-constexpr int kTileVariants = 5;
 constexpr int kTileVariantsMax = 5;
-const int kTiles[kTileVariants][3] = {{16, 8, 4}, {32, 4, 4}, {8, 8, 8}, {16, 16, 2}, {64, 4, 2}};
-
-template <int TX, int TY, int TZ>
-hipError_t launch_deriv_t(const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
-                          hipStream_t st) {
-  const int ntiles = ((bd.nx + TX - 1) / TX) * ((bd.ny + TY - 1) / TY) * ((bd.nz + TZ - 1) / TZ);
-  hipLaunchKernelGGL((k_deriv<TX, TY, TZ>), dim3(ntiles, NF), dim3(TX * TY * TZ), 0, st, bd, u, D, sigma, sa, UP);
-  return hipGetLastError();
-}
-
-hipError_t launch_deriv(int variant, const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
-                        hipStream_t st) {
-  switch (variant) {
-    case 1: return launch_deriv_t<32, 4, 4>(bd, u, D, sigma, sa, UP, st);
-    case 2: return launch_deriv_t<8, 8, 8>(bd, u, D, sigma, sa, UP, st);
-    case 3: return launch_deriv_t<16, 16, 2>(bd, u, D, sigma, sa, UP, st);
-    case 4: return launch_deriv_t<64, 4, 2>(bd, u, D, sigma, sa, UP, st);
-    default: return launch_deriv_t<16, 8, 4>(bd, u, D, sigma, sa, UP, st);
-  }
-}
-
 int g_tile_variant = 0;
 
 // Optional per-kernel timing with HIP events recorded on the launch stream
@@ -157,28 +135,22 @@ void prof_mark(int which, hipStream_t st) {
 hipError_t launch_point(int mode, int sa, const BoxDev& bd, const grf_point_params& pp, const double* us,
                         const double* D, const double* u0, double* out, double* acc, StageCoef sc, unsigned* status,
                         hipStream_t st) {
-  const int64_t nblk = (bd.ncell + kPointThreads - 1) / kPointThreads;
-  if (sa)
-    hipLaunchKernelGGL((k_point<1>), dim3((unsigned)nblk), dim3(kPointThreads), 0, st, bd, mode, pp, us, D, u0, out,
-                       acc, sc, status);
-  else
-    hipLaunchKernelGGL((k_point<0>), dim3((unsigned)nblk), dim3(kPointThreads), 0, st, bd, mode, pp, us, D, u0, out,
-                       acc, sc, status);
-  return hipGetLastError();
+  switch (mode) {
+    case 1: return launch_point_m<1>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
+    case 2: return launch_point_m<2>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
+    case 4: return launch_point_m<4>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
+    default: return launch_point_m<0>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
+  }
 }
 
-hipError_t launch_periodic(const BoxDev& bd, double* u, hipStream_t st) {
-  const int n[3] = {bd.nx, bd.ny, bd.nz};
-  for (int axis = 0; axis < 3; ++axis) {
-    int64_t cells = 6;
-    for (int d = 0; d < 3; ++d)
-      if (d != axis) cells *= (d < axis) ? (n[d] + 6) : n[d];
-    const int64_t total = cells * NF;
-    hipLaunchKernelGGL(k_periodic, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, bd, u, axis);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+hipError_t launch_point_batch(int mode, int sa, int grid, const BatchBoxDev* boxes, const CellEntry* cells,
+                              int ncells, int stage, int parity, const grf_point_params& pp, unsigned* status,
+                              hipStream_t st) {
+  switch (mode) {
+    case 1: return launch_point_batch_m<1>(sa, grid, boxes, cells, ncells, stage, parity, pp, status, st);
+    case 2: return launch_point_batch_m<2>(sa, grid, boxes, cells, ncells, stage, parity, pp, status, st);
+    default: return launch_point_batch_m<4>(sa, grid, boxes, cells, ncells, stage, parity, pp, status, st);
   }
-  return hipSuccess;
 }
 
 }  // namespace grf
@@ -205,8 +177,7 @@ int64_t grf_flops_per_cell(int which) {
 
 grf_status grf_status_clear(void* workspace, hipStream_t stream) {
   if (!workspace) return fail(GRF_EINVAL, "workspace is null");
-  hipLaunchKernelGGL(k_status_clear, dim3(1), dim3(64), 0, stream, (unsigned*)workspace);
-  GRF_HIP_CHECK(hipGetLastError());
+  GRF_HIP_CHECK(launch_status_clear((unsigned*)workspace, stream));
   return GRF_OK;
 }
 
@@ -344,24 +315,9 @@ grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u,
   const int sa = p->shift_advec != 0.0;
   prof_mark(2, stream);
   GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, sa, UP, stream));
-  const unsigned nblk = (unsigned)((bd.ncell + 63) / 64);
-  if (sa)
-    hipLaunchKernelGGL((k_vjp_point<1>), dim3(nblk), dim3(64), 0, stream, bd, pp, u, D, UP, w, u_bar, Dbar, TH);
-  else
-    hipLaunchKernelGGL((k_vjp_point<0>), dim3(nblk), dim3(64), 0, stream, bd, pp, u, D, UP, w, u_bar, Dbar, TH);
-  GRF_HIP_CHECK(hipGetLastError());
-  {
-    constexpr int TX = 16, TY = 8, TZ = 4;
-    const int ntiles = ((bd.nx + 6 + TX - 1) / TX) * ((bd.ny + 6 + TY - 1) / TY) * ((bd.nz + 6 + TZ - 1) / TZ);
-    hipLaunchKernelGGL((k_vjp_transpose<TX, TY, TZ>), dim3(ntiles, NF), dim3(TX * TY * TZ), 0, stream, bd, u, w,
-                       Dbar, p->ko_sigma, sa, u_bar);
-    GRF_HIP_CHECK(hipGetLastError());
-  }
-  hipLaunchKernelGGL(k_reduce_partial, dim3(L.nparts, NTH), dim3(kRedThreads), 0, stream, TH, bd.ncell, kRedChunk,
-                     part);
-  GRF_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_reduce_final, dim3(NTH), dim3(kRedThreads), 0, stream, part, L.nparts, theta_bar);
-  GRF_HIP_CHECK(hipGetLastError());
+  GRF_HIP_CHECK(launch_vjp_point(sa, bd, pp, u, D, UP, w, u_bar, Dbar, TH, stream));
+  GRF_HIP_CHECK(launch_vjp_transpose(bd, u, w, Dbar, p->ko_sigma, sa, u_bar, stream));
+  GRF_HIP_CHECK(launch_reduce(TH, bd.ncell, kRedChunk, L.nparts, part, theta_bar, stream));
   prof_mark(2, stream);
   return GRF_OK;
 }
@@ -392,30 +348,29 @@ grf_status grf_rk4_step_vjp(const grf_params* p, const grf_box* box, double dt, 
   double* kbar = (double*)((char*)workspace + L.total);
   double* sbar = (double*)((char*)workspace + L.total + sstate);
   const int64_t n = (int64_t)NF * box->field_stride;
-  const dim3 g((unsigned)((n + 255) / 256)), blk(256);
   auto vjp = [&](const double* at, const double* w, double* out) {
     return grf_rhs_vjp(p, box, at, w, out, theta_bar, workspace, L.total, stream);
   };
   // stage 4: k4 = f(u4), u_new = u + dt/6 (k1 + 2k2 + 2k3 + k4), u4 = u + dt k3
-  hipLaunchKernelGGL(k_axpby, g, blk, 0, stream, n, dt / 6.0, ubar_new, 0.0, (const double*)nullptr, kbar);
-  hipLaunchKernelGGL(k_fill, g, blk, 0, stream, n, 0.0, sbar);
+  GRF_HIP_CHECK(launch_axpby(n, dt / 6.0, ubar_new, 0.0, (const double*)nullptr, kbar, stream));
+  GRF_HIP_CHECK(launch_fill(n, 0.0, sbar, stream));
   GRF_HIP_CHECK(hipGetLastError());
   if ((s = vjp(u4, kbar, sbar)) != GRF_OK) return s;
-  hipLaunchKernelGGL(k_axpby, g, blk, 0, stream, n, 1.0, ubar_new, 1.0, (const double*)sbar, ubar);
+  GRF_HIP_CHECK(launch_axpby(n, 1.0, ubar_new, 1.0, (const double*)sbar, ubar, stream));
   // stage 3: k3 = f(u3), u3 = u + dt/2 k2
-  hipLaunchKernelGGL(k_axpby, g, blk, 0, stream, n, dt / 3.0, ubar_new, dt, (const double*)sbar, kbar);
-  hipLaunchKernelGGL(k_fill, g, blk, 0, stream, n, 0.0, sbar);
+  GRF_HIP_CHECK(launch_axpby(n, dt / 3.0, ubar_new, dt, (const double*)sbar, kbar, stream));
+  GRF_HIP_CHECK(launch_fill(n, 0.0, sbar, stream));
   GRF_HIP_CHECK(hipGetLastError());
   if ((s = vjp(u3, kbar, sbar)) != GRF_OK) return s;
-  hipLaunchKernelGGL(k_axpby, g, blk, 0, stream, n, 1.0, (const double*)ubar, 1.0, (const double*)sbar, ubar);
+  GRF_HIP_CHECK(launch_axpby(n, 1.0, (const double*)ubar, 1.0, (const double*)sbar, ubar, stream));
   // stage 2: k2 = f(u2), u2 = u + dt/2 k1
-  hipLaunchKernelGGL(k_axpby, g, blk, 0, stream, n, dt / 3.0, ubar_new, 0.5 * dt, (const double*)sbar, kbar);
-  hipLaunchKernelGGL(k_fill, g, blk, 0, stream, n, 0.0, sbar);
+  GRF_HIP_CHECK(launch_axpby(n, dt / 3.0, ubar_new, 0.5 * dt, (const double*)sbar, kbar, stream));
+  GRF_HIP_CHECK(launch_fill(n, 0.0, sbar, stream));
   GRF_HIP_CHECK(hipGetLastError());
   if ((s = vjp(u2, kbar, sbar)) != GRF_OK) return s;
-  hipLaunchKernelGGL(k_axpby, g, blk, 0, stream, n, 1.0, (const double*)ubar, 1.0, (const double*)sbar, ubar);
+  GRF_HIP_CHECK(launch_axpby(n, 1.0, (const double*)ubar, 1.0, (const double*)sbar, ubar, stream));
   // stage 1: k1 = f(u)
-  hipLaunchKernelGGL(k_axpby, g, blk, 0, stream, n, dt / 6.0, ubar_new, 0.5 * dt, (const double*)sbar, kbar);
+  GRF_HIP_CHECK(launch_axpby(n, dt / 6.0, ubar_new, 0.5 * dt, (const double*)sbar, kbar, stream));
   GRF_HIP_CHECK(hipGetLastError());
   if ((s = vjp(u, kbar, ubar)) != GRF_OK) return s;
   return GRF_OK;
@@ -445,49 +400,6 @@ namespace grf {
 
 std::map<std::tuple<int, int, int>, int> g_tile_cache;  // autotuned tile variant per box shape
 
-template <int TX, int TY, int TZ>
-int tiles_of(const BoxDev& b) {
-  return ((b.nx + TX - 1) / TX) * ((b.ny + TY - 1) / TY) * ((b.nz + TZ - 1) / TZ);
-}
-int tiles_of_variant(int v, const BoxDev& b) {
-  switch (v) {
-    case 1: return tiles_of<32, 4, 4>(b);
-    case 2: return tiles_of<8, 8, 8>(b);
-    case 3: return tiles_of<16, 16, 2>(b);
-    case 4: return tiles_of<64, 4, 2>(b);
-    default: return tiles_of<16, 8, 4>(b);
-  }
-}
-
-template <int TX, int TY, int TZ>
-hipError_t launch_deriv_batch_t(grf_batch* B, int v, int stage, hipStream_t st) {
-  hipLaunchKernelGGL((k_deriv_batch<TX, TY, TZ>), dim3(B->grid_deriv[v]), dim3(TX * TY * TZ), 0, st, B->dev,
-                     B->tiles[v], B->ntiles[v], stage, B->parity, B->params.ko_sigma, B->params.shift_advec != 0.0);
-  return hipGetLastError();
-}
-hipError_t launch_deriv_batch(grf_batch* B, int v, int stage, hipStream_t st) {
-  switch (v) {
-    case 1: return launch_deriv_batch_t<32, 4, 4>(B, v, stage, st);
-    case 2: return launch_deriv_batch_t<8, 8, 8>(B, v, stage, st);
-    case 3: return launch_deriv_batch_t<16, 16, 2>(B, v, stage, st);
-    case 4: return launch_deriv_batch_t<64, 4, 2>(B, v, stage, st);
-    default: return launch_deriv_batch_t<16, 8, 4>(B, v, stage, st);
-  }
-}
-
-template <typename K>
-int persistent_grid(K kernel, int threads, int64_t work) {
-  int dev = 0, cus = 256, per = 1;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-  }
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per < 1) per = 1;
-  int64_t g = (int64_t)cus * per;
-  if (g > work) g = work;
-  return (int)(g < 1 ? 1 : g);
-}
-
 grf_status batch_upload_tiles(grf_batch* B) {
   std::vector<TileEntry> lists[kTileVariantsMax];
   for (size_t b = 0; b < B->boxes.size(); ++b) {
@@ -502,16 +414,7 @@ grf_status batch_upload_tiles(grf_batch* B) {
     if (lists[v].empty()) continue;
     GRF_HIP_CHECK(hipMalloc(&B->tiles[v], lists[v].size() * sizeof(TileEntry)));
     GRF_HIP_CHECK(hipMemcpy(B->tiles[v], lists[v].data(), lists[v].size() * sizeof(TileEntry), hipMemcpyHostToDevice));
-    const int threads = kTiles[v][0] * kTiles[v][1] * kTiles[v][2];
-    int g = 0;
-    switch (v) {
-      case 1: g = persistent_grid(k_deriv_batch<32, 4, 4>, threads, (int64_t)lists[v].size() * NF); break;
-      case 2: g = persistent_grid(k_deriv_batch<8, 8, 8>, threads, (int64_t)lists[v].size() * NF); break;
-      case 3: g = persistent_grid(k_deriv_batch<16, 16, 2>, threads, (int64_t)lists[v].size() * NF); break;
-      case 4: g = persistent_grid(k_deriv_batch<64, 4, 2>, threads, (int64_t)lists[v].size() * NF); break;
-      default: g = persistent_grid(k_deriv_batch<16, 8, 4>, threads, (int64_t)lists[v].size() * NF); break;
-    }
-    B->grid_deriv[v] = g;
+    B->grid_deriv[v] = grid_deriv_batch(v, (int64_t)lists[v].size() * NF);
   }
   return GRF_OK;
 }
@@ -520,18 +423,15 @@ grf_status batch_stage(grf_batch* B, int stage, hipStream_t st) {
   for (int v = 0; v < kTileVariants; ++v) {
     if (!B->ntiles[v]) continue;
     prof_mark(0, st);
-    GRF_HIP_CHECK(launch_deriv_batch(B, v, stage, st));
+    GRF_HIP_CHECK(launch_deriv_batch(v, B->grid_deriv[v], B->dev, B->tiles[v], B->ntiles[v], stage, B->parity,
+                                     B->params.ko_sigma, B->params.shift_advec != 0.0, st));
     prof_mark(0, st);
   }
   const grf_point_params pp = make_pp(&B->params);
   prof_mark(1, st);
-  if (B->params.shift_advec != 0.0)
-    hipLaunchKernelGGL((k_point_batch<1>), dim3(B->grid_point), dim3(kPointThreads), 0, st, B->dev, B->cells,
-                       B->ncells, stage, B->parity, pp, B->status);
-  else
-    hipLaunchKernelGGL((k_point_batch<0>), dim3(B->grid_point), dim3(kPointThreads), 0, st, B->dev, B->cells,
-                       B->ncells, stage, B->parity, pp, B->status);
-  GRF_HIP_CHECK(hipGetLastError());
+  const int mode = stage == 1 ? 1 : (stage == 4 ? 4 : 2);
+  GRF_HIP_CHECK(launch_point_batch(mode, B->params.shift_advec != 0.0, B->grid_point, B->dev, B->cells, B->ncells,
+                                   stage, B->parity, pp, B->status, st));
   prof_mark(1, st);
   return GRF_OK;
 }
@@ -607,8 +507,7 @@ grf_status grf_batch_create(const grf_params* p, const grf_box* boxes, int nboxe
     return cleanup(fail(GRF_EHIP, "hipMemcpy"));
   if (hipMalloc(&B->status, 256) != hipSuccess) return cleanup(fail(GRF_EHIP, "hipMalloc"));
   if (hipMemset(B->status, 0, 256) != hipSuccess) return cleanup(fail(GRF_EHIP, "hipMemset"));
-  B->grid_point = (p->shift_advec != 0.0) ? persistent_grid(k_point_batch<1>, kPointThreads, B->ncells)
-                                          : persistent_grid(k_point_batch<0>, kPointThreads, B->ncells);
+  B->grid_point = grid_point_batch_m<2>(p->shift_advec != 0.0, B->ncells);
   if ((s = batch_upload_tiles(B)) != GRF_OK) return cleanup(s);
   *out = B;
   return GRF_OK;

@@ -1,0 +1,244 @@
+// Stencil-stage, ghost-fill, reduction and elementwise kernels of libgrf and
+// their host launchers.
+#include "kernels_fwd.h"
+#include "kernels_batch.h"
+#include "kernels_vjp.h"
+#include "launch.h"
+
+namespace grf {
+
+const int kTiles[kTileVariants][3] = {{16, 8, 4}, {32, 4, 4}, {8, 8, 8}, {16, 16, 2}, {64, 4, 2}};
+
+// ---------------------------------------------------------------------------
+// Periodic ghost fill, one axis per launch (x, then y over x-ghosts, then z over
+// everything), so that edges and corners end up congruent to interior cells.
+__global__ void k_periodic(BoxDev b, double* __restrict__ u, int axis) {
+  const int n[3] = {b.nx, b.ny, b.nz};
+  // extents of the ghost slab of this axis in state coordinates
+  int ext[3], off[3];
+  for (int d = 0; d < 3; ++d) {
+    if (d == axis) {
+      ext[d] = 6;
+      off[d] = 0;
+    } else if (d < axis) {
+      ext[d] = n[d] + 6;
+      off[d] = 0;
+    } else {
+      ext[d] = n[d];
+      off[d] = 3;
+    }
+  }
+  const int64_t total = (int64_t)ext[0] * ext[1] * ext[2];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total * NF) return;
+  const int f = (int)(e / total);
+  int64_t r = e % total;
+  int x[3];
+  x[0] = (int)(r % ext[0]);
+  r /= ext[0];
+  x[1] = (int)(r % ext[1]);
+  x[2] = (int)(r / ext[1]);
+  int src[3];
+  for (int d = 0; d < 3; ++d) {
+    int v = x[d] + off[d];
+    if (d == axis) {
+      const int g = x[d];                 // 0..5
+      v = g < 3 ? g : n[d] + g;           // ghost state coordinate
+      src[d] = (((v - 3) % n[d]) + n[d]) % n[d] + 3;  // congruent interior cell
+      x[d] = v;
+    } else {
+      x[d] = v;
+      src[d] = v;
+    }
+  }
+  const int64_t base = (int64_t)f * b.fs;
+  u[base + (int64_t)x[2] * b.sz + (int64_t)x[1] * b.sy + x[0]] =
+      u[base + (int64_t)src[2] * b.sz + (int64_t)src[1] * b.sy + src[0]];
+}
+
+__global__ void k_status_clear(unsigned* s) {
+  if (threadIdx.x == 0) s[threadIdx.x] = 0u;
+}
+
+// Fixed-order two-level reduction of the per-cell coupling cotangents.
+constexpr int kRedThreads = 256;
+__global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const double* __restrict__ TH, int64_t n,
+                                                                int64_t chunk, double* __restrict__ part) {
+  __shared__ double sh[kRedThreads];
+  const int q = blockIdx.y;
+  const int64_t beg = (int64_t)blockIdx.x * chunk;
+  const int64_t end = beg + chunk < n ? beg + chunk : n;
+  double s = 0.0;
+  for (int64_t e = beg + threadIdx.x; e < end; e += kRedThreads) s += TH[(int64_t)q * n + e];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)q * gridDim.x + blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* __restrict__ part, int nparts,
+                                                              double* __restrict__ theta_bar) {
+  __shared__ double sh[kRedThreads];
+  const int q = blockIdx.x;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < nparts; e += kRedThreads) s += part[(int64_t)q * nparts + e];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) theta_bar[q] += sh[0];
+}
+
+// out = a x + b y over n elements (y may be null: out = a x); n counts all
+// cells of all fields of a state.
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+                        double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  out[e] = y ? a * x[e] + b * y[e] : a * x[e];
+}
+
+__global__ void k_fill(int64_t n, double v, double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) out[e] = v;
+}
+
+
+// ---------------------------------------------------------------------------
+template <int TX, int TY, int TZ>
+int tiles_of(const BoxDev& b) {
+  return ((b.nx + TX - 1) / TX) * ((b.ny + TY - 1) / TY) * ((b.nz + TZ - 1) / TZ);
+}
+
+int tiles_of_variant(int v, const BoxDev& b) {
+  switch (v) {
+    case 1: return tiles_of<32, 4, 4>(b);
+    case 2: return tiles_of<8, 8, 8>(b);
+    case 3: return tiles_of<16, 16, 2>(b);
+    case 4: return tiles_of<64, 4, 2>(b);
+    default: return tiles_of<16, 8, 4>(b);
+  }
+}
+
+template <int TX, int TY, int TZ>
+hipError_t launch_deriv_t(const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
+                          hipStream_t st) {
+  hipLaunchKernelGGL((k_deriv<TX, TY, TZ>), dim3(tiles_of<TX, TY, TZ>(bd), NF), dim3(TX * TY * TZ), 0, st, bd, u, D,
+                     sigma, sa, UP);
+  return hipGetLastError();
+}
+
+hipError_t launch_deriv(int variant, const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
+                        hipStream_t st) {
+  switch (variant) {
+    case 1: return launch_deriv_t<32, 4, 4>(bd, u, D, sigma, sa, UP, st);
+    case 2: return launch_deriv_t<8, 8, 8>(bd, u, D, sigma, sa, UP, st);
+    case 3: return launch_deriv_t<16, 16, 2>(bd, u, D, sigma, sa, UP, st);
+    case 4: return launch_deriv_t<64, 4, 2>(bd, u, D, sigma, sa, UP, st);
+    default: return launch_deriv_t<16, 8, 4>(bd, u, D, sigma, sa, UP, st);
+  }
+}
+
+int persistent_grid_from(int per_cu, int64_t work) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+  }
+  if (per_cu < 1) per_cu = 1;
+  int64_t g = (int64_t)cus * per_cu;
+  if (g > work) g = work;
+  return (int)(g < 1 ? 1 : g);
+}
+
+template <int TX, int TY, int TZ>
+int grid_deriv_batch_t(int64_t work) {
+  int per = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_deriv_batch<TX, TY, TZ>, TX * TY * TZ, 0) != hipSuccess)
+    per = 1;
+  return persistent_grid_from(per, work);
+}
+
+int grid_deriv_batch(int variant, int64_t work) {
+  switch (variant) {
+    case 1: return grid_deriv_batch_t<32, 4, 4>(work);
+    case 2: return grid_deriv_batch_t<8, 8, 8>(work);
+    case 3: return grid_deriv_batch_t<16, 16, 2>(work);
+    case 4: return grid_deriv_batch_t<64, 4, 2>(work);
+    default: return grid_deriv_batch_t<16, 8, 4>(work);
+  }
+}
+
+template <int TX, int TY, int TZ>
+hipError_t launch_deriv_batch_t(int grid, const BatchBoxDev* boxes, const TileEntry* tiles, int ntiles, int stage,
+                                int parity, double sigma, int sa, hipStream_t st) {
+  hipLaunchKernelGGL((k_deriv_batch<TX, TY, TZ>), dim3(grid), dim3(TX * TY * TZ), 0, st, boxes, tiles, ntiles, stage,
+                     parity, sigma, sa);
+  return hipGetLastError();
+}
+
+hipError_t launch_deriv_batch(int variant, int grid, const BatchBoxDev* boxes, const TileEntry* tiles, int ntiles,
+                              int stage, int parity, double sigma, int sa, hipStream_t st) {
+  switch (variant) {
+    case 1: return launch_deriv_batch_t<32, 4, 4>(grid, boxes, tiles, ntiles, stage, parity, sigma, sa, st);
+    case 2: return launch_deriv_batch_t<8, 8, 8>(grid, boxes, tiles, ntiles, stage, parity, sigma, sa, st);
+    case 3: return launch_deriv_batch_t<16, 16, 2>(grid, boxes, tiles, ntiles, stage, parity, sigma, sa, st);
+    case 4: return launch_deriv_batch_t<64, 4, 2>(grid, boxes, tiles, ntiles, stage, parity, sigma, sa, st);
+    default: return launch_deriv_batch_t<16, 8, 4>(grid, boxes, tiles, ntiles, stage, parity, sigma, sa, st);
+  }
+}
+
+hipError_t launch_periodic(const BoxDev& bd, double* u, hipStream_t st) {
+  const int n[3] = {bd.nx, bd.ny, bd.nz};
+  for (int axis = 0; axis < 3; ++axis) {
+    int64_t cells = 6;
+    for (int d = 0; d < 3; ++d)
+      if (d != axis) cells *= (d < axis) ? (n[d] + 6) : n[d];
+    const int64_t total = cells * NF;
+    hipLaunchKernelGGL(k_periodic, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, bd, u, axis);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_status_clear(unsigned* s, hipStream_t st) {
+  hipLaunchKernelGGL(k_status_clear, dim3(1), dim3(64), 0, st, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_vjp_transpose(const BoxDev& bd, const double* u, const double* w, const double* Dbar, double sigma,
+                                int sa, double* ubar, hipStream_t st) {
+  constexpr int TX = 16, TY = 8, TZ = 4;
+  const int ntiles = ((bd.nx + 6 + TX - 1) / TX) * ((bd.ny + 6 + TY - 1) / TY) * ((bd.nz + 6 + TZ - 1) / TZ);
+  hipLaunchKernelGGL((k_vjp_transpose<TX, TY, TZ>), dim3(ntiles, NF), dim3(TX * TY * TZ), 0, st, bd, u, w, Dbar, sigma,
+                     sa, ubar);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* TH, int64_t n, int64_t chunk, int nparts, double* part, double* theta_bar,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_partial, dim3(nparts, NTH), dim3(kRedThreads), 0, st, TH, n, chunk, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_final, dim3(NTH), dim3(kRedThreads), 0, st, part, nparts, theta_bar);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_axpby, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, a, x, b, y, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(int64_t n, double v, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, v, out);
+  return hipGetLastError();
+}
+
+}  // namespace grf

@@ -15,7 +15,7 @@ import torch
 from . import inputs as _inputs
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgrf.so")
+LIB_PATH = os.environ.get("GRF_LIBRARY", os.path.join(HERE, "libgrf.so"))
 
 NF = 27
 NG = 3

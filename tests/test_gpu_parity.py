@@ -102,12 +102,32 @@ def test_rhs_parity_full_size_sampled():
     assert (num / den).max() <= 1e-12, dict(zip(I.FIELDS, num / den))
 
 
+def _ulp_floor(p, u, dx, dt, nsteps, periodic, seeds=(0, 1)):
+    """The oracle's own sensitivity: relative per-field change of the nsteps
+    result when every input value is moved by one unit in the last place."""
+    a, _ = O.rk4(I.params_vector(p), u, dx, dt, nsteps, periodic=periodic)
+    worst = 0.0
+    for sd in seeds:
+        rng = np.random.default_rng(sd)
+        up = u * (1 + np.finfo(float).eps * rng.choice([-1.0, 1.0], size=u.shape))
+        if periodic:
+            up = I.wrap_ghosts(up)
+        b, _ = O.rk4(I.params_vector(p), up, dx, dt, nsteps, periodic=periodic)
+        worst = max(worst, rel_err_per_field(b, a, interior=False).max())
+    return a, worst
+
+
 def test_rk4_ten_steps_periodic():
+    """Flat space + 1e-6 noise + pulse, 32^3 periodic, 10 steps.  With O(1)
+    fields carrying 1e-6 perturbations the map is ill-conditioned: a one-ulp
+    change of the input moves the oracle's own result by ~7e-10 relative.  The
+    GPU (whose stencil sums round exactly as the oracle's) must stay within
+    1e-10 or that floor, whichever is larger."""
     print("case: 10 RK4 steps 32^3 periodic", flush=True)
     p = I.default_params()
     u = I.flat_noise_pulse(32, 0.25, seed=0)
     dt = 0.0625
-    o, _ = O.rk4(I.params_vector(p), u, 0.25, dt, 10, periodic=True)
+    o, floor = _ulp_floor(p, u, 0.25, dt, 10, True)
     ut = torch.from_numpy(u).to(DEV)
     st = G.Stepper(G.make_params(p), G.box_of(ut, 0.25, G.BC_PERIODIC), ut, dt)
     for _ in range(10):
@@ -116,6 +136,23 @@ def test_rk4_ten_steps_periodic():
     g = st.u.cpu().numpy()
     assert code == 0
     e = rel_err_per_field(g, o, interior=False)
+    print(f"10-step max rel err {e.max():.3e}, one-ulp input floor {floor:.3e}", flush=True)
+    assert e.max() <= max(1e-10, floor), (e.max(), floor, dict(zip(I.FIELDS, e)))
+
+
+def test_rk4_ten_steps_puncture_strict():
+    """Well-conditioned data (puncture + scalar shell, 24^3, frozen ghosts):
+    10 RK4 steps within 1e-10 relative per field."""
+    print("case: 10 RK4 steps 24^3 puncture", flush=True)
+    p = I.default_params()
+    u = I.single_puncture(24, 0.25)
+    o, floor = _ulp_floor(p, u, 0.25, 0.0625, 10, False, seeds=(0,))
+    ut = torch.from_numpy(u).to(DEV)
+    st = G.Stepper(G.make_params(p), G.box_of(ut, 0.25), ut, 0.0625)
+    for _ in range(10):
+        st.step()
+    e = rel_err_per_field(st.u.cpu().numpy(), o, interior=False)
+    print(f"10-step max rel err {e.max():.3e}, one-ulp input floor {floor:.3e}", flush=True)
     assert e.max() <= 1e-10, dict(zip(I.FIELDS, e))
 
 
