@@ -60,6 +60,66 @@ def cpu_baseline(params, u, dx, dt):
             "sample": f"one full RK4 step of the same {u.shape[3] - 6}^3 box ({t:.1f} s wall)"}
 
 
+def adjoint_ratio(torch, G, I):
+    """64^3 puncture box, dx = M/4, 50 RK4 steps, checkpoints every 10:
+    (backward incl. recomputation) / forward time, J = sum_{8<r<10} phi^2."""
+    from paper_2309_06225_amd import adjoint as A
+    n, dx, nsteps = 64, 0.25, 50
+    p = I.default_params()
+    u0 = torch.from_numpy(I.single_puncture(n, dx)).to("cuda")
+    mask = torch.from_numpy(I.shell_mask((n, n, n), dx, 8.0, 10.0)).to("cuda")
+    traj = A.Trajectory(p, G.box_of(u0, dx), 0.25 * dx, nsteps, every=10)
+    theta = torch.tensor([p["lambda_gb"], p["g2"]], dtype=torch.float64, requires_grad=True)
+    times = []
+    for rep in range(2):  # the first repetition allocates the buffers
+        x = u0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = A.shell_phi2(A.Evolve.apply(theta, x, traj), mask)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append((t1 - t0, t2 - t1))
+    f, b = times[-1]
+    return {"ratio": b / f, "forward_s": f, "backward_s": b, "workload": "single_puncture_64_dx0.25_50steps_ckpt10",
+            "dJ_dlambda_gb": float(theta.grad[0]), "dJ_dg2": float(theta.grad[1])}
+
+
+def batched_speedup(torch, G, I, steps=4):
+    """96 uneven boxes (levels 0-5): one-launch-per-box RK4 steps vs the batched
+    persistent form replayed from a hipGraph (two steps per replay)."""
+    spec = I.amr_boxes()
+    states, dts = I.amr_states(spec)
+    p = I.default_params()
+    boxes = [G.make_box(b["dims"], b["dx"]) for b in spec]
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        B = G.Batch(G.make_params(p), boxes, [torch.from_numpy(x).to("cuda") for x in states], dts)
+        B.autotune(st)
+        g = B.capture(st)
+
+        def timed(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(reps):
+                fn()
+            e1.record(st)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        per_box = timed(lambda: B.step_perbox(st), steps)
+        graph = timed(lambda: B.replay(g, st), steps // 2) / 2
+        code, bits = B.status(st)
+        B.close()
+    ncell = sum(int(b["dims"][0] * b["dims"][1] * b["dims"][2]) for b in spec)
+    return {"per_box_ms_per_step": per_box, "batched_graph_ms_per_step": graph, "speedup": per_box / graph,
+            "cells": ncell, "boxes": len(spec), "status": code}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +127,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=128, help="box edge (cells)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the adjoint and batched measurements")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run one plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -150,6 +211,11 @@ def main():
         "kernels_ms_per_step": {"stencil": deriv_ms / args.steps, "pointwise_rk4": point_ms / args.steps},
         "rhs_cells_per_s": ncell * 4 * args.steps / (ms_total * 1e-3),
     }
+    if not args.no_extra:
+        del st
+        torch.cuda.empty_cache()
+        out["adjoint_forward_ratio"] = adjoint_ratio(torch, G, I)
+        out["batched"] = batched_speedup(torch, G, I)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(params, u_host, dx, dt)
     print(json.dumps(out), flush=True)

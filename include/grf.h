@@ -62,7 +62,9 @@ enum { GRF_FLAG_NONFINITE = 1, GRF_FLAG_HYPERBOLIC = 2, GRF_FLAG_NONPOSITIVE = 4
  *   - lapse_coeff alpha^lapse_power (K - 2 Theta) / (1 + a)   (lapse_power 1 only);
  * shift (B form): d_t beta^i = shift_advec beta.d beta^i + shift_gamma_coeff B^i
  *   - a/(1+a) alpha D^i alpha,  d_t B^i = d_t Gam^i/(1+a) - eta B^i (+ advection).
- * enforce / chi_min / lapse_min: post-stage algebraic enforcement (0 = off). */
+ * enforce / chi_min / lapse_min: post-stage algebraic enforcement (0 = off, the
+ * default everywhere; 1 = grf_enforce applied to every stage output of
+ * grf_rk4_stage before its ghost fill; the batched and adjoint paths reject it). */
 typedef struct {
   double lambda_gb;
   int32_t lambda_kind;
@@ -110,6 +112,12 @@ grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u
 grf_status grf_rk4_stage(const grf_params* p, const grf_box* box, int stage, double dt, const double* u0,
                          const double* us, double* unext, double* acc, void* workspace, size_t workspace_bytes,
                          hipStream_t stream);
+
+/* Algebraic enforcement on the interior cells of a state, in place:
+ * h_ij <- h_ij det(h)^(-1/3) (unit determinant), A_ij <- A_ij - 1/3 h_ij h^kl A_kl
+ * with the corrected h, chi <- max(chi, chi_min), lapse <- max(lapse, lapse_min).
+ * Uses p->chi_min and p->lapse_min whatever p->enforce is. */
+grf_status grf_enforce(const grf_params* p, const grf_box* box, double* u, hipStream_t stream);
 
 /* Periodic ghost fill of a state (every ghost copies the interior cell congruent
  * to it modulo the box size), on the device. */

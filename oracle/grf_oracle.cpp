@@ -1159,6 +1159,39 @@ int oracle_rhs_point(const double* params, const double* u, const double* d1, co
   return o.flags;
 }
 
+// Post-stage algebraic enforcement (interior cells, in place): the conformal
+// metric is rescaled to unit determinant, A_ij loses its trace with respect to
+// the rescaled metric, chi and the lapse are floored.
+void oracle_enforce(const int* dims, double* u, double chi_min, double lapse_min) {
+  const double sp[3] = {1.0, 1.0, 1.0};
+  Box b = make_box(dims, sp);
+  for (int k = 0; k < b.nz; ++k)
+    for (int j = 0; j < b.ny; ++j)
+      for (int i = 0; i < b.nx; ++i) {
+        const int64_t c = cell_index(b, i, j, k);
+        double h[3][3], A[3][3], hu[3][3];
+        for (int a = 0; a < 3; ++a)
+          for (int bb = 0; bb < 3; ++bb) {
+            h[a][bb] = u[(H11 + SYM[a][bb]) * b.fstride + c];
+            A[a][bb] = u[(A11 + SYM[a][bb]) * b.fstride + c];
+          }
+        const double scale = 1.0 / std::cbrt(det3(h));
+        for (int a = 0; a < 3; ++a)
+          for (int bb = 0; bb < 3; ++bb) h[a][bb] *= scale;
+        inv3(h, hu);
+        double tr = 0.0;
+        for (int a = 0; a < 3; ++a)
+          for (int bb = 0; bb < 3; ++bb) tr += hu[a][bb] * A[a][bb];
+        for (int a = 0; a < 3; ++a)
+          for (int bb = a; bb < 3; ++bb) {
+            u[(H11 + SYM[a][bb]) * b.fstride + c] = h[a][bb];
+            u[(A11 + SYM[a][bb]) * b.fstride + c] = A[a][bb] - h[a][bb] * tr / 3.0;
+          }
+        if (u[CHI * b.fstride + c] < chi_min) u[CHI * b.fstride + c] = chi_min;
+        if (u[LAPSE * b.fstride + c] < lapse_min) u[LAPSE * b.fstride + c] = lapse_min;
+      }
+}
+
 // The oracle's dense solver, exposed for checking against a library solve.
 double oracle_gepp(int n, const double* A, const double* b, double* x) {
   std::vector<double> Aw(A, A + n * n), bw(b, b + n);

@@ -54,6 +54,7 @@ def lib():
         L.oracle_rk4.argtypes = [_dp, _ip, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp]
         L.oracle_rk4_cs.argtypes = [_dp, _dp, _ip, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp, _dp]
         L.oracle_rhs_point.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_enforce.argtypes = [_ip, _dp, ctypes.c_double, ctypes.c_double]
         L.oracle_gepp.argtypes = [ctypes.c_int, _dp, _dp, _dp]
         L.oracle_gepp.restype = ctypes.c_double
         L.oracle_stencils.argtypes = [_ip, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
@@ -172,6 +173,14 @@ def rhs_point(params, u, d1, d2, adv):
     ex = dict(ham=extra[0], mom=extra[1:4], C=extra[4:10], p=extra[10],
               A=extra[11:60].reshape(7, 7), b=extra[60:67], pivot_ratio=extra[67])
     return out, ex, flags
+
+
+def enforce(u, chi_min, lapse_min):
+    """Post-stage enforcement on the interior cells (returns a new state)."""
+    u = _c(u).copy()
+    dims = _dims(u)
+    lib().oracle_enforce(dims.ctypes.data_as(_ip), _d(u), float(chi_min), float(lapse_min))
+    return u
 
 
 def gepp(A, b):

@@ -2,11 +2,12 @@
 
 Forward: n RK4 steps through libgrf, keeping the state every `every` steps.
 Backward: for each segment, last first, the segment is re-run from its
-checkpoint keeping every step-start state (and, if `keep_stages`, the three
-stage states of every step), then libgrf's RK4-step adjoint is applied step by
-step in reverse.  The couplings theta = (lambda_gb, g2) and the initial state
-receive gradients.  All arithmetic runs in libgrf's kernels; this module only
-orders the calls and owns the buffers.
+checkpoint keeping every step-start state and the three stage states of every
+step, then libgrf's RK4-step adjoint is applied step by step in reverse.  The
+couplings theta = (lambda_gb, g2) and the initial state receive gradients.
+All arithmetic runs in libgrf's kernels; this module only orders the calls and
+owns the buffers.  Buffers are allocated once per trajectory; with frozen
+ghosts their ghost cells are set from the initial state once and never change.
 """
 from __future__ import annotations
 
@@ -16,14 +17,16 @@ from . import grf as G
 
 
 class Trajectory:
-    def __init__(self, params: dict, box: G.Box, dt: float, nsteps: int, every: int = 10, keep_stages: bool = True):
+    def __init__(self, params: dict, box: G.Box, dt: float, nsteps: int, every: int = 10):
         if box.bc != G.BC_FROZEN:
             raise ValueError("the trajectory adjoint is implemented for frozen ghosts")
         self.pdict, self.box, self.dt, self.nsteps = dict(params), box, float(dt), int(nsteps)
         self.every = max(1, int(every))
-        self.keep_stages = keep_stages
         self._ws = None
         self._vws = None
+        self._pool = None     # segment buffers: every x (start, u2, u3, u4) + output
+        self._fwd = None      # forward ping-pong buffers
+        self._acc = None
 
     def _params(self, theta):
         return G.make_params(self.pdict, lambda_gb=float(theta[0]), g2=float(theta[1]))
@@ -38,61 +41,73 @@ class Trajectory:
             self._vws = G.alloc_workspace(G.step_vjp_workspace_bytes(self.box), dev)
         return self._vws
 
-    def step(self, P, u, acc, bufs=None):
-        """One RK4 step from u; returns (u_new, (u2, u3, u4))."""
+    def _accbuf(self, dev):
+        if self._acc is None:
+            b = self.box
+            self._acc = torch.empty((G.NF, b.nx * b.ny * b.nz), dtype=torch.float64, device=dev)
+        return self._acc
+
+    def step(self, P, u, acc, bufs):
+        """One RK4 step from u into bufs = (u2, u3, u4, u_new); bufs carry u's ghosts."""
         ws = self._ws_fwd(u.device)
-        u2, u3, u4, un = bufs if bufs is not None else (u.clone(), u.clone(), u.clone(), u.clone())
+        u2, u3, u4, un = bufs
         G.rk4_stage(P, self.box, 1, self.dt, u, u, u2, acc, ws)
         G.rk4_stage(P, self.box, 2, self.dt, u, u2, u3, acc, ws)
         G.rk4_stage(P, self.box, 3, self.dt, u, u3, u4, acc, ws)
         G.rk4_stage(P, self.box, 4, self.dt, u, u4, un, acc, ws)
-        return un, (u2, u3, u4)
-
-    def _acc(self, u):
-        b = self.box
-        return torch.empty((G.NF, b.nx * b.ny * b.nz), dtype=torch.float64, device=u.device)
+        return un
 
     def forward(self, theta, u0):
-        """Returns (u_n, checkpoints)."""
+        """Returns (u_n, checkpoints); u_n is a fresh tensor."""
         P = self._params(theta)
-        acc = self._acc(u0)
+        acc = self._accbuf(u0.device)
+        if self._fwd is None or self._fwd[0].device != u0.device:
+            self._fwd = [u0.clone() for _ in range(5)]
+        else:
+            for b in self._fwd:
+                b.copy_(u0)  # ghosts (and everything) from this initial state
         cps = {0: u0.clone()}
-        u = u0
+        stage_bufs = self._fwd[:3]
+        out_bufs = self._fwd[3:5]
+        cur = u0
         for s in range(self.nsteps):
-            u, _ = self.step(P, u, acc)
+            nxt = out_bufs[s % 2]
+            self.step(P, cur, acc, (*stage_bufs, nxt))
+            cur = nxt
             if (s + 1) % self.every == 0 and s + 1 < self.nsteps:
-                cps[s + 1] = u.clone()
-        return u, cps
+                cps[s + 1] = cur.clone()
+        return cur.clone(), cps
 
     def backward(self, theta, cps, ubar_n):
         """Given d J / d u_n, returns (d J / d u_0, d J / d theta)."""
         P = self._params(theta)
         dev = ubar_n.device
-        acc = self._acc(ubar_n)
+        acc = self._accbuf(dev)
         vws = self._ws_vjp(dev)
         theta_bar = torch.zeros(2, dtype=torch.float64, device=dev)
         ubar = ubar_n.clone()
         out = torch.empty_like(ubar)
-        starts = sorted(cps)
-        for seg_start in reversed(starts):
+        u0 = cps[0]
+        if self._pool is None or self._pool[0].device != dev:
+            self._pool = [u0.clone() for _ in range(4 * self.every + 1)]
+        else:
+            for b in self._pool:
+                b.copy_(u0)
+        for seg_start in reversed(sorted(cps)):
             seg_end = min(seg_start + self.every, self.nsteps)
-            # re-run the segment, keeping step-start (and stage) states
-            states, stages = [cps[seg_start]], []
-            u = cps[seg_start]
-            for s in range(seg_start, seg_end):
-                un, st = self.step(P, u, acc)
-                stages.append(st if self.keep_stages else None)
-                if s + 1 < seg_end:
-                    states.append(un)
-                u = un
-            for s in reversed(range(seg_end - seg_start)):
-                us = states[s]
-                st = stages[s]
-                if st is None:
-                    _, st = self.step(P, us, acc)
-                G.rk4_step_vjp(P, self.box, self.dt, us, st[0], st[1], st[2], ubar, out, theta_bar, vws)
+            nseg = seg_end - seg_start
+            # re-run the segment: step k starts from starts[k], keeps its stage states
+            starts = [cps[seg_start]]
+            stages = []
+            for k in range(nseg):
+                u2, u3, u4, un = self._pool[4 * k:4 * k + 4]
+                self.step(P, starts[k], acc, (u2, u3, u4, un))
+                stages.append((u2, u3, u4))
+                starts.append(un)
+            for k in reversed(range(nseg)):
+                u2, u3, u4 = stages[k]
+                G.rk4_step_vjp(P, self.box, self.dt, starts[k], u2, u3, u4, ubar, out, theta_bar, vws)
                 ubar, out = out, ubar
-            del states, stages
         return ubar, theta_bar
 
 

@@ -58,7 +58,9 @@ grf_status check_params(const grf_params* p) {
   if (p->lambda_kind != GRF_LAMBDA_QUADRATIC) return fail(GRF_EUNSUPPORTED, "only lambda_kind 0 (quadratic)");
   if (p->lapse_power != 1.0) return fail(GRF_EUNSUPPORTED, "only lapse_power 1");
   if (p->a_gauge == -1.0 || p->b_gauge == -1.0) return fail(GRF_EINVAL, "a and b must differ from -1");
-  if (p->enforce) return fail(GRF_EUNSUPPORTED, "post-stage enforcement is not implemented");
+  if (p->enforce != 0 && p->enforce != 1) return fail(GRF_EINVAL, "enforce must be 0 or 1");
+  if (p->enforce && !(std::isfinite(p->chi_min) && std::isfinite(p->lapse_min)))
+    return fail(GRF_EINVAL, "chi_min and lapse_min must be finite");
   return GRF_OK;
 }
 
@@ -261,7 +263,18 @@ grf_status grf_rk4_stage(const grf_params* p, const grf_box* box, int stage, dou
   prof_mark(1, stream);
   GRF_HIP_CHECK(launch_point(mode, sa, bd, pp, us, D, u0, unext, acc, sc, status, stream));
   prof_mark(1, stream);
+  if (p->enforce) GRF_HIP_CHECK(launch_enforce(bd, unext, p->chi_min, p->lapse_min, stream));
   if (box->bc == GRF_BC_PERIODIC) GRF_HIP_CHECK(launch_periodic(bd, unext, stream));
+  return GRF_OK;
+}
+
+grf_status grf_enforce(const grf_params* p, const grf_box* box, double* u, hipStream_t stream) {
+  grf_status s = check_params(p);
+  if (s != GRF_OK) return s;
+  if ((s = check_box(box)) != GRF_OK) return s;
+  if (!u) return fail(GRF_EINVAL, "u is null");
+  BoxDev bd = make_boxdev(box);
+  GRF_HIP_CHECK(launch_enforce(bd, u, p->chi_min, p->lapse_min, stream));
   return GRF_OK;
 }
 
@@ -336,6 +349,7 @@ grf_status grf_rk4_step_vjp(const grf_params* p, const grf_box* box, double dt, 
   s = check_box(box);
   if (s != GRF_OK) return s;
   if (box->bc != GRF_BC_FROZEN) return fail(GRF_EUNSUPPORTED, "the step adjoint is implemented for frozen ghosts");
+  if (p->enforce) return fail(GRF_EUNSUPPORTED, "the step adjoint does not differentiate the enforcement");
   if (!u || !u2 || !u3 || !u4 || !ubar_new || !ubar || !theta_bar || !workspace) return fail(GRF_EINVAL, "null pointer");
   if (ubar == ubar_new || ubar == u || ubar == u2 || ubar == u3 || ubar == u4)
     return fail(GRF_EINVAL, "ubar must not alias an input");
@@ -457,6 +471,7 @@ grf_status grf_batch_create(const grf_params* p, const grf_box* boxes, int nboxe
                             const double* dts, void* scratch, size_t scratch_bytes, grf_batch** out) {
   grf_status s = check_params(p);
   if (s != GRF_OK) return s;
+  if (p->enforce) return fail(GRF_EUNSUPPORTED, "the batched form has no post-stage enforcement");
   if (!boxes || nboxes < 1 || !u || !dts || !out || !scratch) return fail(GRF_EINVAL, "null argument");
   for (int b = 0; b < nboxes; ++b) {
     if ((s = check_box(&boxes[b])) != GRF_OK) return s;

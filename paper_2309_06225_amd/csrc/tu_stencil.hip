@@ -56,6 +56,43 @@ __global__ void k_periodic(BoxDev b, double* __restrict__ u, int axis) {
       u[base + (int64_t)src[2] * b.sz + (int64_t)src[1] * b.sy + src[0]];
 }
 
+// Post-stage algebraic enforcement on interior cells, in place:
+// h <- h det(h)^(-1/3); A <- A - 1/3 h tr_h(A) with the corrected h;
+// chi <- max(chi, chi_min); lapse <- max(lapse, lapse_min).
+__global__ void k_enforce(BoxDev b, double* __restrict__ u, double chi_min, double lapse_min) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= b.ncell) return;
+  const int i = (int)(c % b.nx);
+  const int64_t r = c / b.nx;
+  const int j = (int)(r % b.ny);
+  const int k = (int)(r / b.ny);
+  const int64_t s = (int64_t)(k + 3) * b.sz + (int64_t)(j + 3) * b.sy + (i + 3);
+  double h[6], A[6];
+  for (int q = 0; q < 6; ++q) {
+    h[q] = u[(int64_t)(1 + q) * b.fs + s];
+    A[q] = u[(int64_t)(8 + q) * b.fs + s];
+  }
+  // packed order xx, xy, xz, yy, yz, zz
+  const double det = h[0] * (h[3] * h[5] - h[4] * h[4]) - h[1] * (h[1] * h[5] - h[4] * h[2]) +
+                     h[2] * (h[1] * h[4] - h[3] * h[2]);
+  const double f = 1.0 / cbrt(det);
+  for (int q = 0; q < 6; ++q) h[q] *= f;
+  const double d2 = h[0] * (h[3] * h[5] - h[4] * h[4]) - h[1] * (h[1] * h[5] - h[4] * h[2]) +
+                    h[2] * (h[1] * h[4] - h[3] * h[2]);
+  const double id = 1.0 / d2;
+  const double hu[6] = {(h[3] * h[5] - h[4] * h[4]) * id, (h[2] * h[4] - h[1] * h[5]) * id,
+                        (h[1] * h[4] - h[2] * h[3]) * id, (h[0] * h[5] - h[2] * h[2]) * id,
+                        (h[1] * h[2] - h[0] * h[4]) * id, (h[0] * h[3] - h[1] * h[1]) * id};
+  const double tr = hu[0] * A[0] + hu[3] * A[3] + hu[5] * A[5] + 2.0 * (hu[1] * A[1] + hu[2] * A[2] + hu[4] * A[4]);
+  for (int q = 0; q < 6; ++q) {
+    u[(int64_t)(1 + q) * b.fs + s] = h[q];
+    u[(int64_t)(8 + q) * b.fs + s] = A[q] - h[q] * tr / 3.0;
+  }
+  const int64_t qc = s, qa = (int64_t)18 * b.fs + s;
+  if (u[qc] < chi_min) u[qc] = chi_min;
+  if (u[qa] < lapse_min) u[qa] = lapse_min;
+}
+
 __global__ void k_status_clear(unsigned* s) {
   if (threadIdx.x == 0) s[threadIdx.x] = 0u;
 }
@@ -205,6 +242,12 @@ hipError_t launch_periodic(const BoxDev& bd, double* u, hipStream_t st) {
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_enforce(const BoxDev& bd, double* u, double chi_min, double lapse_min, hipStream_t st) {
+  hipLaunchKernelGGL(k_enforce, dim3((unsigned)((bd.ncell + 255) / 256)), dim3(256), 0, st, bd, u, chi_min,
+                     lapse_min);
+  return hipGetLastError();
 }
 
 hipError_t launch_status_clear(unsigned* s, hipStream_t st) {

@@ -66,6 +66,7 @@ def lib():
         L.grf_rhs_eval.argtypes = [P, B, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.grf_rk4_stage.argtypes = [P, B, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.grf_fill_periodic.argtypes = [B, _vp, _vp]
+        L.grf_enforce.argtypes = [P, B, _vp, _vp]
         L.grf_rhs_vjp.argtypes = [P, B, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.grf_rk4_step_vjp_workspace_bytes.argtypes = [B]
         L.grf_rk4_step_vjp_workspace_bytes.restype = ctypes.c_size_t
@@ -95,7 +96,7 @@ def lib():
         L.grf_prof_end.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         for name in ("grf_rhs_eval", "grf_rk4_stage", "grf_fill_periodic", "grf_rhs_vjp", "grf_status_fetch",
                      "grf_status_clear", "grf_set_tile_variant", "grf_prof_begin", "grf_prof_end",
-                     "grf_rk4_step_vjp", "grf_batch_create", "grf_batch_step", "grf_batch_step_perbox",
+                     "grf_rk4_step_vjp", "grf_enforce", "grf_batch_create", "grf_batch_step", "grf_batch_step_perbox",
                      "grf_batch_autotune", "grf_batch_capture", "grf_batch_state", "grf_batch_tile_variant",
                      "grf_batch_status_fetch", "grf_graph_launch", "grf_graph_destroy"):
             getattr(L, name).restype = ctypes.c_int
@@ -115,7 +116,8 @@ def make_params(p: dict | None = None, **over) -> Params:
                   kappa1=d["kappa1"], kappa2=d["kappa2"], kappa3=d["kappa3"], lapse_coeff=d["lapse_coeff"],
                   lapse_power=d["lapse_power"], lapse_advec=d["lapse_advec"],
                   shift_gamma_coeff=d["shift_gamma_coeff"], shift_advec=d["shift_advec"], eta=d["eta"],
-                  ko_sigma=d["ko_sigma"], enforce=0, chi_min=0.0, lapse_min=0.0)
+                  ko_sigma=d["ko_sigma"], enforce=int(d.get("enforce", 0)), chi_min=d.get("chi_min", 0.0),
+                  lapse_min=d.get("lapse_min", 0.0))
 
 
 def make_box(dims, dx, bc=BC_FROZEN, origin=(0.0, 0.0, 0.0)) -> Box:
@@ -166,6 +168,10 @@ def rhs_eval(params: Params, box: Box, u, rhs, ws, stream=None):
 def rk4_stage(params: Params, box: Box, stage, dt, u0, us, unext, acc, ws, stream=None):
     _check(lib().grf_rk4_stage(ctypes.byref(params), ctypes.byref(box), int(stage), float(dt), _ptr(u0), _ptr(us),
                                _ptr(unext), _ptr(acc), _ptr(ws), ws.numel() * 8, _stream(stream)))
+
+
+def enforce(params: Params, box: Box, u, stream=None):
+    _check(lib().grf_enforce(ctypes.byref(params), ctypes.byref(box), _ptr(u), _stream(stream)))
 
 
 def fill_periodic(box: Box, u, stream=None):

@@ -431,3 +431,36 @@ def test_robust_stability_noise_long():
         h = _growth_run(n, 1000, 100 + n)
         assert h[1:, 0].max() < 10 * h[0, 0]
         assert h[2, 1] < 2.5 * h[1, 1]
+
+
+# ------------------------------------------------------------------ enforcement
+def test_enforcement_definition():
+    """After enforcement det(h) = 1, tr_h(A) = 0, chi >= chi_min, lapse >=
+    lapse_min; applying it twice changes nothing beyond rounding."""
+    rng = np.random.default_rng(8)
+    u = I.set_flat(I.empty_state((5, 4, 3)))
+    inner = (slice(3, -3),) * 3
+    for f in range(1, 14):
+        u[(f,) + inner] += 0.1 * rng.standard_normal(u[(f,) + inner].shape)
+    u[(0,) + inner] = rng.uniform(-0.1, 1.0, u[(0,) + inner].shape)
+    u[(18,) + inner] = rng.uniform(-0.1, 1.0, u[(18,) + inner].shape)
+    e = O.enforce(u, 1e-4, 1e-3)
+    sl = (slice(None),) + inner
+    h = np.zeros((3, 3) + e[(0,) + inner].shape)
+    A = np.zeros_like(h)
+    pack = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    for q, (i, j) in enumerate(pack):
+        h[i, j] = h[j, i] = e[(1 + q,) + inner]
+        A[i, j] = A[j, i] = e[(8 + q,) + inner]
+    H = np.moveaxis(h, (0, 1), (-2, -1))
+    Am = np.moveaxis(A, (0, 1), (-2, -1))
+    np.testing.assert_allclose(np.linalg.det(H), 1.0, rtol=0, atol=1e-14)
+    tr = np.einsum("...ij,...ij->...", np.linalg.inv(H), Am)
+    assert np.abs(tr).max() < 1e-14
+    assert e[(0,) + inner].min() >= 1e-4 and e[(18,) + inner].min() >= 1e-3
+    e2 = O.enforce(e, 1e-4, 1e-3)
+    np.testing.assert_allclose(e2[sl], e[sl], rtol=0, atol=1e-14)
+    # ghosts untouched
+    ghost = np.ones(u.shape[1:], bool)
+    ghost[inner] = False
+    assert np.array_equal(e[:, ghost], u[:, ghost])
