@@ -199,6 +199,14 @@ grf_status grf_graph_destroy(hipGraphExec_t exec);
  * 1: 32x4x4, 2: 8x8x8, 3: 16x16x2, 4: 64x4x2.  Results do not depend on it. */
 grf_status grf_set_tile_variant(int variant);
 
+/* Stage path of grf_rhs_eval / grf_rk4_stage: 0 (default) = a stencil kernel
+ * writing the derivative records of the whole box, then a pointwise kernel;
+ * 1 = one fused kernel per stage (each workgroup stages the 27 fields of an
+ * 8x8x4 tile in LDS, keeps the records in a small per-workgroup scratch, then
+ * runs the pointwise algebra on the same cells; slower on a 128^3 box, 9.9 vs
+ * 4.2 ms per stage).  Results are bitwise identical. */
+grf_status grf_set_stage_path(int path);
+
 /* Kernel timing with HIP events recorded on the launch stream around each
  * launch, for up to max_launches launches per kernel class; grf_prof_end waits
  * for the events and returns per class (0 stencil stage, 1 pointwise + RK4,

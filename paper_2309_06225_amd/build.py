@@ -23,6 +23,7 @@ HIPCC_FLAGS = [
 UNITS = [("libgrf.hip", "api", []), ("tu_stencil.hip", "stencil", []), ("tu_vjp.hip", "vjp", [])]
 UNITS += [("tu_point.hip", f"point_m{m}", [f"-DGRF_TU_MODE={m}"]) for m in (0, 1, 2, 4)]
 UNITS += [("tu_batch.hip", f"batch_m{m}", [f"-DGRF_TU_MODE={m}"]) for m in (1, 2, 4)]
+UNITS += [("tu_fused.hip", f"fused_m{m}", [f"-DGRF_TU_MODE={m}"]) for m in (0, 1, 2, 4)]
 
 
 def hipcc() -> str:

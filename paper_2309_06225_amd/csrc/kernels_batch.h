@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kPointThreads) void k_point_batch(const BatchBoxDev
     stage_roles(B, stage, parity, base, in, out);
     StageCoef sc;
     sc.cnext = stage == 4 ? B.dt / 6.0 : (stage == 3 ? 1.0 * B.dt : 0.5 * B.dt);
-    point_cell<MODE, SHIFTADV>(B.bd, c, P, in, B.D, base, out, B.acc, sc, status);
+    point_cell<MODE, SHIFTADV>(B.bd, c, P, in, B.D, B.bd.ncell, c, base, out, B.acc, sc, status);
   }
 }
 

@@ -79,20 +79,13 @@ __device__ __forceinline__ double sten_mixed(const double* t, int c0, int sd, in
 // Output record: D[comp * ncell + cell], cell = (k*ny + j)*nx + i.
 // With UP non-null the three upwinded derivatives are also stored (for the VJP):
 //   UP[(3 f + k) * ncell + cell].
-template <int TX, int TY, int TZ>
-__device__ __forceinline__ void deriv_tile(const BoxDev& b, int tile, int f, const double* __restrict__ u,
-                                           double* __restrict__ D, double ko_sigma, int shift_adv,
-                                           double* __restrict__ UP, double* t) {
+// Load one field of a tile (interior origin tx0, ty0, tz0) and its 3-deep halo
+// into t (coalesced rows); cells beyond the stored box are left untouched.
+template <int TX, int TY, int TZ, int NT>
+__device__ __forceinline__ void stage_tile(const BoxDev& b, int tx0, int ty0, int tz0, const double* __restrict__ uf,
+                                           double* t) {
   constexpr int LX = TX + 6, LY = TY + 6, LZ = TZ + 6;
-  const int ntx = (b.nx + TX - 1) / TX, nty = (b.ny + TY - 1) / TY;
-  const int tx0 = (tile % ntx) * TX;
-  tile /= ntx;
-  const int ty0 = (tile % nty) * TY;
-  const int tz0 = (tile / nty) * TZ;
-  const double* __restrict__ uf = u + (int64_t)f * b.fs;
-  __syncthreads();  // the previous work item of this workgroup is done with t
-  // tile origin in state coordinates is (tx0, ty0, tz0): state coord = interior + 3
-  for (int e = threadIdx.x; e < LX * LY * LZ; e += TX * TY * TZ) {
+  for (int e = threadIdx.x; e < LX * LY * LZ; e += NT) {
     const int lx = e % LX;
     const int r = e / LX;
     const int ly = r % LY;
@@ -100,18 +93,37 @@ __device__ __forceinline__ void deriv_tile(const BoxDev& b, int tile, int f, con
     const int gx = tx0 + lx, gy = ty0 + ly, gz = tz0 + lz;
     if (gx < b.nx + 6 && gy < b.ny + 6 && gz < b.nz + 6) t[e] = uf[(int64_t)gz * b.sz + (int64_t)gy * b.sy + gx];
   }
-  __syncthreads();
+}
+
+__device__ __forceinline__ void tile_origin(const BoxDev& b, int tile, int TX, int TY, int TZ, int& tx0, int& ty0,
+                                            int& tz0) {
+  const int ntx = (b.nx + TX - 1) / TX, nty = (b.ny + TY - 1) / TY;
+  tx0 = (tile % ntx) * TX;
+  tile /= ntx;
+  ty0 = (tile % nty) * TY;
+  tz0 = (tile / nty) * TZ;
+}
+
+// Derivative record of field f for this thread's cell of the tile, from the
+// staged tile t.  Record layout: component q of the cell lives at
+// D[q * dstride + dcell], with dcell the interior cell index (whole-box record,
+// dstride = ncell) or the thread's index within the tile (per-workgroup record,
+// dstride = tile size).  Threads whose cell lies outside the box do nothing.
+template <int TX, int TY, int TZ, bool LOCAL_RECORD>
+__device__ __forceinline__ void compute_tile(const BoxDev& b, int tx0, int ty0, int tz0, int f,
+                                             const double* __restrict__ u, double* __restrict__ D, double ko_sigma,
+                                             int shift_adv, double* __restrict__ UP, const double* t) {
+  constexpr int LX = TX + 6, LY = TY + 6;
   const int ix = threadIdx.x % TX;
   const int iy = (threadIdx.x / TX) % TY;
   const int iz = threadIdx.x / (TX * TY);
   const int i = tx0 + ix, j = ty0 + iy, k = tz0 + iz;
-  if (i >= b.nx || j >= b.ny || k >= b.nz) return;  // no barrier follows in this function
+  if (i >= b.nx || j >= b.ny || k >= b.nz) return;
   const int64_t cell = ((int64_t)k * b.ny + j) * b.nx + i;
   const int c0 = ((iz + 3) * LY + (iy + 3)) * LX + (ix + 3);
   const int st[3] = {1, LX, LX * LY};
-  double* __restrict__ Dc = D + cell;
-  const int64_t nc = b.ncell;
-
+  double* __restrict__ Dc = D + (LOCAL_RECORD ? (int64_t)threadIdx.x : cell);
+  const int64_t nc = LOCAL_RECORD ? (int64_t)(TX * TY * TZ) : b.ncell;
   double line[3][7];
 #pragma unroll
   for (int d = 0; d < 3; ++d)
@@ -140,13 +152,26 @@ __device__ __forceinline__ void deriv_tile(const BoxDev& b, int tile, int f, con
   for (int d = 0; d < 3; ++d) {
     beta[d] = u[(int64_t)(F_SHIFT + d) * b.fs + sc];
     up[d] = (beta[d] >= 0.0 ? sten_up_plus(line[d]) : sten_up_minus(line[d])) * b.i12h[d];
-    if (UP) UP[(int64_t)(3 * f + d) * nc + cell] = up[d];
+    if (UP) UP[(int64_t)(3 * f + d) * b.ncell + cell] = up[d];
   }
   if (advected(f, shift_adv)) Dc[(int64_t)(GRF_OFF_ADV + f) * nc] = beta[0] * up[0] + beta[1] * up[1] + beta[2] * up[2];
   double ko = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) ko += sten_ko(line[d]) * b.i64h[d];
   Dc[(int64_t)(GRF_OFF_KO + f) * nc] = ko_sigma * ko;
+}
+
+
+template <int TX, int TY, int TZ, bool LOCAL_RECORD = false>
+__device__ __forceinline__ void deriv_tile(const BoxDev& b, int tile, int f, const double* __restrict__ u,
+                                           double* __restrict__ D, double ko_sigma, int shift_adv,
+                                           double* __restrict__ UP, double* t) {
+  int tx0, ty0, tz0;
+  tile_origin(b, tile, TX, TY, TZ, tx0, ty0, tz0);
+  __syncthreads();  // the previous work item of this workgroup is done with t
+  stage_tile<TX, TY, TZ, TX * TY * TZ>(b, tx0, ty0, tz0, u + (int64_t)f * b.fs, t);
+  __syncthreads();
+  compute_tile<TX, TY, TZ, LOCAL_RECORD>(b, tx0, ty0, tz0, f, u, D, ko_sigma, shift_adv, UP, t);
 }
 
 template <int TX, int TY, int TZ>
@@ -173,11 +198,11 @@ struct StageCoef {
 #pragma clang fp contract(off)
 template <int MODE>
 __device__ __forceinline__ void stage_one(int f, double rhs_f, const BoxDev& b, const double* __restrict__ D,
-                                          int64_t c, int64_t s, const double* __restrict__ u0,
-                                          double* __restrict__ out, double* __restrict__ acc, StageCoef sc,
-                                          unsigned& flags) {
+                                          int64_t dstride, int64_t dcell, int64_t c, int64_t s,
+                                          const double* __restrict__ u0, double* __restrict__ out,
+                                          double* __restrict__ acc, StageCoef sc, unsigned& flags) {
   const int64_t nc = b.ncell;
-  const double kf = rhs_f + D[(int64_t)(GRF_OFF_KO + f) * nc + c];
+  const double kf = rhs_f + D[(int64_t)(GRF_OFF_KO + f) * dstride + dcell];
   if (!isfinite(kf)) flags |= 1u;
   const int64_t q = (int64_t)f * b.fs + s;
   const int64_t qa = (int64_t)f * nc + c;
@@ -200,8 +225,9 @@ __device__ __forceinline__ void stage_one(int f, double rhs_f, const BoxDev& b, 
 template <int MODE, int SHIFTADV>
 __device__ __forceinline__ void point_cell(const BoxDev& b, int64_t c, const grf_point_params& P,
                                            const double* __restrict__ us, const double* __restrict__ D,
-                                           const double* __restrict__ u0, double* __restrict__ out,
-                                           double* __restrict__ acc, StageCoef sc, unsigned* __restrict__ status) {
+                                           int64_t dstride, int64_t dcell, const double* __restrict__ u0,
+                                           double* __restrict__ out, double* __restrict__ acc, StageCoef sc,
+                                           unsigned* __restrict__ status) {
   const int i = (int)(c % b.nx);
   const int64_t r = c / b.nx;
   const int j = (int)(r % b.ny);
@@ -211,9 +237,9 @@ __device__ __forceinline__ void point_cell(const BoxDev& b, int64_t c, const grf
   int bad = 0;
   unsigned flags = 0u;
 #define GRF_U(f) us[(int64_t)(f) * b.fs + s]
-#define GRF_D(cc) D[(int64_t)(cc) * nc + c]
+#define GRF_D(cc) D[(int64_t)(cc) * dstride + dcell]
 #define GRF_P(n) P.n
-#define GRF_RHS(f, v) stage_one<MODE>(f, (v), b, D, c, s, u0, out, acc, sc, flags)
+#define GRF_RHS(f, v) stage_one<MODE>(f, (v), b, D, dstride, dcell, c, s, u0, out, acc, sc, flags)
 #define GRF_PIVCHK(v) bad |= !(fabs(v) <= 1e12)
 #define GRF_SHIFT_ADVEC (SHIFTADV != 0)
 #include "gen/gen_rhs.inc"
@@ -235,7 +261,65 @@ __global__ __launch_bounds__(kPointThreads) void k_point(BoxDev b, grf_point_par
                                                          unsigned* __restrict__ status) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= b.ncell) return;
-  point_cell<MODE, SHIFTADV>(b, c, P, us, D, u0, out, acc, sc, status);
+  point_cell<MODE, SHIFTADV>(b, c, P, us, D, b.ncell, c, u0, out, acc, sc, status);
+}
+
+// ---------------------------------------------------------------------------
+// Fused RK4 stage.  A persistent workgroup takes 8x8x4 tiles (tile = blockIdx.x,
+// blockIdx.x + gridDim.x, ...).  For each tile it stages the 27 fields three at
+// a time into LDS, writes the derivative records of its 256 cells into its own
+// slice of Dwg (kept small so that it stays cache-resident between the two
+// phases), then runs the pointwise right-hand side and the stage update on the
+// same cells.  Per cell the arithmetic is the one of k_deriv + k_point.
+constexpr int kFusedTX = 8, kFusedTY = 8, kFusedTZ = 4;
+constexpr int kFusedNT = kFusedTX * kFusedTY * kFusedTZ;
+constexpr int kFusedFB = 3;  // fields staged per LDS round (27 = 9 x 3)
+constexpr int kFusedLSZ = (kFusedTX + 6) * (kFusedTY + 6) * (kFusedTZ + 6);
+
+__host__ __device__ inline int fused_tiles(const BoxDev& b) {
+  return ((b.nx + kFusedTX - 1) / kFusedTX) * ((b.ny + kFusedTY - 1) / kFusedTY) * ((b.nz + kFusedTZ - 1) / kFusedTZ);
+}
+
+template <int MODE, int SHIFTADV>
+__device__ __forceinline__ void fused_tile(const BoxDev& b, int tile, const grf_point_params& P,
+                                           const double* __restrict__ us, const double* __restrict__ u0,
+                                           double* __restrict__ out, double* __restrict__ acc, StageCoef sc,
+                                           double* __restrict__ D, double ko_sigma, unsigned* __restrict__ status,
+                                           double* t) {
+  int tx0, ty0, tz0;
+  tile_origin(b, tile, kFusedTX, kFusedTY, kFusedTZ, tx0, ty0, tz0);
+  for (int f0 = 0; f0 < NF; f0 += kFusedFB) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kFusedFB; ++q)
+      stage_tile<kFusedTX, kFusedTY, kFusedTZ, kFusedNT>(b, tx0, ty0, tz0, us + (int64_t)(f0 + q) * b.fs,
+                                                        t + q * kFusedLSZ);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kFusedFB; ++q)
+      compute_tile<kFusedTX, kFusedTY, kFusedTZ, true>(b, tx0, ty0, tz0, f0 + q, us, D, ko_sigma, SHIFTADV, nullptr,
+                                                       t + q * kFusedLSZ);
+  }
+  const int ix = threadIdx.x % kFusedTX, iy = (threadIdx.x / kFusedTX) % kFusedTY;
+  const int iz = threadIdx.x / (kFusedTX * kFusedTY);
+  const int i = tx0 + ix, j = ty0 + iy, k = tz0 + iz;
+  if (i < b.nx && j < b.ny && k < b.nz) {
+    const int64_t c = ((int64_t)k * b.ny + j) * b.nx + i;
+    point_cell<MODE, SHIFTADV>(b, c, P, us, D, kFusedNT, threadIdx.x, u0, out, acc, sc, status);
+  }
+}
+
+template <int MODE, int SHIFTADV>
+__global__ __launch_bounds__(kFusedNT) void k_stage_fused(BoxDev b, grf_point_params P, const double* __restrict__ us,
+                                                          const double* __restrict__ u0, double* __restrict__ out,
+                                                          double* __restrict__ acc, StageCoef sc,
+                                                          double* __restrict__ Dwg, double ko_sigma,
+                                                          unsigned* __restrict__ status) {
+  __shared__ double t[kFusedFB * kFusedLSZ];
+  double* __restrict__ D = Dwg + (int64_t)blockIdx.x * GRF_NCOMP * kFusedNT;
+  const int ntiles = fused_tiles(b);
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+    fused_tile<MODE, SHIFTADV>(b, tile, P, us, u0, out, acc, sc, D, ko_sigma, status, t);
 }
 
 }  // namespace grf

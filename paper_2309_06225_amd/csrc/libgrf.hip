@@ -108,8 +108,30 @@ grf_point_params make_pp(const grf_params* p) {
   return q;
 }
 
+// Stage path of the single-box calls: 0 = stencil kernel + pointwise kernel
+// (record of the whole box through HBM), 1 = fused per-tile kernel.
+int g_stage_path = 0;
+
+// Persistent grid of the fused kernel (workgroups resident at once) and the
+// size of its per-workgroup record scratch.
+int fused_grid_max() {
+  static int g = 0;
+  if (g == 0) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      hipDeviceProp_t prop;
+      if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    }
+    g = fused_blocks_per_cu_m<2>(0) * cus;
+    if (g < 1) g = 1;
+  }
+  return g;
+}
+
 size_t deriv_bytes(const grf_box* b) {
-  return (size_t)GRF_NCOMP * (size_t)b->nx * b->ny * b->nz * sizeof(double);
+  const size_t whole = (size_t)GRF_NCOMP * (size_t)b->nx * b->ny * b->nz * sizeof(double);
+  const size_t fused = (size_t)fused_grid_max() * GRF_NCOMP * kFusedNT * sizeof(double);
+  return whole > fused ? whole : fused;
 }
 
 constexpr int kTileVariantsMax = 5;
@@ -142,6 +164,20 @@ hipError_t launch_point(int mode, int sa, const BoxDev& bd, const grf_point_para
     case 2: return launch_point_m<2>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
     case 4: return launch_point_m<4>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
     default: return launch_point_m<0>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
+  }
+}
+
+hipError_t launch_fused(int mode, int sa, const BoxDev& bd, const grf_point_params& pp, const double* us,
+                        const double* u0, double* out, double* acc, StageCoef sc, double* Dwg, double sigma,
+                        unsigned* status, hipStream_t st) {
+  int grid = fused_grid_max();
+  const int nt = fused_tiles(bd);
+  if (grid > nt) grid = nt;
+  switch (mode) {
+    case 1: return launch_fused_m<1>(sa, grid, bd, pp, us, u0, out, acc, sc, Dwg, sigma, status, st);
+    case 2: return launch_fused_m<2>(sa, grid, bd, pp, us, u0, out, acc, sc, Dwg, sigma, status, st);
+    case 4: return launch_fused_m<4>(sa, grid, bd, pp, us, u0, out, acc, sc, Dwg, sigma, status, st);
+    default: return launch_fused_m<0>(sa, grid, bd, pp, us, u0, out, acc, sc, Dwg, sigma, status, st);
   }
 }
 
@@ -226,6 +262,12 @@ grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u
   unsigned* status = (unsigned*)workspace;
   double* D = (double*)((char*)workspace + kStatusBytes);
   const int sa = p->shift_advec != 0.0;
+  if (g_stage_path == 1) {
+    prof_mark(1, stream);
+    GRF_HIP_CHECK(launch_fused(0, sa, bd, pp, u, nullptr, rhs, nullptr, StageCoef{0.0}, D, p->ko_sigma, status, stream));
+    prof_mark(1, stream);
+    return GRF_OK;
+  }
   prof_mark(0, stream);
   GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, sa, nullptr, stream));
   prof_mark(0, stream);
@@ -257,12 +299,18 @@ grf_status grf_rk4_stage(const grf_params* p, const grf_box* box, int stage, dou
     case 3: mode = 2; sc = StageCoef{1.0 * dt}; break;
     default: mode = 4; sc = StageCoef{dt / 6.0}; break;
   }
-  prof_mark(0, stream);
-  GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, us, D, p->ko_sigma, sa, nullptr, stream));
-  prof_mark(0, stream);
-  prof_mark(1, stream);
-  GRF_HIP_CHECK(launch_point(mode, sa, bd, pp, us, D, u0, unext, acc, sc, status, stream));
-  prof_mark(1, stream);
+  if (g_stage_path == 1) {
+    prof_mark(1, stream);
+    GRF_HIP_CHECK(launch_fused(mode, sa, bd, pp, us, u0, unext, acc, sc, D, p->ko_sigma, status, stream));
+    prof_mark(1, stream);
+  } else {
+    prof_mark(0, stream);
+    GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, us, D, p->ko_sigma, sa, nullptr, stream));
+    prof_mark(0, stream);
+    prof_mark(1, stream);
+    GRF_HIP_CHECK(launch_point(mode, sa, bd, pp, us, D, u0, unext, acc, sc, status, stream));
+    prof_mark(1, stream);
+  }
   if (p->enforce) GRF_HIP_CHECK(launch_enforce(bd, unext, p->chi_min, p->lapse_min, stream));
   if (box->bc == GRF_BC_PERIODIC) GRF_HIP_CHECK(launch_periodic(bd, unext, stream));
   return GRF_OK;
@@ -690,6 +738,13 @@ grf_status grf_prof_end(double* ms, int* count) {
     if (count) count[k] = c.used / 2;
     c.used = 0;
   }
+  return GRF_OK;
+}
+
+// Select the stage path of the single-box calls: 0 split, 1 fused.
+grf_status grf_set_stage_path(int path) {
+  if (path != 0 && path != 1) return fail(GRF_EINVAL, "stage path must be 0 or 1");
+  g_stage_path = path;
   return GRF_OK;
 }
 

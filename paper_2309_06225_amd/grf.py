@@ -92,10 +92,11 @@ def lib():
         L.grf_flops_per_cell.restype = ctypes.c_int64
         L.grf_last_error.restype = ctypes.c_char_p
         L.grf_set_tile_variant.argtypes = [ctypes.c_int]
+        L.grf_set_stage_path.argtypes = [ctypes.c_int]
         L.grf_prof_begin.argtypes = [ctypes.c_int]
         L.grf_prof_end.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         for name in ("grf_rhs_eval", "grf_rk4_stage", "grf_fill_periodic", "grf_rhs_vjp", "grf_status_fetch",
-                     "grf_status_clear", "grf_set_tile_variant", "grf_prof_begin", "grf_prof_end",
+                     "grf_status_clear", "grf_set_tile_variant", "grf_set_stage_path", "grf_prof_begin", "grf_prof_end",
                      "grf_rk4_step_vjp", "grf_enforce", "grf_batch_create", "grf_batch_step", "grf_batch_step_perbox",
                      "grf_batch_autotune", "grf_batch_capture", "grf_batch_state", "grf_batch_tile_variant",
                      "grf_batch_status_fetch", "grf_graph_launch", "grf_graph_destroy"):
@@ -205,6 +206,11 @@ def status_clear(ws, stream=None):
 
 def set_tile_variant(v: int):
     _check(lib().grf_set_tile_variant(int(v)))
+
+
+def set_stage_path(path: int):
+    """0: stencil kernel + pointwise kernel (default); 1: fused per-tile stage kernel."""
+    _check(lib().grf_set_stage_path(int(path)))
 
 
 def prof_begin(max_launches: int):

@@ -21,15 +21,19 @@ def _setup():
     G.lib()
 
 
-def gpu_rhs(params, u, dx, bc=G.BC_FROZEN, variant=0):
+def gpu_rhs(params, u, dx, bc=G.BC_FROZEN, variant=0, path=0):
     ut = torch.from_numpy(u).to(DEV)
     box = G.box_of(ut, dx, bc)
     ws = G.alloc_workspace(G.workspace_bytes(box))
     out = torch.zeros_like(ut)
     G.set_tile_variant(variant)
-    G.rhs_eval(G.make_params(params), box, ut, out, ws)
-    code, bits = G.status_fetch(ws)
-    G.set_tile_variant(0)
+    G.set_stage_path(path)
+    try:
+        G.rhs_eval(G.make_params(params), box, ut, out, ws)
+        code, bits = G.status_fetch(ws)
+    finally:
+        G.set_tile_variant(0)
+        G.set_stage_path(0)
     return out.cpu().numpy(), code, bits
 
 
@@ -64,14 +68,12 @@ def test_rhs_parity_puncture_ragged():
     u[I.IDX["shift1"]:I.IDX["shift3"] + 1] += 0.01 * rng.standard_normal(u[19:22].shape)
     u[I.IDX["K"]] += 0.01 * rng.standard_normal(u[7].shape)
     o, _ = O.rhs(I.params_vector(p), u, dx)
-    for variant in range(5):
-        g, code, bits = gpu_rhs(p, u, dx, G.BC_FROZEN, variant)
-        e = rel_err_per_field(g, o)
-        assert e.max() <= 1e-12, (variant, dict(zip(I.FIELDS, e)))
-        if variant == 0:
-            g0 = g
-        else:
-            assert np.array_equal(g, g0), "tile shape changed the arithmetic"
+    g0, _, _ = gpu_rhs(p, u, dx, G.BC_FROZEN, 0, path=1)  # fused per-tile kernel
+    e = rel_err_per_field(g0, o)
+    assert e.max() <= 1e-12, dict(zip(I.FIELDS, e))
+    for variant in range(5):  # split path, every stencil tile shape
+        g, code, bits = gpu_rhs(p, u, dx, G.BC_FROZEN, variant, path=0)
+        assert np.array_equal(g, g0), ("tile shape / stage path changed the arithmetic", variant)
 
 
 def test_rhs_parity_single_puncture_64():
@@ -180,6 +182,25 @@ def test_periodic_fill_gpu_matches_wrap():
     ut = torch.from_numpy(u).to(DEV)
     G.fill_periodic(G.box_of(ut, 1.0, G.BC_PERIODIC), ut)
     assert np.array_equal(ut.cpu().numpy(), I.wrap_ghosts(u))
+
+
+def test_fused_and_split_stage_paths_bitwise():
+    """Ten RK4 steps through the fused stage kernel and through the split
+    stencil + pointwise kernels give identical bits."""
+    p = I.default_params(shift_advec=1.0)
+    u = I.single_puncture(20, 0.25)
+    res = []
+    for path in (1, 0):
+        G.set_stage_path(path)
+        try:
+            ut = torch.from_numpy(u).to(DEV)
+            st = G.Stepper(G.make_params(p), G.box_of(ut, 0.25), ut, 0.0625)
+            for _ in range(10):
+                st.step()
+            res.append(st.u.clone())
+        finally:
+            G.set_stage_path(0)
+    assert torch.equal(res[0], res[1])
 
 
 def test_deterministic_bitwise():
