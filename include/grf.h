@@ -195,17 +195,29 @@ void grf_batch_destroy(grf_batch* batch);
 grf_status grf_graph_launch(hipGraphExec_t exec, hipStream_t stream);
 grf_status grf_graph_destroy(hipGraphExec_t exec);
 
-/* Stencil-stage tile shape used by the single-box calls: 0: 16x8x4 (default),
- * 1: 32x4x4, 2: 8x8x8, 3: 16x16x2, 4: 64x4x2.  Results do not depend on it. */
+/* Stencil-stage variant used by the single-box calls.  Tiled (a workgroup per
+ * field of an LDS tile plus halo): 0: 16x8x4, 1: 32x4x4, 2: 8x8x8, 3: 16x16x2,
+ * 4: 64x4x2.  z-marching (a workgroup per field of an x-y column of cells
+ * walking a chunk of z-planes through a ring of LDS planes), column x chunk:
+ * 5: 16x8x32, 6: 32x8x32, 7: 32x4x32, 8: 16x16x32 (default), 9: 32x8x16,
+ * 10: 64x4x32, 11: 32x8x32 with fields as the slowest work index, 12: 32x8x64.
+ * Results do not depend on it.  GRF_EINVAL outside 0..12. */
 grf_status grf_set_tile_variant(int variant);
+int grf_get_tile_variant(void);
 
-/* Stage path of grf_rhs_eval / grf_rk4_stage: 0 (default) = a stencil kernel
- * writing the derivative records of the whole box, then a pointwise kernel;
+/* Stage path of grf_rhs_eval / grf_rk4_stage:
+ * 0 = a stencil kernel writing the derivative records of the whole box, then a
+ *     pointwise kernel reading them;
  * 1 = one fused kernel per stage (each workgroup stages the 27 fields of an
- * 8x8x4 tile in LDS, keeps the records in a small per-workgroup scratch, then
- * runs the pointwise algebra on the same cells; slower on a 128^3 box, 9.9 vs
- * 4.2 ms per stage).  Results are bitwise identical. */
+ *     8x8x4 tile in LDS, keeps the records in a small per-workgroup scratch,
+ *     then runs the pointwise algebra on the same cells);
+ * 2 (default) = as 0, but the pointwise kernel copies its inputs (record
+ *     components, state, u0, accumulator) phase by phase into LDS with
+ *     LDS-direct loads, one phase ahead of the arithmetic.
+ * On a 128^3 box one stage takes about 4.2 ms (0), 9.9 ms (1) and 3.2 ms (2).
+ * Results are bitwise identical.  GRF_EINVAL outside 0..2. */
 grf_status grf_set_stage_path(int path);
+int grf_get_stage_path(void);
 
 /* Kernel timing with HIP events recorded on the launch stream around each
  * launch, for up to max_launches launches per kernel class; grf_prof_end waits

@@ -350,4 +350,4 @@ def build(shift_advec: bool = False):
 
     inputs = {n.name: n for n in g.nodes if n.op == "in"}
     return dict(graph=g, rhs=rhs, pivots=pivots, pivot_check=pivot_check, inputs=inputs, params=P,
-                theta=[P["lambda_gb"], P["g2"]])
+                theta=[P["lambda_gb"], P["g2"]], solution=x)

@@ -247,9 +247,39 @@ def count_flops(g: Graph, outputs):
     return total, c
 
 
-def dfs_order(outputs):
+def register_need(outputs):
+    """Sethi-Ullman register need of every node on the tree expansion of the
+    graph: a leaf needs 1, a binary node max(n1, n2 + 1) with n1 >= n2."""
+    need = {}
+    for o in outputs:
+        stack = [o]
+        while stack:
+            x = stack[-1]
+            if x.idx in need:
+                stack.pop()
+                continue
+            chs = [c for c in (x.a, x.b) if c is not None]
+            pend = [c for c in chs if c.idx not in need]
+            if pend:
+                stack.extend(pend)
+                continue
+            stack.pop()
+            if x.op in ("c", "p"):
+                need[x.idx] = 0
+            elif not chs:
+                need[x.idx] = 1
+            else:
+                v = sorted((need[c.idx] for c in chs), reverse=True)
+                need[x.idx] = max(v[0], 1) if len(v) == 1 else max(v[0], v[1] + 1)
+    return need
+
+
+def dfs_order(outputs, heavy_first=False):
     """Post-order depth-first node order: each output's dependencies are placed
-    just before it, so intermediates are computed close to their uses."""
+    just before it, so intermediates are computed close to their uses.  With
+    heavy_first, the operand with the larger register need is visited first
+    (fewer values held while the other operand is computed)."""
+    need = register_need(outputs) if heavy_first else None
     order, seen = [], set()
     for o in outputs:
         stack = [(o, False)]
@@ -262,10 +292,64 @@ def dfs_order(outputs):
                 order.append(n.idx)
                 continue
             stack.append((n, True))
-            for ch in (n.b, n.a):
-                if ch is not None and ch.idx not in seen:
-                    stack.append((ch, False))
+            chs = [ch for ch in (n.a, n.b) if ch is not None and ch.idx not in seen]
+            if heavy_first:
+                chs.sort(key=lambda c: need.get(c.idx, 0), reverse=True)
+            for ch in reversed(chs):
+                stack.append((ch, False))
     return order
+
+
+def fusion_plan(g: Graph, seq, outputs):
+    """Multiply-adds to emit as explicit fused multiply-adds.  Every add or
+    subtract with a product operand takes that product into an fma (the first
+    operand when both are products); a product is still computed on its own
+    only where something other than such an fma uses it.  Returns
+    ({add node: (product node, operand position)}, {products not emitted}).
+    Fusing by this fixed rule (with compiler contraction off) makes the
+    rounding of the generated code the same in every kernel that includes it."""
+    plan = {}
+    other_use = set()
+    outs = {o.idx for o in outputs}
+    for i in seq:
+        n = g.nodes[i]
+        k_fused = None
+        if n.op in ("+", "-"):
+            for k, ch in enumerate((n.a, n.b)):
+                if ch.op == "*":
+                    k_fused = k
+                    plan[i] = (ch.idx, k)
+                    break
+        for k, ch in enumerate((n.a, n.b)):
+            if ch is not None and k != k_fused:
+                other_use.add(ch.idx)
+    skipped = {m for m, _ in plan.values() if m not in other_use and m not in outs}
+    return plan, skipped
+
+
+def _node_expr(g, n, name_of, plan):
+    """C expression of an arithmetic node (with fma fusion per plan)."""
+    if n.idx in plan:
+        m_idx, k = plan[n.idx]
+        m = g.nodes[m_idx]
+        x, y = name_of(m.a), name_of(m.b)
+        other = name_of(n.b if k == 0 else n.a)
+        if n.op == "+":
+            return f"fma({x}, {y}, {other})"
+        if k == 0:  # x*y - other
+            return f"fma({x}, {y}, -{other})"
+        return f"fma(-{x}, {y}, {other})"  # other - x*y
+    if n.op == "+":
+        return f"{name_of(n.a)} + {name_of(n.b)}"
+    if n.op == "-":
+        return f"{name_of(n.a)} - {name_of(n.b)}"
+    if n.op == "*":
+        return f"{name_of(n.a)} * {name_of(n.b)}"
+    if n.op == "neg":
+        return f"-{name_of(n.a)}"
+    if n.op == "rcp":
+        return f"1.0 / {name_of(n.a)}"
+    raise ValueError(n.op)
 
 
 def emit(g: Graph, outputs, out_names, input_expr, param_expr, indent="  ", prefix="t", order="dfs"):
@@ -275,6 +359,8 @@ def emit(g: Graph, outputs, out_names, input_expr, param_expr, indent="  ", pref
     statement is placed right after the last node it needs."""
     if order == "dfs":
         seq = dfs_order(outputs)
+    elif order == "dfs_heavy":
+        seq = dfs_order(outputs, heavy_first=True)
     else:
         seq = sorted(reachable(outputs))
     pos = {i: k for k, i in enumerate(seq)}
@@ -284,6 +370,7 @@ def emit(g: Graph, outputs, out_names, input_expr, param_expr, indent="  ", pref
         after.setdefault(pos[o.idx] if o.op != "c" else -1, []).append((o, tmpl))
     lines = []
     names = {}
+    plan, fused = fusion_plan(g, seq, outputs)
 
     def name_of(n):
         return names[n.idx]
@@ -294,26 +381,116 @@ def emit(g: Graph, outputs, out_names, input_expr, param_expr, indent="  ", pref
         n = g.nodes[i]
         if n.op == "c":
             names[i] = _lit(n.val) if n.val >= 0 else f"({_lit(n.val)})"
+        elif i in fused:
+            pass  # emitted inside the fma of its single user
         else:
             if n.op == "in":
                 expr = input_expr(n.name)
             elif n.op == "p":
                 expr = param_expr(n.name)
-            elif n.op == "+":
-                expr = f"{name_of(n.a)} + {name_of(n.b)}"
-            elif n.op == "-":
-                expr = f"{name_of(n.a)} - {name_of(n.b)}"
-            elif n.op == "*":
-                expr = f"{name_of(n.a)} * {name_of(n.b)}"
-            elif n.op == "neg":
-                expr = f"-{name_of(n.a)}"
-            elif n.op == "rcp":
-                expr = f"1.0 / {name_of(n.a)}"
             else:
-                raise ValueError(n.op)
+                expr = _node_expr(g, n, name_of, plan)
             nm = f"{prefix}{i}"
             names[i] = nm
             lines.append(f"{indent}const double {nm} = {expr};")
         for o, tmpl in after.get(k, []):
             lines.append(indent + tmpl.format(names[o.idx]) + ";")
     return "\n".join(lines)
+
+
+def emit_staged(g: Graph, outputs, out_stmts, input_key, param_expr, slots, indent="  ", prefix="t"):
+    """Straight-line C like `emit`, with every memory input staged through two
+    alternating buffers of `slots` slots each (the including kernel copies them
+    asynchronously from memory into fast local storage).
+
+    The node order is the depth-first one of `emit`.  It is cut into phases of
+    at most `slots` staged items each; phase j reads buffer j % 2 while the
+    items of phase j + 1 are being fetched into the other buffer.
+      input_key(name)  -> staging key of a graph input, e.g. ("D", 17)
+      out_stmts[k]     -> (template, extra_keys): the statement of output k,
+                          with '{v}' for the value and '{sN}' for the slot of
+                          extra_keys[N] (items the statement itself reads).
+    Emitted macros: GRF_PHASE_SYNC(); GRF_STAGE_<KIND>(buf, slot, index);
+    GRF_LDS(buf, slot) for a staged value.  Returns (code, number of phases,
+    largest slot count used)."""
+    seq = dfs_order(outputs)
+    pos = {i: k for k, i in enumerate(seq)}
+    after = {}
+    for o, st in zip(outputs, out_stmts):
+        if o.op == "c":
+            raise ValueError("constant output in staged emission")
+        after.setdefault(pos[o.idx], []).append((o, st))
+    # statement list: ("node", idx) or ("out", node, template, keys)
+    stmts = []
+    for k, i in enumerate(seq):
+        stmts.append(("node", i))
+        for o, (tmpl, keys) in after.get(k, []):
+            stmts.append(("out", o, tmpl, keys))
+
+    def keys_of(st):
+        if st[0] == "node":
+            n = g.nodes[st[1]]
+            return [input_key(n.name)] if n.op == "in" else []
+        return list(st[3])
+
+    # phases: greedy cut, each item staged in the phase of the statement using it
+    phases = [[]]       # per phase: list of statement indices
+    phase_items = [{}]  # per phase: key -> slot
+    for si, st in enumerate(stmts):
+        ks = [k for k in keys_of(st) if k not in phase_items[-1]]
+        if len(phase_items[-1]) + len(ks) > slots and phases[-1]:
+            phases.append([])
+            phase_items.append({})
+            ks = keys_of(st)
+        for k in ks:
+            if k not in phase_items[-1]:
+                phase_items[-1][k] = len(phase_items[-1])
+        if len(phase_items[-1]) > slots:
+            raise ValueError("a single statement needs more slots than available")
+        phases[-1].append(si)
+
+    lines = []
+    names = {}
+    plan, fused = fusion_plan(g, seq, outputs)
+
+    def name_of(n):
+        return names[n.idx]
+
+    def stage_lines(j):
+        buf = j % 2
+        return [f"{indent}GRF_STAGE_{kind}({buf}, {slot}, {idx});"
+                for (kind, idx), slot in sorted(phase_items[j].items(), key=lambda kv: kv[1])]
+
+    lines += stage_lines(0)
+    for j, plist in enumerate(phases):
+        buf = j % 2
+        lines.append(f"{indent}GRF_PHASE_SYNC();")
+        if j + 1 < len(phases):
+            lines += stage_lines(j + 1)
+        items = phase_items[j]
+        for si in plist:
+            st = stmts[si]
+            if st[0] == "node":
+                i = st[1]
+                n = g.nodes[i]
+                if n.op == "c":
+                    names[i] = _lit(n.val) if n.val >= 0 else f"({_lit(n.val)})"
+                    continue
+                if i in fused:
+                    continue  # emitted inside the fma of its single user
+                if n.op == "in":
+                    expr = f"GRF_LDS({buf}, {items[input_key(n.name)]})"
+                elif n.op == "p":
+                    expr = param_expr(n.name)
+                else:
+                    expr = _node_expr(g, n, name_of, plan)
+                nm = f"{prefix}{i}"
+                names[i] = nm
+                lines.append(f"{indent}const double {nm} = {expr};")
+            else:
+                _, o, tmpl, keys = st
+                fmt = {"v": names[o.idx], "b": str(buf)}
+                for q, k in enumerate(keys):
+                    fmt[f"s{q}"] = str(items[k])
+                lines.append(indent + tmpl.format(**fmt) + ";")
+    return "\n".join(lines), len(phases), max(len(p) for p in phase_items)

@@ -14,7 +14,7 @@ import os
 import sys
 
 from . import ccz4_4dst as M
-from .expr import count_flops, emit, vjp
+from .expr import count_flops, emit, emit_staged, vjp
 
 NCOMP_D1 = 3 * len(M.D1_FIELDS)
 NCOMP_D2 = 6 * len(M.D2_FIELDS)
@@ -60,9 +60,42 @@ def forward_code(shift_advec: bool):
     names = ([f"GRF_RHS({f}, {{}})" for f in indep] + ["GRF_PIVCHK({})"] * len(b["pivot_check"])
              + [f"GRF_RHS({f}, {{}})" for f in dep])
     del solve_nodes
-    code = emit(g, outs, names, input_expr, param_expr)
+    code = emit(g, outs, names, input_expr, param_expr, order=os.environ.get("GRF_GEN_ORDER", "dfs"))
     flops, ops = count_flops(g, b["rhs"])
     return code, flops, ops
+
+
+# staged item slots per buffer of the staged pointwise kernel (64 lanes x 8 bytes
+# each; two buffers per wave)
+STAGE_SLOTS = 40
+
+
+def _stage_key(name: str):
+    if name.startswith("u"):
+        return ("U", int(name[1:]))
+    return ("D", comp_of(name))
+
+
+def forward_code_staged(shift_advec: bool, rhs_only: bool):
+    """Forward right-hand side with staged inputs (see emit_staged).  Each
+    right-hand-side statement also stages its Kreiss-Oliger component and, for
+    the RK4 stage modes, u0 and the accumulator of its field."""
+    b = M.build(shift_advec)
+    g = b["graph"]
+    from .expr import reachable
+    rhs = b["rhs"]
+    indep = [f for f in range(M.NF) if not (reachable([rhs[f]]) & {p.idx for p in b["pivots"]})]
+    dep = [f for f in range(M.NF) if f not in indep]
+    outs = [rhs[f] for f in indep] + b["pivot_check"] + [rhs[f] for f in dep]
+
+    def rhs_stmt(f):
+        if rhs_only:
+            return (f"GRF_RHS_ST({f}, {{v}}, {{b}}, {{s0}}, 0, 0)", [("KO", f)])
+        return (f"GRF_RHS_ST({f}, {{v}}, {{b}}, {{s0}}, {{s1}}, {{s2}})", [("KO", f), ("U0", f), ("ACC", f)])
+
+    stmts = ([rhs_stmt(f) for f in indep] + [("GRF_PIVCHK({v})", [])] * len(b["pivot_check"])
+             + [rhs_stmt(f) for f in dep])
+    return emit_staged(g, outs, stmts, _stage_key, param_expr, STAGE_SLOTS)
 
 
 def vjp_code(shift_advec: bool):
@@ -99,6 +132,15 @@ def vjp_code(shift_advec: bool):
     return code, flops, ops
 
 
+# every block of generated code rounds exactly as written: explicit fma() where
+# the fusion plan says so, no contraction by the compiler
+PRAGMA = "#pragma clang fp contract(off)\n"
+
+
+def block(cond: str, then_code: str, else_code: str) -> str:
+    return (f"if constexpr ({cond}) {{\n" + PRAGMA + then_code + "\n} else {\n" + PRAGMA + else_code + "\n}\n")
+
+
 def main(outdir: str):
     os.makedirs(outdir, exist_ok=True)
     fw0, fl0, ops0 = forward_code(False)
@@ -117,6 +159,7 @@ def main(outdir: str):
         f"#define GRF_FLOPS_RHS_SHIFTADV {fl1}",
         f"#define GRF_FLOPS_VJP {vfl0}",
         f"#define GRF_FLOPS_VJP_SHIFTADV {vfl1}",
+        f"#define GRF_STAGE_SLOTS {STAGE_SLOTS}  // slots per buffer of the staged pointwise kernel",
         "// parameters read by the generated code (derived combinations precomputed on the host)",
         "struct grf_point_params {",
     ] + [f"  double {n};" for n in M.PARAMS] + [
@@ -127,17 +170,34 @@ def main(outdir: str):
         "// d2 component of (field f, packed xx,xy,xz,yy,yz,zz q): GRF_OFF_D2 + 6*d2_slot[f] + q",
         "static constexpr int grf_d2_slot[27] = {" + ",".join(
             str(M.D2_FIELDS.index(f)) if f in M.D2_FIELDS else "-1" for f in range(M.NF)) + "};",
+        "// field of each d1 / d2 slot (inverse of the tables above)",
+        f"static constexpr int grf_d1_field[{len(M.D1_FIELDS)}] = {{" + ",".join(str(f) for f in M.D1_FIELDS) + "};",
+        f"static constexpr int grf_d2_field[{len(M.D2_FIELDS)}] = {{" + ",".join(str(f) for f in M.D2_FIELDS) + "};",
     ]
     with open(os.path.join(outdir, "gen_layout.h"), "w") as fh:
         fh.write("\n".join(hdr) + "\n")
     with open(os.path.join(outdir, "gen_rhs.inc"), "w") as fh:
         fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
         fh.write(f"// forward right-hand side: {fl0} flops/cell ({ops0})\n")
-        fh.write("if constexpr (GRF_SHIFT_ADVEC) {\n" + fw1 + "\n} else {\n" + fw0 + "\n}\n")
+        fh.write(block("GRF_SHIFT_ADVEC", fw1, fw0))
+    staged = {}
+    for ro in (True, False):
+        for sa in (True, False):
+            staged[(ro, sa)] = forward_code_staged(sa, ro)
+    with open(os.path.join(outdir, "gen_rhs_staged.inc"), "w") as fh:
+        fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
+        fh.write(f"// forward right-hand side with inputs staged through two buffers of {STAGE_SLOTS} slots;\n")
+        fh.write("// phases (rhs only / stage, shift advection on / off): "
+                 + ", ".join(f"{v[1]}" for v in staged.values()) + "\n")
+        fh.write("if constexpr (GRF_STAGE_RHS_ONLY) {\n")
+        fh.write(block("GRF_SHIFT_ADVEC", staged[(True, True)][0], staged[(True, False)][0]))
+        fh.write("} else {\n")
+        fh.write(block("GRF_SHIFT_ADVEC", staged[(False, True)][0], staged[(False, False)][0]))
+        fh.write("}\n")
     with open(os.path.join(outdir, "gen_vjp.inc"), "w") as fh:
         fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
         fh.write(f"// vector-Jacobian product: {vfl0} flops/cell ({vops0})\n")
-        fh.write("if constexpr (GRF_SHIFT_ADVEC) {\n" + vj1 + "\n} else {\n" + vj0 + "\n}\n")
+        fh.write(block("GRF_SHIFT_ADVEC", vj1, vj0))
     return dict(flops_rhs=fl0, flops_rhs_shiftadv=fl1, flops_vjp=vfl0, ops=ops0, vops=vops0)
 
 

@@ -50,10 +50,12 @@ __device__ __forceinline__ double sten_up_minus(const double* L) {  // offsets 1
 __device__ __forceinline__ double sten_ko(const double* L) {  // 1, -6, 15, -20, 15, -6, 1
   return (((((L[0] - 6.0 * L[1]) + 15.0 * L[2]) - 20.0 * L[3]) + 15.0 * L[4]) - 6.0 * L[5]) + L[6];
 }
-// 16-point mixed derivative: sum over a (axis d, outer) and b (axis e, inner)
-// of c_a c_b u(a, b), c = (1, -8, 0, 8, -1); the weights are powers of two, so
-// every product is exact.
-__device__ __forceinline__ double sten_mixed(const double* t, int c0, int sd, int se) {
+// 16-point mixed derivative of the axis pair PAIR (0: x-y, 1: x-z, 2: y-z):
+// sum over a (first axis, outer) and b (second axis, inner) of c_a c_b u(a, b),
+// c = (1, -8, 0, 8, -1); the weights are powers of two, so every product is
+// exact.  Staged values are addressed as t[pb[dz + 3] + cxy + dy * LX + dx].
+template <int LX, int PAIR>
+__device__ __forceinline__ double sten_mixed(const double* t, const int* pb, int cxy) {
   const double w[5] = {1.0, -8.0, 0.0, 8.0, -1.0};
   double s = 0.0;
 #pragma unroll
@@ -62,7 +64,8 @@ __device__ __forceinline__ double sten_mixed(const double* t, int c0, int sd, in
 #pragma unroll
     for (int bb = -2; bb <= 2; ++bb) {
       if (bb == 0) continue;
-      s += (w[a + 2] * w[bb + 2]) * t[c0 + a * sd + bb * se];
+      const int e = PAIR == 0 ? pb[3] + cxy + bb * LX + a : PAIR == 1 ? pb[bb + 3] + cxy + a : pb[bb + 3] + cxy + a * LX;
+      s += (w[a + 2] * w[bb + 2]) * t[e];
     }
   }
   return s;
@@ -104,32 +107,24 @@ __device__ __forceinline__ void tile_origin(const BoxDev& b, int tile, int TX, i
   tz0 = (tile / nty) * TZ;
 }
 
-// Derivative record of field f for this thread's cell of the tile, from the
-// staged tile t.  Record layout: component q of the cell lives at
-// D[q * dstride + dcell], with dcell the interior cell index (whole-box record,
-// dstride = ncell) or the thread's index within the tile (per-workgroup record,
-// dstride = tile size).  Threads whose cell lies outside the box do nothing.
-template <int TX, int TY, int TZ, bool LOCAL_RECORD>
-__device__ __forceinline__ void compute_tile(const BoxDev& b, int tx0, int ty0, int tz0, int f,
-                                             const double* __restrict__ u, double* __restrict__ D, double ko_sigma,
-                                             int shift_adv, double* __restrict__ UP, const double* t) {
-  constexpr int LX = TX + 6, LY = TY + 6;
-  const int ix = threadIdx.x % TX;
-  const int iy = (threadIdx.x / TX) % TY;
-  const int iz = threadIdx.x / (TX * TY);
-  const int i = tx0 + ix, j = ty0 + iy, k = tz0 + iz;
-  if (i >= b.nx || j >= b.ny || k >= b.nz) return;
-  const int64_t cell = ((int64_t)k * b.ny + j) * b.nx + i;
-  const int c0 = ((iz + 3) * LY + (iy + 3)) * LX + (ix + 3);
-  const int st[3] = {1, LX, LX * LY};
-  double* __restrict__ Dc = D + (LOCAL_RECORD ? (int64_t)threadIdx.x : cell);
-  const int64_t nc = LOCAL_RECORD ? (int64_t)(TX * TY * TZ) : b.ncell;
+// Derivative record of field f for one cell (interior i, j, k) from staged
+// values.  The staged neighbourhood is addressed as t[pb[dz + 3] + cxy + dy*LX + dx]
+// (pb: base of the plane at z offset dz, cxy: the cell within a plane), so the
+// same arithmetic serves a 3-D tile and a ring of z-planes.  Record layout:
+// component q of the cell lives at Dc[q * nc].
+template <int LX>
+__device__ __forceinline__ void compute_cell(const BoxDev& b, int i, int j, int k, int f, const double* __restrict__ u,
+                                             double* __restrict__ Dc, int64_t nc, int64_t cell, double ko_sigma,
+                                             int shift_adv, double* __restrict__ UP, const double* t, const int* pb,
+                                             int cxy) {
+#define GRF_AT(dx, dy, dz) t[pb[(dz) + 3] + cxy + (dy) * LX + (dx)]
   double line[3][7];
 #pragma unroll
-  for (int d = 0; d < 3; ++d)
-#pragma unroll
-    for (int o = -3; o <= 3; ++o) line[d][o + 3] = t[c0 + o * st[d]];
-
+  for (int o = -3; o <= 3; ++o) {
+    line[0][o + 3] = GRF_AT(o, 0, 0);
+    line[1][o + 3] = GRF_AT(0, o, 0);
+    line[2][o + 3] = GRF_AT(0, 0, o);
+  }
   const int s1 = grf_d1_slot[f];
   if (s1 >= 0) {
 #pragma unroll
@@ -140,11 +135,11 @@ __device__ __forceinline__ void compute_tile(const BoxDev& b, int tx0, int ty0, 
     const int pure[3] = {0, 3, 5};
 #pragma unroll
     for (int d = 0; d < 3; ++d) Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc] = sten_d2(line[d]) * b.i12h2[d];
-    const int pd[3] = {0, 0, 1}, pe[3] = {1, 2, 2}, pq[3] = {1, 2, 4};
-#pragma unroll
-    for (int m = 0; m < 3; ++m)
-      Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + pq[m]) * nc] = sten_mixed(t, c0, st[pd[m]], st[pe[m]]) * b.i144[m];
+    Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 1) * nc] = sten_mixed<LX, 0>(t, pb, cxy) * b.i144[0];
+    Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 2) * nc] = sten_mixed<LX, 1>(t, pb, cxy) * b.i144[1];
+    Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 4) * nc] = sten_mixed<LX, 2>(t, pb, cxy) * b.i144[2];
   }
+#undef GRF_AT
   // upwinded advection: the lopsided stencil on the side the shift points to
   const int64_t sc = (int64_t)(k + 3) * b.sz + (int64_t)(j + 3) * b.sy + (i + 3);
   double beta[3], up[3];
@@ -161,6 +156,29 @@ __device__ __forceinline__ void compute_tile(const BoxDev& b, int tx0, int ty0, 
   Dc[(int64_t)(GRF_OFF_KO + f) * nc] = ko_sigma * ko;
 }
 
+// Derivative record of field f for this thread's cell of a staged 3-D tile.
+// Record layout: D[q * dstride + dcell] with dcell the interior cell index
+// (whole-box record, dstride = ncell) or the thread's index within the tile
+// (per-workgroup record, dstride = tile size).  Threads outside the box do nothing.
+template <int TX, int TY, int TZ, bool LOCAL_RECORD>
+__device__ __forceinline__ void compute_tile(const BoxDev& b, int tx0, int ty0, int tz0, int f,
+                                             const double* __restrict__ u, double* __restrict__ D, double ko_sigma,
+                                             int shift_adv, double* __restrict__ UP, const double* t) {
+  constexpr int LX = TX + 6, LY = TY + 6;
+  const int ix = threadIdx.x % TX;
+  const int iy = (threadIdx.x / TX) % TY;
+  const int iz = threadIdx.x / (TX * TY);
+  const int i = tx0 + ix, j = ty0 + iy, k = tz0 + iz;
+  if (i >= b.nx || j >= b.ny || k >= b.nz) return;
+  const int64_t cell = ((int64_t)k * b.ny + j) * b.nx + i;
+  int pb[7];
+#pragma unroll
+  for (int o = 0; o < 7; ++o) pb[o] = (iz + o) * LX * LY;
+  const int cxy = (iy + 3) * LX + (ix + 3);
+  double* __restrict__ Dc = D + (LOCAL_RECORD ? (int64_t)threadIdx.x : cell);
+  const int64_t nc = LOCAL_RECORD ? (int64_t)(TX * TY * TZ) : b.ncell;
+  compute_cell<LX>(b, i, j, k, f, u, Dc, nc, cell, ko_sigma, shift_adv, UP, t, pb, cxy);
+}
 
 template <int TX, int TY, int TZ, bool LOCAL_RECORD = false>
 __device__ __forceinline__ void deriv_tile(const BoxDev& b, int tile, int f, const double* __restrict__ u,
@@ -182,6 +200,74 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_deriv(BoxDev b, const double* __
   deriv_tile<TX, TY, TZ>(b, blockIdx.x, blockIdx.y, u, D, ko_sigma, shift_adv, UP, t);
 }
 
+// Stencil stage, z-marching form.  One workgroup = one field of a TX*TY column
+// of cells over a chunk of ZC z-planes.  The workgroup walks up the column with a
+// ring of 8 LDS planes (each TX+6 by TY+6): every step loads one new plane and
+// computes one plane of cells from the 7 planes around it, so each plane of the
+// field is read from memory once per column instead of once per overlapping
+// tile.  With 8 slots for a 7-plane stencil, one barrier per step suffices: the
+// slot a step loads is never one the previous step reads.
+// Work-item order with XCDMAP: consecutive items are the 27 fields of one column
+// chunk, and the hardware's round-robin dealing of workgroups over the 8 XCDs
+// is undone so that consecutive items share an XCD, and with it the L2 that
+// holds the column's shift values and the halo of the previous column.
+__device__ __forceinline__ int xcd_item(int w, int nblocks) {
+  const int per = nblocks >> 3, rem = nblocks & 7;
+  const int x = w & 7, s = w >> 3;
+  return x * per + (x < rem ? x : rem) + s;
+}
+
+template <int TX, int TY, int ZC, bool XCDMAP>
+__global__ __launch_bounds__(TX* TY) void k_deriv_zm(BoxDev b, const double* __restrict__ u,
+                                                      double* __restrict__ D, double ko_sigma, int shift_adv,
+                                                      double* __restrict__ UP) {
+  constexpr int LX = TX + 6, LY = TY + 6, PL = LX * LY, NT = TX * TY;
+  __shared__ double t[8 * PL];
+  const int ntx = (b.nx + TX - 1) / TX, nty = (b.ny + TY - 1) / TY;
+  int item = blockIdx.x, f;
+  if (XCDMAP) {
+    item = xcd_item(item, (int)gridDim.x);
+    f = item % NF;
+    item /= NF;
+  } else {  // field slowest, as in the tiled form
+    const int per_field = (int)gridDim.x / NF;
+    f = item / per_field;
+    item %= per_field;
+  }
+  const int tx0 = (item % ntx) * TX;
+  item /= ntx;
+  const int ty0 = (item % nty) * TY;
+  const int z0 = (item / nty) * ZC;
+  const int z1 = min(z0 + ZC, b.nz);
+  const double* __restrict__ uf = u + (int64_t)f * b.fs;
+  const int ix = threadIdx.x % TX, iy = threadIdx.x / TX;
+  const int i = tx0 + ix, j = ty0 + iy;
+  const bool inside = i < b.nx && j < b.ny;
+  const int cxy = (iy + 3) * LX + (ix + 3);
+  // state plane gz (ghost-inclusive z) into its ring slot gz mod 8
+  auto load_plane = [&](int gz) {
+    double* tp = t + (gz & 7) * PL;
+    const double* up = uf + (int64_t)gz * b.sz;
+    for (int e = threadIdx.x; e < PL; e += NT) {
+      const int lx = e % LX, ly = e / LX;
+      const int gx = tx0 + lx, gy = ty0 + ly;
+      if (gx < b.nx + 6 && gy < b.ny + 6) tp[e] = up[(int64_t)gy * b.sy + gx];
+    }
+  };
+  for (int gz = z0; gz < z0 + 6; ++gz) load_plane(gz);
+  for (int k = z0; k < z1; ++k) {
+    load_plane(k + 6);
+    __syncthreads();
+    if (inside) {
+      int pb[7];
+#pragma unroll
+      for (int o = 0; o < 7; ++o) pb[o] = ((k + o) & 7) * PL;
+      const int64_t cell = ((int64_t)k * b.ny + j) * b.nx + i;
+      compute_cell<LX>(b, i, j, k, f, u, D + cell, b.ncell, cell, ko_sigma, shift_adv, UP, t, pb, cxy);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Pointwise right-hand side (generated algebra) fused with the RK4 stage.
 // MODE 0: rhs[f] = k;  MODE 1: first stage;  MODE 2: middle stage;  MODE 4: last stage.
@@ -197,12 +283,11 @@ struct StageCoef {
 // Kreiss-Oliger term stored by the stencil stage.
 #pragma clang fp contract(off)
 template <int MODE>
-__device__ __forceinline__ void stage_one(int f, double rhs_f, const BoxDev& b, const double* __restrict__ D,
-                                          int64_t dstride, int64_t dcell, int64_t c, int64_t s,
+__device__ __forceinline__ void stage_one(int f, double rhs_f, double ko_f, const BoxDev& b, int64_t c, int64_t s,
                                           const double* __restrict__ u0, double* __restrict__ out,
                                           double* __restrict__ acc, StageCoef sc, unsigned& flags) {
   const int64_t nc = b.ncell;
-  const double kf = rhs_f + D[(int64_t)(GRF_OFF_KO + f) * dstride + dcell];
+  const double kf = rhs_f + ko_f;
   if (!isfinite(kf)) flags |= 1u;
   const int64_t q = (int64_t)f * b.fs + s;
   const int64_t qa = (int64_t)f * nc + c;
@@ -239,13 +324,17 @@ __device__ __forceinline__ void point_cell(const BoxDev& b, int64_t c, const grf
 #define GRF_U(f) us[(int64_t)(f) * b.fs + s]
 #define GRF_D(cc) D[(int64_t)(cc) * dstride + dcell]
 #define GRF_P(n) P.n
-#define GRF_RHS(f, v) stage_one<MODE>(f, (v), b, D, dstride, dcell, c, s, u0, out, acc, sc, flags)
+#define GRF_RHS(f, v) \
+  stage_one<MODE>(f, (v), D[(int64_t)(GRF_OFF_KO + (f)) * dstride + dcell], b, c, s, u0, out, acc, sc, flags)
 #define GRF_PIVCHK(v) bad |= !(fabs(v) <= 1e12)
 #define GRF_SHIFT_ADVEC (SHIFTADV != 0)
 #include "gen/gen_rhs.inc"
 #undef GRF_SHIFT_ADVEC
 #undef GRF_RHS
 #undef GRF_PIVCHK
+#undef GRF_U
+#undef GRF_D
+#undef GRF_P
   if (bad) flags |= 2u;
   if (!(us[(int64_t)F_CHI * b.fs + s] > 0.0) || !(us[(int64_t)F_LAPSE * b.fs + s] > 0.0)) flags |= 4u;
   if (flags) atomicOr(status, flags);

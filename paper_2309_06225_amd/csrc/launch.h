@@ -15,10 +15,11 @@ struct BatchBoxDev;
 struct TileEntry;
 struct CellEntry;
 
-constexpr int kTileVariants = 5;
+constexpr int kTileVariants = 5;      // tiled stencil shapes (single-box and batched calls)
+constexpr int kDerivVariants = 13;    // plus z-marching shapes 5..12 (single-box calls)
 extern const int kTiles[kTileVariants][3];
 
-// stencil stage (tile variant 0..4), optionally storing the upwinded derivatives
+// stencil stage (variant 0..12), optionally storing the upwinded derivatives
 hipError_t launch_deriv(int variant, const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
                         hipStream_t st);
 int tiles_of_variant(int variant, const BoxDev& bd);
@@ -59,6 +60,21 @@ template <> int grid_point_batch_m<1>(int, int64_t);
 template <> int grid_point_batch_m<2>(int, int64_t);
 template <> int grid_point_batch_m<4>(int, int64_t);
 
+// pointwise right-hand side + stage update with inputs staged through LDS (same
+// arguments and results as launch_point_m)
+template <int MODE>
+hipError_t launch_staged_m(int sa, const BoxDev& bd, const grf_point_params& pp, const double* us, const double* D,
+                           const double* u0, double* out, double* acc, const StageCoef& sc, unsigned* status,
+                           hipStream_t st);
+#define GRF_DECL_STAGED(M)                                                                                      \
+  template <> hipError_t launch_staged_m<M>(int, const BoxDev&, const grf_point_params&, const double*,        \
+                                            const double*, const double*, double*, double*, const StageCoef&, \
+                                            unsigned*, hipStream_t);
+GRF_DECL_STAGED(0)
+GRF_DECL_STAGED(1)
+GRF_DECL_STAGED(2)
+GRF_DECL_STAGED(4)
+#undef GRF_DECL_STAGED
 
 // fused stage (stencil records in a per-workgroup slice of Dwg, then pointwise + stage update)
 template <int MODE>

@@ -110,7 +110,7 @@ grf_point_params make_pp(const grf_params* p) {
 
 // Stage path of the single-box calls: 0 = stencil kernel + pointwise kernel
 // (record of the whole box through HBM), 1 = fused per-tile kernel.
-int g_stage_path = 0;
+int g_stage_path = 2;  // split, pointwise inputs staged through LDS
 
 // Persistent grid of the fused kernel (workgroups resident at once) and the
 // size of its per-workgroup record scratch.
@@ -135,7 +135,7 @@ size_t deriv_bytes(const grf_box* b) {
 }
 
 constexpr int kTileVariantsMax = 5;
-int g_tile_variant = 0;
+int g_tile_variant = 8;  // z-marching 16x16 columns, 32-plane chunks
 
 // Optional per-kernel timing with HIP events recorded on the launch stream
 // around each stencil-stage and pointwise launch (enabled by grf_prof_begin).
@@ -179,6 +179,25 @@ hipError_t launch_fused(int mode, int sa, const BoxDev& bd, const grf_point_para
     case 4: return launch_fused_m<4>(sa, grid, bd, pp, us, u0, out, acc, sc, Dwg, sigma, status, st);
     default: return launch_fused_m<0>(sa, grid, bd, pp, us, u0, out, acc, sc, Dwg, sigma, status, st);
   }
+}
+
+hipError_t launch_staged(int mode, int sa, const BoxDev& bd, const grf_point_params& pp, const double* us,
+                         const double* D, const double* u0, double* out, double* acc, StageCoef sc,
+                         unsigned* status, hipStream_t st) {
+  switch (mode) {
+    case 1: return launch_staged_m<1>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
+    case 2: return launch_staged_m<2>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
+    case 4: return launch_staged_m<4>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
+    default: return launch_staged_m<0>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
+  }
+}
+
+// pointwise kernel of the split path: 0 plain, 2 with staged inputs
+hipError_t launch_pointwise(int path, int mode, int sa, const BoxDev& bd, const grf_point_params& pp,
+                            const double* us, const double* D, const double* u0, double* out, double* acc,
+                            StageCoef sc, unsigned* status, hipStream_t st) {
+  if (path == 2) return launch_staged(mode, sa, bd, pp, us, D, u0, out, acc, sc, status, st);
+  return launch_point(mode, sa, bd, pp, us, D, u0, out, acc, sc, status, st);
 }
 
 hipError_t launch_point_batch(int mode, int sa, int grid, const BatchBoxDev* boxes, const CellEntry* cells,
@@ -272,7 +291,8 @@ grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u
   GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, sa, nullptr, stream));
   prof_mark(0, stream);
   prof_mark(1, stream);
-  GRF_HIP_CHECK(launch_point(0, sa, bd, pp, u, D, nullptr, rhs, nullptr, StageCoef{0.0}, status, stream));
+  GRF_HIP_CHECK(
+      launch_pointwise(g_stage_path, 0, sa, bd, pp, u, D, nullptr, rhs, nullptr, StageCoef{0.0}, status, stream));
   prof_mark(1, stream);
   return GRF_OK;
 }
@@ -308,7 +328,7 @@ grf_status grf_rk4_stage(const grf_params* p, const grf_box* box, int stage, dou
     GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, us, D, p->ko_sigma, sa, nullptr, stream));
     prof_mark(0, stream);
     prof_mark(1, stream);
-    GRF_HIP_CHECK(launch_point(mode, sa, bd, pp, us, D, u0, unext, acc, sc, status, stream));
+    GRF_HIP_CHECK(launch_pointwise(g_stage_path, mode, sa, bd, pp, us, D, u0, unext, acc, sc, status, stream));
     prof_mark(1, stream);
   }
   if (p->enforce) GRF_HIP_CHECK(launch_enforce(bd, unext, p->chi_min, p->lapse_min, stream));
@@ -741,16 +761,20 @@ grf_status grf_prof_end(double* ms, int* count) {
   return GRF_OK;
 }
 
-// Select the stage path of the single-box calls: 0 split, 1 fused.
+// Select the stage path of the single-box calls: 0 split, 1 fused per tile,
+// 2 split with the pointwise kernel's inputs staged through LDS.
 grf_status grf_set_stage_path(int path) {
-  if (path != 0 && path != 1) return fail(GRF_EINVAL, "stage path must be 0 or 1");
+  if (path < 0 || path > 2) return fail(GRF_EINVAL, "stage path must be 0, 1 or 2");
   g_stage_path = path;
   return GRF_OK;
 }
 
-// Select the stencil tile shape (0..4) used by the single-box calls.
+int grf_get_stage_path(void) { return g_stage_path; }
+int grf_get_tile_variant(void) { return g_tile_variant; }
+
+// Select the stencil variant (0..12) used by the single-box calls.
 grf_status grf_set_tile_variant(int variant) {
-  if (variant < 0 || variant >= kTileVariants) return fail(GRF_EINVAL, "tile variant out of range");
+  if (variant < 0 || variant >= kDerivVariants) return fail(GRF_EINVAL, "tile variant out of range");
   g_tile_variant = variant;
   return GRF_OK;
 }

@@ -170,9 +170,26 @@ hipError_t launch_deriv_t(const BoxDev& bd, const double* u, double* D, double s
   return hipGetLastError();
 }
 
+template <int TX, int TY, int ZC, bool XCDMAP>
+hipError_t launch_deriv_zm_t(const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
+                             hipStream_t st) {
+  const int64_t items = (int64_t)((bd.nx + TX - 1) / TX) * ((bd.ny + TY - 1) / TY) * ((bd.nz + ZC - 1) / ZC) * NF;
+  hipLaunchKernelGGL((k_deriv_zm<TX, TY, ZC, XCDMAP>), dim3((unsigned)items), dim3(TX * TY), 0, st, bd, u, D, sigma,
+                     sa, UP);
+  return hipGetLastError();
+}
+
 hipError_t launch_deriv(int variant, const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
                         hipStream_t st) {
   switch (variant) {
+    case 5: return launch_deriv_zm_t<16, 8, 32, true>(bd, u, D, sigma, sa, UP, st);
+    case 6: return launch_deriv_zm_t<32, 8, 32, true>(bd, u, D, sigma, sa, UP, st);
+    case 7: return launch_deriv_zm_t<32, 4, 32, true>(bd, u, D, sigma, sa, UP, st);
+    case 8: return launch_deriv_zm_t<16, 16, 32, true>(bd, u, D, sigma, sa, UP, st);
+    case 9: return launch_deriv_zm_t<32, 8, 16, true>(bd, u, D, sigma, sa, UP, st);
+    case 10: return launch_deriv_zm_t<64, 4, 32, true>(bd, u, D, sigma, sa, UP, st);
+    case 11: return launch_deriv_zm_t<32, 8, 32, false>(bd, u, D, sigma, sa, UP, st);
+    case 12: return launch_deriv_zm_t<32, 8, 64, true>(bd, u, D, sigma, sa, UP, st);
     case 1: return launch_deriv_t<32, 4, 4>(bd, u, D, sigma, sa, UP, st);
     case 2: return launch_deriv_t<8, 8, 8>(bd, u, D, sigma, sa, UP, st);
     case 3: return launch_deriv_t<16, 16, 2>(bd, u, D, sigma, sa, UP, st);

@@ -209,8 +209,17 @@ def set_tile_variant(v: int):
 
 
 def set_stage_path(path: int):
-    """0: stencil kernel + pointwise kernel (default); 1: fused per-tile stage kernel."""
+    """0: stencil kernel + pointwise kernel; 1: fused per-tile stage kernel;
+    2 (default): stencil kernel + pointwise kernel with LDS-staged inputs."""
     _check(lib().grf_set_stage_path(int(path)))
+
+
+def get_stage_path() -> int:
+    return int(lib().grf_get_stage_path())
+
+
+def get_tile_variant() -> int:
+    return int(lib().grf_get_tile_variant())
 
 
 def prof_begin(max_launches: int):

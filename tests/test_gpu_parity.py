@@ -21,19 +21,23 @@ def _setup():
     G.lib()
 
 
-def gpu_rhs(params, u, dx, bc=G.BC_FROZEN, variant=0, path=0):
+def gpu_rhs(params, u, dx, bc=G.BC_FROZEN, variant=None, path=None):
+    """RHS through the C-ABI; variant / path None: the library's defaults."""
     ut = torch.from_numpy(u).to(DEV)
     box = G.box_of(ut, dx, bc)
     ws = G.alloc_workspace(G.workspace_bytes(box))
     out = torch.zeros_like(ut)
-    G.set_tile_variant(variant)
-    G.set_stage_path(path)
+    v0, p0 = G.get_tile_variant(), G.get_stage_path()
+    if variant is not None:
+        G.set_tile_variant(variant)
+    if path is not None:
+        G.set_stage_path(path)
     try:
         G.rhs_eval(G.make_params(params), box, ut, out, ws)
         code, bits = G.status_fetch(ws)
     finally:
-        G.set_tile_variant(0)
-        G.set_stage_path(0)
+        G.set_tile_variant(v0)
+        G.set_stage_path(p0)
     return out.cpu().numpy(), code, bits
 
 
@@ -71,9 +75,37 @@ def test_rhs_parity_puncture_ragged():
     g0, _, _ = gpu_rhs(p, u, dx, G.BC_FROZEN, 0, path=1)  # fused per-tile kernel
     e = rel_err_per_field(g0, o)
     assert e.max() <= 1e-12, dict(zip(I.FIELDS, e))
-    for variant in range(5):  # split path, every stencil tile shape
-        g, code, bits = gpu_rhs(p, u, dx, G.BC_FROZEN, variant, path=0)
-        assert np.array_equal(g, g0), ("tile shape / stage path changed the arithmetic", variant)
+    for path in (0, 2):  # split paths, plain and staged pointwise kernel
+        for variant in range(13):  # every stencil variant
+            g, code, bits = gpu_rhs(p, u, dx, G.BC_FROZEN, variant, path=path)
+            assert np.array_equal(g, g0), ("stencil variant / stage path changed the arithmetic", path, variant)
+
+
+def test_stencil_variants_bitwise_multi_chunk():
+    """Every stencil variant (tiled and z-marching) gives the same bits on a box
+    whose z extent spans several marching chunks with a ragged last one and
+    whose x-y extent leaves ragged columns; variant 0 is checked against the
+    oracle on sampled cells."""
+    print("case: puncture 37x21x71 frozen, stencil variants 0..12", flush=True)
+    p = I.default_params(shift_advec=1.0)
+    dims, dx = (37, 21, 71), 0.2
+    u = I.puncture(dims, dx, centre=(0.3, 0.1, -0.2), phi_fn=I.shell_pulse(0.1, 2.0))
+    rng = np.random.default_rng(5)
+    u[I.IDX["shift1"]:I.IDX["shift3"] + 1] += 0.01 * rng.standard_normal(u[19:22].shape)
+    g0, code, bits = gpu_rhs(p, u, dx, G.BC_FROZEN, 0, path=0)
+    assert code == 0
+    cells = np.stack([rng.integers(0, n, size=400) for n in dims], axis=1)
+    cells = np.concatenate([cells, np.array([[36, 20, 70], [0, 0, 64], [36, 0, 63], [5, 20, 31], [0, 0, 0]])])
+    o, _ = O.rhs_cells(I.params_vector(p), u, dx, cells)
+    gs = g0[:, cells[:, 2] + 3, cells[:, 1] + 3, cells[:, 0] + 3].T
+    num = np.abs(gs - o).max(axis=0)
+    den = np.abs(o).max(axis=0)
+    den = np.where(den > 0, den, den.max())
+    assert (num / den).max() <= 1e-12, dict(zip(I.FIELDS, num / den))
+    for path in (0, 2):
+        for variant in range(13):
+            g, code, bits = gpu_rhs(p, u, dx, G.BC_FROZEN, variant, path=path)
+            assert np.array_equal(g, g0), ("stencil variant / stage path changed the arithmetic", path, variant)
 
 
 def test_rhs_parity_single_puncture_64():
@@ -184,13 +216,16 @@ def test_periodic_fill_gpu_matches_wrap():
     assert np.array_equal(ut.cpu().numpy(), I.wrap_ghosts(u))
 
 
-def test_fused_and_split_stage_paths_bitwise():
-    """Ten RK4 steps through the fused stage kernel and through the split
-    stencil + pointwise kernels give identical bits."""
-    p = I.default_params(shift_advec=1.0)
-    u = I.single_puncture(20, 0.25)
+@pytest.mark.parametrize("shift_advec", [0.0, 1.0])
+def test_stage_paths_bitwise(shift_advec):
+    """Ten RK4 steps through the fused stage kernel, the split stencil +
+    pointwise kernels and the split path with staged pointwise inputs give
+    identical bits (a 20x21x19 box: the last wave of cells is partial)."""
+    p = I.default_params(shift_advec=shift_advec)
+    u = I.puncture((20, 21, 19), 0.25, centre=(0.1, 0.2, -0.1), phi_fn=I.shell_pulse(0.1, 2.0))
     res = []
-    for path in (1, 0):
+    p0 = G.get_stage_path()
+    for path in (1, 0, 2):
         G.set_stage_path(path)
         try:
             ut = torch.from_numpy(u).to(DEV)
@@ -198,9 +233,10 @@ def test_fused_and_split_stage_paths_bitwise():
             for _ in range(10):
                 st.step()
             res.append(st.u.clone())
+            assert G.status_fetch(st.ws) == (0, 0)
         finally:
-            G.set_stage_path(0)
-    assert torch.equal(res[0], res[1])
+            G.set_stage_path(p0)
+    assert torch.equal(res[0], res[1]) and torch.equal(res[0], res[2])
 
 
 def test_deterministic_bitwise():
