@@ -26,7 +26,8 @@ PEAK_HBM = 8000.0  # GB/s
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for rel in ("paper_2309_06225_amd/csrc/kernels_fwd.h", "paper_2309_06225_amd/csrc/gen/gen_rhs.inc",
+    for rel in ("paper_2309_06225_amd/csrc/kernels_fwd.h", "paper_2309_06225_amd/csrc/kernels_staged.h",
+                "paper_2309_06225_amd/csrc/gen/gen_rhs.inc", "paper_2309_06225_amd/csrc/gen/gen_rhs_staged.inc",
                 "paper_2309_06225_amd/csrc/libgrf.hip"):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
@@ -72,6 +73,7 @@ def adjoint_ratio(torch, G, I):
     theta = torch.tensor([p["lambda_gb"], p["g2"]], dtype=torch.float64, requires_grad=True)
     times = []
     for rep in range(2):  # the first repetition allocates the buffers
+        theta.grad = None
         x = u0.clone().requires_grad_(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -128,6 +130,8 @@ def main():
     ap.add_argument("--n", type=int, default=128, help="box edge (cells)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the adjoint and batched measurements")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only run the adjoint/forward measurement (for kernel traces of the adjoint)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run one plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -148,6 +152,10 @@ def main():
     import torch
     from paper_2309_06225_amd import grf as G
     from paper_2309_06225_amd import inputs as I
+
+    if args.adjoint_only:
+        print(json.dumps({"adjoint_forward_ratio": adjoint_ratio(torch, G, I)}), flush=True)
+        return
 
     n = args.n
     dx = 1.0 / 8.0
@@ -189,7 +197,8 @@ def main():
     # averaged over the four stages ((2 + 4 + 4 + 3) / 4)
     flops_cell = G.flops_per_cell(0) + 27 * (1.0 + 13.0 / 4.0)
     achieved = flops_cell * ncell / (avg_point * 1e-3) / 1e12
-    traffic = load_traffic("k_point", f"single_puncture_{n}")
+    kname = {0: "k_point", 1: "k_stage_fused", 2: "k_point_staged"}[G.get_stage_path()]
+    traffic = load_traffic(kname, f"single_puncture_{n}")
     out = {
         "metric": METRIC,
         "value": value,
@@ -206,7 +215,7 @@ def main():
         "config": {"workload": f"single_puncture_{n}", "cells": ncell, "ghosts": 3, "dx": dx, "dt": dt,
                    "bc": "frozen", "lambda_gb": params["lambda_gb"], "g2": params["g2"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64, "traffic": traffic, "kernel": "k_point",
+                     "frac": achieved / PEAK_FP64, "traffic": traffic, "kernel": kname,
                      "flops_per_cell": flops_cell, "avg_launch_ms": avg_point},
         "kernels_ms_per_step": {"stencil": deriv_ms / args.steps, "pointwise_rk4": point_ms / args.steps},
         "rhs_cells_per_s": ncell * 4 * args.steps / (ms_total * 1e-3),

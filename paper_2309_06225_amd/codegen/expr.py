@@ -398,7 +398,7 @@ def emit(g: Graph, outputs, out_names, input_expr, param_expr, indent="  ", pref
     return "\n".join(lines)
 
 
-def emit_staged(g: Graph, outputs, out_stmts, input_key, param_expr, slots, indent="  ", prefix="t"):
+def emit_staged(g: Graph, outputs, out_stmts, input_key, param_expr, slots, indent="  ", prefix="t", order="dfs"):
     """Straight-line C like `emit`, with every memory input staged through two
     alternating buffers of `slots` slots each (the including kernel copies them
     asynchronously from memory into fast local storage).
@@ -413,7 +413,7 @@ def emit_staged(g: Graph, outputs, out_stmts, input_key, param_expr, slots, inde
     Emitted macros: GRF_PHASE_SYNC(); GRF_STAGE_<KIND>(buf, slot, index);
     GRF_LDS(buf, slot) for a staged value.  Returns (code, number of phases,
     largest slot count used)."""
-    seq = dfs_order(outputs)
+    seq = dfs_order(outputs, heavy_first=(order == "dfs_heavy"))
     pos = {i: k for k, i in enumerate(seq)}
     after = {}
     for o, st in zip(outputs, out_stmts):

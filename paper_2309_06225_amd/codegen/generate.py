@@ -60,7 +60,7 @@ def forward_code(shift_advec: bool):
     names = ([f"GRF_RHS({f}, {{}})" for f in indep] + ["GRF_PIVCHK({})"] * len(b["pivot_check"])
              + [f"GRF_RHS({f}, {{}})" for f in dep])
     del solve_nodes
-    code = emit(g, outs, names, input_expr, param_expr, order=os.environ.get("GRF_GEN_ORDER", "dfs"))
+    code = emit(g, outs, names, input_expr, param_expr, order="dfs")
     flops, ops = count_flops(g, b["rhs"])
     return code, flops, ops
 
@@ -95,7 +95,8 @@ def forward_code_staged(shift_advec: bool, rhs_only: bool):
 
     stmts = ([rhs_stmt(f) for f in indep] + [("GRF_PIVCHK({v})", [])] * len(b["pivot_check"])
              + [rhs_stmt(f) for f in dep])
-    return emit_staged(g, outs, stmts, _stage_key, param_expr, STAGE_SLOTS)
+    # heavier operand first: about a quarter less spilling in this kernel
+    return emit_staged(g, outs, stmts, _stage_key, param_expr, STAGE_SLOTS, order="dfs_heavy")
 
 
 def vjp_code(shift_advec: bool):

@@ -5,6 +5,7 @@
 // launches (results are bitwise identical).
 #pragma once
 #include "kernels_fwd.h"
+#include "kernels_staged.h"
 
 namespace grf {
 
@@ -22,7 +23,7 @@ struct TileEntry {
   int box;
   int tile;
 };
-struct CellEntry {
+struct CellEntry {  // 64 cells c0 .. c0 + 63 of a box (fewer at its end)
   int box;
   int pad;
   int64_t c0;
@@ -60,22 +61,25 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_deriv_batch(const BatchBoxDev* _
   }
 }
 
+// Pointwise + RK4 stage over (box, 64-cell block) entries, one wave per
+// workgroup, with the staged inputs of k_point_staged.
 template <int MODE, int SHIFTADV>
-__global__ __launch_bounds__(kPointThreads) void k_point_batch(const BatchBoxDev* __restrict__ boxes,
-                                                               const CellEntry* __restrict__ entries, int nentries,
-                                                               int stage, int parity, grf_point_params P,
-                                                               unsigned* __restrict__ status) {
+__global__ __launch_bounds__(kStagedThreads) void k_point_batch(const BatchBoxDev* __restrict__ boxes,
+                                                                const CellEntry* __restrict__ entries, int nentries,
+                                                                int stage, int parity, grf_point_params P,
+                                                                unsigned* __restrict__ status) {
+  __shared__ double lbuf0_[GRF_STAGE_SLOTS * 64];
+  __shared__ double lbuf1_[GRF_STAGE_SLOTS * 64];
   for (int g = blockIdx.x; g < nentries; g += gridDim.x) {
     const CellEntry en = entries[g];
     const BatchBoxDev B = boxes[en.box];
-    const int64_t c = en.c0 + threadIdx.x;
-    if (c >= B.bd.ncell) continue;
     const double *base, *in;
     double* out;
     stage_roles(B, stage, parity, base, in, out);
     StageCoef sc;
     sc.cnext = stage == 4 ? B.dt / 6.0 : (stage == 3 ? 1.0 * B.dt : 0.5 * B.dt);
-    point_cell<MODE, SHIFTADV>(B.bd, c, P, in, B.D, B.bd.ncell, c, base, out, B.acc, sc, status);
+    staged_wave<MODE, SHIFTADV>(B.bd, en.c0, P, in, B.D, base, out, B.acc, sc, status, (grf_lds_double*)lbuf0_,
+                                (grf_lds_double*)lbuf1_);
   }
 }
 

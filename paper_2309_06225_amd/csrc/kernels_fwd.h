@@ -206,7 +206,8 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_deriv(BoxDev b, const double* __
 // computes one plane of cells from the 7 planes around it, so each plane of the
 // field is read from memory once per column instead of once per overlapping
 // tile.  With 8 slots for a 7-plane stencil, one barrier per step suffices: the
-// slot a step loads is never one the previous step reads.
+// slot a step writes is never one the previous step reads.  The global loads of
+// the next plane are in flight while the current plane is computed.
 // Work-item order with XCDMAP: consecutive items are the 27 fields of one column
 // chunk, and the hardware's round-robin dealing of workgroups over the 8 XCDs
 // is undone so that consecutive items share an XCD, and with it the L2 that
@@ -244,20 +245,38 @@ __global__ __launch_bounds__(TX* TY) void k_deriv_zm(BoxDev b, const double* __r
   const int i = tx0 + ix, j = ty0 + iy;
   const bool inside = i < b.nx && j < b.ny;
   const int cxy = (iy + 3) * LX + (ix + 3);
-  // state plane gz (ghost-inclusive z) into its ring slot gz mod 8
-  auto load_plane = [&](int gz) {
-    double* tp = t + (gz & 7) * PL;
+  // a plane of the column (ghost-inclusive z = gz) is fetched into registers,
+  // PER values per thread, and later written to its ring slot gz mod 8; the
+  // fetch of the next plane is issued before the current plane is computed
+  constexpr int PER = (PL + NT - 1) / NT;
+  double pre[PER];
+  auto fetch_plane = [&](int gz) {
     const double* up = uf + (int64_t)gz * b.sz;
-    for (int e = threadIdx.x; e < PL; e += NT) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * NT;
       const int lx = e % LX, ly = e / LX;
       const int gx = tx0 + lx, gy = ty0 + ly;
-      if (gx < b.nx + 6 && gy < b.ny + 6) tp[e] = up[(int64_t)gy * b.sy + gx];
+      pre[q] = (e < PL && gx < b.nx + 6 && gy < b.ny + 6) ? up[(int64_t)gy * b.sy + gx] : 0.0;
     }
   };
-  for (int gz = z0; gz < z0 + 6; ++gz) load_plane(gz);
+  auto store_plane = [&](int gz) {
+    double* tp = t + (gz & 7) * PL;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * NT;
+      if (e < PL) tp[e] = pre[q];
+    }
+  };
+  for (int gz = z0; gz < z0 + 6; ++gz) {
+    fetch_plane(gz);
+    store_plane(gz);
+  }
+  fetch_plane(z0 + 6);
   for (int k = z0; k < z1; ++k) {
-    load_plane(k + 6);
+    store_plane(k + 6);
     __syncthreads();
+    if (k + 1 < z1) fetch_plane(k + 7);
     if (inside) {
       int pb[7];
 #pragma unroll

@@ -71,21 +71,15 @@ __device__ __forceinline__ void stage_one_st(int f, double rhs_f, double ko_f, d
 }
 #pragma clang fp contract(fast)
 
+// The 64 cells c0 .. c0 + 63 of box b (one wave; lbuf0 / lbuf1: this wave's
+// two LDS buffers of GRF_STAGE_SLOTS items).
 template <int MODE, int SHIFTADV>
-__global__ __launch_bounds__(kStagedThreads) void k_point_staged(BoxDev b, grf_point_params P,
-                                                                 const double* __restrict__ us,
-                                                                 const double* __restrict__ D,
-                                                                 const double* __restrict__ u0,
-                                                                 double* __restrict__ out, double* __restrict__ acc,
-                                                                 StageCoef sc, unsigned* __restrict__ status) {
-  __shared__ double lbuf0_[GRF_STAGE_SLOTS * 64];
-  __shared__ double lbuf1_[GRF_STAGE_SLOTS * 64];
-  // the buffers as LDS-typed pointers, so that slot addresses are plain LDS
-  // offsets (no generic-pointer conversion at each copy)
-  grf_lds_double* const lbuf0 = (grf_lds_double*)lbuf0_;
-  grf_lds_double* const lbuf1 = (grf_lds_double*)lbuf1_;
+__device__ __forceinline__ void staged_wave(const BoxDev& b, int64_t c0, const grf_point_params& P,
+                                            const double* __restrict__ us, const double* __restrict__ D,
+                                            const double* __restrict__ u0, double* __restrict__ out,
+                                            double* __restrict__ acc, StageCoef sc, unsigned* __restrict__ status,
+                                            grf_lds_double* const lbuf0, grf_lds_double* const lbuf1) {
   const int lane = threadIdx.x;
-  const int64_t c0 = (int64_t)blockIdx.x * kStagedThreads;
   const int64_t last = b.ncell - 1;
   // lanes past the end of the box redo the last cell: same inputs, same
   // results, so their stores write the bits that the last cell's lane writes
@@ -122,11 +116,13 @@ __global__ __launch_bounds__(kStagedThreads) void k_point_staged(BoxDev b, grf_p
     __builtin_amdgcn_sched_barrier(0);          \
   } while (0)
 #define GRF_P(n) P.n
-#define GRF_RHS_ST(f, v, bb, sko, su0, sacc)                                                                   \
+#define GRF_RHS_ST(f, v, bb, sko, su0, sacc) \
   stage_one_st<MODE>(f, (v), GRF_LDS(bb, sko), GRF_LDS(bb, su0), GRF_LDS(bb, sacc), b, c, s, out, acc, sc, flags)
 #define GRF_PIVCHK(v) bad |= !(fabs(v) <= 1e12)
 #define GRF_SHIFT_ADVEC (SHIFTADV != 0)
 #define GRF_STAGE_RHS_ONLY (MODE == 0)
+  // nothing of an earlier call may still read the buffers or write memory
+  GRF_PHASE_SYNC();
 #include "gen/gen_rhs_staged.inc"
 #undef GRF_STAGE_RHS_ONLY
 #undef GRF_SHIFT_ADVEC
@@ -144,6 +140,21 @@ __global__ __launch_bounds__(kStagedThreads) void k_point_staged(BoxDev b, grf_p
   if (bad) flags |= 2u;
   if (!(us[(int64_t)F_CHI * b.fs + s] > 0.0) || !(us[(int64_t)F_LAPSE * b.fs + s] > 0.0)) flags |= 4u;
   if (flags) atomicOr(status, flags);
+}
+
+template <int MODE, int SHIFTADV>
+__global__ __launch_bounds__(kStagedThreads) void k_point_staged(BoxDev b, grf_point_params P,
+                                                                 const double* __restrict__ us,
+                                                                 const double* __restrict__ D,
+                                                                 const double* __restrict__ u0,
+                                                                 double* __restrict__ out, double* __restrict__ acc,
+                                                                 StageCoef sc, unsigned* __restrict__ status) {
+  __shared__ double lbuf0_[GRF_STAGE_SLOTS * 64];
+  __shared__ double lbuf1_[GRF_STAGE_SLOTS * 64];
+  // the buffers as LDS-typed pointers, so that slot addresses are plain LDS
+  // offsets (no generic-pointer conversion at each copy)
+  staged_wave<MODE, SHIFTADV>(b, (int64_t)blockIdx.x * kStagedThreads, P, us, D, u0, out, acc, sc, status,
+                              (grf_lds_double*)lbuf0_, (grf_lds_double*)lbuf1_);
 }
 
 }  // namespace grf

@@ -575,7 +575,7 @@ grf_status grf_batch_create(const grf_params* p, const grf_box* boxes, int nboxe
     B->host.push_back(d);
     const auto it = g_tile_cache.find(std::make_tuple(boxes[b].nx, boxes[b].ny, boxes[b].nz));
     if (it != g_tile_cache.end()) B->variant[b] = it->second;
-    for (int64_t c0 = 0; c0 < (int64_t)n; c0 += kPointThreads) cells.push_back(CellEntry{b, 0, c0});
+    for (int64_t c0 = 0; c0 < (int64_t)n; c0 += kStagedThreads) cells.push_back(CellEntry{b, 0, c0});
   }
   auto cleanup = [&](grf_status code) {
     grf_batch_destroy(B);
@@ -632,7 +632,7 @@ grf_status grf_batch_step_perbox(grf_batch* B, hipStream_t stream) {
       GRF_HIP_CHECK(launch_deriv(B->variant[b], d.bd, in, d.D, B->params.ko_sigma, sa, nullptr, stream));
       prof_mark(0, stream);
       prof_mark(1, stream);
-      GRF_HIP_CHECK(launch_point(mode, sa, d.bd, pp, in, d.D, b0, o, d.acc, sc, B->status, stream));
+      GRF_HIP_CHECK(launch_staged(mode, sa, d.bd, pp, in, d.D, b0, o, d.acc, sc, B->status, stream));
       prof_mark(1, stream);
     }
   }

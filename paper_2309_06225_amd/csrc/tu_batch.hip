@@ -10,10 +10,10 @@ hipError_t launch_point_batch_m<GRF_TU_MODE>(int sa, int grid, const BatchBoxDev
                                              int ncells, int stage, int parity, const grf_point_params& pp,
                                              unsigned* status, hipStream_t st) {
   if (sa)
-    hipLaunchKernelGGL((k_point_batch<GRF_TU_MODE, 1>), dim3(grid), dim3(kPointThreads), 0, st, boxes, cells, ncells,
+    hipLaunchKernelGGL((k_point_batch<GRF_TU_MODE, 1>), dim3(grid), dim3(kStagedThreads), 0, st, boxes, cells, ncells,
                        stage, parity, pp, status);
   else
-    hipLaunchKernelGGL((k_point_batch<GRF_TU_MODE, 0>), dim3(grid), dim3(kPointThreads), 0, st, boxes, cells, ncells,
+    hipLaunchKernelGGL((k_point_batch<GRF_TU_MODE, 0>), dim3(grid), dim3(kStagedThreads), 0, st, boxes, cells, ncells,
                        stage, parity, pp, status);
   return hipGetLastError();
 }
@@ -21,8 +21,8 @@ hipError_t launch_point_batch_m<GRF_TU_MODE>(int sa, int grid, const BatchBoxDev
 template <>
 int grid_point_batch_m<GRF_TU_MODE>(int sa, int64_t work) {
   int per = 1;
-  hipError_t e = sa ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_point_batch<GRF_TU_MODE, 1>, kPointThreads, 0)
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_point_batch<GRF_TU_MODE, 0>, kPointThreads, 0);
+  hipError_t e = sa ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_point_batch<GRF_TU_MODE, 1>, kStagedThreads, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_point_batch<GRF_TU_MODE, 0>, kStagedThreads, 0);
   if (e != hipSuccess) per = 1;
   return persistent_grid_from(per, work);
 }
