@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the adjoint and batched measurements")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only run the adjoint/forward measurement (for kernel traces of the adjoint)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the batched vs per-box measurement (for kernel traces of the batch)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run one plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -155,6 +157,9 @@ def main():
 
     if args.adjoint_only:
         print(json.dumps({"adjoint_forward_ratio": adjoint_ratio(torch, G, I)}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": batched_speedup(torch, G, I)}), flush=True)
         return
 
     n = args.n

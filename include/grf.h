@@ -159,12 +159,13 @@ int64_t grf_flops_per_cell(int which /* 0 rhs, 1 rhs with shift advection, 2 vjp
 
 /* ---- Batched boxes (uneven sizes and refinement levels, frozen ghosts).
  * One RK4 step of the batch is four stages; each stage is one persistent
- * stencil launch per tile shape in use and one persistent pointwise launch,
- * covering every box (work lists of (box, tile) and (box, 128-cell block)
- * entries, fixed assignment to workgroups, no atomics).  Per cell the device
- * code is the one of grf_rk4_stage, so results are bitwise identical to
- * per-box launches (grf_batch_step_perbox runs that reference form on the same
- * buffers).
+ * stencil launch per stencil variant in use and one persistent pointwise
+ * launch, covering every box (work lists of (box, tile or column chunk) and
+ * (box, 64-cell wave) entries, fixed assignment to workgroups, no atomics).
+ * Per cell the device code is the one of grf_rk4_stage, so results are
+ * bitwise identical to per-box launches (grf_batch_step_perbox runs that
+ * reference form on the same buffers).  Boxes use stencil variant 8 (the
+ * z-marching 16x16x32 form) until grf_batch_autotune chooses.
  *   u[b]      state of box b (device, caller-owned); after an even number of
  *             steps the current state is back in u[b], after an odd number it
  *             is in the batch's second buffer (grf_batch_state gives it);
@@ -183,9 +184,10 @@ grf_status grf_batch_step_perbox(grf_batch* batch, hipStream_t stream);
 /* Captures two batched RK4 steps (so that buffer roles are the same before
  * and after every replay) on a non-null stream into an executable graph. */
 grf_status grf_batch_capture(grf_batch* batch, hipStream_t stream, hipGraphExec_t* exec);
-/* Times every stencil tile shape on one box of each box-shape class and keeps
- * the fastest (ties: lower variant index); choices are cached per shape class
- * for the life of the process and reused by later batches. */
+/* Times the stencil variants the batch can run (tiled 0..4, z-marching 8; see
+ * grf_set_tile_variant) on one box of each box-shape class and keeps the
+ * fastest (ties: lower variant index); choices are cached per shape class for
+ * the life of the process and reused by later batches. */
 grf_status grf_batch_autotune(grf_batch* batch, hipStream_t stream);
 grf_status grf_batch_state(const grf_batch* batch, int box, double** current);
 grf_status grf_batch_tile_variant(const grf_batch* batch, int box, int* variant);
@@ -199,7 +201,7 @@ grf_status grf_graph_destroy(hipGraphExec_t exec);
  * field of an LDS tile plus halo): 0: 16x8x4, 1: 32x4x4, 2: 8x8x8, 3: 16x16x2,
  * 4: 64x4x2.  z-marching (a workgroup per field of an x-y column of cells
  * walking a chunk of z-planes through a ring of LDS planes), column x chunk:
- * 5: 16x8x32, 6: 32x8x32, 7: 32x4x32, 8: 16x16x32 (default), 9: 32x8x16,
+ * 5: 16x8x32, 6: 32x8x32 (default), 7: 32x4x32, 8: 16x16x32, 9: 32x8x16,
  * 10: 64x4x32, 11: 32x8x32 with fields as the slowest work index, 12: 32x8x64.
  * Results do not depend on it.  GRF_EINVAL outside 0..12. */
 grf_status grf_set_tile_variant(int variant);

@@ -61,6 +61,25 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_deriv_batch(const BatchBoxDev* _
   }
 }
 
+// z-marching stencil stage over (box, column chunk) entries, the 27 fields of
+// an entry consecutive.
+template <int TX, int TY, int ZC>
+__global__ __launch_bounds__(TX* TY) void k_deriv_batch_zm(const BatchBoxDev* __restrict__ boxes,
+                                                           const TileEntry* __restrict__ entries, int nentries,
+                                                           int stage, int parity, double ko_sigma, int shift_adv) {
+  __shared__ double t[8 * (TX + 6) * (TY + 6)];
+  const int64_t total = (int64_t)nentries * NF;
+  for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    const int e = (int)(g / NF), f = (int)(g % NF);
+    const TileEntry en = entries[e];
+    const BatchBoxDev B = boxes[en.box];
+    const double *base, *in;
+    double* out;
+    stage_roles(B, stage, parity, base, in, out);
+    zm_column<TX, TY, ZC>(B.bd, en.tile, f, in, B.D, ko_sigma, shift_adv, nullptr, t);
+  }
+}
+
 // Pointwise + RK4 stage over (box, 64-cell block) entries, one wave per
 // workgroup, with the staged inputs of k_point_staged.
 template <int MODE, int SHIFTADV>

@@ -218,23 +218,20 @@ __device__ __forceinline__ int xcd_item(int w, int nblocks) {
   return x * per + (x < rem ? x : rem) + s;
 }
 
-template <int TX, int TY, int ZC, bool XCDMAP>
-__global__ __launch_bounds__(TX* TY) void k_deriv_zm(BoxDev b, const double* __restrict__ u,
-                                                      double* __restrict__ D, double ko_sigma, int shift_adv,
-                                                      double* __restrict__ UP) {
+// Number of (column, z-chunk) items of a box for the z-marching form.
+template <int TX, int TY, int ZC>
+__host__ __device__ inline int zm_items(const BoxDev& b) {
+  return ((b.nx + TX - 1) / TX) * ((b.ny + TY - 1) / TY) * ((b.nz + ZC - 1) / ZC);
+}
+
+// One field of one (column, z-chunk) item: item = column x + ntx (column y +
+// nty chunk).  t: 8 * (TX+6)(TY+6) doubles of LDS.
+template <int TX, int TY, int ZC>
+__device__ __forceinline__ void zm_column(const BoxDev& b, int item, int f, const double* __restrict__ u,
+                                          double* __restrict__ D, double ko_sigma, int shift_adv,
+                                          double* __restrict__ UP, double* t) {
   constexpr int LX = TX + 6, LY = TY + 6, PL = LX * LY, NT = TX * TY;
-  __shared__ double t[8 * PL];
   const int ntx = (b.nx + TX - 1) / TX, nty = (b.ny + TY - 1) / TY;
-  int item = blockIdx.x, f;
-  if (XCDMAP) {
-    item = xcd_item(item, (int)gridDim.x);
-    f = item % NF;
-    item /= NF;
-  } else {  // field slowest, as in the tiled form
-    const int per_field = (int)gridDim.x / NF;
-    f = item / per_field;
-    item %= per_field;
-  }
   const int tx0 = (item % ntx) * TX;
   item /= ntx;
   const int ty0 = (item % nty) * TY;
@@ -268,6 +265,7 @@ __global__ __launch_bounds__(TX* TY) void k_deriv_zm(BoxDev b, const double* __r
       if (e < PL) tp[e] = pre[q];
     }
   };
+  __syncthreads();  // an earlier item of this workgroup is done with t
   for (int gz = z0; gz < z0 + 6; ++gz) {
     fetch_plane(gz);
     store_plane(gz);
@@ -285,6 +283,24 @@ __global__ __launch_bounds__(TX* TY) void k_deriv_zm(BoxDev b, const double* __r
       compute_cell<LX>(b, i, j, k, f, u, D + cell, b.ncell, cell, ko_sigma, shift_adv, UP, t, pb, cxy);
     }
   }
+}
+
+template <int TX, int TY, int ZC, bool XCDMAP>
+__global__ __launch_bounds__(TX* TY) void k_deriv_zm(BoxDev b, const double* __restrict__ u,
+                                                      double* __restrict__ D, double ko_sigma, int shift_adv,
+                                                      double* __restrict__ UP) {
+  __shared__ double t[8 * (TX + 6) * (TY + 6)];
+  int item = blockIdx.x, f;
+  if (XCDMAP) {
+    item = xcd_item(item, (int)gridDim.x);
+    f = item % NF;
+    item /= NF;
+  } else {  // field slowest, as in the tiled form
+    const int per_field = (int)gridDim.x / NF;
+    f = item / per_field;
+    item %= per_field;
+  }
+  zm_column<TX, TY, ZC>(b, item, f, u, D, ko_sigma, shift_adv, UP, t);
 }
 
 // ---------------------------------------------------------------------------

@@ -23,6 +23,7 @@ extern const int kTiles[kTileVariants][3];
 hipError_t launch_deriv(int variant, const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
                         hipStream_t st);
 int tiles_of_variant(int variant, const BoxDev& bd);
+// batched stencil stage: tiled variants 0..4 and the z-marching variant 8
 hipError_t launch_deriv_batch(int variant, int grid, const BatchBoxDev* boxes, const TileEntry* tiles, int ntiles,
                               int stage, int parity, double sigma, int sa, hipStream_t st);
 int grid_deriv_batch(int variant, int64_t work);

@@ -134,8 +134,10 @@ size_t deriv_bytes(const grf_box* b) {
   return whole > fused ? whole : fused;
 }
 
-constexpr int kTileVariantsMax = 5;
-int g_tile_variant = 8;  // z-marching 16x16 columns, 32-plane chunks
+constexpr int kTileVariantsMax = kDerivVariants;
+// stencil variants the batched form can run (tiled shapes, z-marching 16x16x32)
+constexpr int kBatchVariants[] = {0, 1, 2, 3, 4, 8};
+int g_tile_variant = 6;  // z-marching 32x8 columns, 32-plane chunks
 
 // Optional per-kernel timing with HIP events recorded on the launch stream
 // around each stencil-stage and pointwise launch (enabled by grf_prof_begin).
@@ -489,7 +491,7 @@ grf_status batch_upload_tiles(grf_batch* B) {
     const int nt = tiles_of_variant(v, B->host[b].bd);
     for (int t = 0; t < nt; ++t) lists[v].push_back(TileEntry{(int)b, t});
   }
-  for (int v = 0; v < kTileVariants; ++v) {
+  for (int v : kBatchVariants) {
     if (B->tiles[v]) GRF_HIP_CHECK(hipFree(B->tiles[v]));
     B->tiles[v] = nullptr;
     B->ntiles[v] = (int)lists[v].size();
@@ -502,7 +504,7 @@ grf_status batch_upload_tiles(grf_batch* B) {
 }
 
 grf_status batch_stage(grf_batch* B, int stage, hipStream_t st) {
-  for (int v = 0; v < kTileVariants; ++v) {
+  for (int v : kBatchVariants) {
     if (!B->ntiles[v]) continue;
     prof_mark(0, st);
     GRF_HIP_CHECK(launch_deriv_batch(v, B->grid_deriv[v], B->dev, B->tiles[v], B->ntiles[v], stage, B->parity,
@@ -551,7 +553,7 @@ grf_status grf_batch_create(const grf_params* p, const grf_box* boxes, int nboxe
   grf_batch* B = new grf_batch();
   B->params = *p;
   B->boxes.assign(boxes, boxes + nboxes);
-  B->variant.assign(nboxes, 0);
+  B->variant.assign(nboxes, 8);  // z-marching until autotuned
   char* sp = (char*)scratch;
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   std::vector<CellEntry> cells;
@@ -671,7 +673,7 @@ grf_status grf_batch_autotune(grf_batch* B, hipStream_t stream) {
     const BatchBoxDev& d = B->host[kv.second];
     int best = 0;
     float best_t = 1e30f;
-    for (int v = 0; v < kTileVariants; ++v) {
+    for (int v : kBatchVariants) {
       float tmin = 1e30f;
       for (int rep_i = 0; rep_i < 4; ++rep_i) {
         GRF_HIP_CHECK(hipEventRecord(e0, stream));

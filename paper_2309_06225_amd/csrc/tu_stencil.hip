@@ -154,6 +154,7 @@ int tiles_of(const BoxDev& b) {
 
 int tiles_of_variant(int v, const BoxDev& b) {
   switch (v) {
+    case 8: return zm_items<16, 16, 32>(b);
     case 1: return tiles_of<32, 4, 4>(b);
     case 2: return tiles_of<8, 8, 8>(b);
     case 3: return tiles_of<16, 16, 2>(b);
@@ -218,8 +219,16 @@ int grid_deriv_batch_t(int64_t work) {
   return persistent_grid_from(per, work);
 }
 
+int grid_deriv_batch_zm(int64_t work) {
+  int per = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_deriv_batch_zm<16, 16, 32>, 256, 0) != hipSuccess)
+    per = 1;
+  return persistent_grid_from(per, work);
+}
+
 int grid_deriv_batch(int variant, int64_t work) {
   switch (variant) {
+    case 8: return grid_deriv_batch_zm(work);
     case 1: return grid_deriv_batch_t<32, 4, 4>(work);
     case 2: return grid_deriv_batch_t<8, 8, 8>(work);
     case 3: return grid_deriv_batch_t<16, 16, 2>(work);
@@ -239,6 +248,10 @@ hipError_t launch_deriv_batch_t(int grid, const BatchBoxDev* boxes, const TileEn
 hipError_t launch_deriv_batch(int variant, int grid, const BatchBoxDev* boxes, const TileEntry* tiles, int ntiles,
                               int stage, int parity, double sigma, int sa, hipStream_t st) {
   switch (variant) {
+    case 8:
+      hipLaunchKernelGGL((k_deriv_batch_zm<16, 16, 32>), dim3(grid), dim3(256), 0, st, boxes, tiles, ntiles, stage,
+                         parity, sigma, sa);
+      return hipGetLastError();
     case 1: return launch_deriv_batch_t<32, 4, 4>(grid, boxes, tiles, ntiles, stage, parity, sigma, sa, st);
     case 2: return launch_deriv_batch_t<8, 8, 8>(grid, boxes, tiles, ntiles, stage, parity, sigma, sa, st);
     case 3: return launch_deriv_batch_t<16, 16, 2>(grid, boxes, tiles, ntiles, stage, parity, sigma, sa, st);

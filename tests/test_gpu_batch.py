@@ -100,7 +100,7 @@ def test_autotune_is_cached_and_result_independent():
     A = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
     A.autotune()
     v1 = [A.tile_variant(b) for b in range(len(boxes))]
-    assert all(0 <= v < 5 for v in v1)
+    assert all(v in (0, 1, 2, 3, 4, 8) for v in v1)
     B = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
     assert [B.tile_variant(b) for b in range(len(boxes))] == v1  # cached per shape class
     C = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
