@@ -116,10 +116,19 @@ def batched_speedup(torch, G, I, steps=4):
         per_box = timed(lambda: B.step_perbox(st), steps)
         graph = timed(lambda: B.replay(g, st), steps // 2) / 2
         code, bits = B.status(st)
+        chosen = [B.tile_variant(b) for b in range(len(spec))]
+        # per-box launches again with every box on the tiled 16x8x4 stencil,
+        # the per-box form's own best uniform choice on these boxes
+        for b in range(len(spec)):
+            B.set_tile_variant(b, 0)
+        per_box_tiled = timed(lambda: B.step_perbox(st), steps)
         B.close()
     ncell = sum(int(b["dims"][0] * b["dims"][1] * b["dims"][2]) for b in spec)
-    return {"per_box_ms_per_step": per_box, "batched_graph_ms_per_step": graph, "speedup": per_box / graph,
-            "cells": ncell, "boxes": len(spec), "status": code}
+    best_per_box = min(per_box, per_box_tiled)
+    return {"per_box_ms_per_step": per_box, "per_box_tiled_ms_per_step": per_box_tiled,
+            "batched_graph_ms_per_step": graph, "speedup": per_box / graph,
+            "speedup_vs_best_per_box": best_per_box / graph, "batched_cell_updates_per_s": ncell / (graph * 1e-3),
+            "stencil_variants": sorted(set(chosen)), "cells": ncell, "boxes": len(spec), "status": code}
 
 
 def main():

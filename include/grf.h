@@ -184,13 +184,22 @@ grf_status grf_batch_step_perbox(grf_batch* batch, hipStream_t stream);
 /* Captures two batched RK4 steps (so that buffer roles are the same before
  * and after every replay) on a non-null stream into an executable graph. */
 grf_status grf_batch_capture(grf_batch* batch, hipStream_t stream, hipGraphExec_t* exec);
-/* Times the stencil variants the batch can run (tiled 0..4, z-marching 8; see
- * grf_set_tile_variant) on one box of each box-shape class and keeps the
- * fastest (ties: lower variant index); choices are cached per shape class for
- * the life of the process and reused by later batches. */
+/* Chooses a stencil variant per box-shape class among those the batch can
+ * run (tiled 0..4, z-marching 8; see grf_set_tile_variant): each variant is
+ * timed on one box of each class alone, giving a per-class mix; then the mix
+ * and each variant used for all boxes are timed as the batched stencil stage
+ * runs them, and the fastest assignment is kept (ties: the earlier candidate).
+ * The stage's derivative records are overwritten, nothing else.  Choices are
+ * cached per shape class for the life of the process; classes already cached
+ * keep their variant in later batches. */
 grf_status grf_batch_autotune(grf_batch* batch, hipStream_t stream);
 grf_status grf_batch_state(const grf_batch* batch, int box, double** current);
 grf_status grf_batch_tile_variant(const grf_batch* batch, int box, int* variant);
+/* Sets the stencil variant of one box (0..4 or 8; GRF_EINVAL otherwise) and
+ * rebuilds the work lists (device allocations owned by the batch).  Results
+ * do not depend on it.  Graphs captured earlier keep the old work lists:
+ * capture again after changing variants. */
+grf_status grf_batch_set_tile_variant(grf_batch* batch, int box, int variant);
 grf_status grf_batch_status_fetch(const grf_batch* batch, hipStream_t stream, uint32_t* bits);
 void grf_batch_destroy(grf_batch* batch);
 /* Launch / destroy an executable graph made by grf_batch_capture. */

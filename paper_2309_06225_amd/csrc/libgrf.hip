@@ -660,41 +660,92 @@ grf_status grf_batch_capture(grf_batch* B, hipStream_t stream, hipGraphExec_t* e
 
 grf_status grf_batch_autotune(grf_batch* B, hipStream_t stream) {
   if (!B) return fail(GRF_EINVAL, "batch is null");
-  // one representative box per shape class; each tile variant timed on it
-  std::map<std::tuple<int, int, int>, int> rep;
-  for (size_t b = 0; b < B->boxes.size(); ++b)
-    rep.emplace(std::make_tuple(B->boxes[b].nx, B->boxes[b].ny, B->boxes[b].nz), (int)b);
-  hipEvent_t e0, e1;
-  GRF_HIP_CHECK(hipEventCreate(&e0));
-  GRF_HIP_CHECK(hipEventCreate(&e1));
-  const int sa = B->params.shift_advec != 0.0;
-  for (auto& kv : rep) {
-    if (g_tile_cache.count(kv.first)) continue;
-    const BatchBoxDev& d = B->host[kv.second];
-    int best = 0;
-    float best_t = 1e30f;
-    for (int v : kBatchVariants) {
-      float tmin = 1e30f;
+  using Shape = std::tuple<int, int, int>;
+  auto shape_of = [&](size_t b) { return std::make_tuple(B->boxes[b].nx, B->boxes[b].ny, B->boxes[b].nz); };
+  bool all_cached = true;
+  for (size_t b = 0; b < B->boxes.size(); ++b) all_cached = all_cached && g_tile_cache.count(shape_of(b));
+  if (!all_cached) {
+    hipEvent_t e0, e1;
+    GRF_HIP_CHECK(hipEventCreate(&e0));
+    GRF_HIP_CHECK(hipEventCreate(&e1));
+    const int sa = B->params.shift_advec != 0.0;
+    auto timed = [&](auto&& launch, float& best) -> grf_status {
+      best = 1e30f;
       for (int rep_i = 0; rep_i < 4; ++rep_i) {
         GRF_HIP_CHECK(hipEventRecord(e0, stream));
-        GRF_HIP_CHECK(launch_deriv(v, d.bd, d.u, d.D, B->params.ko_sigma, sa, nullptr, stream));
+        grf_status st = launch();
+        if (st != GRF_OK) return st;
         GRF_HIP_CHECK(hipEventRecord(e1, stream));
         GRF_HIP_CHECK(hipEventSynchronize(e1));
         float t = 0.f;
         GRF_HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
-        if (rep_i > 0 && t < tmin) tmin = t;  // first launch warms up
+        if (rep_i > 0 && t < best) best = t;  // the first launch warms up
       }
-      if (tmin < best_t) {  // strict: ties keep the lower variant index
-        best_t = tmin;
-        best = v;
+      return GRF_OK;
+    };
+    // (1) per shape class: the variant fastest on one box of the class alone
+    std::map<Shape, int> rep, mix;
+    for (size_t b = 0; b < B->boxes.size(); ++b) rep.emplace(shape_of(b), (int)b);
+    for (auto& kv : rep) {
+      const BatchBoxDev& d = B->host[kv.second];
+      int best = kBatchVariants[0];
+      float best_t = 1e30f;
+      for (int v : kBatchVariants) {
+        float t;
+        grf_status st = timed(
+            [&]() -> grf_status {
+              GRF_HIP_CHECK(launch_deriv(v, d.bd, d.u, d.D, B->params.ko_sigma, sa, nullptr, stream));
+              return GRF_OK;
+            },
+            t);
+        if (st != GRF_OK) return st;
+        if (t < best_t) {  // strict: ties keep the earlier candidate
+          best_t = t;
+          best = v;
+        }
+      }
+      mix[kv.first] = best;
+    }
+    // (2) whole assignments timed as the batched stencil stage runs them: the
+    // per-class mix, then every variant for all boxes; boxes of one class run
+    // concurrently with all others in one persistent launch, so a variant that
+    // loses on a box alone can win in the batch
+    std::vector<std::vector<int>> cands;
+    {
+      std::vector<int> m(B->boxes.size());
+      for (size_t b = 0; b < B->boxes.size(); ++b) m[b] = mix[shape_of(b)];
+      cands.push_back(m);
+    }
+    for (int v : kBatchVariants) cands.push_back(std::vector<int>(B->boxes.size(), v));
+    size_t best_c = 0;
+    float best_t = 1e30f;
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+      B->variant = cands[ci];
+      grf_status st = batch_upload_tiles(B);
+      if (st != GRF_OK) return st;
+      float t;
+      st = timed(
+          [&]() -> grf_status {
+            for (int v : kBatchVariants) {
+              if (!B->ntiles[v]) continue;
+              GRF_HIP_CHECK(launch_deriv_batch(v, B->grid_deriv[v], B->dev, B->tiles[v], B->ntiles[v], 1, B->parity,
+                                               B->params.ko_sigma, sa, stream));
+            }
+            return GRF_OK;
+          },
+          t);
+      if (st != GRF_OK) return st;
+      if (t < best_t) {
+        best_t = t;
+        best_c = ci;
       }
     }
-    g_tile_cache[kv.first] = best;
+    for (size_t b = 0; b < B->boxes.size(); ++b)
+      if (!g_tile_cache.count(shape_of(b))) g_tile_cache[shape_of(b)] = cands[best_c][b];
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  for (size_t b = 0; b < B->boxes.size(); ++b)
-    B->variant[b] = g_tile_cache[std::make_tuple(B->boxes[b].nx, B->boxes[b].ny, B->boxes[b].nz)];
+  for (size_t b = 0; b < B->boxes.size(); ++b) B->variant[b] = g_tile_cache[shape_of(b)];
   return batch_upload_tiles(B);
 }
 
@@ -708,6 +759,15 @@ grf_status grf_batch_tile_variant(const grf_batch* B, int box, int* variant) {
   if (!B || !variant || box < 0 || box >= (int)B->host.size()) return fail(GRF_EINVAL, "bad argument");
   *variant = B->variant[box];
   return GRF_OK;
+}
+
+grf_status grf_batch_set_tile_variant(grf_batch* B, int box, int variant) {
+  if (!B || box < 0 || box >= (int)B->host.size()) return fail(GRF_EINVAL, "bad argument");
+  bool ok = false;
+  for (int v : kBatchVariants) ok = ok || v == variant;
+  if (!ok) return fail(GRF_EINVAL, "variant %d cannot run batched", variant);
+  B->variant[box] = variant;
+  return batch_upload_tiles(B);
 }
 
 grf_status grf_graph_launch(hipGraphExec_t exec, hipStream_t stream) {

@@ -81,6 +81,7 @@ def lib():
         L.grf_batch_capture.argtypes = [_vp, _vp, ctypes.POINTER(_vp)]
         L.grf_batch_state.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_vp)]
         L.grf_batch_tile_variant.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.grf_batch_set_tile_variant.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
         L.grf_batch_status_fetch.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_uint32)]
         L.grf_batch_destroy.argtypes = [_vp]
         L.grf_batch_destroy.restype = None
@@ -99,6 +100,7 @@ def lib():
                      "grf_status_clear", "grf_set_tile_variant", "grf_set_stage_path", "grf_prof_begin", "grf_prof_end",
                      "grf_rk4_step_vjp", "grf_enforce", "grf_batch_create", "grf_batch_step", "grf_batch_step_perbox",
                      "grf_batch_autotune", "grf_batch_capture", "grf_batch_state", "grf_batch_tile_variant",
+                     "grf_batch_set_tile_variant",
                      "grf_batch_status_fetch", "grf_graph_launch", "grf_graph_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -303,6 +305,9 @@ class Batch:
         v = ctypes.c_int(0)
         _check(lib().grf_batch_tile_variant(self.h, int(b), ctypes.byref(v)))
         return v.value
+
+    def set_tile_variant(self, b, v):
+        _check(lib().grf_batch_set_tile_variant(self.h, int(b), int(v)))
 
     def capture(self, stream):
         """Executable graph of two batched steps, captured on `stream` (non-default)."""

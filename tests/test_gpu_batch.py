@@ -57,6 +57,27 @@ def test_batched_equals_per_box_bitwise(shift_advec):
     B.close()
 
 
+def test_mixed_stencil_variants_bitwise():
+    """Boxes of one batch on different stencil variants (tiled and z-marching,
+    one launch per variant per stage) against per-box launches on the default
+    variants; a variant the batched form cannot run is rejected."""
+    p, boxes, states, dts = _make(SMALL)
+    A = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
+    B = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
+    for b, v in enumerate((0, 8, 2, 4)):
+        A.set_tile_variant(b, v)
+        assert A.tile_variant(b) == v
+    with pytest.raises(G.GrfError):
+        A.set_tile_variant(0, 6)
+    for _ in range(2):
+        A.step()
+        B.step_perbox()
+    for b in range(len(boxes)):
+        assert torch.equal(A.state(b), B.state(b)), b
+    A.close()
+    B.close()
+
+
 def test_batched_matches_oracle():
     print("case: batch vs oracle, 2 steps", flush=True)
     p, boxes, states, dts = _make(SMALL[:3])
