@@ -89,6 +89,29 @@ def adjoint_ratio(torch, G, I):
             "dJ_dlambda_gb": float(theta.grad[0]), "dJ_dg2": float(theta.grad[1])}
 
 
+def large_box(torch, G, I, steps=3):
+    """256^3 two-puncture box, dx = M/16, lambda_gb = 0.2, g2 = 0.02: forward
+    cell-updates/s of full RK4 steps (one warm-up step)."""
+    n, dx = 256, 1.0 / 16.0
+    p = I.default_params(lambda_gb=0.2, g2=0.02)
+    u = torch.from_numpy(I.two_punctures(n, dx)).to("cuda")
+    st = G.Stepper(G.make_params(p), G.box_of(u, dx, G.BC_FROZEN), u, 0.25 * dx)
+    st.step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        st.step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    code, _ = st.status()
+    del st, u
+    torch.cuda.empty_cache()
+    return {"workload": "two_punctures_256", "cells": n ** 3, "ms_per_step": ms,
+            "cell_updates_per_s": n ** 3 / (ms * 1e-3), "steps": steps, "status": code}
+
+
 def batched_speedup(torch, G, I, steps=4):
     """96 uneven boxes (levels 0-5): one-launch-per-box RK4 steps vs the batched
     persistent form replayed from a hipGraph (two steps per replay)."""
@@ -239,6 +262,7 @@ def main():
         torch.cuda.empty_cache()
         out["adjoint_forward_ratio"] = adjoint_ratio(torch, G, I)
         out["batched"] = batched_speedup(torch, G, I)
+        out["large_box"] = large_box(torch, G, I)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(params, u_host, dx, dt)
     print(json.dumps(out), flush=True)

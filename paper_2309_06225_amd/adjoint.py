@@ -22,7 +22,6 @@ class Trajectory:
             raise ValueError("the trajectory adjoint is implemented for frozen ghosts")
         self.pdict, self.box, self.dt, self.nsteps = dict(params), box, float(dt), int(nsteps)
         self.every = max(1, int(every))
-        self._ws = None
         self._vws = None
         self._pool = None     # segment buffers: every x (start, u2, u3, u4) + output
         self._fwd = None      # forward ping-pong buffers
@@ -31,15 +30,17 @@ class Trajectory:
     def _params(self, theta):
         return G.make_params(self.pdict, lambda_gb=float(theta[0]), g2=float(theta[1]))
 
-    def _ws_fwd(self, dev):
-        if self._ws is None:
-            self._ws = G.alloc_workspace(G.workspace_bytes(self.box), dev)
-        return self._ws
-
     def _ws_vjp(self, dev):
+        # one workspace for the forward stages and the step adjoint: both start
+        # with the status word and the derivative record and run one after the
+        # other on one stream
         if self._vws is None:
-            self._vws = G.alloc_workspace(G.step_vjp_workspace_bytes(self.box), dev)
+            nbytes = max(G.step_vjp_workspace_bytes(self.box), G.workspace_bytes(self.box))
+            self._vws = G.alloc_workspace(nbytes, dev)
         return self._vws
+
+    def _ws_fwd(self, dev):
+        return self._ws_vjp(dev)
 
     def _accbuf(self, dev):
         if self._acc is None:

@@ -287,10 +287,9 @@ hipError_t launch_status_clear(unsigned* s, hipStream_t st) {
 
 hipError_t launch_vjp_transpose(const BoxDev& bd, const double* u, const double* w, const double* Dbar, double sigma,
                                 int sa, double* ubar, hipStream_t st) {
-  constexpr int TX = 16, TY = 8, TZ = 4;
-  const int ntiles = ((bd.nx + 6 + TX - 1) / TX) * ((bd.ny + 6 + TY - 1) / TY) * ((bd.nz + 6 + TZ - 1) / TZ);
-  hipLaunchKernelGGL((k_vjp_transpose<TX, TY, TZ>), dim3(ntiles, NF), dim3(TX * TY * TZ), 0, st, bd, u, w, Dbar, sigma,
-                     sa, ubar);
+  const int64_t n = (int64_t)(bd.nx + 6) * (bd.ny + 6) * (bd.nz + 6);
+  hipLaunchKernelGGL(k_vjp_gather<kGatherThreads>, dim3((unsigned)((n + kGatherThreads - 1) / kGatherThreads), NF),
+                     dim3(kGatherThreads), 0, st, bd, u, w, Dbar, sigma, sa, ubar);
   return hipGetLastError();
 }
 

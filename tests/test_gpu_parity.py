@@ -151,6 +151,31 @@ def _ulp_floor(p, u, dx, dt, nsteps, periodic, seeds=(0, 1)):
     return a, worst
 
 
+def test_rhs_parity_two_punctures_256_sampled():
+    """256^3 two-puncture box at dx = M/16 with lambda_gb = 0.2, g2 = 0.02 (the
+    large single-box workload): GPU right-hand side at every cell, oracle at
+    2000 sampled cells plus cells at the punctures and the box corners."""
+    print("case: two punctures 256^3 sampled", flush=True)
+    p = I.default_params(lambda_gb=0.2, g2=0.02)
+    dx = 1.0 / 16.0
+    u = I.two_punctures(256, dx)
+    g, code, bits = gpu_rhs(p, u, dx)
+    assert code == 0, bits
+    rng = np.random.default_rng(11)
+    cells = rng.integers(0, 256, size=(2000, 3))
+    # punctures at x = +-3 (cell centres x_i = -8 + (i + 1/2)/16), box corners
+    special = [[79, 127, 127], [80, 128, 128], [175, 127, 128], [176, 128, 127], [0, 0, 0], [255, 255, 255],
+               [0, 255, 0], [128, 0, 255]]
+    cells = np.concatenate([cells, np.array(special)])
+    o, _ = O.rhs_cells(I.params_vector(p), u, dx, cells)
+    gs = g[:, cells[:, 2] + 3, cells[:, 1] + 3, cells[:, 0] + 3].T
+    del g
+    num = np.abs(gs - o).max(axis=0)
+    den = np.abs(o).max(axis=0)
+    den = np.where(den > 0, den, den.max())
+    assert (num / den).max() <= 1e-12, dict(zip(I.FIELDS, num / den))
+
+
 def test_rk4_ten_steps_periodic():
     """Flat space + 1e-6 noise + pulse, 32^3 periodic, 10 steps.  With O(1)
     fields carrying 1e-6 perturbations the map is ill-conditioned: a one-ulp

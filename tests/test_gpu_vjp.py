@@ -183,6 +183,56 @@ def test_trajectory_gradient_vs_central_fd_cfg3():
     np.testing.assert_allclose(gth, fd4, rtol=1e-6)
 
 
+def test_trajectory_gradient_vs_central_fd_256():
+    """The large single-box workload: 256^3 two punctures, dx = M/16,
+    lambda_gb = 0.2, g2 = 0.02, 20 RK4 steps with checkpoints every 2 steps
+    (the checkpoint and stage buffers of a 3.9 GB state fit in HBM), J = sum
+    over 8 < r < 10 of phi^2.  The adjoint's d J / d phi_0 . v (v smooth and
+    random, on every stored cell) and d J / d lambda_gb are held against central
+    differences with steps 1e-6 and 1e-4 respectively (relative 1e-6 plus the
+    rounding floor ulp(J) / (2 h |J'|) of the difference quotient)."""
+    print("case: trajectory 256^3 x 20 steps vs central differences", flush=True)
+    p = I.default_params(lambda_gb=0.2, g2=0.02)
+    n, dx, nsteps = 256, 1.0 / 16.0, 20
+    dt = 0.25 * dx
+    u0 = I.two_punctures(n, dx)
+    mask = torch.from_numpy(I.shell_mask((n, n, n), dx, 8.0, 10.0)).to(DEV)
+    ut = torch.from_numpy(u0).to(DEV)
+    del u0
+    traj = A.Trajectory(p, G.box_of(ut, dx), dt, nsteps, every=2)
+    theta = torch.tensor([p["lambda_gb"], p["g2"]], dtype=torch.float64, requires_grad=True)
+    u0t = ut.clone().requires_grad_(True)
+    J = A.shell_phi2(A.Evolve.apply(theta, u0t, traj), mask)
+    J.backward()
+    gth = theta.grad.numpy().copy()
+    X, Y, Z = I.coords((n, n, n), dx)
+    rng = np.random.default_rng(3)
+    v = torch.from_numpy(np.exp(-(X * X + Y * Y + Z * Z) / 40.0)
+                         * rng.standard_normal(X.shape)).to(DEV)
+    del X, Y, Z
+    gdir = float((u0t.grad[I.IDX["phi"]] * v).sum())
+    u0t.grad = None
+
+    def Jof(th, phi_shift):
+        with torch.no_grad():
+            uin = ut.clone()
+            uin[I.IDX["phi"]] += phi_shift
+            un, _ = traj.forward(th, uin)
+            return float(A.shell_phi2(un, mask))
+
+    th0 = [p["lambda_gb"], p["g2"]]
+    Jv = float(J.detach())
+    assert Jv > 0
+    h = 1e-6
+    fd_u = (Jof(th0, h * v) - Jof(th0, -h * v)) / (2 * h)
+    floor = np.spacing(Jv) / (2 * h * abs(gdir))
+    assert abs(gdir - fd_u) <= (1e-6 + floor) * abs(gdir), (gdir, fd_u, floor)
+    h = 1e-4
+    fd_l = (Jof([th0[0] + h, th0[1]], 0.0) - Jof([th0[0] - h, th0[1]], 0.0)) / (2 * h)
+    floor = np.spacing(Jv) / (2 * h * abs(gth[0]))
+    assert abs(gth[0] - fd_l) <= (1e-6 + floor) * abs(gth[0]), (gth[0], fd_l, floor)
+
+
 def test_trajectory_gradient_vs_oracle_tangent_cfg3_box():
     """64^3 box, dx = M/4, 10 RK4 steps: d J / d lambda_gb from the adjoint
     against the oracle's complex-step tangent through the same steps."""
