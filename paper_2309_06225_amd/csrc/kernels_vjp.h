@@ -20,8 +20,11 @@ constexpr int NTH = 2;
 // components of the cotangent record Dbar (same numbering as D, without Kreiss-Oliger)
 constexpr int NCOMP_BAR = GRF_OFF_KO;
 
+// Two waves per SIMD (256 registers each): the kernel spills ~12 KB per lane
+// either way, and the second wave hides part of that traffic's latency
+// (3.86 -> 3.04 ms at 64^3; three or four waves per SIMD measured slower).
 template <int SHIFTADV>
-__global__ __launch_bounds__(64) void k_vjp_point(BoxDev b, grf_point_params P, const double* __restrict__ us,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_vjp_point(BoxDev b, grf_point_params P, const double* __restrict__ us,
                                                   const double* __restrict__ D, const double* __restrict__ UP,
                                                   const double* __restrict__ w, double* __restrict__ ubar,
                                                   double* __restrict__ Dbar, double* __restrict__ TH) {
