@@ -236,6 +236,15 @@ def main():
     achieved = flops_cell * ncell / (avg_point * 1e-3) / 1e12
     kname = {0: "k_point", 1: "k_stage_fused", 2: "k_point_staged"}[G.get_stage_path()]
     traffic = load_traffic(kname, f"single_puncture_{n}")
+    # the same kernel against HBM: its own algorithmic bytes per cell, the
+    # derivative record it reads (72 + 72 first/second derivatives, the
+    # advection sums in use, 27 KO terms) plus u_s, u_0, out and the
+    # accumulator as the four stage modes use them (acc read in 3 of 4 stages,
+    # written in 3 of 4)
+    n_adv = 27 if params["shift_advec"] != 0.0 else 21
+    words = 72 + 72 + n_adv + 27 + 27 + 27 + 27 + 0.75 * 27 + 0.75 * 27
+    hbm_bytes = words * 8 * ncell
+    hbm_achieved = hbm_bytes / (avg_point * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": value,
@@ -253,7 +262,9 @@ def main():
                    "bc": "frozen", "lambda_gb": params["lambda_gb"], "g2": params["g2"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64, "traffic": traffic, "kernel": kname,
-                     "flops_per_cell": flops_cell, "avg_launch_ms": avg_point},
+                     "flops_per_cell": flops_cell, "avg_launch_ms": avg_point,
+                     "hbm_view": {"bytes_per_cell": words * 8, "achieved": hbm_achieved, "peak": PEAK_HBM,
+                                  "unit": "GB/s", "frac": hbm_achieved / PEAK_HBM}},
         "kernels_ms_per_step": {"stencil": deriv_ms / args.steps, "pointwise_rk4": point_ms / args.steps},
         "rhs_cells_per_s": ncell * 4 * args.steps / (ms_total * 1e-3),
     }
