@@ -107,12 +107,23 @@ __device__ __forceinline__ void tile_origin(const BoxDev& b, int tile, int TX, i
   tz0 = (tile / nty) * TZ;
 }
 
+// Store of one record component.  Streamed (non-temporal) where the record of
+// a whole box goes to memory and is read back by a later kernel; plain where
+// the record is a small per-workgroup slice meant to stay in cache.
+template <bool STREAM>
+__device__ __forceinline__ void rec_store(double* p, double v) {
+  if constexpr (STREAM)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
 // Derivative record of field f for one cell (interior i, j, k) from staged
 // values.  The staged neighbourhood is addressed as t[pb[dz + 3] + cxy + dy*LX + dx]
 // (pb: base of the plane at z offset dz, cxy: the cell within a plane), so the
 // same arithmetic serves a 3-D tile and a ring of z-planes.  Record layout:
 // component q of the cell lives at Dc[q * nc].
-template <int LX>
+template <int LX, bool STREAM = true>
 __device__ __forceinline__ void compute_cell(const BoxDev& b, int i, int j, int k, int f, const double* __restrict__ u,
                                              double* __restrict__ Dc, int64_t nc, int64_t cell, double ko_sigma,
                                              int shift_adv, double* __restrict__ UP, const double* t, const int* pb,
@@ -128,16 +139,17 @@ __device__ __forceinline__ void compute_cell(const BoxDev& b, int i, int j, int 
   const int s1 = grf_d1_slot[f];
   if (s1 >= 0) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) Dc[(int64_t)(GRF_OFF_D1 + 3 * s1 + d) * nc] = sten_d1(line[d]) * b.i12h[d];
+    for (int d = 0; d < 3; ++d) rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D1 + 3 * s1 + d) * nc], sten_d1(line[d]) * b.i12h[d]);
   }
   const int s2 = grf_d2_slot[f];
   if (s2 >= 0) {
     const int pure[3] = {0, 3, 5};
 #pragma unroll
-    for (int d = 0; d < 3; ++d) Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc] = sten_d2(line[d]) * b.i12h2[d];
-    Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 1) * nc] = sten_mixed<LX, 0>(t, pb, cxy) * b.i144[0];
-    Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 2) * nc] = sten_mixed<LX, 1>(t, pb, cxy) * b.i144[1];
-    Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 4) * nc] = sten_mixed<LX, 2>(t, pb, cxy) * b.i144[2];
+    for (int d = 0; d < 3; ++d)
+      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc], sten_d2(line[d]) * b.i12h2[d]);
+    rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 1) * nc], sten_mixed<LX, 0>(t, pb, cxy) * b.i144[0]);
+    rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 2) * nc], sten_mixed<LX, 1>(t, pb, cxy) * b.i144[1]);
+    rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 4) * nc], sten_mixed<LX, 2>(t, pb, cxy) * b.i144[2]);
   }
 #undef GRF_AT
   // upwinded advection: the lopsided stencil on the side the shift points to
@@ -149,11 +161,12 @@ __device__ __forceinline__ void compute_cell(const BoxDev& b, int i, int j, int 
     up[d] = (beta[d] >= 0.0 ? sten_up_plus(line[d]) : sten_up_minus(line[d])) * b.i12h[d];
     if (UP) UP[(int64_t)(3 * f + d) * b.ncell + cell] = up[d];
   }
-  if (advected(f, shift_adv)) Dc[(int64_t)(GRF_OFF_ADV + f) * nc] = beta[0] * up[0] + beta[1] * up[1] + beta[2] * up[2];
+  if (advected(f, shift_adv))
+    rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_ADV + f) * nc], beta[0] * up[0] + beta[1] * up[1] + beta[2] * up[2]);
   double ko = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) ko += sten_ko(line[d]) * b.i64h[d];
-  Dc[(int64_t)(GRF_OFF_KO + f) * nc] = ko_sigma * ko;
+  rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_KO + f) * nc], ko_sigma * ko);
 }
 
 // Derivative record of field f for this thread's cell of a staged 3-D tile.
@@ -177,7 +190,7 @@ __device__ __forceinline__ void compute_tile(const BoxDev& b, int tx0, int ty0, 
   const int cxy = (iy + 3) * LX + (ix + 3);
   double* __restrict__ Dc = D + (LOCAL_RECORD ? (int64_t)threadIdx.x : cell);
   const int64_t nc = LOCAL_RECORD ? (int64_t)(TX * TY * TZ) : b.ncell;
-  compute_cell<LX>(b, i, j, k, f, u, Dc, nc, cell, ko_sigma, shift_adv, UP, t, pb, cxy);
+  compute_cell<LX, !LOCAL_RECORD>(b, i, j, k, f, u, Dc, nc, cell, ko_sigma, shift_adv, UP, t, pb, cxy);
 }
 
 template <int TX, int TY, int TZ, bool LOCAL_RECORD = false>

@@ -41,9 +41,11 @@ __device__ __forceinline__ int64_t state_offset(const BoxDev& b, int64_t c) {
 // Copy one item (64 doubles) into an LDS slot: p0 / p1 point at the double of
 // this lane's cell pair for the first / second half of the wave; wb is this
 // lane's word offset in bytes (0 or 4).
+// AUX: cache policy bits of the load (2: non-temporal, for data read once).
+template <int AUX = 0>
 __device__ __forceinline__ void stage_item(const double* p0, const double* p1, int wb, grf_lds_double* slot) {
-  __builtin_amdgcn_global_load_lds((grf_global_void*)((const char*)p0 + wb), (grf_lds_void*)slot, 4, 0, 0);
-  __builtin_amdgcn_global_load_lds((grf_global_void*)((const char*)p1 + wb), (grf_lds_void*)(slot + 32), 4, 0, 0);
+  __builtin_amdgcn_global_load_lds((grf_global_void*)((const char*)p0 + wb), (grf_lds_void*)slot, 4, 0, AUX);
+  __builtin_amdgcn_global_load_lds((grf_global_void*)((const char*)p1 + wb), (grf_lds_void*)(slot + 32), 4, 0, AUX);
 }
 
 // RK4 stage update of one field from staged values (the order and rounding of
@@ -94,8 +96,9 @@ __device__ __forceinline__ void staged_wave(const BoxDev& b, int64_t c0, const g
   unsigned flags = 0u;
 #define GRF_BUF(bb) ((bb) ? lbuf1 : lbuf0)
 #define GRF_LDS(bb, slot) GRF_BUF(bb)[(slot) * 64 + lane]
+// record components are read once: non-temporal
 #define GRF_STAGE_D(bb, slot, cc) \
-  stage_item(D + (int64_t)(cc) * nc + vc0, D + (int64_t)(cc) * nc + vc1, wb, &GRF_BUF(bb)[(slot) * 64])
+  stage_item<2>(D + (int64_t)(cc) * nc + vc0, D + (int64_t)(cc) * nc + vc1, wb, &GRF_BUF(bb)[(slot) * 64])
 #define GRF_STAGE_KO(bb, slot, f) GRF_STAGE_D(bb, slot, GRF_OFF_KO + (f))
 #define GRF_STAGE_U(bb, slot, f) \
   stage_item(us + (int64_t)(f) * b.fs + vs0, us + (int64_t)(f) * b.fs + vs1, wb, &GRF_BUF(bb)[(slot) * 64])
