@@ -154,6 +154,7 @@ int tiles_of(const BoxDev& b) {
 
 int tiles_of_variant(int v, const BoxDev& b) {
   switch (v) {
+    case 6: return zm_items<32, 8, 32>(b);
     case 8: return zm_items<16, 16, 32>(b);
     case 1: return tiles_of<32, 4, 4>(b);
     case 2: return tiles_of<8, 8, 8>(b);
@@ -219,16 +220,18 @@ int grid_deriv_batch_t(int64_t work) {
   return persistent_grid_from(per, work);
 }
 
+template <int TX, int TY, int ZC>
 int grid_deriv_batch_zm(int64_t work) {
   int per = 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_deriv_batch_zm<16, 16, 32>, 256, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_deriv_batch_zm<TX, TY, ZC>, TX * TY, 0) != hipSuccess)
     per = 1;
   return persistent_grid_from(per, work);
 }
 
 int grid_deriv_batch(int variant, int64_t work) {
   switch (variant) {
-    case 8: return grid_deriv_batch_zm(work);
+    case 6: return grid_deriv_batch_zm<32, 8, 32>(work);
+    case 8: return grid_deriv_batch_zm<16, 16, 32>(work);
     case 1: return grid_deriv_batch_t<32, 4, 4>(work);
     case 2: return grid_deriv_batch_t<8, 8, 8>(work);
     case 3: return grid_deriv_batch_t<16, 16, 2>(work);
@@ -248,6 +251,10 @@ hipError_t launch_deriv_batch_t(int grid, const BatchBoxDev* boxes, const TileEn
 hipError_t launch_deriv_batch(int variant, int grid, const BatchBoxDev* boxes, const TileEntry* tiles, int ntiles,
                               int stage, int parity, double sigma, int sa, hipStream_t st) {
   switch (variant) {
+    case 6:
+      hipLaunchKernelGGL((k_deriv_batch_zm<32, 8, 32>), dim3(grid), dim3(256), 0, st, boxes, tiles, ntiles, stage,
+                         parity, sigma, sa);
+      return hipGetLastError();
     case 8:
       hipLaunchKernelGGL((k_deriv_batch_zm<16, 16, 32>), dim3(grid), dim3(256), 0, st, boxes, tiles, ntiles, stage,
                          parity, sigma, sa);
