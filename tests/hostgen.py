@@ -22,8 +22,8 @@ def lib():
         src = os.path.join(HERE, "host_point.cpp")
         deps = [src] + [os.path.join(GEN, f) for f in ("gen_rhs.inc", "gen_vjp.inc", "gen_layout.h")]
         if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(d) for d in deps):
-            subprocess.run(["g++", "-O1", "-std=c++17", "-fPIC", "-shared", "-I", GEN, "-o", LIB + ".tmp", src],
-                           check=True)
+            subprocess.run(["g++", "-O1", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-I", GEN, "-o",
+                            LIB + ".tmp", src], check=True)
             os.replace(LIB + ".tmp", LIB)
         _lib = ctypes.CDLL(LIB)
     return _lib
@@ -53,16 +53,16 @@ def pack_inputs(d1, d2, advsum):
     return D
 
 
-def rhs_point(pp, u, D):
+def rhs_point(pp, u, D, sa=1):
     out = np.zeros(27)
-    bad = lib().host_rhs_point(pp.ctypes.data_as(_dp), np.ascontiguousarray(u).ctypes.data_as(_dp),
+    bad = lib().host_rhs_point(int(sa), pp.ctypes.data_as(_dp), np.ascontiguousarray(u).ctypes.data_as(_dp),
                                np.ascontiguousarray(D).ctypes.data_as(_dp), out.ctypes.data_as(_dp))
     return out, bad
 
 
-def vjp_point(pp, u, D, w):
+def vjp_point(pp, u, D, w, sa=1):
     ub, Db, tb = np.zeros(27), np.zeros(198), np.zeros(2)
-    lib().host_vjp_point(pp.ctypes.data_as(_dp), np.ascontiguousarray(u).ctypes.data_as(_dp),
+    lib().host_vjp_point(int(sa), pp.ctypes.data_as(_dp), np.ascontiguousarray(u).ctypes.data_as(_dp),
                          np.ascontiguousarray(D).ctypes.data_as(_dp), np.ascontiguousarray(w).ctypes.data_as(_dp),
                          ub.ctypes.data_as(_dp), Db.ctypes.data_as(_dp), tb.ctypes.data_as(_dp))
     return ub, Db, tb

@@ -1,0 +1,79 @@
+"""CPU checks of the generated pointwise code (host build of gen_rhs.inc and
+gen_vjp.inc): the forward right-hand side against the oracle's pointwise
+right-hand side on random inputs, and the reverse-mode code against central
+differences of the forward code."""
+import numpy as np
+import pytest
+
+import hostgen as H
+from oracle import oracle as O
+from paper_2309_06225_amd import inputs as I
+
+NF = 27
+
+
+def _point(rng):
+    """Random pointwise inputs near a perturbed puncture background."""
+    u = 0.05 * rng.standard_normal(NF)
+    u[I.IDX["chi"]] = 0.6 + 0.3 * rng.random()
+    for n in ("h11", "h22", "h33"):
+        u[I.IDX[n]] += 1.0
+    u[I.IDX["lapse"]] = 0.5 + 0.4 * rng.random()
+    d1 = 0.2 * rng.standard_normal((NF, 3))
+    d2 = 0.2 * rng.standard_normal((NF, 6))
+    adv = 0.2 * rng.standard_normal((NF, 3))
+    return u, d1, d2, adv
+
+
+def _record(u, d1, d2, adv, sa):
+    """The derivative-record vector the generated code reads: advection sums
+    beta^k adv_k for the advected fields (shift and B only with shift
+    advection); the Kreiss-Oliger slots stay zero (the stage adds them)."""
+    beta = u[I.IDX["shift1"]:I.IDX["shift3"] + 1]
+    advsum = np.array([np.dot(beta, adv[f]) for f in range(NF)])
+    if not sa:
+        advsum[19:25] = 0.0
+    return H.pack_inputs(d1, d2, advsum)
+
+
+@pytest.mark.parametrize("sa", [0, 1])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_generated_rhs_matches_oracle_point(sa, seed):
+    rng = np.random.default_rng(seed)
+    p = I.default_params(shift_advec=float(sa), lambda_gb=0.3, g2=0.05)
+    u, d1, d2, adv = _point(rng)
+    if not sa:
+        adv[19:25] = 0.0  # the oracle multiplies them by shift_advec = 0 anyway
+    o, _, flags = O.rhs_point(I.params_vector(p), u, d1, d2, adv)
+    g, bad = H.rhs_point(H.point_params(p), u, _record(u, d1, d2, adv, sa), sa)
+    assert bad == 0 and flags == 0
+    np.testing.assert_allclose(g, o, rtol=1e-12, atol=1e-12 * np.abs(o).max())
+
+
+@pytest.mark.parametrize("sa", [0, 1])
+def test_generated_vjp_matches_central_differences(sa):
+    rng = np.random.default_rng(7 + sa)
+    p = I.default_params(shift_advec=float(sa), lambda_gb=0.3, g2=0.05)
+    pp = H.point_params(p)
+    u, d1, d2, adv = _point(rng)
+    D = _record(u, d1, d2, adv, sa)
+    w = rng.standard_normal(NF)
+    ub, Db, tb = H.vjp_point(pp, u, D, w, sa)
+    du = rng.standard_normal(NF)
+    dD = rng.standard_normal(D.shape)
+    dD[171:] = 0.0  # Kreiss-Oliger slots are not read by the pointwise code
+    if not sa:
+        dD[144 + 19:144 + 25] = 0.0
+    dth = np.array([0.7, -0.4])
+    h = 1e-6
+
+    def J(s):
+        q = pp.copy()
+        q[0] += s * dth[0]
+        q[1] += s * dth[1]
+        r, _ = H.rhs_point(q, u + s * du, D + s * dD, sa)
+        return float(w @ r)
+
+    fd = (J(h) - J(-h)) / (2 * h)
+    ad = float(ub @ du + Db @ dD + tb @ dth)
+    assert ad == pytest.approx(fd, rel=1e-7, abs=1e-9)
