@@ -31,6 +31,16 @@ PACK = [[0, 1, 2], [1, 3, 4], [2, 4, 5]]
 ADV_ALWAYS = [f for f in range(NF) if not (SHIFT0 <= f < BB0 + 3)]
 ADV_SHIFT = list(range(SHIFT0, BB0 + 3))
 
+
+def merged_adv(shift_advec: bool):
+    """Fields whose advection sum enters only their own right-hand side, with
+    coefficient 1: all advected fields but the lapse (coefficient lapse_advec)
+    and Gamma^i (its right-hand side, advection included, also drives B^i).
+    The stencil stage adds their sum to the field's Kreiss-Oliger term, so the
+    pointwise algebra never reads it."""
+    del shift_advec  # the same set with and without shift advection
+    return [f for f in ADV_ALWAYS if f != LAPSE and not (GH0 <= f < GH0 + 3)]
+
 PARAMS = ("lambda_gb", "g2", "kappa1", "kappa3", "k1_1pk2", "k1_2pk2", "k1k2",
           "lapse_coeff", "lapse_advec", "shift_gamma_coeff", "shift_advec", "eta",
           "inv1pa", "a_1pa", "fb", "cfac", "b4")
@@ -46,7 +56,8 @@ def input_names(shift_advec: bool):
     names = [f"u{f}" for f in range(NF)]
     names += [f"d1_{f}_{k}" for f in D1_FIELDS for k in range(3)]
     names += [f"d2_{f}_{q}" for f in D2_FIELDS for q in range(6)]
-    names += [f"adv{f}" for f in (ADV_ALWAYS + (ADV_SHIFT if shift_advec else []))]
+    names += [f"adv{f}" for f in (ADV_ALWAYS + (ADV_SHIFT if shift_advec else []))
+              if f not in merged_adv(shift_advec)]
     return names
 
 
@@ -58,7 +69,8 @@ def build(shift_advec: bool = False):
     d1 = {f: [g.input(f"d1_{f}_{k}") for k in range(3)] for f in D1_FIELDS}
     d2 = {f: [[g.input(f"d2_{f}_{PACK[k][l]}") for l in range(3)] for k in range(3)] for f in D2_FIELDS}
     adv_fields = ADV_ALWAYS + (ADV_SHIFT if shift_advec else [])
-    adv = {f: g.input(f"adv{f}") for f in adv_fields}
+    merged = merged_adv(shift_advec)
+    adv = {f: g.input(f"adv{f}") for f in adv_fields if f not in merged}
     zero = g.const(0.0)
 
     def sym(vals):

@@ -171,6 +171,11 @@ def main(outdir: str):
         "// d2 component of (field f, packed xx,xy,xz,yy,yz,zz q): GRF_OFF_D2 + 6*d2_slot[f] + q",
         "static constexpr int grf_d2_slot[27] = {" + ",".join(
             str(M.D2_FIELDS.index(f)) if f in M.D2_FIELDS else "-1" for f in range(M.NF)) + "};",
+        "// 1 where the stencil stage adds the field's advection sum into the field's",
+        "// Kreiss-Oliger slot instead of storing it (index: shift advection off / on)",
+        "static constexpr int grf_adv_merged[2][27] = {" + ", ".join(
+            "{" + ",".join("1" if f in M.merged_adv(sa) else "0" for f in range(M.NF)) + "}" for sa in (False, True))
+        + "};",
         "// field of each d1 / d2 slot (inverse of the tables above)",
         f"static constexpr int grf_d1_field[{len(M.D1_FIELDS)}] = {{" + ",".join(str(f) for f in M.D1_FIELDS) + "};",
         f"static constexpr int grf_d2_field[{len(M.D2_FIELDS)}] = {{" + ",".join(str(f) for f in M.D2_FIELDS) + "};",

@@ -161,12 +161,18 @@ __device__ __forceinline__ void compute_cell(const BoxDev& b, int i, int j, int 
     up[d] = (beta[d] >= 0.0 ? sten_up_plus(line[d]) : sten_up_minus(line[d])) * b.i12h[d];
     if (UP) UP[(int64_t)(3 * f + d) * b.ncell + cell] = up[d];
   }
-  if (advected(f, shift_adv))
-    rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_ADV + f) * nc], beta[0] * up[0] + beta[1] * up[1] + beta[2] * up[2]);
+  // a field whose advection sum enters only its own right-hand side, with
+  // coefficient 1, has it added to its Kreiss-Oliger term (one stored value)
+  const bool merged = grf_adv_merged[shift_adv != 0][f] != 0;
+  double adv = 0.0;
+  if (advected(f, shift_adv)) {
+    adv = beta[0] * up[0] + beta[1] * up[1] + beta[2] * up[2];
+    if (!merged) rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_ADV + f) * nc], adv);
+  }
   double ko = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) ko += sten_ko(line[d]) * b.i64h[d];
-  rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_KO + f) * nc], ko_sigma * ko);
+  rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_KO + f) * nc], merged ? adv + ko_sigma * ko : ko_sigma * ko);
 }
 
 // Derivative record of field f for this thread's cell of a staged 3-D tile.

@@ -57,7 +57,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     double sb = 0.0;
     for (int f = 0; f < NF; ++f) {
       if (!advected(f, SHIFTADV)) continue;
-      sb += Dbar[(int64_t)(GRF_OFF_ADV + f) * nc + c] * UP[(int64_t)(3 * f + d) * nc + c];
+      // the cotangent of a field's advection sum: w_f where the sum is carried
+      // in the Kreiss-Oliger slot, else the generated code's value
+      const double abar = grf_adv_merged[SHIFTADV != 0][f] ? w[(int64_t)f * b.fs + s]
+                                                           : Dbar[(int64_t)(GRF_OFF_ADV + f) * nc + c];
+      sb += abar * UP[(int64_t)(3 * f + d) * nc + c];
     }
     ub[F_SHIFT + d] += sb;
   }
@@ -143,6 +147,10 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
     const double wp[7] = {0.0, 0.0, -3.0, -10.0, 18.0, -6.0, 1.0};
     const double wm[7] = {-1.0, 6.0, -18.0, 10.0, 3.0, 0.0, 0.0};
     const double* comp = Dbar + (int64_t)(GRF_OFF_ADV + f) * nc;
+    // the advection sum's cotangent: w_f where the sum rides in the
+    // Kreiss-Oliger slot, else the cotangent record
+    const bool merged = grf_adv_merged[shift_adv != 0][f] != 0;
+    const double* wf_adv = w + (int64_t)f * b.fs;
     for (int d = 0; d < 3; ++d) {
       const double* beta = u + (int64_t)(F_SHIFT + d) * b.fs;
       double s = 0.0;
@@ -152,7 +160,8 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
         double vp = 0.0, vm = 0.0;
         const int ix = sx - 3, iy = sy - 3, iz = sz - 3;
         if (ix >= 0 && ix < b.nx && iy >= 0 && iy < b.ny && iz >= 0 && iz < b.nz) {
-          const double a = comp[((int64_t)iz * b.ny + iy) * b.nx + ix];
+          const double a = merged ? wf_adv[(int64_t)sz * b.sz + (int64_t)sy * b.sy + sx]
+                                  : comp[((int64_t)iz * b.ny + iy) * b.nx + ix];
           const double bd = beta[(int64_t)sz * b.sz + (int64_t)sy * b.sy + sx];
           if (bd >= 0.0)
             vp = a * bd;
