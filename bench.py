@@ -238,11 +238,12 @@ def main():
     traffic = load_traffic(kname, f"single_puncture_{n}")
     # the same kernel against HBM: its own algorithmic bytes per cell, the
     # derivative record it reads (72 + 72 first/second derivatives, the
-    # advection sums in use, 27 KO terms) plus u_s, u_0, out and the
-    # accumulator as the four stage modes use them (acc read in 3 of 4 stages,
-    # written in 3 of 4)
-    n_adv = 27 if params["shift_advec"] != 0.0 else 21
-    words = 72 + 72 + n_adv + 27 + 27 + 27 + 27 + 0.75 * 27 + 0.75 * 27
+    # advection sums stored apart: lapse and Gamma^i, with shift advection also
+    # shift and B; 27 KO slots) plus the 24 state values the algebra uses, u_0
+    # and out, and the accumulator as the four stage modes use it (read in 3 of
+    # 4 stages, written in 3 of 4)
+    n_adv = 10 if params["shift_advec"] != 0.0 else 4
+    words = 72 + 72 + n_adv + 27 + 24 + 27 + 27 + 0.75 * 27 + 0.75 * 27
     hbm_bytes = words * 8 * ncell
     hbm_achieved = hbm_bytes / (avg_point * 1e-3) / 1e9
     out = {
