@@ -269,6 +269,11 @@ def main():
         "kernels_ms_per_step": {"stencil": deriv_ms / args.steps, "pointwise_rk4": point_ms / args.steps},
         "rhs_cells_per_s": ncell * 4 * args.steps / (ms_total * 1e-3),
     }
+    # measured peaks of this device beside the datasheet ones
+    fp64_meas, copy_meas = G.measure_peaks()
+    out["roofline"]["measured_peaks"] = {"fp64_tflops": fp64_meas, "copy_gbps": copy_meas,
+                                         "frac_of_measured_fp64": achieved / fp64_meas,
+                                         "hbm_view_frac_of_measured_copy": hbm_achieved / copy_meas}
     if not args.no_extra:
         del st
         torch.cuda.empty_cache()

@@ -235,6 +235,13 @@ int grf_get_stage_path(void);
  * for the events and returns per class (0 stencil stage, 1 pointwise + RK4,
  * 2 VJP kernels) the summed milliseconds and launch counts (arrays of 3).
  * Host-side state, not thread-safe; intended for benchmarks. */
+/* Measured peaks of the device, for roofline fractions next to the datasheet
+ * ones: an FP64 FMA-chain kernel (TFLOP/s, fused multiply-add = 2 flops) and a
+ * plain device copy over the caller's scratch (GB/s counting bytes read plus
+ * written; scratch_bytes >= 16 MiB, split in two halves; contents overwritten).
+ * Synchronises the stream. */
+grf_status grf_measure_peaks(void* scratch, size_t scratch_bytes, hipStream_t stream, double* fp64_tflops,
+                             double* copy_gbps);
 grf_status grf_prof_begin(int max_launches);
 grf_status grf_prof_end(double* ms, int* count);
 

@@ -29,6 +29,9 @@ hipError_t launch_deriv_batch(int variant, int grid, const BatchBoxDev* boxes, c
 int grid_deriv_batch(int variant, int64_t work);
 hipError_t launch_periodic(const BoxDev& bd, double* u, hipStream_t st);
 hipError_t launch_status_clear(unsigned* s, hipStream_t st);
+constexpr int kPeakChains = 8;  // independent FMA chains per thread of the FP64 peak probe
+hipError_t launch_fma_peak(int blocks, int iters, double* out, hipStream_t st);
+hipError_t launch_copy_peak(int blocks, int64_t n, const double* x, double* y, hipStream_t st);
 hipError_t launch_enforce(const BoxDev& bd, double* u, double chi_min, double lapse_min, hipStream_t st);
 
 // pointwise right-hand side + stage update (mode 0, 1, 2, 4)

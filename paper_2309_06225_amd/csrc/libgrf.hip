@@ -788,6 +788,47 @@ grf_status grf_batch_status_fetch(const grf_batch* B, hipStream_t stream, uint32
 }
 
 // Start recording up to max_launches timed launches per kernel class.
+grf_status grf_measure_peaks(void* scratch, size_t scratch_bytes, hipStream_t stream, double* fp64_tflops,
+                             double* copy_gbps) {
+  if (!scratch || !fp64_tflops || !copy_gbps) return fail(GRF_EINVAL, "null argument");
+  const int64_t n = (int64_t)(scratch_bytes / 16);  // two halves of n doubles
+  if (n < (1 << 20)) return fail(GRF_ENOMEM, "scratch below 16 MiB");
+  int dev = 0, cus = 256;
+  GRF_HIP_CHECK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  GRF_HIP_CHECK(hipGetDeviceProperties(&prop, dev));
+  cus = prop.multiProcessorCount;
+  double* x = (double*)scratch;
+  double* y = x + n;
+  hipEvent_t e0, e1;
+  GRF_HIP_CHECK(hipEventCreate(&e0));
+  GRF_HIP_CHECK(hipEventCreate(&e1));
+  const int blocks = cus * 32;  // 32 workgroups of 256 threads per CU: many rounds of full occupancy
+  const int iters = 4096;
+  if (n < (int64_t)blocks * 256) return fail(GRF_ENOMEM, "scratch too small for the FMA probe");
+  float best_f = 1e30f, best_c = 1e30f;
+  for (int rep = 0; rep < 4; ++rep) {
+    float t = 0.f;
+    GRF_HIP_CHECK(hipEventRecord(e0, stream));
+    GRF_HIP_CHECK(launch_fma_peak(blocks, iters, x, stream));
+    GRF_HIP_CHECK(hipEventRecord(e1, stream));
+    GRF_HIP_CHECK(hipEventSynchronize(e1));
+    GRF_HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
+    if (rep > 0 && t < best_f) best_f = t;
+    GRF_HIP_CHECK(hipEventRecord(e0, stream));
+    GRF_HIP_CHECK(launch_copy_peak(cus * 64, n, x, y, stream));
+    GRF_HIP_CHECK(hipEventRecord(e1, stream));
+    GRF_HIP_CHECK(hipEventSynchronize(e1));
+    GRF_HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
+    if (rep > 0 && t < best_c) best_c = t;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *fp64_tflops = (double)blocks * 256 * iters * kPeakChains * 2.0 / (best_f * 1e-3) / 1e12;
+  *copy_gbps = 2.0 * (double)n * 8.0 / (best_c * 1e-3) / 1e9;
+  return GRF_OK;
+}
+
 grf_status grf_prof_begin(int max_launches) {
   if (max_launches < 1 || max_launches > (1 << 20)) return fail(GRF_EINVAL, "max_launches out of range");
   for (auto& c : g_prof.cls) {

@@ -287,6 +287,38 @@ hipError_t launch_enforce(const BoxDev& bd, double* u, double chi_min, double la
   return hipGetLastError();
 }
 
+// Peak probes.  k_fma_peak: every thread runs 8 independent dependent chains of
+// FP64 fused multiply-adds (16 flops per chain step); the sum is stored so that
+// nothing is removed.  k_copy_peak: a grid-stride copy of n doubles.
+__global__ __launch_bounds__(256) void k_fma_peak(int iters, double a, double b, double* __restrict__ out) {
+  double v[kPeakChains];
+#pragma unroll
+  for (int q = 0; q < kPeakChains; ++q) v[q] = (double)(threadIdx.x + q);
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int q = 0; q < kPeakChains; ++q) v[q] = fma(v[q], a, b);
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < kPeakChains; ++q) s += v[q];
+  out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_copy_peak(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    y[e] = x[e];
+}
+
+hipError_t launch_fma_peak(int blocks, int iters, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_fma_peak, dim3(blocks), dim3(256), 0, st, iters, 1.0 - 1e-9, 1e-9, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_peak(int blocks, int64_t n, const double* x, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_peak, dim3(blocks), dim3(256), 0, st, n, x, y);
+  return hipGetLastError();
+}
+
 hipError_t launch_status_clear(unsigned* s, hipStream_t st) {
   hipLaunchKernelGGL(k_status_clear, dim3(1), dim3(64), 0, st, s);
   return hipGetLastError();

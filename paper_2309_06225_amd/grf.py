@@ -95,6 +95,9 @@ def lib():
         L.grf_set_tile_variant.argtypes = [ctypes.c_int]
         L.grf_set_stage_path.argtypes = [ctypes.c_int]
         L.grf_prof_begin.argtypes = [ctypes.c_int]
+        L.grf_measure_peaks.argtypes = [_vp, ctypes.c_size_t, _vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]
+        L.grf_measure_peaks.restype = ctypes.c_int
         L.grf_prof_end.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         for name in ("grf_rhs_eval", "grf_rk4_stage", "grf_fill_periodic", "grf_rhs_vjp", "grf_status_fetch",
                      "grf_status_clear", "grf_set_tile_variant", "grf_set_stage_path", "grf_prof_begin", "grf_prof_end",
@@ -222,6 +225,15 @@ def get_stage_path() -> int:
 
 def get_tile_variant() -> int:
     return int(lib().grf_get_tile_variant())
+
+
+def measure_peaks(nbytes: int = 1 << 31, stream=None):
+    """-> (FP64 TFLOP/s of an FMA-chain kernel, GB/s of a device copy)."""
+    scratch = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    f, c = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib().grf_measure_peaks(_ptr(scratch), scratch.numel() * 8, _stream(stream), ctypes.byref(f),
+                                   ctypes.byref(c)))
+    return f.value, c.value
 
 
 def prof_begin(max_launches: int):
