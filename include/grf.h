@@ -185,7 +185,7 @@ grf_status grf_batch_step_perbox(grf_batch* batch, hipStream_t stream);
  * and after every replay) on a non-null stream into an executable graph. */
 grf_status grf_batch_capture(grf_batch* batch, hipStream_t stream, hipGraphExec_t* exec);
 /* Chooses a stencil variant per box-shape class among those the batch can
- * run (tiled 0..4, z-marching 6 and 8; see grf_set_tile_variant): each variant is
+ * run (tiled 0..4, z-marching 5, 6 and 8; see grf_set_tile_variant): each variant is
  * timed on one box of each class alone, giving a per-class mix; then the mix
  * and each variant used for all boxes are timed as the batched stencil stage
  * runs them, and the fastest assignment is kept (ties: the earlier candidate).
@@ -195,7 +195,7 @@ grf_status grf_batch_capture(grf_batch* batch, hipStream_t stream, hipGraphExec_
 grf_status grf_batch_autotune(grf_batch* batch, hipStream_t stream);
 grf_status grf_batch_state(const grf_batch* batch, int box, double** current);
 grf_status grf_batch_tile_variant(const grf_batch* batch, int box, int* variant);
-/* Sets the stencil variant of one box (0..4, 6 or 8; GRF_EINVAL otherwise) and
+/* Sets the stencil variant of one box (0..6 or 8; GRF_EINVAL otherwise) and
  * rebuilds the work lists (device allocations owned by the batch).  Results
  * do not depend on it.  Graphs captured earlier keep the old work lists:
  * capture again after changing variants. */

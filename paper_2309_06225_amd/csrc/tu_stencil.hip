@@ -154,6 +154,7 @@ int tiles_of(const BoxDev& b) {
 
 int tiles_of_variant(int v, const BoxDev& b) {
   switch (v) {
+    case 5: return zm_items<16, 8, 32>(b);
     case 6: return zm_items<32, 8, 32>(b);
     case 8: return zm_items<16, 16, 32>(b);
     case 1: return tiles_of<32, 4, 4>(b);
@@ -230,6 +231,7 @@ int grid_deriv_batch_zm(int64_t work) {
 
 int grid_deriv_batch(int variant, int64_t work) {
   switch (variant) {
+    case 5: return grid_deriv_batch_zm<16, 8, 32>(work);
     case 6: return grid_deriv_batch_zm<32, 8, 32>(work);
     case 8: return grid_deriv_batch_zm<16, 16, 32>(work);
     case 1: return grid_deriv_batch_t<32, 4, 4>(work);
@@ -251,6 +253,10 @@ hipError_t launch_deriv_batch_t(int grid, const BatchBoxDev* boxes, const TileEn
 hipError_t launch_deriv_batch(int variant, int grid, const BatchBoxDev* boxes, const TileEntry* tiles, int ntiles,
                               int stage, int parity, double sigma, int sa, hipStream_t st) {
   switch (variant) {
+    case 5:
+      hipLaunchKernelGGL((k_deriv_batch_zm<16, 8, 32>), dim3(grid), dim3(128), 0, st, boxes, tiles, ntiles, stage,
+                         parity, sigma, sa);
+      return hipGetLastError();
     case 6:
       hipLaunchKernelGGL((k_deriv_batch_zm<32, 8, 32>), dim3(grid), dim3(256), 0, st, boxes, tiles, ntiles, stage,
                          parity, sigma, sa);
