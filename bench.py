@@ -16,6 +16,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -57,8 +59,27 @@ def cpu_baseline(params, u, dx, dt):
     O.rk4(I.params_vector(params), u, dx, dt, 1, periodic=False)
     t = time.perf_counter() - t0
     ncell = (u.shape[1] - 6) * (u.shape[2] - 6) * (u.shape[3] - 6)
-    return {"value": ncell / t, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"one full RK4 step of the same {u.shape[3] - 6}^3 box ({t:.1f} s wall)"}
+    out = {"value": ncell / t, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"one full RK4 step of the same {u.shape[3] - 6}^3 box ({t:.1f} s wall)"}
+    # one core: one RK4 step of a 4-plane slab of the same box (its neighbouring
+    # planes as frozen ghosts)
+    try:
+        import ctypes
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        mid = u.shape[1] // 2
+        slab = np.ascontiguousarray(u[:, mid - 5:mid + 5])
+        t0 = time.perf_counter()
+        O.rk4(I.params_vector(params), slab, dx, dt, 1, periodic=False)
+        t1 = time.perf_counter() - t0
+        gomp.omp_set_num_threads(threads)
+        nslab = (slab.shape[1] - 6) * (slab.shape[2] - 6) * (slab.shape[3] - 6)
+        out["single_core"] = {"value": nslab / t1, "cores": 1,
+                              "sample": f"one RK4 step of a {slab.shape[3] - 6}x{slab.shape[2] - 6}x4 slab "
+                                        f"of the same box ({t1:.1f} s wall)"}
+    except OSError:
+        pass
+    return out
 
 
 def adjoint_ratio(torch, G, I):
