@@ -17,7 +17,6 @@ struct CellEntry;
 
 constexpr int kTileVariants = 5;      // tiled stencil shapes (single-box and batched calls)
 constexpr int kDerivVariants = 13;    // plus z-marching shapes 5..12 (single-box calls)
-extern const int kTiles[kTileVariants][3];
 
 // stencil stage (variant 0..12), optionally storing the upwinded derivatives
 hipError_t launch_deriv(int variant, const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,

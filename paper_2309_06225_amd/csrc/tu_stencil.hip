@@ -7,7 +7,6 @@
 
 namespace grf {
 
-const int kTiles[kTileVariants][3] = {{16, 8, 4}, {32, 4, 4}, {8, 8, 8}, {16, 16, 2}, {64, 4, 2}};
 
 // ---------------------------------------------------------------------------
 // Periodic ghost fill, one axis per launch (x, then y over x-ghosts, then z over
