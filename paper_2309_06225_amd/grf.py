@@ -358,3 +358,12 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def __getattr__(name):
+    """grf.Evolve / grf.Trajectory: the checkpointed trajectory adjoint of
+    adjoint.py (imported on first use; that module builds on this one)."""
+    if name in ("Evolve", "Trajectory", "shell_phi2"):
+        from . import adjoint
+        return getattr(adjoint, name)
+    raise AttributeError(name)
