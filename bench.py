@@ -290,6 +290,17 @@ def main():
         "kernels_ms_per_step": {"stencil": deriv_ms / args.steps, "pointwise_rk4": point_ms / args.steps},
         "rhs_cells_per_s": ncell * 4 * args.steps / (ms_total * 1e-3),
     }
+    # constraint diagnostics (stencil stage + constraint kernel) on the same box
+    G.constraints(G.make_params(params), box, st.u, st.ws)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(5):
+        G.constraints(G.make_params(params), box, st.u, st.ws)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    out["constraints"] = {"ms_per_evaluation": c0.elapsed_time(c1) / 5,
+                          "flops_per_cell": G.flops_per_cell(3)}
     # measured peaks of this device beside the datasheet ones
     fp64_meas, copy_meas = G.measure_peaks()
     out["roofline"]["measured_peaks"] = {"fp64_tflops": fp64_meas, "copy_gbps": copy_meas,

@@ -153,9 +153,22 @@ grf_status grf_status_fetch(const void* workspace, hipStream_t stream, uint32_t*
 grf_status grf_status_clear(void* workspace, hipStream_t stream);
 
 /* Algorithmic FP64 flops per interior cell: the pointwise algebra of one RHS
- * (shift advection on or off) and of its VJP, counted on the expression graph
- * (add, sub, mul and reciprocal each 1), stencils not included. */
-int64_t grf_flops_per_cell(int which /* 0 rhs, 1 rhs with shift advection, 2 vjp */);
+ * (shift advection on or off), of its VJP and of the constraint diagnostics,
+ * counted on the expression graph (add, sub, mul and reciprocal each 1),
+ * stencils not included; -1 for another `which`. */
+int64_t grf_flops_per_cell(int which /* 0 rhs, 1 rhs with shift advection, 2 vjp, 3 constraints */);
+
+/* Constraint diagnostics (Key features, "Diagnostics": constraint monitoring):
+ * per interior cell the Hamiltonian constraint R + (2/3) K^2 - A_ij A^ij -
+ * 2 (8 pi rho) and the momentum constraint M_i - 8 pi S_i (M_i = D_j K^j_i -
+ * D_i K, the scalar's energy and momentum densities including the
+ * Gauss-Bonnet terms, R the Ricci scalar without the Z terms), from the same
+ * stencils as the right-hand side.  Asynchronous on stream.
+ *   u    state (device, state layout), ghosts filled;
+ *   out  device [4][nz][ny][nx]: Hamiltonian, then momentum x, y, z;
+ *   workspace as for grf_rhs_eval (its record is overwritten). */
+grf_status grf_constraints(const grf_params* p, const grf_box* box, const double* u, double* out, void* workspace,
+                           size_t workspace_bytes, hipStream_t stream);
 
 /* ---- Batched boxes (uneven sizes and refinement levels, frozen ghosts).
  * One RK4 step of the batch is four stages; each stage is one persistent

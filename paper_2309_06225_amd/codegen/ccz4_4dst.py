@@ -361,5 +361,8 @@ def build(shift_advec: bool = False):
     rhs[PI] = ad(PI) + al * ps
 
     inputs = {n.name: n for n in g.nodes if n.op == "in"}
+    # constraint diagnostics: Hamiltonian R + 2/3 K^2 - A_ij A^ij - 2 (8 pi rho)
+    # (with the pure Ricci scalar) and momentum M_i - 8 pi S_i
+    constraints = [Hg - 2.0 * rho8] + [Mi[i] - S8i[i] for i in R3]
     return dict(graph=g, rhs=rhs, pivots=pivots, pivot_check=pivot_check, inputs=inputs, params=P,
-                theta=[P["lambda_gb"], P["g2"]], solution=x)
+                theta=[P["lambda_gb"], P["g2"]], solution=x, constraints=constraints)

@@ -99,6 +99,18 @@ def forward_code_staged(shift_advec: bool, rhs_only: bool):
     return emit_staged(g, outs, stmts, _stage_key, param_expr, STAGE_SLOTS, order="dfs_heavy")
 
 
+def constraints_code():
+    """Hamiltonian and momentum constraints of one cell: GRF_CON(q, v), q = 0
+    Hamiltonian, 1..3 momentum (they do not involve the advection sums)."""
+    b = M.build(False)
+    g = b["graph"]
+    outs = b["constraints"]
+    names = [f"GRF_CON({q}, {{}})" for q in range(len(outs))]
+    code = emit(g, outs, names, input_expr, param_expr, order="dfs")
+    flops, ops = count_flops(g, outs)
+    return code, flops
+
+
 def vjp_code(shift_advec: bool):
     b = M.build(shift_advec)
     g = b["graph"]
@@ -160,6 +172,7 @@ def main(outdir: str):
         f"#define GRF_FLOPS_RHS_SHIFTADV {fl1}",
         f"#define GRF_FLOPS_VJP {vfl0}",
         f"#define GRF_FLOPS_VJP_SHIFTADV {vfl1}",
+        f"#define GRF_FLOPS_CONSTRAINTS {constraints_code()[1]}",
         f"#define GRF_STAGE_SLOTS {STAGE_SLOTS}  // slots per buffer of the staged pointwise kernel",
         "// parameters read by the generated code (derived combinations precomputed on the host)",
         "struct grf_point_params {",
@@ -200,6 +213,11 @@ def main(outdir: str):
         fh.write("} else {\n")
         fh.write(block("GRF_SHIFT_ADVEC", staged[(False, True)][0], staged[(False, False)][0]))
         fh.write("}\n")
+    con, cfl = constraints_code()
+    with open(os.path.join(outdir, "gen_constraints.inc"), "w") as fh:
+        fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
+        fh.write(f"// Hamiltonian and momentum constraints: {cfl} flops/cell\n")
+        fh.write("{\n" + PRAGMA + con + "\n}\n")
     with open(os.path.join(outdir, "gen_vjp.inc"), "w") as fh:
         fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
         fh.write(f"// vector-Jacobian product: {vfl0} flops/cell ({vops0})\n")

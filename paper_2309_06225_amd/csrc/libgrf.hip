@@ -230,6 +230,7 @@ int64_t grf_flops_per_cell(int which) {
     case 0: return GRF_FLOPS_RHS;
     case 1: return GRF_FLOPS_RHS_SHIFTADV;
     case 2: return GRF_FLOPS_VJP;
+    case 3: return GRF_FLOPS_CONSTRAINTS;
     default: return -1;
   }
 }
@@ -335,6 +336,19 @@ grf_status grf_rk4_stage(const grf_params* p, const grf_box* box, int stage, dou
   }
   if (p->enforce) GRF_HIP_CHECK(launch_enforce(bd, unext, p->chi_min, p->lapse_min, stream));
   if (box->bc == GRF_BC_PERIODIC) GRF_HIP_CHECK(launch_periodic(bd, unext, stream));
+  return GRF_OK;
+}
+
+grf_status grf_constraints(const grf_params* p, const grf_box* box, const double* u, double* out, void* workspace,
+                           size_t workspace_bytes, hipStream_t stream) {
+  grf_status s = common_checks(p, box, workspace, workspace_bytes);
+  if (s != GRF_OK) return s;
+  if (!u || !out) return fail(GRF_EINVAL, "u/out is null");
+  BoxDev bd = make_boxdev(box);
+  grf_point_params pp = make_pp(p);
+  double* D = (double*)((char*)workspace + kStatusBytes);
+  GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, p->shift_advec != 0.0, nullptr, stream));
+  GRF_HIP_CHECK(launch_constraints(bd, pp, u, D, out, stream));
   return GRF_OK;
 }
 

@@ -1,0 +1,37 @@
+// Constraint diagnostics (Hamiltonian and momentum constraints per interior
+// cell) from the derivative record of the stencil stage and the state.
+#include "kernels_fwd.h"
+#include "launch.h"
+
+namespace grf {
+
+__global__ __launch_bounds__(kPointThreads) void k_constraints(BoxDev b, grf_point_params P,
+                                                               const double* __restrict__ us,
+                                                               const double* __restrict__ D,
+                                                               double* __restrict__ out) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= b.ncell) return;
+  const int i = (int)(c % b.nx);
+  const int64_t r = c / b.nx;
+  const int j = (int)(r % b.ny);
+  const int k = (int)(r / b.ny);
+  const int64_t s = (int64_t)(k + 3) * b.sz + (int64_t)(j + 3) * b.sy + (i + 3);
+#define GRF_U(f) us[(int64_t)(f) * b.fs + s]
+#define GRF_D(cc) D[(int64_t)(cc) * b.ncell + c]
+#define GRF_P(n) P.n
+#define GRF_CON(q, v) out[(int64_t)(q) * b.ncell + c] = (v)
+#include "gen/gen_constraints.inc"
+#undef GRF_CON
+#undef GRF_P
+#undef GRF_D
+#undef GRF_U
+}
+
+hipError_t launch_constraints(const BoxDev& bd, const grf_point_params& pp, const double* u, const double* D,
+                              double* out, hipStream_t st) {
+  const int64_t nblk = (bd.ncell + kPointThreads - 1) / kPointThreads;
+  hipLaunchKernelGGL(k_constraints, dim3((unsigned)nblk), dim3(kPointThreads), 0, st, bd, pp, u, D, out);
+  return hipGetLastError();
+}
+
+}  // namespace grf

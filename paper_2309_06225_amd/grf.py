@@ -64,6 +64,8 @@ def lib():
         L.grf_vjp_workspace_bytes.argtypes = [B]
         L.grf_vjp_workspace_bytes.restype = ctypes.c_size_t
         L.grf_rhs_eval.argtypes = [P, B, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.grf_constraints.argtypes = [P, B, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.grf_constraints.restype = ctypes.c_int
         L.grf_rk4_stage.argtypes = [P, B, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.grf_fill_periodic.argtypes = [B, _vp, _vp]
         L.grf_enforce.argtypes = [P, B, _vp, _vp]
@@ -174,6 +176,14 @@ def rhs_eval(params: Params, box: Box, u, rhs, ws, stream=None):
 def rk4_stage(params: Params, box: Box, stage, dt, u0, us, unext, acc, ws, stream=None):
     _check(lib().grf_rk4_stage(ctypes.byref(params), ctypes.byref(box), int(stage), float(dt), _ptr(u0), _ptr(us),
                                _ptr(unext), _ptr(acc), _ptr(ws), ws.numel() * 8, _stream(stream)))
+
+
+def constraints(params: Params, box: Box, u, ws, stream=None):
+    """-> (Hamiltonian (nz, ny, nx), momentum (3, nz, ny, nx)) on the interior."""
+    out = torch.empty((4, box.nz, box.ny, box.nx), dtype=torch.float64, device=u.device)
+    _check(lib().grf_constraints(ctypes.byref(params), ctypes.byref(box), _ptr(u), _ptr(out), _ptr(ws),
+                                 ws.numel() * 8, _stream(stream)))
+    return out[0], out[1:]
 
 
 def enforce(params: Params, box: Box, u, stream=None):

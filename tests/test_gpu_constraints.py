@@ -1,0 +1,89 @@
+"""GPU constraint diagnostics against the oracle, and the fourth-order
+self-convergence of the Hamiltonian constraint measured with the GPU path."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import oracle as O
+from paper_2309_06225_amd import grf as G
+from paper_2309_06225_amd import inputs as I
+from test_oracle_pins import _smooth_periodic
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    O.build(force=False)
+    G.lib()
+
+
+def gpu_constraints(p, u, dx, bc=G.BC_FROZEN):
+    ut = torch.from_numpy(u).to(DEV)
+    box = G.box_of(ut, dx, bc)
+    ws = G.alloc_workspace(G.workspace_bytes(box))
+    ham, mom = G.constraints(G.make_params(p), box, ut, ws)
+    return ham.cpu().numpy(), mom.cpu().numpy()
+
+
+def _rel(g, o):
+    return np.abs(g - o).max() / max(np.abs(o).max(), 1e-300)
+
+
+def test_flat_space_constraints_exactly_zero():
+    u = I.set_flat(I.empty_state((19, 13, 11)))
+    ham, mom = gpu_constraints(I.default_params(), u, 0.25)
+    assert np.all(ham == 0.0) and np.all(mom == 0.0)
+
+
+@pytest.mark.parametrize("case", ["noise32", "puncture_ragged"])
+def test_constraints_match_oracle(case):
+    print("case: constraints", case, flush=True)
+    p = I.default_params(lambda_gb=0.3, g2=0.05)
+    if case == "noise32":
+        u, dx, bc = I.flat_noise_pulse(32, 0.25, seed=0), 0.25, G.BC_PERIODIC
+    else:
+        dx, bc = 0.3, G.BC_FROZEN
+        u = I.puncture((21, 17, 13), dx, centre=(0.4, -0.2, 0.1), phi_fn=I.shell_pulse(0.1, 2.0))
+        rng = np.random.default_rng(4)
+        u[I.IDX["K"]] += 0.01 * rng.standard_normal(u[7].shape)
+        u[I.IDX["A11"]:I.IDX["A33"] + 1] += 0.01 * rng.standard_normal(u[8:14].shape)
+        u[I.IDX["Pi"]] += 0.01 * rng.standard_normal(u[26].shape)
+    ho, mo = O.constraints(I.params_vector(p), u, dx)
+    hg, mg = gpu_constraints(p, u, dx, bc)
+    assert _rel(hg, ho) <= 1e-12, _rel(hg, ho)
+    for d in range(3):
+        assert _rel(mg[d], mo[d]) <= 1e-12, (d, _rel(mg[d], mo[d]))
+
+
+def test_hamiltonian_self_convergence_fourth_order_gpu():
+    """Smooth periodic data varying along x, evolved to t = 1 with the GPU RK4
+    path on 32, 64 and 128 cells; the lowest Fourier modes of the GPU
+    Hamiltonian constraint converge at fourth order."""
+    print("case: Hamiltonian self-convergence on the GPU", flush=True)
+    L, T = 8.0, 1.0
+    p = I.default_params()
+    P = G.make_params(p)
+    coefs = []
+    for n in (32, 64, 128):
+        u, dx = _smooth_periodic(n, L)
+        dt = 0.25 * dx
+        steps = int(round(T / dt))
+        ut = torch.from_numpy(u).to(DEV)
+        box = G.box_of(ut, dx, G.BC_PERIODIC)
+        st = G.Stepper(P, box, ut, dt)
+        for _ in range(steps):
+            st.step()
+        assert st.status() == (0, 0)
+        ham, _ = G.constraints(P, box, st.u, st.ws)
+        ham = ham.cpu().numpy()
+        X, _, _ = I.coords((n, 4, 4), dx)
+        x = I.interior(X[None])[0]
+        coefs.append(np.array([np.mean(ham * np.exp(-1j * m * 2 * np.pi * x / L)) for m in (0, 1, 2)]))
+    coefs = np.array(coefs)
+    order = np.log2(np.abs(coefs[0] - coefs[1]) / np.abs(coefs[1] - coefs[2]))
+    assert np.all(np.abs(order - 4.0) < 0.3), order
