@@ -147,6 +147,7 @@ struct PointOut {
   T rhs[NF];
   T ham;          // Hamiltonian constraint  R + 2/3 K^2 - A_ij A^ij - 2 (8 pi rho)
   T mom[3];       // momentum constraint  M_i - 8 pi S_i
+  T rho[3];       // energy density n^a n^b T_ab of the canonical (X), X^2 and Gauss-Bonnet terms
   T C[6];         // solved C_ij = 4R_{i n j n}
   T p;            // solved Lie_n Pi
   T sysA[49];     // the assembled 7x7 system (row-major), for solver checks
@@ -829,6 +830,11 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
   for (int f = 0; f < NF; ++f)
     if (!finite_val(r[f])) flags |= FLAG_NONFINITE;
   out.ham = Hg - 2.0 * rho8;
+  // the three pieces of 8 pi rho, one per term of the action, divided by 8 pi
+  const T inv8pi = 1.0 / (8.0 * M_PI);
+  out.rho[0] = (0.5 * Pi * Pi - 0.5 * X) * inv8pi;
+  out.rho[1] = g2 * (X * Pi * Pi - 0.5 * X * X) * inv8pi;
+  out.rho[2] = H00 * inv8pi;
   for (int i = 0; i < 3; ++i) out.mom[i] = Mi[i] - S8i[i];
   out.flags = flags;
 }
@@ -960,7 +966,7 @@ void gather_point(const Box& b, const T* u, int i, int j, int k, PointIn<T>& in,
 }
 
 template <class T>
-int box_rhs(const Params<T>& P, const Box& b, const T* u, T* rhs, T* ham, T* mom) {
+int box_rhs(const Params<T>& P, const Box& b, const T* u, T* rhs, T* ham, T* mom, T* rho = nullptr) {
   int flags_all = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : flags_all)
   for (int k = 0; k < b.nz; ++k) {
@@ -977,6 +983,8 @@ int box_rhs(const Params<T>& P, const Box& b, const T* u, T* rhs, T* ham, T* mom
         if (ham) ham[c] = out.ham;
         if (mom)
           for (int d = 0; d < 3; ++d) mom[d * b.fstride + c] = out.mom[d];
+        if (rho)
+          for (int d = 0; d < 3; ++d) rho[d * b.fstride + c] = out.rho[d];
         flags_all |= out.flags;
       }
   }
@@ -1097,6 +1105,14 @@ int oracle_constraints(const double* params, const int* dims, const double* spac
   return box_rhs(P, b, u, (double*)nullptr, ham, mom);
 }
 
+// Energy densities of the canonical, X^2 and Gauss-Bonnet terms on interior cells (rho: three fields).
+int oracle_energy_densities(const double* params, const int* dims, const double* spacing, const double* u,
+                            double* rho) {
+  Box b = make_box(dims, spacing);
+  Params<double> P = read_params<double>(params, nullptr);
+  return box_rhs(P, b, u, (double*)nullptr, (double*)nullptr, (double*)nullptr, rho);
+}
+
 void oracle_fill_periodic(const int* dims, double* u) {
   const double sp[3] = {1.0, 1.0, 1.0};
   Box b = make_box(dims, sp);
@@ -1155,6 +1171,7 @@ int oracle_rhs_point(const double* params, const double* u, const double* d1, co
     for (int d = 0; d < 49; ++d) extra[q++] = o.sysA[d];
     for (int d = 0; d < 7; ++d) extra[q++] = o.sysb[d];
     extra[q++] = o.pivot_ratio;
+    for (int d = 0; d < 3; ++d) extra[q++] = o.rho[d];
   }
   return o.flags;
 }

@@ -50,6 +50,7 @@ def lib():
         L.oracle_rhs_cells.argtypes = [_dp, _ip, _dp, _dp, ctypes.c_int, _ip, _dp]
         L.oracle_rhs_cs.argtypes = [_dp, _dp, _ip, _dp, _dp, _dp, _dp, _dp]
         L.oracle_constraints.argtypes = [_dp, _ip, _dp, _dp, _dp, _dp]
+        L.oracle_energy_densities.argtypes = [_dp, _ip, _dp, _dp, _dp]
         L.oracle_fill_periodic.argtypes = [_ip, _dp]
         L.oracle_rk4.argtypes = [_dp, _ip, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp]
         L.oracle_rk4_cs.argtypes = [_dp, _dp, _ip, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp, _dp]
@@ -130,6 +131,18 @@ def constraints(params, u, dx):
     return ham[s], mom[(slice(0, 3),) + s]
 
 
+def energy_densities(params, u, dx):
+    """Energy densities (3,nz,ny,nx) of the canonical, X^2 and Gauss-Bonnet
+    terms of the action on the interior."""
+    u = _c(u)
+    rho = np.zeros((NF,) + u.shape[1:])  # only the first 3 fields are written
+    p = _c(params)
+    dims = _dims(u)
+    lib().oracle_energy_densities(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(u), _d(rho))
+    s = (slice(NG, -NG),) * 3
+    return rho[(slice(0, 3),) + s]
+
+
 def fill_periodic(u):
     u = _c(u).copy()
     dims = _dims(u)
@@ -168,10 +181,10 @@ def rhs_point(params, u, d1, d2, adv):
     d2 = _c(d2)
     adv = _c(adv)
     out = np.zeros(NF)
-    extra = np.zeros(68)
+    extra = np.zeros(71)
     flags = lib().oracle_rhs_point(_d(p), _d(u), _d(d1), _d(d2), _d(adv), _d(out), _d(extra))
     ex = dict(ham=extra[0], mom=extra[1:4], C=extra[4:10], p=extra[10],
-              A=extra[11:60].reshape(7, 7), b=extra[60:67], pivot_ratio=extra[67])
+              A=extra[11:60].reshape(7, 7), b=extra[60:67], pivot_ratio=extra[67], rho=extra[68:71])
     return out, ex, flags
 
 

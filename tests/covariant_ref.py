@@ -218,7 +218,13 @@ def field_equations(st: RandomSpacetime, params: dict, x0=None):
     Ephi = FX * box + dphi_up @ (2.0 * g2c * dX) + dlam * LGB
 
     res = torch.stack([E[m, n] for m in range(4) for n in range(m, 4)] + [Ephi])
-    return res, dict(g=g, gi=gi, Riem=Riem, R_low=R_low, n_up=n_up, LGB=LGB)
+    # n^mu n^nu T_mu nu (times 8 pi) of each term of the action: canonical X,
+    # g2 X^2 and the Gauss-Bonnet coupling
+    T_parts = [0.5 * torch.outer(dphi_up, dphi) + 0.5 * torch.eye(4) * X,
+               g2c * X * torch.outer(dphi_up, dphi) + 0.5 * torch.eye(4) * g2c * X * X,
+               -P]
+    rho8 = torch.stack([n_low @ (Tm @ gi) @ n_low for Tm in T_parts])
+    return res, dict(g=g, gi=gi, Riem=Riem, R_low=R_low, n_up=n_up, LGB=LGB, rho8=rho8)
 
 
 def solve_unknowns(st: RandomSpacetime, params: dict):
@@ -318,4 +324,4 @@ def reference_point(seed, params):
     p_true = n_up @ jacfwd(Pi_f)(x0)
     return dict(u=u.numpy(), d1=d1.numpy(), d2=d2.numpy(), dt=dt_true.numpy(),
                 C=np.array([C[i, j].item() for i, j in SYM]), p=p_true.item(),
-                residual=res.abs().max().item(), LGB=info["LGB"].item())
+                residual=res.abs().max().item(), LGB=info["LGB"].item(), rho8=info["rho8"].numpy())

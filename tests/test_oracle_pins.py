@@ -125,6 +125,65 @@ def test_covariant_pointwise_pin(case, seed):
     assert ex["p"] == pytest.approx(ref["p"], abs=1e-12 * max(1.0, abs(ref["p"])))
 
 
+@pytest.mark.parametrize("case", [0, 3, 4])
+@pytest.mark.parametrize("seed", [11, 12])
+def test_energy_densities_covariant_pin(case, seed):
+    """The per-term energy densities against n^mu n^nu T_mu nu of each term of
+    the action, evaluated covariantly on a random spacetime."""
+    import covariant_ref as C
+    params = I.default_params(kappa3=1.0, a_gauge=0.0, **COV_PARAMS[case])
+    ref = C.reference_point(seed + 7 * case, params)
+    _, ex, flags = O.rhs_point(I.params_vector(params), ref["u"], ref["d1"], ref["d2"], ref["d1"])
+    assert flags == 0
+    rho8 = 8.0 * np.pi * ex["rho"]
+    np.testing.assert_allclose(rho8, ref["rho8"], rtol=0, atol=1e-12 * np.abs(ref["rho8"]).max())
+    if COV_PARAMS[case]["lambda_gb"] == 0.0:
+        assert ex["rho"][2] == 0.0
+    if COV_PARAMS[case]["g2"] == 0.0:
+        assert ex["rho"][1] == 0.0
+
+
+def test_energy_densities_flat_closed_form():
+    """Flat metric, K_ij = 0, phi linear in x, y, z and Pi constant: the stencils
+    are exact, the Gauss-Bonnet piece vanishes and the other two take their
+    closed forms rho_X = (Pi^2 + |grad phi|^2)/(32 pi) and
+    rho_X2 = g2 (X Pi^2 - X^2/2)/(8 pi), X = (Pi^2 - |grad phi|^2)/2."""
+    g2, lam = 0.3, 0.4
+    u = I.set_flat(I.empty_state((6, 5, 7)))
+    dx = 0.25
+    X_, Y_, Z_ = I.coords((6, 5, 7), dx)
+    a = np.array([0.3, -0.2, 0.5])
+    u[I.IDX["phi"]] = 0.1 + a[0] * X_ + a[1] * Y_ + a[2] * Z_
+    u[I.IDX["Pi"]] = 0.7
+    rho = O.energy_densities(I.params_vector(I.default_params(lambda_gb=lam, g2=g2)), u, dx)
+    grad2 = float(a @ a)
+    Xv = 0.5 * (0.49 - grad2)
+    np.testing.assert_allclose(rho[0], (0.49 + grad2) / (32 * np.pi), rtol=1e-13)
+    np.testing.assert_allclose(rho[1], g2 * (Xv * 0.49 - 0.5 * Xv * Xv) / (8 * np.pi), rtol=1e-12)
+    assert np.abs(rho[2]).max() < 1e-15
+
+
+def test_energy_densities_sum_to_hamiltonian_source():
+    """On a box, the three densities carry the whole matter source of the
+    Hamiltonian constraint: H(lambda, g2) - H(0, 0) = -16 pi (rho_X2 + rho_GB)
+    and H(0, 0) + 16 pi rho_X is the purely geometric part."""
+    dx = 0.3
+    u = I.puncture((9, 8, 7), dx, centre=(0.4, -0.2, 0.1), phi_fn=I.shell_pulse(0.1, 2.0))
+    rng = np.random.default_rng(3)
+    u[I.IDX["K"]] += 0.01 * rng.standard_normal(u[7].shape)
+    u[I.IDX["Pi"]] += 0.05 * rng.standard_normal(u[26].shape)
+    pc = I.params_vector(I.default_params(lambda_gb=0.3, g2=0.05))
+    p0 = I.params_vector(I.default_params(lambda_gb=0.0, g2=0.0))
+    h1, _ = O.constraints(pc, u, dx)
+    h0, _ = O.constraints(p0, u, dx)
+    rho = O.energy_densities(pc, u, dx)
+    rho0 = O.energy_densities(p0, u, dx)
+    scale = np.abs(h0).max()
+    np.testing.assert_allclose(h1 - h0, -16 * np.pi * (rho[1] + rho[2]), rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(rho[0], rho0[0], rtol=0, atol=0)
+    assert np.abs(rho[2]).max() > 1e-8 and np.abs(rho[1]).max() > 1e-8
+
+
 def test_standard_gauge_when_a_is_zero():
     """a = 0 gives back the 1+log lapse and the B-form Gamma-driver."""
     rng = np.random.default_rng(5)
