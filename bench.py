@@ -301,6 +301,13 @@ def main():
     torch.cuda.synchronize()
     out["constraints"] = {"ms_per_evaluation": c0.elapsed_time(c1) / 5,
                           "flops_per_cell": G.flops_per_cell(3)}
+    c0.record(stream)
+    for _ in range(5):
+        G.energy_densities(G.make_params(params), box, st.u, st.ws)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    out["energy_densities"] = {"ms_per_evaluation": c0.elapsed_time(c1) / 5,
+                               "flops_per_cell": G.flops_per_cell(4)}
     # measured peaks of this device beside the datasheet ones
     fp64_meas, copy_meas = G.measure_peaks()
     out["roofline"]["measured_peaks"] = {"fp64_tflops": fp64_meas, "copy_gbps": copy_meas,

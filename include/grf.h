@@ -153,10 +153,10 @@ grf_status grf_status_fetch(const void* workspace, hipStream_t stream, uint32_t*
 grf_status grf_status_clear(void* workspace, hipStream_t stream);
 
 /* Algorithmic FP64 flops per interior cell: the pointwise algebra of one RHS
- * (shift advection on or off), of its VJP and of the constraint diagnostics,
- * counted on the expression graph (add, sub, mul and reciprocal each 1),
- * stencils not included; -1 for another `which`. */
-int64_t grf_flops_per_cell(int which /* 0 rhs, 1 rhs with shift advection, 2 vjp, 3 constraints */);
+ * (shift advection on or off), of its VJP, of the constraint diagnostics and
+ * of the energy densities, counted on the expression graph (add, sub, mul and
+ * reciprocal each 1), stencils not included; -1 for another `which`. */
+int64_t grf_flops_per_cell(int which /* 0 rhs, 1 rhs with shift advection, 2 vjp, 3 constraints, 4 energy */);
 
 /* Constraint diagnostics (Key features, "Diagnostics": constraint monitoring):
  * per interior cell the Hamiltonian constraint R + (2/3) K^2 - A_ij A^ij -
@@ -169,6 +169,17 @@ int64_t grf_flops_per_cell(int which /* 0 rhs, 1 rhs with shift advection, 2 vjp
  *   workspace as for grf_rhs_eval (its record is overwritten). */
 grf_status grf_constraints(const grf_params* p, const grf_box* box, const double* u, double* out, void* workspace,
                            size_t workspace_bytes, hipStream_t stream);
+
+/* Energy densities (Key features, "Diagnostics": energy densities of the
+ * scalar terms of the action): per interior cell rho = n^a n^b T_ab of each
+ * term, the canonical kinetic term X, the g2 X^2 term and the Gauss-Bonnet
+ * coupling lambda(phi) L_GB, in units where the Hamiltonian constraint reads
+ * R + (2/3) K^2 - A_ij A^ij = 16 pi (rho_X + rho_X2 + rho_GB).  The three sum
+ * to the source of grf_constraints' Hamiltonian constraint.  Same stencils,
+ * arguments, workspace and errors as grf_constraints;
+ *   out  device [3][nz][ny][nx]: rho_X, rho_X2, rho_GB. */
+grf_status grf_energy_densities(const grf_params* p, const grf_box* box, const double* u, double* out,
+                                void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ---- Batched boxes (uneven sizes and refinement levels, frozen ghosts).
  * One RK4 step of the batch is four stages; each stage is one persistent

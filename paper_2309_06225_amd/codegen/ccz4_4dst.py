@@ -17,6 +17,8 @@ kernel), plus the pivots of the elimination (for the hyperbolicity flag).
 """
 from __future__ import annotations
 
+import math
+
 from .expr import Graph, Node
 
 NF = 27
@@ -365,4 +367,17 @@ def build(shift_advec: bool = False):
     # (with the pure Ricci scalar) and momentum M_i - 8 pi S_i
     constraints = [Hg - 2.0 * rho8] + [Mi[i] - S8i[i] for i in R3]
     return dict(graph=g, rhs=rhs, pivots=pivots, pivot_check=pivot_check, inputs=inputs, params=P,
-                theta=[P["lambda_gb"], P["g2"]], solution=x, constraints=constraints)
+                theta=[P["lambda_gb"], P["g2"]], solution=x, constraints=constraints,
+                scalar_parts=dict(X=X, Pi=Pi, GW=GW, g2=g2))
+
+
+def energies(b):
+    """Energy densities n^a n^b T_ab of the canonical, X^2 and Gauss-Bonnet
+    terms (the three pieces of rho8, divided by 8 pi), added to the graph of
+    build() on request only, so that the other outputs keep their node order."""
+    q = b["scalar_parts"]
+    X, Pi, GW, g2 = q["X"], q["Pi"], q["GW"], q["g2"]
+    inv8pi = 1.0 / (8.0 * math.pi)
+    return [(0.5 * Pi * Pi - 0.5 * X) * inv8pi,
+            g2 * (X * Pi * Pi - 0.5 * X * X) * inv8pi,
+            (-4.0 * GW) * inv8pi]

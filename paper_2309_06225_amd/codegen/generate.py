@@ -111,6 +111,18 @@ def constraints_code():
     return code, flops
 
 
+def energy_code():
+    """Energy densities of the canonical, X^2 and Gauss-Bonnet terms of one
+    cell: GRF_CON(q, v), q = 0, 1, 2."""
+    b = M.build(False)
+    g = b["graph"]
+    outs = M.energies(b)
+    names = [f"GRF_CON({q}, {{}})" for q in range(len(outs))]
+    code = emit(g, outs, names, input_expr, param_expr, order="dfs")
+    flops, ops = count_flops(g, outs)
+    return code, flops
+
+
 def vjp_code(shift_advec: bool):
     b = M.build(shift_advec)
     g = b["graph"]
@@ -173,6 +185,7 @@ def main(outdir: str):
         f"#define GRF_FLOPS_VJP {vfl0}",
         f"#define GRF_FLOPS_VJP_SHIFTADV {vfl1}",
         f"#define GRF_FLOPS_CONSTRAINTS {constraints_code()[1]}",
+        f"#define GRF_FLOPS_ENERGY {energy_code()[1]}",
         f"#define GRF_STAGE_SLOTS {STAGE_SLOTS}  // slots per buffer of the staged pointwise kernel",
         "// parameters read by the generated code (derived combinations precomputed on the host)",
         "struct grf_point_params {",
@@ -218,6 +231,11 @@ def main(outdir: str):
         fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
         fh.write(f"// Hamiltonian and momentum constraints: {cfl} flops/cell\n")
         fh.write("{\n" + PRAGMA + con + "\n}\n")
+    en, efl = energy_code()
+    with open(os.path.join(outdir, "gen_energy.inc"), "w") as fh:
+        fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
+        fh.write(f"// energy densities of the canonical, X^2 and Gauss-Bonnet terms: {efl} flops/cell\n")
+        fh.write("{\n" + PRAGMA + en + "\n}\n")
     with open(os.path.join(outdir, "gen_vjp.inc"), "w") as fh:
         fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
         fh.write(f"// vector-Jacobian product: {vfl0} flops/cell ({vops0})\n")

@@ -231,6 +231,7 @@ int64_t grf_flops_per_cell(int which) {
     case 1: return GRF_FLOPS_RHS_SHIFTADV;
     case 2: return GRF_FLOPS_VJP;
     case 3: return GRF_FLOPS_CONSTRAINTS;
+    case 4: return GRF_FLOPS_ENERGY;
     default: return -1;
   }
 }
@@ -339,8 +340,8 @@ grf_status grf_rk4_stage(const grf_params* p, const grf_box* box, int stage, dou
   return GRF_OK;
 }
 
-grf_status grf_constraints(const grf_params* p, const grf_box* box, const double* u, double* out, void* workspace,
-                           size_t workspace_bytes, hipStream_t stream) {
+static grf_status diagnostics(int which, const grf_params* p, const grf_box* box, const double* u, double* out,
+                              void* workspace, size_t workspace_bytes, hipStream_t stream) {
   grf_status s = common_checks(p, box, workspace, workspace_bytes);
   if (s != GRF_OK) return s;
   if (!u || !out) return fail(GRF_EINVAL, "u/out is null");
@@ -348,8 +349,18 @@ grf_status grf_constraints(const grf_params* p, const grf_box* box, const double
   grf_point_params pp = make_pp(p);
   double* D = (double*)((char*)workspace + kStatusBytes);
   GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, p->shift_advec != 0.0, nullptr, stream));
-  GRF_HIP_CHECK(launch_constraints(bd, pp, u, D, out, stream));
+  GRF_HIP_CHECK(launch_constraints(which, bd, pp, u, D, out, stream));
   return GRF_OK;
+}
+
+grf_status grf_constraints(const grf_params* p, const grf_box* box, const double* u, double* out, void* workspace,
+                           size_t workspace_bytes, hipStream_t stream) {
+  return diagnostics(0, p, box, u, out, workspace, workspace_bytes, stream);
+}
+
+grf_status grf_energy_densities(const grf_params* p, const grf_box* box, const double* u, double* out,
+                                void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  return diagnostics(1, p, box, u, out, workspace, workspace_bytes, stream);
 }
 
 grf_status grf_enforce(const grf_params* p, const grf_box* box, double* u, hipStream_t stream) {

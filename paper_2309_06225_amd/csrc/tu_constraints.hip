@@ -1,10 +1,13 @@
-// Constraint diagnostics (Hamiltonian and momentum constraints per interior
-// cell) from the derivative record of the stencil stage and the state.
+// Diagnostics per interior cell from the derivative record of the stencil
+// stage and the state: the Hamiltonian and momentum constraints (WHICH = 0)
+// and the energy densities of the canonical, X^2 and Gauss-Bonnet terms of the
+// action (WHICH = 1).
 #include "kernels_fwd.h"
 #include "launch.h"
 
 namespace grf {
 
+template <int WHICH>
 __global__ __launch_bounds__(kPointThreads) void k_constraints(BoxDev b, grf_point_params P,
                                                                const double* __restrict__ us,
                                                                const double* __restrict__ D,
@@ -20,17 +23,24 @@ __global__ __launch_bounds__(kPointThreads) void k_constraints(BoxDev b, grf_poi
 #define GRF_D(cc) D[(int64_t)(cc) * b.ncell + c]
 #define GRF_P(n) P.n
 #define GRF_CON(q, v) out[(int64_t)(q) * b.ncell + c] = (v)
+  if constexpr (WHICH == 0) {
 #include "gen/gen_constraints.inc"
+  } else {
+#include "gen/gen_energy.inc"
+  }
 #undef GRF_CON
 #undef GRF_P
 #undef GRF_D
 #undef GRF_U
 }
 
-hipError_t launch_constraints(const BoxDev& bd, const grf_point_params& pp, const double* u, const double* D,
-                              double* out, hipStream_t st) {
+hipError_t launch_constraints(int which, const BoxDev& bd, const grf_point_params& pp, const double* u,
+                              const double* D, double* out, hipStream_t st) {
   const int64_t nblk = (bd.ncell + kPointThreads - 1) / kPointThreads;
-  hipLaunchKernelGGL(k_constraints, dim3((unsigned)nblk), dim3(kPointThreads), 0, st, bd, pp, u, D, out);
+  if (which == 0)
+    hipLaunchKernelGGL(k_constraints<0>, dim3((unsigned)nblk), dim3(kPointThreads), 0, st, bd, pp, u, D, out);
+  else
+    hipLaunchKernelGGL(k_constraints<1>, dim3((unsigned)nblk), dim3(kPointThreads), 0, st, bd, pp, u, D, out);
   return hipGetLastError();
 }
 

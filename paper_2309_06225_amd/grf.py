@@ -66,6 +66,8 @@ def lib():
         L.grf_rhs_eval.argtypes = [P, B, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.grf_constraints.argtypes = [P, B, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.grf_constraints.restype = ctypes.c_int
+        L.grf_energy_densities.argtypes = [P, B, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.grf_energy_densities.restype = ctypes.c_int
         L.grf_rk4_stage.argtypes = [P, B, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.grf_fill_periodic.argtypes = [B, _vp, _vp]
         L.grf_enforce.argtypes = [P, B, _vp, _vp]
@@ -184,6 +186,15 @@ def constraints(params: Params, box: Box, u, ws, stream=None):
     _check(lib().grf_constraints(ctypes.byref(params), ctypes.byref(box), _ptr(u), _ptr(out), _ptr(ws),
                                  ws.numel() * 8, _stream(stream)))
     return out[0], out[1:]
+
+
+def energy_densities(params: Params, box: Box, u, ws, stream=None):
+    """-> (3, nz, ny, nx): energy densities of the canonical, X^2 and
+    Gauss-Bonnet terms on the interior."""
+    out = torch.empty((3, box.nz, box.ny, box.nx), dtype=torch.float64, device=u.device)
+    _check(lib().grf_energy_densities(ctypes.byref(params), ctypes.byref(box), _ptr(u), _ptr(out), _ptr(ws),
+                                      ws.numel() * 8, _stream(stream)))
+    return out
 
 
 def enforce(params: Params, box: Box, u, stream=None):

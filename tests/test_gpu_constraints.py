@@ -1,5 +1,6 @@
-"""GPU constraint diagnostics against the oracle, and the fourth-order
-self-convergence of the Hamiltonian constraint measured with the GPU path."""
+"""GPU diagnostics against the oracle: the constraints, the fourth-order
+self-convergence of the Hamiltonian constraint measured with the GPU path, and
+the energy densities of the three terms of the scalar action."""
 import numpy as np
 import pytest
 
@@ -30,6 +31,25 @@ def gpu_constraints(p, u, dx, bc=G.BC_FROZEN):
     return ham.cpu().numpy(), mom.cpu().numpy()
 
 
+def gpu_energy(p, u, dx, bc=G.BC_FROZEN):
+    ut = torch.from_numpy(u).to(DEV)
+    box = G.box_of(ut, dx, bc)
+    ws = G.alloc_workspace(G.workspace_bytes(box))
+    return G.energy_densities(G.make_params(p), box, ut, ws).cpu().numpy()
+
+
+def _case(case):
+    if case == "noise32":
+        return I.flat_noise_pulse(32, 0.25, seed=0), 0.25, G.BC_PERIODIC
+    dx, bc = 0.3, G.BC_FROZEN
+    u = I.puncture((21, 17, 13), dx, centre=(0.4, -0.2, 0.1), phi_fn=I.shell_pulse(0.1, 2.0))
+    rng = np.random.default_rng(4)
+    u[I.IDX["K"]] += 0.01 * rng.standard_normal(u[7].shape)
+    u[I.IDX["A11"]:I.IDX["A33"] + 1] += 0.01 * rng.standard_normal(u[8:14].shape)
+    u[I.IDX["Pi"]] += 0.01 * rng.standard_normal(u[26].shape)
+    return u, dx, bc
+
+
 def _rel(g, o):
     return np.abs(g - o).max() / max(np.abs(o).max(), 1e-300)
 
@@ -44,15 +64,7 @@ def test_flat_space_constraints_exactly_zero():
 def test_constraints_match_oracle(case):
     print("case: constraints", case, flush=True)
     p = I.default_params(lambda_gb=0.3, g2=0.05)
-    if case == "noise32":
-        u, dx, bc = I.flat_noise_pulse(32, 0.25, seed=0), 0.25, G.BC_PERIODIC
-    else:
-        dx, bc = 0.3, G.BC_FROZEN
-        u = I.puncture((21, 17, 13), dx, centre=(0.4, -0.2, 0.1), phi_fn=I.shell_pulse(0.1, 2.0))
-        rng = np.random.default_rng(4)
-        u[I.IDX["K"]] += 0.01 * rng.standard_normal(u[7].shape)
-        u[I.IDX["A11"]:I.IDX["A33"] + 1] += 0.01 * rng.standard_normal(u[8:14].shape)
-        u[I.IDX["Pi"]] += 0.01 * rng.standard_normal(u[26].shape)
+    u, dx, bc = _case(case)
     ho, mo = O.constraints(I.params_vector(p), u, dx)
     hg, mg = gpu_constraints(p, u, dx, bc)
     assert _rel(hg, ho) <= 1e-12, _rel(hg, ho)
@@ -87,3 +99,21 @@ def test_hamiltonian_self_convergence_fourth_order_gpu():
     coefs = np.array(coefs)
     order = np.log2(np.abs(coefs[0] - coefs[1]) / np.abs(coefs[1] - coefs[2]))
     assert np.all(np.abs(order - 4.0) < 0.3), order
+
+
+def test_flat_space_energy_densities_exactly_zero():
+    u = I.set_flat(I.empty_state((19, 13, 11)))
+    rho = gpu_energy(I.default_params(lambda_gb=0.3, g2=0.05), u, 0.25)
+    assert np.all(rho == 0.0)
+
+
+@pytest.mark.parametrize("case", ["noise32", "puncture_ragged"])
+def test_energy_densities_match_oracle(case):
+    print("case: energy densities", case, flush=True)
+    p = I.default_params(lambda_gb=0.3, g2=0.05)
+    u, dx, bc = _case(case)
+    ro = O.energy_densities(I.params_vector(p), u, dx)
+    rg = gpu_energy(p, u, dx, bc)
+    for q in range(3):
+        assert np.abs(ro[q]).max() > 0.0, q
+        assert _rel(rg[q], ro[q]) <= 1e-12, (q, _rel(rg[q], ro[q]))
