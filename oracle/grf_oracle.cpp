@@ -1046,6 +1046,187 @@ int rk4_steps(const Params<T>& P, const Box& b, int bc_periodic, double dt, int 
   return flags;
 }
 
+// ---------------------------------------------------------------- boundary rules
+// Key features, "Boundary Conditions": extrapolating, Sommerfeld (radiative),
+// reflective and periodic faces.  Faces are numbered x-, x+, y-, y+, z-, z+.
+// Every ghost cell belongs to exactly one face: the x face when its x index is
+// outside the interior, else the y face when its y index is, else the z face.
+// Frozen and Sommerfeld ghosts are evolved by the RK4 step (right-hand side 0
+// and the radiative right-hand side respectively); periodic, reflective and
+// extrapolating ghosts are refilled from the new state after every stage, the
+// z faces first, then y, then x, so that each face reads finished cells only.
+enum { FACE_FROZEN = 0, FACE_PERIODIC = 1, FACE_REFLECTIVE = 2, FACE_EXTRAPOLATING = 3, FACE_SOMMERFELD = 4 };
+
+struct BcSpec {
+  int rule[6];
+  int extrap_order;      // 0: copy the boundary cell, 1: linear through the two outermost interior cells
+  double origin[3];      // coordinates of the centre of interior cell (0, 0, 0)
+  double centre[3];      // centre of the radiative condition
+  double speed[NF];      // radiative speed per field
+  double asymptote[NF];  // value at infinity per field
+  int parity_phi;        // sign of phi and Pi under a reflection
+};
+
+// packed as doubles: rule[6], extrap_order, origin[3], centre[3], speed[27], asymptote[27], parity_phi
+BcSpec read_bc(const double* v) {
+  BcSpec s;
+  int q = 0;
+  for (int f = 0; f < 6; ++f) s.rule[f] = (int)v[q++];
+  s.extrap_order = (int)v[q++];
+  for (int d = 0; d < 3; ++d) s.origin[d] = v[q++];
+  for (int d = 0; d < 3; ++d) s.centre[d] = v[q++];
+  for (int f = 0; f < NF; ++f) s.speed[f] = v[q++];
+  for (int f = 0; f < NF; ++f) s.asymptote[f] = v[q++];
+  s.parity_phi = (int)v[q++];
+  return s;
+}
+
+// face owning cell (i, j, k), -1 for an interior cell
+int owner_face(const Box& b, int i, int j, int k) {
+  if (i < 0) return 0;
+  if (i >= b.nx) return 1;
+  if (j < 0) return 2;
+  if (j >= b.ny) return 3;
+  if (k < 0) return 4;
+  if (k >= b.nz) return 5;
+  return -1;
+}
+
+// Sign of field f under the reflection x_axis -> -x_axis: one factor -1 per
+// tensor index of the field along that axis (h_ij and A_ij two indices,
+// Gamma^i, beta^i and B^i one); the scalar and its momentum take parity_phi.
+int field_parity(int f, int axis, int parity_phi) {
+  if (f == PHI || f == PI_) return parity_phi;
+  int count = 0;
+  auto sym_pair = [&](int base) {
+    for (int a = 0; a < 3; ++a)
+      for (int c = a; c < 3; ++c)
+        if (f == base + SYM[a][c]) count = (a == axis) + (c == axis);
+  };
+  if (f >= H11 && f < H11 + 6) sym_pair(H11);
+  if (f >= A11 && f < A11 + 6) sym_pair(A11);
+  if (f >= GH1 && f < GH1 + 3) count = (f - GH1 == axis);
+  if (f >= SHIFT1 && f < SHIFT1 + 3) count = (f - SHIFT1 == axis);
+  if (f >= BB1 && f < BB1 + 3) count = (f - BB1 == axis);
+  return (count % 2) ? -1 : 1;
+}
+
+template <class T>
+void fill_faces(const Box& b, const BcSpec& bc, T* u) {
+  const int n[3] = {b.nx, b.ny, b.nz};
+  for (int axis = 2; axis >= 0; --axis) {
+    for (int k = -NG; k < b.nz + NG; ++k)
+      for (int j = -NG; j < b.ny + NG; ++j)
+        for (int i = -NG; i < b.nx + NG; ++i) {
+          const int face = owner_face(b, i, j, k);
+          if (face < 0 || face / 2 != axis) continue;
+          const int rule = bc.rule[face];
+          if (rule != FACE_PERIODIC && rule != FACE_REFLECTIVE && rule != FACE_EXTRAPOLATING) continue;
+          int idx[3] = {i, j, k};
+          const int m = idx[axis], na = n[axis];
+          const bool low = m < 0;
+          auto at = [&](int f, int mm) {
+            int q[3] = {idx[0], idx[1], idx[2]};
+            q[axis] = mm;
+            return u[f * b.fstride + cell_index(b, q[0], q[1], q[2])];
+          };
+          const int64_t dst = cell_index(b, i, j, k);
+          for (int f = 0; f < NF; ++f) {
+            T v;
+            if (rule == FACE_PERIODIC) {
+              v = at(f, ((m % na) + na) % na);
+            } else if (rule == FACE_REFLECTIVE) {
+              v = T(field_parity(f, axis, bc.parity_phi)) * at(f, low ? -1 - m : 2 * na - 1 - m);
+            } else {
+              const int e = low ? 0 : na - 1;      // outermost interior cell
+              const int e2 = low ? 1 : na - 2;     // its interior neighbour
+              const T ue = at(f, e);
+              v = bc.extrap_order == 0 ? ue : ue + T(double(std::abs(m - e))) * (ue - at(f, e2));
+            }
+            u[f * b.fstride + dst] = v;
+          }
+        }
+  }
+}
+
+// Radiative right-hand side of field f at ghost cell (i, j, k):
+//   d_t f = -v (x^a d_a f) / r - v (f - f_inf) / r,   x^a relative to the centre,
+// with second-order differences: one-sided towards the interior along the axes
+// on which the cell lies outside the interior, centred along the others.
+template <class T>
+T sommerfeld_rhs(const Box& b, const BcSpec& bc, const T* u, int f, int i, int j, int k) {
+  const int n[3] = {b.nx, b.ny, b.nz};
+  const int idx[3] = {i, j, k};
+  const T* uf = u + f * b.fstride;
+  auto at = [&](int axis, int off) {
+    int q[3] = {i, j, k};
+    q[axis] += off;
+    return uf[cell_index(b, q[0], q[1], q[2])];
+  };
+  double x[3];
+  double r2 = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    x[a] = bc.origin[a] + idx[a] * b.dx[a] - bc.centre[a];
+    r2 += x[a] * x[a];
+  }
+  const double r = std::sqrt(r2);
+  T xdf = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    T d;
+    if (idx[a] < 0)
+      d = (-3.0 * at(a, 0) + 4.0 * at(a, 1) - at(a, 2)) / (2.0 * b.dx[a]);
+    else if (idx[a] >= n[a])
+      d = (3.0 * at(a, 0) - 4.0 * at(a, -1) + at(a, -2)) / (2.0 * b.dx[a]);
+    else
+      d = (at(a, 1) - at(a, -1)) / (2.0 * b.dx[a]);
+    xdf += x[a] * d;
+  }
+  const T fv = at(0, 0);
+  return -bc.speed[f] * xdf / r - bc.speed[f] * (fv - bc.asymptote[f]) / r;
+}
+
+// right-hand side in the ghost cells: radiative on Sommerfeld faces, 0 elsewhere
+template <class T>
+void ghost_rhs(const Box& b, const BcSpec& bc, const T* u, T* rhs) {
+  for (int k = -NG; k < b.nz + NG; ++k)
+    for (int j = -NG; j < b.ny + NG; ++j)
+      for (int i = -NG; i < b.nx + NG; ++i) {
+        const int face = owner_face(b, i, j, k);
+        if (face < 0) continue;
+        const int64_t c = cell_index(b, i, j, k);
+        for (int f = 0; f < NF; ++f)
+          rhs[f * b.fstride + c] = bc.rule[face] == FACE_SOMMERFELD ? sommerfeld_rhs(b, bc, u, f, i, j, k) : T(0.0);
+      }
+}
+
+// classic RK4 over interior and ghost cells with the face rules above
+template <class T>
+int rk4_steps_bc(const Params<T>& P, const Box& b, const BcSpec& bc, double dt, int nsteps, T* u) {
+  const int64_t ntot = b.fstride * NF;
+  std::vector<T> k1(ntot), k2(ntot), k3(ntot), k4(ntot), us(ntot);
+  int flags = 0;
+  auto rhs_all = [&](const T* v, std::vector<T>& kk) {
+    flags |= box_rhs(P, b, v, kk.data(), (T*)nullptr, (T*)nullptr);
+    ghost_rhs(b, bc, v, kk.data());
+  };
+  for (int step = 0; step < nsteps; ++step) {
+    auto stage_state = [&](const std::vector<T>& kk, double c) {
+      for (int64_t q = 0; q < ntot; ++q) us[q] = u[q] + c * dt * kk[q];
+      fill_faces(b, bc, us.data());
+    };
+    rhs_all(u, k1);
+    stage_state(k1, 0.5);
+    rhs_all(us.data(), k2);
+    stage_state(k2, 0.5);
+    rhs_all(us.data(), k3);
+    stage_state(k3, 1.0);
+    rhs_all(us.data(), k4);
+    for (int64_t q = 0; q < ntot; ++q) u[q] = u[q] + (dt / 6.0) * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
+    fill_faces(b, bc, u);
+  }
+  return flags;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- C ABI
@@ -1111,6 +1292,26 @@ int oracle_energy_densities(const double* params, const int* dims, const double*
   Box b = make_box(dims, spacing);
   Params<double> P = read_params<double>(params, nullptr);
   return box_rhs(P, b, u, (double*)nullptr, (double*)nullptr, (double*)nullptr, rho);
+}
+
+// Fill the ghosts of periodic, reflective and extrapolating faces (bc packed as above).
+void oracle_fill_bc(const int* dims, const double* spacing, const double* bcv, double* u) {
+  Box b = make_box(dims, spacing);
+  fill_faces(b, read_bc(bcv), u);
+}
+
+// Ghost right-hand side (radiative on Sommerfeld faces, 0 on other ghosts); interior of rhs untouched.
+void oracle_ghost_rhs(const int* dims, const double* spacing, const double* bcv, const double* u, double* rhs) {
+  Box b = make_box(dims, spacing);
+  ghost_rhs(b, read_bc(bcv), u, rhs);
+}
+
+// nsteps RK4 steps in place with per-face boundary rules.
+int oracle_rk4_bc(const double* params, const int* dims, const double* spacing, const double* bcv, double dt,
+                  int nsteps, double* u) {
+  Box b = make_box(dims, spacing);
+  Params<double> P = read_params<double>(params, nullptr);
+  return rk4_steps_bc(P, b, read_bc(bcv), dt, nsteps, u);
 }
 
 void oracle_fill_periodic(const int* dims, double* u) {

@@ -52,6 +52,9 @@ def lib():
         L.oracle_constraints.argtypes = [_dp, _ip, _dp, _dp, _dp, _dp]
         L.oracle_energy_densities.argtypes = [_dp, _ip, _dp, _dp, _dp]
         L.oracle_fill_periodic.argtypes = [_ip, _dp]
+        L.oracle_fill_bc.argtypes = [_ip, _dp, _dp, _dp]
+        L.oracle_ghost_rhs.argtypes = [_ip, _dp, _dp, _dp, _dp]
+        L.oracle_rk4_bc.argtypes = [_dp, _ip, _dp, _dp, ctypes.c_double, ctypes.c_int, _dp]
         L.oracle_rk4.argtypes = [_dp, _ip, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp]
         L.oracle_rk4_cs.argtypes = [_dp, _dp, _ip, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp, _dp]
         L.oracle_rhs_point.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, _dp]
@@ -141,6 +144,50 @@ def energy_densities(params, u, dx):
     lib().oracle_energy_densities(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(u), _d(rho))
     s = (slice(NG, -NG),) * 3
     return rho[(slice(0, 3),) + s]
+
+
+FACE_RULES = {"frozen": 0, "periodic": 1, "reflective": 2, "extrapolating": 3, "sommerfeld": 4}
+
+
+def pack_bc(bc):
+    """Boundary rules as the oracle reads them.  bc: dict with `rules` (six of
+    FACE_RULES' names, faces x-, x+, y-, y+, z-, z+), `extrap_order`, `origin`
+    (coordinates of interior cell (0,0,0)), `centre`, `speed[27]`,
+    `asymptote[27]`, `parity_phi`."""
+    v = [float(FACE_RULES[r]) for r in bc["rules"]] + [float(bc.get("extrap_order", 1))]
+    v += [float(x) for x in bc.get("origin", (0.0, 0.0, 0.0))] + [float(x) for x in bc.get("centre", (0.0, 0.0, 0.0))]
+    v += [float(x) for x in bc.get("speed", np.ones(NF))] + [float(x) for x in bc.get("asymptote", np.zeros(NF))]
+    v += [float(bc.get("parity_phi", 1))]
+    assert len(v) == 68
+    return np.array(v)
+
+
+def fill_bc(u, dx, bc):
+    """Ghosts of periodic, reflective and extrapolating faces refilled (new state)."""
+    u = _c(u).copy()
+    dims = _dims(u)
+    lib().oracle_fill_bc(dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(pack_bc(bc)), _d(u))
+    return u
+
+
+def ghost_rhs(u, dx, bc):
+    """Right-hand side in the ghost cells (radiative on Sommerfeld faces, 0 on
+    the others); interior cells are 0."""
+    u = _c(u)
+    r = np.zeros_like(u)
+    dims = _dims(u)
+    lib().oracle_ghost_rhs(dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(pack_bc(bc)), _d(u), _d(r))
+    return r
+
+
+def rk4_bc(params, u, dx, dt, nsteps, bc):
+    """nsteps classic RK4 steps with per-face boundary rules; (state, flags)."""
+    u = _c(u).copy()
+    p = _c(params)
+    dims = _dims(u)
+    flags = lib().oracle_rk4_bc(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(pack_bc(bc)), float(dt),
+                                int(nsteps), _d(u))
+    return u, flags
 
 
 def fill_periodic(u):

@@ -1,0 +1,289 @@
+"""Pins of the oracle's boundary rules (Key features, "Boundary Conditions":
+extrapolating, Sommerfeld, reflective and periodic faces) against geometry,
+brute force and closed forms, and of its RK4 with face rules against its
+plain RK4."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2309_06225_amd import inputs as I
+
+NF, NG = I.NF, I.NG
+IDX = I.IDX
+FACES = ("x-", "x+", "y-", "y+", "z-", "z+")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _build():
+    O.build(force=False)
+
+
+def _axes(dims, h, origin):
+    """Coordinates of every cell (ghosts included) along x, y, z."""
+    return [origin[a] + h * np.arange(-NG, dims[a] + NG, dtype=np.float64) for a in range(3)]
+
+
+def _grid(dims, h, origin):
+    x, y, z = _axes(dims, h, origin)
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    return X, Y, Z
+
+
+def _bc(rules, **kw):
+    d = dict(rules=rules)
+    d.update(kw)
+    return d
+
+
+def _ghost_mask(dims):
+    nx, ny, nz = dims
+    m = np.ones((nz + 2 * NG, ny + 2 * NG, nx + 2 * NG), bool)
+    m[NG:-NG, NG:-NG, NG:-NG] = False
+    return m
+
+
+def _face_mask(dims, face):
+    """Ghost cells owned by a face: the x face when x is outside the interior,
+    else y, else z."""
+    nx, ny, nz = dims
+    k, j, i = np.meshgrid(np.arange(-NG, nz + NG), np.arange(-NG, ny + NG), np.arange(-NG, nx + NG), indexing="ij")
+    out_x = (i < 0) | (i >= nx)
+    out_y = (j < 0) | (j >= ny)
+    out_z = (k < 0) | (k >= nz)
+    sel = {"x-": i < 0, "x+": i >= nx,
+           "y-": ~out_x & (j < 0), "y+": ~out_x & (j >= ny),
+           "z-": ~out_x & ~out_y & (k < 0), "z+": ~out_x & ~out_y & (k >= nz)}
+    return sel[face]
+
+
+# ------------------------------------------------------------------ reflective
+def _symmetric_state(dims, h, origin, axis, phi_odd):
+    """Fields built covariantly from a scalar S that is even under the
+    reflection x_axis -> -x_axis: tensors from derivatives of S transform as
+    tensors, so their reflected values follow from geometry alone."""
+    X = _grid(dims, h, origin)
+    cen = [0.3, -0.4, 0.2]
+    cen[axis] = 0.0
+    q = [X[a] - cen[a] for a in range(3)]
+    w = 1.7
+    S = np.exp(-(q[0] ** 2 + q[1] ** 2 + q[2] ** 2) / w)
+    dS = [-2.0 * q[a] / w * S for a in range(3)]
+    ddS = [[(4.0 * q[a] * q[b] / w ** 2 - (2.0 / w if a == b else 0.0)) * S for b in range(3)] for a in range(3)]
+    u = I.empty_state(dims)
+    sym = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    u[IDX["chi"]] = 1.0 + 0.1 * S
+    u[IDX["K"]] = S
+    u[IDX["Theta"]] = 0.2 * S
+    u[IDX["lapse"]] = 1.0 + 0.1 * S
+    for n, (a, b) in enumerate(sym):
+        u[IDX["h11"] + n] = (1.0 if a == b else 0.0) + 0.05 * ddS[a][b]
+        u[IDX["A11"] + n] = 0.1 * ddS[a][b]
+    for a in range(3):
+        u[IDX["Gam1"] + a] = dS[a]
+        u[IDX["shift1"] + a] = 0.1 * dS[a]
+        u[IDX["B1"] + a] = 0.3 * dS[a]
+    # a scalar even (or odd) under the reflection
+    u[IDX["phi"]] = (q[axis] if phi_odd else 1.0) * S
+    u[IDX["Pi"]] = 0.5 * (q[axis] if phi_odd else 1.0) * S
+    return u
+
+
+@pytest.mark.parametrize("face", FACES)
+@pytest.mark.parametrize("phi_odd", [False, True])
+def test_reflective_matches_tensor_transformation(face, phi_odd):
+    dims, h = (6, 5, 7), 0.25
+    axis = "xyz".index(face[0])
+    # put the reflection plane on the chosen face: low face at 0, high face at n h
+    origin = [0.5 * h - 0.8, 0.5 * h + 0.3, 0.5 * h - 0.6]
+    origin[axis] = 0.5 * h if face[1] == "-" else 0.5 * h - dims[axis] * h
+    u = _symmetric_state(dims, h, origin, axis, phi_odd)
+    rules = ["frozen"] * 6
+    rules[FACES.index(face)] = "reflective"
+    m = _face_mask(dims, face)
+    junk = u.copy()
+    junk[:, m] = 123.0
+    got = O.fill_bc(junk, h, _bc(rules, parity_phi=-1 if phi_odd else 1))
+    np.testing.assert_allclose(got[:, m], u[:, m], rtol=0, atol=1e-15)
+    other = _ghost_mask(dims) & ~m
+    assert np.array_equal(got[:, other], junk[:, other])   # other faces untouched
+    assert np.array_equal(got[:, ~_ghost_mask(dims)], junk[:, ~_ghost_mask(dims)])
+
+
+# ------------------------------------------------------------------ extrapolating
+def test_extrapolating_first_order_exact_on_linear_functions():
+    dims, h = (5, 6, 4), 0.5
+    X, Y, Z = _grid(dims, h, (0.1, -0.2, 0.3))
+    rng = np.random.default_rng(0)
+    u = I.empty_state(dims)
+    for f in range(NF):
+        a = rng.standard_normal(4)
+        u[f] = a[0] + a[1] * X + a[2] * Y + a[3] * Z
+    junk = u.copy()
+    junk[:, _ghost_mask(dims)] = -7.0
+    got = O.fill_bc(junk, h, _bc(["extrapolating"] * 6, extrap_order=1))
+    np.testing.assert_allclose(got, u, rtol=0, atol=1e-12)
+
+
+def test_extrapolating_zeroth_order_is_clamped_copy():
+    dims = (5, 6, 4)
+    rng = np.random.default_rng(1)
+    u = rng.standard_normal((NF, dims[2] + 6, dims[1] + 6, dims[0] + 6))
+    got = O.fill_bc(u, 0.5, _bc(["extrapolating"] * 6, extrap_order=0))
+    # brute force: every ghost takes the interior cell nearest to it index by index
+    nx, ny, nz = dims
+    for k in range(nz + 6):
+        for j in range(ny + 6):
+            for i in range(nx + 6):
+                ci, cj, ck = (min(max(i, NG), nx + NG - 1), min(max(j, NG), ny + NG - 1),
+                              min(max(k, NG), nz + NG - 1))
+                assert np.array_equal(got[:, k, j, i], u[:, ck, cj, ci])
+
+
+def test_periodic_faces_equal_numpy_wrap():
+    dims = (5, 6, 4)
+    rng = np.random.default_rng(2)
+    u = rng.standard_normal((NF, dims[2] + 6, dims[1] + 6, dims[0] + 6))
+    got = O.fill_bc(u, 0.5, _bc(["periodic"] * 6))
+    inner = u[:, NG:-NG, NG:-NG, NG:-NG]
+    want = np.pad(inner, ((0, 0), (NG, NG), (NG, NG), (NG, NG)), mode="wrap")
+    assert np.array_equal(got, want)
+
+
+def test_mixed_faces_each_ghost_owned_once():
+    """x periodic, y reflective, z extrapolating: the ghosts of each face follow
+    that face's rule, x ghosts at y/z ghost positions copy finished y/z ghosts."""
+    dims, h = (4, 5, 6), 0.25
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal((NF, dims[2] + 6, dims[1] + 6, dims[0] + 6))
+    bc = _bc(["periodic", "periodic", "reflective", "reflective", "extrapolating", "extrapolating"],
+             extrap_order=0, parity_phi=1)
+    got = O.fill_bc(u, h, bc)
+    nx, ny, nz = dims
+    # z ghosts (x, y interior): clamped copy along z
+    for k in list(range(NG)) + list(range(nz + NG, nz + 2 * NG)):
+        ck = NG if k < NG else nz + NG - 1
+        assert np.array_equal(got[:, k, NG:-NG, NG:-NG], u[:, ck, NG:-NG, NG:-NG])
+    # y ghosts (x interior, any z): mirrored along y with the field's parity along y
+    par = np.ones(NF)
+    for n in ("h12", "h23", "A12", "A23", "Gam2", "shift2", "B2"):
+        par[IDX[n]] = -1.0
+    for j in list(range(NG)) + list(range(ny + NG, ny + 2 * NG)):
+        mj = 2 * NG - 1 - j if j < NG else 2 * (ny + NG) - 1 - j
+        np.testing.assert_array_equal(got[:, :, j, NG:-NG], par[:, None, None] * got[:, :, mj, NG:-NG])
+    # x ghosts (any y, z): periodic copy of the finished cells
+    for i in list(range(NG)) + list(range(nx + NG, nx + 2 * NG)):
+        si = (i - NG) % nx + NG
+        assert np.array_equal(got[:, :, :, i], got[:, :, :, si])
+
+
+# ------------------------------------------------------------------ Sommerfeld
+def test_sommerfeld_exact_on_quadratics():
+    """The one-sided and centred second-order differences are exact on
+    quadratics, so the radiative right-hand side takes its closed form
+    -v (x . grad q + q - q_inf) / r in every ghost cell."""
+    dims, h = (6, 5, 7), 0.25
+    origin, centre = (1.0, -2.0, 0.5), (-3.0, 1.0, -4.0)
+    X, Y, Z = _grid(dims, h, origin)
+    rng = np.random.default_rng(4)
+    u = I.empty_state(dims)
+    want = np.zeros_like(u)
+    speed = 0.5 + rng.random(NF)
+    asym = rng.standard_normal(NF)
+    xr, yr, zr = X - centre[0], Y - centre[1], Z - centre[2]
+    r = np.sqrt(xr * xr + yr * yr + zr * zr)
+    for f in range(NF):
+        c = rng.standard_normal(10)
+        q = (c[0] + c[1] * X + c[2] * Y + c[3] * Z + c[4] * X * X + c[5] * Y * Y + c[6] * Z * Z
+             + c[7] * X * Y + c[8] * Y * Z + c[9] * X * Z)
+        gx = c[1] + 2 * c[4] * X + c[7] * Y + c[9] * Z
+        gy = c[2] + 2 * c[5] * Y + c[7] * X + c[8] * Z
+        gz = c[3] + 2 * c[6] * Z + c[8] * Y + c[9] * X
+        u[f] = q
+        want[f] = -speed[f] * (xr * gx + yr * gy + zr * gz) / r - speed[f] * (q - asym[f]) / r
+    bc = _bc(["sommerfeld"] * 6, origin=origin, centre=centre, speed=speed, asymptote=asym)
+    got = O.ghost_rhs(u, h, bc)
+    g = _ghost_mask(dims)
+    scale = np.abs(want[:, g]).max()
+    np.testing.assert_allclose(got[:, g], want[:, g], rtol=0, atol=1e-12 * scale)
+    assert np.all(got[:, ~g] == 0.0)
+
+
+def test_sommerfeld_second_order_on_outgoing_wave():
+    """f = f_inf + g(r - v t)/r solves the radiative condition exactly; the
+    discrete right-hand side converges to -v g'(r)/r at second order."""
+    v, finf = 0.8, 0.3
+    centre = (0.0, 0.0, 0.0)
+
+    def gfun(s):
+        return np.exp(-((s - 6.0) ** 2) / 4.0)
+
+    def dg(s):
+        return -(s - 6.0) / 2.0 * gfun(s)
+
+    errs = []
+    for h in (0.2, 0.1, 0.05):
+        n = int(round(2.0 / h))
+        dims = (n, n, n)
+        origin = (4.0, 1.0, 0.5)
+        X, Y, Z = _grid(dims, h, origin)
+        r = np.sqrt(X * X + Y * Y + Z * Z)
+        u = I.empty_state(dims)
+        u[:] = finf + gfun(r) / r
+        bc = _bc(["sommerfeld"] * 6, origin=origin, centre=centre, speed=np.full(NF, v),
+                 asymptote=np.full(NF, finf))
+        got = O.ghost_rhs(u, h, bc)[0]
+        want = -v * dg(r) / r
+        m = _ghost_mask(dims)
+        errs.append(np.abs(got[m] - want[m]).max())
+    order = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(order - 2.0) < 0.25), (errs, order)
+
+
+# ------------------------------------------------------------------ RK4 with face rules
+def _noise_state(n, seed):
+    return I.flat_noise_pulse(n, 0.25, seed=seed)
+
+
+def test_rk4_bc_all_frozen_equals_plain_rk4():
+    p = I.params_vector(I.default_params(lambda_gb=0.3, g2=0.05))
+    u = _noise_state(8, 5)
+    a, fa = O.rk4(p, u, 0.25, 0.05, 2, periodic=False)
+    b, fb = O.rk4_bc(p, u, 0.25, 0.05, 2, _bc(["frozen"] * 6))
+    assert fa == fb and np.array_equal(a, b)
+
+
+def test_rk4_bc_all_periodic_equals_plain_periodic_rk4():
+    p = I.params_vector(I.default_params(lambda_gb=0.3, g2=0.05))
+    u = O.fill_periodic(_noise_state(8, 6))
+    a, _ = O.rk4(p, u, 0.25, 0.05, 2, periodic=True)
+    b, _ = O.rk4_bc(p, u, 0.25, 0.05, 2, _bc(["periodic"] * 6))
+    assert np.array_equal(a, b)
+
+
+def test_rk4_bc_sommerfeld_ghosts_follow_the_radiative_rule():
+    """One step on a flat background with a scalar perturbation: the ghost
+    cells of a Sommerfeld face change by dt/6 (k1 + 2k2 + 2k3 + k4) of the
+    radiative right-hand side, checked by recomputing the stages from the
+    oracle's pieces; fill faces stay consistent with their rule."""
+    p = I.params_vector(I.default_params())
+    dims, h, dt = (6, 6, 6), 0.25, 0.05
+    u = I.set_flat(I.empty_state(dims))
+    X, Y, Z = _grid(dims, h, (2.0, 0.1, -0.2))
+    u[IDX["phi"]] = 0.01 * np.exp(-((X - 2.5) ** 2 + Y ** 2 + Z ** 2))
+    bc = _bc(["sommerfeld", "sommerfeld", "reflective", "reflective", "extrapolating", "frozen"],
+             origin=(2.0, 0.1, -0.2), centre=(0.0, 0.0, 0.0), asymptote=I.set_flat(I.empty_state((1, 1, 1)))[:, 3, 3, 3])
+    got, flags = O.rk4_bc(p, u, h, dt, 1, bc)
+    assert flags == 0
+    # the same step assembled from the oracle's interior right-hand side and ghost right-hand side
+    def rhs_all(v):
+        r, _ = O.rhs(p, v, h)
+        return r + O.ghost_rhs(v, h, bc)
+    k1 = rhs_all(u)
+    k2 = rhs_all(O.fill_bc(u + 0.5 * dt * k1, h, bc))
+    k3 = rhs_all(O.fill_bc(u + 0.5 * dt * k2, h, bc))
+    k4 = rhs_all(O.fill_bc(u + dt * k3, h, bc))
+    want = O.fill_bc(u + dt / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4), h, bc)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-15)
+    som = _face_mask(dims, "x-") | _face_mask(dims, "x+")
+    assert np.abs(got[IDX["phi"]][som] - u[IDX["phi"]][som]).max() > 1e-6   # the radiative ghosts moved
+    assert np.array_equal(got[:, _face_mask(dims, "z+")], u[:, _face_mask(dims, "z+")])  # frozen face
