@@ -79,7 +79,8 @@ typedef struct {
 } grf_params;
 
 /* One box: nx, ny, nz interior cells, ng ghosts (must be 3), spacing dx, dy,
- * dz, coordinates x0, y0, z0 of interior cell (0,0,0) (informational),
+ * dz, coordinates x0, y0, z0 of the centre of interior cell (0,0,0) (read by
+ * the radiative boundary rule only),
  * field_stride >= (nx+6)(ny+6)(nz+6), boundary rule bc. */
 typedef struct {
   int32_t nx, ny, nz, ng;
@@ -122,6 +123,72 @@ grf_status grf_enforce(const grf_params* p, const grf_box* box, double* u, hipSt
 /* Periodic ghost fill of a state (every ghost copies the interior cell congruent
  * to it modulo the box size), on the device. */
 grf_status grf_fill_periodic(const grf_box* box, double* u, hipStream_t stream);
+
+/* ---- Boundary rules per face (Key features, "Boundary Conditions": periodic,
+ * reflective, extrapolating and Sommerfeld (radiative) faces).
+ * Faces are numbered x-, x+, y-, y+, z-, z+.  Every ghost cell belongs to one
+ * face: the x face when its x index lies outside the interior, else the y face
+ * when its y index does, else the z face.
+ *   frozen:        the ghost is integrated with right-hand side 0 (keeps its value);
+ *   periodic:      copies the interior cell congruent to it along the face's axis
+ *                  (both faces of that axis must be periodic);
+ *   reflective:    copies the mirror cell across the face (ghost layer d <-> interior
+ *                  layer d), times -1 per tensor index of the field along the face's
+ *                  axis (h_ij, A_ij: two indices; Gamma^i, beta^i, B^i: one;
+ *                  phi and Pi: parity_phi);
+ *   extrapolating: order 0 copies the outermost interior cell along the axis,
+ *                  order 1 extends the line through the two outermost interior cells;
+ *   sommerfeld:    the ghost is integrated with the radiative right-hand side
+ *                  d_t f = -v (x^a d_a f + f - f_inf) / r, x^a = position - centre
+ *                  (cell (i,j,k) at (x0 + i dx, y0 + j dy, z0 + k dz)),
+ *                  r = |x^a|, with second-order differences (one-sided towards the
+ *                  interior along the axes on which the cell is a ghost, centred
+ *                  along the others).
+ * After each RK4 stage the periodic, reflective and extrapolating ghosts are
+ * refilled from the new state, z faces first, then y, then x, so every face
+ * reads only cells that are final. */
+enum { GRF_FACE_FROZEN = 0, GRF_FACE_PERIODIC = 1, GRF_FACE_REFLECTIVE = 2, GRF_FACE_EXTRAPOLATING = 3,
+       GRF_FACE_SOMMERFELD = 4 };
+typedef struct {
+  int32_t rule[6];         /* GRF_FACE_* per face x-, x+, y-, y+, z-, z+ */
+  int32_t extrap_order;    /* 0 or 1 (extrapolating faces) */
+  int32_t parity_phi;      /* +1 or -1: sign of phi and Pi under a reflection */
+  double centre[3];        /* centre of the radiative rule (coordinates as the box's x0, y0,
+                              z0); must not be a ghost cell centre */
+  double speed[27];        /* radiative speed v per field (finite) */
+  double asymptote[27];    /* f_inf per field (finite) */
+} grf_bc;
+
+/* Number of ghost cells of a box ((nx+6)(ny+6)(nz+6) - nx ny nz); the ghost
+ * accumulator of grf_rk4_stage_bc holds 27 times as many doubles.  0 for an
+ * invalid box. */
+int64_t grf_bc_ghost_cells(const grf_box* box);
+
+/* Refill the ghosts of the periodic, reflective and extrapolating faces of u
+ * (device, state layout) from u; other ghosts and the interior untouched.
+ * Errors: GRF_EINVAL for an invalid rule, an unpaired periodic face, an
+ * extrapolation order other than 0/1, a parity other than +-1, a reflective
+ * face on an axis with fewer than 3 cells or an order-1 extrapolating face on
+ * one with fewer than 2. */
+grf_status grf_bc_fill(const grf_bc* bc, const grf_box* box, double* u, hipStream_t stream);
+
+/* Ghost right-hand side: every ghost cell of rhs (device, state layout) gets
+ * the radiative right-hand side of u on Sommerfeld faces and 0 on the others;
+ * interior cells of rhs untouched.  Errors as grf_bc_fill, plus GRF_EINVAL when
+ * the centre is a ghost cell centre or a speed/asymptote is not finite. */
+grf_status grf_bc_ghost_rhs(const grf_bc* bc, const grf_box* box, const double* u, double* rhs,
+                            hipStream_t stream);
+
+/* One RK4 stage with per-face rules: the interior exactly as grf_rk4_stage
+ * with a frozen box (box->bc is not used), the Sommerfeld ghosts with the same
+ * stage formulas on their radiative right-hand side (gacc: device,
+ * [27][grf_bc_ghost_cells] doubles, their accumulator, caller-owned), then
+ * the refill of grf_bc_fill on unext.  Frozen ghosts of unext are not written.
+ * The state passed as u0 at stage 1 must have its fill-rule ghosts filled
+ * (grf_bc_fill).  Errors as grf_rk4_stage and grf_bc_ghost_rhs. */
+grf_status grf_rk4_stage_bc(const grf_params* p, const grf_box* box, const grf_bc* bc, int stage, double dt,
+                            const double* u0, const double* us, double* unext, double* acc, double* gacc,
+                            void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* Vector-Jacobian product of the right-hand side: with w a cotangent of
  * grf_rhs_eval's output (state layout, interior cells read),

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/grf.h"
 #include "gen/gen_layout.h"
 
 namespace grf {
@@ -36,6 +37,22 @@ constexpr int kPeakChains = 8;  // independent FMA chains per thread of the FP64
 hipError_t launch_fma_peak(int blocks, int iters, double* out, hipStream_t st);
 hipError_t launch_copy_peak(int blocks, int64_t n, const double* x, double* y, hipStream_t st);
 hipError_t launch_enforce(const BoxDev& bd, double* u, double chi_min, double lapse_min, hipStream_t st);
+
+// per-face boundary rules, device form of grf_bc (sign: reflection parity per axis and field)
+struct BcDev {
+  int rule[6];
+  int extrap_order;
+  double origin[3], centre[3], h[3], i2h[3];
+  double speed[GRF_NFIELDS], asymptote[GRF_NFIELDS];
+  double sign[3][GRF_NFIELDS];
+};
+int64_t ghost_cells(const BoxDev& bd);
+// refill of the periodic, reflective and extrapolating ghosts (z, y, x)
+hipError_t launch_bc_fill(const BoxDev& bd, const BcDev& bc, double* u, hipStream_t st);
+// mode 0: radiative right-hand side into the ghosts of out (0 off Sommerfeld faces);
+// 1, 2, 4: RK4 stage update of the Sommerfeld ghosts of out
+hipError_t launch_bc_ghost(int mode, const BoxDev& bd, const BcDev& bc, const double* us, const double* u0,
+                           double* out, double* gacc, const StageCoef& sc, hipStream_t st);
 
 // pointwise right-hand side + stage update (mode 0, 1, 2, 4)
 template <int MODE>

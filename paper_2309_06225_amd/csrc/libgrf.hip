@@ -301,9 +301,20 @@ grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u
   return GRF_OK;
 }
 
+static grf_status rk4_stage_impl(const grf_params* p, const grf_box* box, int stage, double dt, const double* u0,
+                                 const double* us, double* unext, double* acc, void* workspace,
+                                 size_t workspace_bytes, hipStream_t stream, bool box_ghosts);
+
 grf_status grf_rk4_stage(const grf_params* p, const grf_box* box, int stage, double dt, const double* u0,
                          const double* us, double* unext, double* acc, void* workspace, size_t workspace_bytes,
                          hipStream_t stream) {
+  return rk4_stage_impl(p, box, stage, dt, u0, us, unext, acc, workspace, workspace_bytes, stream, true);
+}
+
+// interior stage; box_ghosts: apply the box's own ghost rule (periodic fill)
+static grf_status rk4_stage_impl(const grf_params* p, const grf_box* box, int stage, double dt, const double* u0,
+                                 const double* us, double* unext, double* acc, void* workspace,
+                                 size_t workspace_bytes, hipStream_t stream, bool box_ghosts) {
   grf_status s = common_checks(p, box, workspace, workspace_bytes);
   if (s != GRF_OK) return s;
   if (stage < 1 || stage > 4) return fail(GRF_EINVAL, "stage must be 1..4 (got %d)", stage);
@@ -336,7 +347,130 @@ grf_status grf_rk4_stage(const grf_params* p, const grf_box* box, int stage, dou
     prof_mark(1, stream);
   }
   if (p->enforce) GRF_HIP_CHECK(launch_enforce(bd, unext, p->chi_min, p->lapse_min, stream));
-  if (box->bc == GRF_BC_PERIODIC) GRF_HIP_CHECK(launch_periodic(bd, unext, stream));
+  if (box_ghosts && box->bc == GRF_BC_PERIODIC) GRF_HIP_CHECK(launch_periodic(bd, unext, stream));
+  return GRF_OK;
+}
+
+// ---- per-face boundary rules
+
+// tensor indices of each field along each axis (reflection sign = (-1)^count)
+static int index_count(int f, int axis) {
+  static const int sym[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};  // h_ij / A_ij packing
+  if (f >= 1 && f <= 6) return (sym[f - 1][0] == axis) + (sym[f - 1][1] == axis);    // h_ij
+  if (f >= 8 && f <= 13) return (sym[f - 8][0] == axis) + (sym[f - 8][1] == axis);   // A_ij
+  if (f >= 15 && f <= 17) return f - 15 == axis;                                     // Gamma^i
+  if (f >= 19 && f <= 21) return f - 19 == axis;                                     // beta^i
+  if (f >= 22 && f <= 24) return f - 22 == axis;                                     // B^i
+  return 0;
+}
+
+static grf_status make_bcdev(const grf_bc* bc, const grf_box* box, bool radiative, BcDev& d) {
+  if (!bc) return fail(GRF_EINVAL, "bc is null");
+  const int n[3] = {box->nx, box->ny, box->nz};
+  const double h[3] = {box->dx, box->dy, box->dz};
+  for (int f = 0; f < 6; ++f) {
+    const int r = bc->rule[f];
+    if (r < GRF_FACE_FROZEN || r > GRF_FACE_SOMMERFELD) return fail(GRF_EINVAL, "face %d: unknown rule %d", f, r);
+    const int axis = f / 2;
+    if (r == GRF_FACE_PERIODIC && bc->rule[f ^ 1] != GRF_FACE_PERIODIC)
+      return fail(GRF_EINVAL, "face %d: periodic faces come in pairs", f);
+    if (r == GRF_FACE_REFLECTIVE && n[axis] < 3) return fail(GRF_EINVAL, "face %d: reflective needs >= 3 cells", f);
+    if (r == GRF_FACE_EXTRAPOLATING && bc->extrap_order == 1 && n[axis] < 2)
+      return fail(GRF_EINVAL, "face %d: linear extrapolation needs >= 2 cells", f);
+    d.rule[f] = r;
+  }
+  if (bc->extrap_order != 0 && bc->extrap_order != 1) return fail(GRF_EINVAL, "extrap_order must be 0 or 1");
+  if (bc->parity_phi != 1 && bc->parity_phi != -1) return fail(GRF_EINVAL, "parity_phi must be +1 or -1");
+  d.extrap_order = bc->extrap_order;
+  const double origin[3] = {box->x0, box->y0, box->z0};
+  for (int a = 0; a < 3; ++a) {
+    d.origin[a] = origin[a];
+    d.centre[a] = bc->centre[a];
+    d.h[a] = h[a];
+    d.i2h[a] = 1.0 / (2.0 * h[a]);
+    for (int f = 0; f < NF; ++f)
+      d.sign[a][f] = (f == 25 || f == 26) ? (double)bc->parity_phi : ((index_count(f, a) & 1) ? -1.0 : 1.0);
+  }
+  for (int f = 0; f < NF; ++f) {
+    d.speed[f] = bc->speed[f];
+    d.asymptote[f] = bc->asymptote[f];
+  }
+  bool somm = false;
+  for (int f = 0; f < 6; ++f) somm |= d.rule[f] == GRF_FACE_SOMMERFELD;
+  if (radiative && somm) {
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(origin[a]) || !std::isfinite(bc->centre[a])) return fail(GRF_EINVAL, "origin/centre not finite");
+    for (int f = 0; f < NF; ++f)
+      if (!std::isfinite(bc->speed[f]) || !std::isfinite(bc->asymptote[f]))
+        return fail(GRF_EINVAL, "speed/asymptote of field %d not finite", f);
+    // the centre must not coincide with a ghost cell centre (r = 0 there)
+    bool on_cell = true, ghost = false;
+    for (int a = 0; a < 3; ++a) {
+      const double t = (bc->centre[a] - origin[a]) / h[a];
+      const double m = std::nearbyint(t);
+      on_cell &= std::fabs(t - m) < 1e-9 && m >= -3.0 && m <= n[a] + 2.0;
+      ghost |= m < 0.0 || m >= n[a];
+    }
+    if (on_cell && ghost) return fail(GRF_EINVAL, "the radiative centre is a ghost cell centre");
+  }
+  return GRF_OK;
+}
+
+int64_t grf_bc_ghost_cells(const grf_box* box) {
+  if (check_box(box) != GRF_OK) return 0;
+  return ghost_cells(make_boxdev(box));
+}
+
+grf_status grf_bc_fill(const grf_bc* bc, const grf_box* box, double* u, hipStream_t stream) {
+  grf_status s = check_box(box);
+  if (s != GRF_OK) return s;
+  if (!u) return fail(GRF_EINVAL, "u is null");
+  BcDev d;
+  if ((s = make_bcdev(bc, box, false, d)) != GRF_OK) return s;
+  GRF_HIP_CHECK(launch_bc_fill(make_boxdev(box), d, u, stream));
+  return GRF_OK;
+}
+
+grf_status grf_bc_ghost_rhs(const grf_bc* bc, const grf_box* box, const double* u, double* rhs,
+                            hipStream_t stream) {
+  grf_status s = check_box(box);
+  if (s != GRF_OK) return s;
+  if (!u || !rhs) return fail(GRF_EINVAL, "u/rhs is null");
+  if (u == rhs) return fail(GRF_EINVAL, "rhs must not alias u");
+  BcDev d;
+  if ((s = make_bcdev(bc, box, true, d)) != GRF_OK) return s;
+  GRF_HIP_CHECK(launch_bc_ghost(0, make_boxdev(box), d, u, nullptr, rhs, nullptr, StageCoef{0.0}, stream));
+  return GRF_OK;
+}
+
+grf_status grf_rk4_stage_bc(const grf_params* p, const grf_box* box, const grf_bc* bc, int stage, double dt,
+                            const double* u0, const double* us, double* unext, double* acc, double* gacc,
+                            void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  grf_status s = check_box(box);
+  if (s != GRF_OK) return s;
+  BcDev d;
+  if ((s = make_bcdev(bc, box, true, d)) != GRF_OK) return s;
+  bool somm = false, fill = false;
+  for (int f = 0; f < 6; ++f) {
+    somm |= d.rule[f] == GRF_FACE_SOMMERFELD;
+    fill |= d.rule[f] == GRF_FACE_PERIODIC || d.rule[f] == GRF_FACE_REFLECTIVE || d.rule[f] == GRF_FACE_EXTRAPOLATING;
+  }
+  if (somm && !gacc) return fail(GRF_EINVAL, "gacc is null");
+  s = rk4_stage_impl(p, box, stage, dt, u0, us, unext, acc, workspace, workspace_bytes, stream, false);
+  if (s != GRF_OK) return s;
+  const BoxDev bd = make_boxdev(box);
+  if (somm) {
+    int mode;
+    StageCoef sc;
+    switch (stage) {
+      case 1: mode = 1; sc = StageCoef{0.5 * dt}; break;
+      case 2: mode = 2; sc = StageCoef{0.5 * dt}; break;
+      case 3: mode = 2; sc = StageCoef{1.0 * dt}; break;
+      default: mode = 4; sc = StageCoef{dt / 6.0}; break;
+    }
+    GRF_HIP_CHECK(launch_bc_ghost(mode, bd, d, us, u0, unext, gacc, sc, stream));
+  }
+  if (fill) GRF_HIP_CHECK(launch_bc_fill(bd, d, unext, stream));
   return GRF_OK;
 }
 

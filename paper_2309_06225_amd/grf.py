@@ -71,6 +71,13 @@ def lib():
         L.grf_rk4_stage.argtypes = [P, B, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.grf_fill_periodic.argtypes = [B, _vp, _vp]
         L.grf_enforce.argtypes = [P, B, _vp, _vp]
+        C = ctypes.POINTER(BC)
+        L.grf_bc_ghost_cells.argtypes = [B]
+        L.grf_bc_ghost_cells.restype = ctypes.c_int64
+        L.grf_bc_fill.argtypes = [C, B, _vp, _vp]
+        L.grf_bc_ghost_rhs.argtypes = [C, B, _vp, _vp, _vp]
+        L.grf_rk4_stage_bc.argtypes = [P, B, C, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, _vp,
+                                       ctypes.c_size_t, _vp]
         L.grf_rhs_vjp.argtypes = [P, B, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.grf_rk4_step_vjp_workspace_bytes.argtypes = [B]
         L.grf_rk4_step_vjp_workspace_bytes.restype = ctypes.c_size_t
@@ -138,9 +145,31 @@ def make_box(dims, dx, bc=BC_FROZEN, origin=(0.0, 0.0, 0.0)) -> Box:
                z0=origin[2], field_stride=(nx + 6) * (ny + 6) * (nz + 6), bc=bc)
 
 
-def box_of(u: torch.Tensor, dx, bc=BC_FROZEN) -> Box:
+def box_of(u: torch.Tensor, dx, bc=BC_FROZEN, origin=(0.0, 0.0, 0.0)) -> Box:
     nz, ny, nx = (s - 2 * NG for s in u.shape[1:])
-    return make_box((nx, ny, nz), dx, bc)
+    return make_box((nx, ny, nz), dx, bc, origin)
+
+
+class BC(ctypes.Structure):
+    """Per-face boundary rules (grf_bc): faces x-, x+, y-, y+, z-, z+."""
+    _fields_ = [("rule", ctypes.c_int32 * 6), ("extrap_order", ctypes.c_int32), ("parity_phi", ctypes.c_int32),
+                ("centre", ctypes.c_double * 3), ("speed", ctypes.c_double * NF),
+                ("asymptote", ctypes.c_double * NF)]
+
+
+FACE_RULES = {"frozen": 0, "periodic": 1, "reflective": 2, "extrapolating": 3, "sommerfeld": 4}
+
+
+def make_bc(rules, extrap_order=1, parity_phi=1, centre=(0.0, 0.0, 0.0), speed=None, asymptote=None,
+            origin=None) -> BC:
+    """rules: six names of FACE_RULES (faces x-, x+, y-, y+, z-, z+); speed and
+    asymptote per field (default 1 and 0).  The coordinates of the cells come
+    from the box (make_box's origin); `origin` is accepted and ignored here."""
+    speed = [1.0] * NF if speed is None else [float(x) for x in speed]
+    asymptote = [0.0] * NF if asymptote is None else [float(x) for x in asymptote]
+    return BC(rule=(ctypes.c_int32 * 6)(*[FACE_RULES[r] for r in rules]), extrap_order=int(extrap_order),
+              parity_phi=int(parity_phi), centre=(ctypes.c_double * 3)(*[float(x) for x in centre]),
+              speed=(ctypes.c_double * NF)(*speed), asymptote=(ctypes.c_double * NF)(*asymptote))
 
 
 def _ptr(t):
@@ -195,6 +224,27 @@ def energy_densities(params: Params, box: Box, u, ws, stream=None):
     _check(lib().grf_energy_densities(ctypes.byref(params), ctypes.byref(box), _ptr(u), _ptr(out), _ptr(ws),
                                       ws.numel() * 8, _stream(stream)))
     return out
+
+
+def bc_ghost_cells(box: Box) -> int:
+    return int(lib().grf_bc_ghost_cells(ctypes.byref(box)))
+
+
+def bc_fill(bc: BC, box: Box, u, stream=None):
+    _check(lib().grf_bc_fill(ctypes.byref(bc), ctypes.byref(box), _ptr(u), _stream(stream)))
+
+
+def bc_ghost_rhs(bc: BC, box: Box, u, stream=None):
+    """-> state-layout tensor: the ghost right-hand side, interior cells 0."""
+    out = torch.zeros_like(u)
+    _check(lib().grf_bc_ghost_rhs(ctypes.byref(bc), ctypes.byref(box), _ptr(u), _ptr(out), _stream(stream)))
+    return out
+
+
+def rk4_stage_bc(params: Params, box: Box, bc: BC, stage, dt, u0, us, unext, acc, gacc, ws, stream=None):
+    _check(lib().grf_rk4_stage_bc(ctypes.byref(params), ctypes.byref(box), ctypes.byref(bc), int(stage), float(dt),
+                                  _ptr(u0), _ptr(us), _ptr(unext), _ptr(acc), _ptr(gacc), _ptr(ws), ws.numel() * 8,
+                                  _stream(stream)))
 
 
 def enforce(params: Params, box: Box, u, stream=None):
@@ -299,6 +349,27 @@ class Stepper:
 
     def status(self):
         return status_fetch(self.ws)
+
+
+class StepperBC(Stepper):
+    """Classic RK4 steps of one box with per-face boundary rules (BC).  The
+    fill-rule ghosts of u are filled first; gacc accumulates the stages of the
+    Sommerfeld ghosts."""
+
+    def __init__(self, params: Params, box: Box, u: torch.Tensor, dt: float, bc: BC):
+        u = u.contiguous()
+        bc_fill(bc, box, u)
+        super().__init__(params, box, u, dt)
+        self.bc = bc
+        self.gacc = torch.zeros((NF, bc_ghost_cells(box)), dtype=torch.float64, device=u.device)
+
+    def step(self, stream=None):
+        p, b, c, dt = self.params, self.box, self.bc, self.dt
+        rk4_stage_bc(p, b, c, 1, dt, self.u, self.u, self.ua, self.acc, self.gacc, self.ws, stream)
+        rk4_stage_bc(p, b, c, 2, dt, self.u, self.ua, self.ub, self.acc, self.gacc, self.ws, stream)
+        rk4_stage_bc(p, b, c, 3, dt, self.u, self.ub, self.ua, self.acc, self.gacc, self.ws, stream)
+        rk4_stage_bc(p, b, c, 4, dt, self.u, self.ua, self.ub, self.acc, self.gacc, self.ws, stream)
+        self.u, self.ub = self.ub, self.u
 
 
 class Batch:

@@ -38,3 +38,30 @@ def test_host_side_validation_without_device():
     assert code != 0
     assert b"null" in L.grf_last_error() or b"workspace" in L.grf_last_error()
     assert L.grf_flops_per_cell(0) > 1000
+
+
+def test_boundary_rules_rejected_on_the_host():
+    """Invalid face rules are refused before any device work (the state pointer
+    below is never dereferenced)."""
+    from paper_2309_06225_amd import grf as G
+    L = G.lib()
+    box = G.make_box((8, 2, 8), 0.25, origin=(0.125, 0.125, 0.125))
+    dummy = ctypes.c_void_p(8)
+    cases = [
+        G.make_bc(["periodic", "frozen"] + ["frozen"] * 4),                         # unpaired periodic face
+        G.make_bc(["extrapolating"] * 6, extrap_order=2),                           # bad order
+        G.make_bc(["frozen"] * 6, parity_phi=0),                                    # bad parity
+        G.make_bc(["frozen", "frozen", "reflective", "frozen", "frozen", "frozen"]),  # 2 cells along y
+    ]
+    for bc in cases:
+        assert L.grf_bc_fill(ctypes.byref(bc), ctypes.byref(box), dummy, None) == 1, L.grf_last_error()
+    bad_rule = G.make_bc(["frozen"] * 6)
+    bad_rule.rule[3] = 9
+    assert L.grf_bc_fill(ctypes.byref(bad_rule), ctypes.byref(box), dummy, None) == 1
+    # the radiative centre on a ghost cell centre (x index -1, y 0, z 3)
+    som = G.make_bc(["sommerfeld"] * 6, centre=(0.125 - 0.25, 0.125, 0.125 + 3 * 0.25))
+    assert L.grf_bc_ghost_rhs(ctypes.byref(som), ctypes.byref(box), dummy, ctypes.c_void_p(16), None) == 1
+    assert b"centre" in L.grf_last_error()
+    nan_speed = G.make_bc(["sommerfeld"] * 6, centre=(50.0, 0.0, 0.0), speed=[float("nan")] * 27)
+    assert L.grf_bc_ghost_rhs(ctypes.byref(nan_speed), ctypes.byref(box), dummy, ctypes.c_void_p(16), None) == 1
+    assert L.grf_bc_ghost_cells(ctypes.byref(box)) == 14 * 8 * 14 - 8 * 2 * 8
