@@ -308,6 +308,22 @@ def main():
     torch.cuda.synchronize()
     out["energy_densities"] = {"ms_per_evaluation": c0.elapsed_time(c1) / 5,
                                "flops_per_cell": G.flops_per_cell(4)}
+    # per-face boundary rules: Sommerfeld on every face (ghosts integrated with
+    # the radiative right-hand side) against the frozen-ghost step above
+    origin = (-0.5 * n * dx + 0.5 * dx,) * 3
+    flat = I.set_flat(I.empty_state((1, 1, 1)))[:, 3, 3, 3]
+    bc = G.make_bc(["sommerfeld"] * 6, asymptote=flat)
+    sb = G.StepperBC(G.make_params(params), G.box_of(u, dx, origin=origin), u.clone(), dt, bc)
+    sb.step()
+    torch.cuda.synchronize()
+    c0.record(stream)
+    for _ in range(5):
+        sb.step()
+    c1.record(stream)
+    torch.cuda.synchronize()
+    out["boundary_rules"] = {"ms_per_step_sommerfeld_faces": c0.elapsed_time(c1) / 5,
+                             "ms_per_step_frozen": ms_step, "ghost_cells": G.bc_ghost_cells(box)}
+    del sb
     # measured peaks of this device beside the datasheet ones
     fp64_meas, copy_meas = G.measure_peaks()
     out["roofline"]["measured_peaks"] = {"fp64_tflops": fp64_meas, "copy_gbps": copy_meas,
