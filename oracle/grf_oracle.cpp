@@ -73,6 +73,7 @@ struct Params {
   double lapse_coeff, lapse_power, lapse_advec;
   double shift_gamma_coeff, shift_advec, eta;
   double ko_sigma;
+  double decoupled;      // 1: decoupling limit, the scalar does not source the metric
 };
 
 template <class T>
@@ -627,6 +628,18 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
   T Sigtr = 0.0;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) Sigtr += gu[i][j] * Sig[i][j];
+  // Decoupling limit (Key features, "Modified gravity theories": 4dST without
+  // backreaction): the scalar moves on the metric but does not source it, so
+  // the metric equations see no energy, momentum, stress or Gauss-Bonnet
+  // tensor and the metric rows of the system below reduce to C_ij = Q_ij.
+  const bool dec = P.decoupled != 0.0;
+  const T rho8m = dec ? T(0.0) : rho8;
+  T S8im[3], Sigm[3][3];
+  for (int i = 0; i < 3; ++i) {
+    S8im[i] = dec ? T(0.0) : S8i[i];
+    for (int j = 0; j < 3; ++j) Sigm[i][j] = dec ? T(0.0) : Sig[i][j];
+  }
+  const T Sigtrm = dec ? T(0.0) : Sigtr;
 
   // ---- the per-cell linear system for (C_ij, p)
   const double bb = P.b, aa = P.a;
@@ -639,8 +652,8 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
     for (int j = 0; j < 3; ++j) {
       T s = Rz[i][j] + (K - 2.0 * Th) * Kl[i][j];
       for (int k = 0; k < 3; ++k) s -= Kl[i][k] * Kud[k][j];
-      s += -Sig[i][j] + 0.5 * gam[i][j] * Sigtr;
-      s -= gam[i][j] * ((bb / (4.0 * (1.0 + bb))) * Hg + 0.5 * cfac * rho8 +
+      s += -Sigm[i][j] + 0.5 * gam[i][j] * Sigtrm;
+      s -= gam[i][j] * ((bb / (4.0 * (1.0 + bb))) * Hg + 0.5 * cfac * rho8m +
                         0.5 * cfac * k1 * (2.0 + k2) * Th + 0.5 * k1 * k2 * Th);
       Q[i][j] = s;
     }
@@ -677,7 +690,7 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
       trace_rev(Hl, Hr);
       for (int row = 0; row < 6; ++row) {
         const int i = ci[row], j = cj[row];
-        Amat[row * 7 + col] = E[i][j] - Hr[i][j];
+        Amat[row * 7 + col] = dec ? E[i][j] : E[i][j] - Hr[i][j];
       }
       T gE = 0.0;
       for (int i = 0; i < 3; ++i)
@@ -690,7 +703,7 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) Hl[i][j] = 4.0 * Gc[i][j] * dlam;
       trace_rev(Hl, Hr);
-      for (int row = 0; row < 6; ++row) Amat[row * 7 + 6] = -Hr[ci[row]][cj[row]];
+      for (int row = 0; row < 6; ++row) Amat[row * 7 + 6] = dec ? T(0.0) : -Hr[ci[row]][cj[row]];
       Amat[6 * 7 + 6] = DPi;
     }
     // right-hand side: Q_ij + trace-reversed constant part of H
@@ -698,7 +711,7 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) H0[i][j] = 4.0 * Gc[i][j] * Wnn0 + HBV[i][j];
     trace_rev(H0, H0r);
-    for (int row = 0; row < 6; ++row) bvec[row] = Q[ci[row]][cj[row]] + H0r[ci[row]][cj[row]];
+    for (int row = 0; row < 6; ++row) bvec[row] = dec ? Q[ci[row]][cj[row]] : Q[ci[row]][cj[row]] + H0r[ci[row]][cj[row]];
     bvec[6] = s_rhs;
   }
   for (int q = 0; q < 49; ++q) out.sysA[q] = Amat[q];
@@ -723,7 +736,7 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
   T Hs[3][3], S8[3][3];
   Hfull(Cs, ps, Hs);
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) S8[i][j] = Sig[i][j] - Hs[i][j];
+    for (int j = 0; j < 3; ++j) S8[i][j] = dec ? T(0.0) : Sig[i][j] - Hs[i][j];
   T S8tr = 0.0;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) S8tr += gu[i][j] * S8[i][j];
@@ -738,7 +751,7 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
   T divb = 0.0;
   for (int k = 0; k < 3; ++k) divb += dbeta[k][k];
   const double fb = bb / (1.0 + bb);
-  const T Hcal = Hg - 2.0 * rho8 - 2.0 * k1 * (2.0 + k2) * Th;
+  const T Hcal = Hg - 2.0 * rho8m - 2.0 * k1 * (2.0 + k2) * Th;
 
   T* r = out.rhs;
   r[CHI] = adv[CHI] + (2.0 / 3.0) * chi * (alpha * K - divb);
@@ -750,7 +763,7 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
       r[H11 + SYM[i][j]] = s;
     }
   r[KTR] = adv[KTR] - D2a + alpha * (Rzs + K * (K - 2.0 * Th)) - 3.0 * alpha * k1 * (1.0 + k2) * Th +
-           0.5 * alpha * (S8tr - 3.0 * rho8) - 0.75 * alpha * fb * Hcal;
+           0.5 * alpha * (S8tr - 3.0 * rho8m) - 0.75 * alpha * fb * Hcal;
   {
     T Xm[3][3];  // -D_i D_j alpha + alpha (Rz_ij - 8 pi S_ij)
     for (int i = 0; i < 3; ++i)
@@ -775,7 +788,7 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
     T Zda = 0.0;
     for (int k = 0; k < 3; ++k) Zda += Zt[k] * dalpha[k];
     r[THETA] = adv[THETA] + 0.5 * alpha * (Rzs - A2 + (2.0 / 3.0) * K * K - 2.0 * Th * K) - chi * Zda -
-               alpha * k1 * (2.0 + k2) * Th - alpha * rho8 - 0.5 * alpha * fb * Hcal;
+               alpha * k1 * (2.0 + k2) * Th - alpha * rho8m - 0.5 * alpha * fb * Hcal;
   }
   T rGam[3];
   for (int i = 0; i < 3; ++i) {
@@ -800,13 +813,13 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
     for (int j = 0; j < 3; ++j)
       s += 2.0 * hu[i][j] * (alpha * dTh[j] - Th * dalpha[j] - (2.0 / 3.0) * alpha * K * Zl[j]);
     s -= 2.0 * alpha * k1 * Zt[i];
-    for (int j = 0; j < 3; ++j) s -= 2.0 * alpha * hu[i][j] * S8i[j];
+    for (int j = 0; j < 3; ++j) s -= 2.0 * alpha * hu[i][j] * S8im[j];
     {
       T t = 0.0;
       for (int j = 0; j < 3; ++j) {
         T AZ = 0.0;
         for (int k = 0; k < 3; ++k) AZ += A[j][k] * Zt[k];
-        t += hu[i][j] * (Mi[j] - S8i[j] + dTh[j] - k1 * Zl[j] - AZ - K * Zl[j] / 3.0);
+        t += hu[i][j] * (Mi[j] - S8im[j] + dTh[j] - k1 * Zl[j] - AZ - K * Zl[j] / 3.0);
       }
       s -= 2.0 * alpha * fb * t;
     }
@@ -829,13 +842,13 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
 
   for (int f = 0; f < NF; ++f)
     if (!finite_val(r[f])) flags |= FLAG_NONFINITE;
-  out.ham = Hg - 2.0 * rho8;
+  out.ham = Hg - 2.0 * rho8m;
   // the three pieces of 8 pi rho, one per term of the action, divided by 8 pi
   const T inv8pi = 1.0 / (8.0 * M_PI);
   out.rho[0] = (0.5 * Pi * Pi - 0.5 * X) * inv8pi;
   out.rho[1] = g2 * (X * Pi * Pi - 0.5 * X * X) * inv8pi;
   out.rho[2] = H00 * inv8pi;
-  for (int i = 0; i < 3; ++i) out.mom[i] = Mi[i] - S8i[i];
+  for (int i = 0; i < 3; ++i) out.mom[i] = Mi[i] - S8im[i];
   out.flags = flags;
 }
 
@@ -880,6 +893,7 @@ Params<T> read_params(const double* p, const double* pim) {
   P.shift_advec = p[11];
   P.eta = p[12];
   P.ko_sigma = p[13];
+  P.decoupled = p[14];
   (void)pim;
   return P;
 }
@@ -899,6 +913,7 @@ Params<cplx> read_params<cplx>(const double* p, const double* pim) {
   P.lapse_advec = Pd.lapse_advec;
   P.shift_gamma_coeff = Pd.shift_gamma_coeff;
   P.shift_advec = Pd.shift_advec;
+  P.decoupled = Pd.decoupled;
   P.eta = Pd.eta;
   P.ko_sigma = Pd.ko_sigma;
   return P;

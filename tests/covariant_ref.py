@@ -206,8 +206,10 @@ def field_equations(st: RandomSpacetime, params: dict, x0=None):
     div = torch.trace(nZ)
     nZdot = n_low @ Z
     # hat g^{nu b} nabla_b Z^mu = (nZ @ ghat)[mu, nu]
+    # decoupling limit: the scalar is a test field, the metric equations are vacuum
+    source = 0.0 * T8_up if params.get("decoupled", 0.0) else T8_up
     E = (G_up + nZ @ ghat + (nZ @ ghat).T - ghat * div
-         - k1 * (torch.outer(n_up, Z) + torch.outer(Z, n_up) + k2 * gi * nZdot) - T8_up)
+         - k1 * (torch.outer(n_up, Z) + torch.outer(Z, n_up) + k2 * gi * nZdot) - source)
 
     box = torch.einsum("mn,mn->", gi, ddphi - torch.einsum("rmn,r->mn", Gam, dphi))
     R_low = torch.einsum("rk,ksmn->rsmn", g, Riem)

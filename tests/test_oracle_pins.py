@@ -127,6 +127,61 @@ def test_covariant_pointwise_pin(case, seed):
 
 @pytest.mark.parametrize("case", [0, 3, 4])
 @pytest.mark.parametrize("seed", [11, 12])
+def test_decoupled_covariant_pin(case, seed):
+    """Decoupling limit: the metric solves the vacuum equations and the scalar
+    its full equation on that metric, evaluated covariantly; the oracle with
+    decoupled = 1 reproduces every time derivative (gauge fields excluded as
+    above), C_ij and p."""
+    import covariant_ref as C
+    params = I.default_params(kappa3=1.0, a_gauge=0.0, decoupled=1.0, **COV_PARAMS[case])
+    ref = C.reference_point(seed + 7 * case, params)
+    assert ref["residual"] < 1e-12
+    rhs, ex, flags = O.rhs_point(I.params_vector(params), ref["u"], ref["d1"], ref["d2"], ref["d1"])
+    assert flags == 0
+    scale = np.abs(ref["dt"][NONGAUGE]).max()
+    np.testing.assert_allclose(rhs[NONGAUGE], ref["dt"][NONGAUGE], rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(ex["C"], ref["C"], rtol=0, atol=1e-12 * np.abs(ref["C"]).max())
+    assert ex["p"] == pytest.approx(ref["p"], abs=1e-12 * max(1.0, abs(ref["p"])))
+
+
+def test_decoupled_metric_is_vacuum_and_scalar_is_full():
+    """With decoupled = 1 the metric right-hand sides equal those of the same
+    state with the scalar removed (phi = Pi = 0, no couplings), and with no
+    couplings and a vanishing scalar the two forms agree exactly."""
+    rng = np.random.default_rng(5)
+    u = 0.05 * rng.standard_normal(27)
+    u[IDX["chi"]] = 0.8
+    for n in ("h11", "h22", "h33"):
+        u[IDX[n]] += 1.0
+    u[IDX["lapse"]] = 0.9
+    d1 = 0.2 * rng.standard_normal((27, 3))
+    d2 = 0.2 * rng.standard_normal((27, 6))
+    adv = 0.2 * rng.standard_normal((27, 3))
+    pd = I.params_vector(I.default_params(lambda_gb=0.4, g2=0.1, decoupled=1.0))
+    r_dec, ex_dec, _ = O.rhs_point(pd, u, d1, d2, adv)
+    u0, d10, d20 = u.copy(), d1.copy(), d2.copy()
+    for n in ("phi", "Pi"):
+        u0[IDX[n]] = 0.0
+        d10[IDX[n]] = 0.0
+        d20[IDX[n]] = 0.0
+    p0 = I.params_vector(I.default_params(lambda_gb=0.0, g2=0.0))
+    r_vac, ex_vac, _ = O.rhs_point(p0, u0, d10, d20, adv)
+    metric = [f for f in range(27) if f not in (IDX["phi"], IDX["Pi"])]
+    np.testing.assert_allclose(r_dec[metric], r_vac[metric], rtol=1e-13, atol=1e-13 * np.abs(r_vac).max())
+    np.testing.assert_allclose(ex_dec["C"], ex_vac["C"], rtol=1e-13, atol=1e-14)
+    # the scalar does feel the couplings
+    pd0 = I.params_vector(I.default_params(lambda_gb=0.0, g2=0.0, decoupled=1.0))
+    r_free, _, _ = O.rhs_point(pd0, u, d1, d2, adv)
+    assert abs(r_dec[IDX["Pi"]] - r_free[IDX["Pi"]]) > 1e-6
+    # no couplings and no scalar: the two forms are the same equations
+    r_full0, _, _ = O.rhs_point(p0, u0, d10, d20, adv)
+    pdv = I.params_vector(I.default_params(lambda_gb=0.0, g2=0.0, decoupled=1.0))
+    r_dec0, _, _ = O.rhs_point(pdv, u0, d10, d20, adv)
+    np.testing.assert_allclose(r_dec0, r_full0, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("case", [0, 3, 4])
+@pytest.mark.parametrize("seed", [11, 12])
 def test_energy_densities_covariant_pin(case, seed):
     """The per-term energy densities against n^mu n^nu T_mu nu of each term of
     the action, evaluated covariantly on a random spacetime."""
