@@ -324,6 +324,18 @@ def main():
     out["boundary_rules"] = {"ms_per_step_sommerfeld_faces": c0.elapsed_time(c1) / 5,
                              "ms_per_step_frozen": ms_step, "ghost_cells": G.bc_ghost_cells(box)}
     del sb
+    # decoupling limit (scalar without backreaction) on the same box and path
+    sd = G.Stepper(G.make_params(I.default_params(decoupled=1.0)), box, u.clone(), dt)
+    sd.step()
+    torch.cuda.synchronize()
+    c0.record(stream)
+    for _ in range(5):
+        sd.step()
+    c1.record(stream)
+    torch.cuda.synchronize()
+    out["decoupled"] = {"ms_per_step": c0.elapsed_time(c1) / 5, "ms_per_step_full_theory": ms_step,
+                        "flops_per_cell": G.flops_per_cell(5)}
+    del sd
     # measured peaks of this device beside the datasheet ones
     fp64_meas, copy_meas = G.measure_peaks()
     out["roofline"]["measured_peaks"] = {"fp64_tflops": fp64_meas, "copy_gbps": copy_meas,

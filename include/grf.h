@@ -64,7 +64,15 @@ enum { GRF_FLAG_NONFINITE = 1, GRF_FLAG_HYPERBOLIC = 2, GRF_FLAG_NONPOSITIVE = 4
  *   - a/(1+a) alpha D^i alpha,  d_t B^i = d_t Gam^i/(1+a) - eta B^i (+ advection).
  * enforce / chi_min / lapse_min: post-stage algebraic enforcement (0 = off, the
  * default everywhere; 1 = grf_enforce applied to every stage output of
- * grf_rk4_stage before its ghost fill; the batched and adjoint paths reject it). */
+ * grf_rk4_stage before its ghost fill; the batched and adjoint paths reject it).
+ * decoupled: 0 the full theory; 1 the decoupling limit (Key features, "Modified
+ * gravity theories": 4dST without backreaction): the scalar evolves with its
+ * full equation on the metric, which evolves as in vacuum (no energy,
+ * momentum, stress or Gauss-Bonnet tensor in the metric equations; the metric
+ * rows of the per-cell system reduce to C_ij = Q_ij), gauge unchanged.
+ * Supported by grf_rhs_eval, grf_rk4_stage and grf_rk4_stage_bc on stage path
+ * 2 (the default); the other paths, the diagnostics, the batched form and the
+ * adjoint return GRF_EUNSUPPORTED. */
 typedef struct {
   double lambda_gb;
   int32_t lambda_kind;
@@ -76,6 +84,7 @@ typedef struct {
   double ko_sigma;
   int32_t enforce;
   double chi_min, lapse_min;
+  int32_t decoupled;
 } grf_params;
 
 /* One box: nx, ny, nz interior cells, ng ghosts (must be 3), spacing dx, dy,
@@ -223,7 +232,8 @@ grf_status grf_status_clear(void* workspace, hipStream_t stream);
  * (shift advection on or off), of its VJP, of the constraint diagnostics and
  * of the energy densities, counted on the expression graph (add, sub, mul and
  * reciprocal each 1), stencils not included; -1 for another `which`. */
-int64_t grf_flops_per_cell(int which /* 0 rhs, 1 rhs with shift advection, 2 vjp, 3 constraints, 4 energy */);
+int64_t grf_flops_per_cell(int which /* 0 rhs, 1 rhs with shift advection, 2 vjp, 3 constraints, 4 energy,
+                                         5 rhs in the decoupling limit */);
 
 /* Constraint diagnostics (Key features, "Diagnostics": constraint monitoring):
  * per interior cell the Hamiltonian constraint R + (2/3) K^2 - A_ij A^ij -

@@ -63,7 +63,11 @@ def input_names(shift_advec: bool):
     return names
 
 
-def build(shift_advec: bool = False):
+def build(shift_advec: bool = False, decoupled: bool = False):
+    """decoupled: the decoupling limit of 4dST (the scalar moves on the metric
+    without sourcing it): the metric equations see no energy, momentum,
+    stress or Gauss-Bonnet tensor and their rows of the per-cell system reduce
+    to C_ij = Q_ij; the scalar's row is unchanged."""
     g = Graph()
     S = g.sum
     P = {n: g.param(n) for n in PARAMS}
@@ -236,15 +240,20 @@ def build(shift_advec: bool = False):
     S8i = [-0.5 * FX * Pi * dphi[i] - H0i[i] for i in R3]
     Sig = symfill(lambda i, j: 0.5 * FX * dphi[i] * dphi[j] + 0.5 * gam[i][j] * F)
     Sigtr = 0.5 * FX * dphi2 + 1.5 * F
+    # sources as the metric equations see them
+    if decoupled:
+        rho8m, S8im, Sigm, Sigtrm = zero, [zero] * 3, [[zero] * 3 for _ in R3], zero
+    else:
+        rho8m, S8im, Sigm, Sigtrm = rho8, S8i, Sig, Sigtr
 
     # ---------------- per-cell linear system in (C_11..C_33, p)
     Hg = A4tr
     thterm = 0.5 * P["cfac"] * P["k1_2pk2"] * Th + 0.5 * P["k1k2"] * Th
-    trace_part = P["b4"] * Hg + 0.5 * P["cfac"] * rho8 + thterm
+    trace_part = P["b4"] * Hg + 0.5 * P["cfac"] * rho8m + thterm
     KK = symfill(lambda i, j: S(Kl[i][k] * Kud[k][j] for k in R3))
     KmTh = K - 2.0 * Th
-    Q = symfill(lambda i, j: Rz[i][j] + KmTh * Kl[i][j] - KK[i][j] - Sig[i][j]
-                + gam[i][j] * (0.5 * Sigtr - trace_part))
+    Q = symfill(lambda i, j: Rz[i][j] + KmTh * Kl[i][j] - KK[i][j] - Sigm[i][j]
+                + gam[i][j] * (0.5 * Sigtrm - trace_part))
     trW = S(gu[i][j] * W[i][j] for i in R3 for j in R3)
     WG = [[S(W[i][b] * gu[b][a] for b in R3) for a in R3] for i in R3]    # W_i^a
 
@@ -267,15 +276,15 @@ def build(shift_advec: bool = False):
         br = bracket(E)
         Hr = trace_rev(symfill(lambda i, j: -4.0 * br[i][j]))
         for row, (i, j) in enumerate(SYM6):
-            Amat[row][col] = E[i][j] - Hr[i][j]
+            Amat[row][col] = E[i][j] if decoupled else E[i][j] - Hr[i][j]
         Amat[6][col] = -8.0 * dlam * (Gcu[k][l] if k == l else 2.0 * Gcu[k][l])
     Gr = trace_rev(Gc)
     for row, (i, j) in enumerate(SYM6):
-        Amat[row][6] = -4.0 * dlam * Gr[i][j]
+        Amat[row][6] = zero if decoupled else -4.0 * dlam * Gr[i][j]
     DPi = 1.0 + 3.0 * g2 * Pi * Pi - g2 * dphi2
     Amat[6][6] = DPi
     H0c = trace_rev(symfill(lambda i, j: 4.0 * Gc[i][j] * Wnn0 + HBV[i][j]))
-    bvec = [Q[i][j] + H0c[i][j] for (i, j) in SYM6]
+    bvec = [Q[i][j] if decoupled else Q[i][j] + H0c[i][j] for (i, j) in SYM6]
     KDD = S(dphiu[i] * dphiu[j] * (DDphi[i][j] + Kl[i][j] * Pi) for i in R3 for j in R3)
     PiV = S(dphiu[i] * (dPi[i] + Kdphi[i]) for i in R3)
     D2phi = S(gu[i][j] * DDphi[i][j] for i in R3 for j in R3)
@@ -308,7 +317,10 @@ def build(shift_advec: bool = False):
 
     brs = bracket(Cs)
     Wnn = dlam * ps + Wnn0
-    S8 = symfill(lambda i, j: Sig[i][j] - (4.0 * Gc[i][j] * Wnn - 4.0 * brs[i][j] + HBV[i][j]))
+    if decoupled:
+        S8 = [[zero] * 3 for _ in R3]
+    else:
+        S8 = symfill(lambda i, j: Sig[i][j] - (4.0 * Gc[i][j] * Wnn - 4.0 * brs[i][j] + HBV[i][j]))
     S8tr = S(gu[i][j] * S8[i][j] for i in R3 for j in R3)
 
     # ---------------- right-hand sides
@@ -317,14 +329,14 @@ def build(shift_advec: bool = False):
 
     divb = dbe[0][0] + dbe[1][1] + dbe[2][2]
     fb = P["fb"]
-    Hcal = Hg - 2.0 * rho8 - 2.0 * P["k1_2pk2"] * Th
+    Hcal = Hg - 2.0 * rho8m - 2.0 * P["k1_2pk2"] * Th
     rhs = [None] * NF
     rhs[CHI] = ad(CHI) + (2.0 / 3.0) * chi * (al * K - divb)
     for q, (i, j) in enumerate(SYM6):
         rhs[H0 + q] = (ad(H0 + q) + S(h[k][i] * dbe[k][j] + h[k][j] * dbe[k][i] for k in R3)
                        - (2.0 / 3.0) * h[i][j] * divb - 2.0 * al * A[i][j])
     rhs[K_] = (ad(K_) - D2a + al * (Rzs + K * KmTh) - 3.0 * al * P["k1_1pk2"] * Th
-               + 0.5 * al * (S8tr - 3.0 * rho8) - 0.75 * al * fb * Hcal)
+               + 0.5 * al * (S8tr - 3.0 * rho8m) - 0.75 * al * fb * Hcal)
     Xm = symfill(lambda i, j: -DDa[i][j] + al * (Rz[i][j] - S8[i][j]))
     trX = S(hu[k][l] * Xm[k][l] for k in R3 for l in R3)
     for q, (i, j) in enumerate(SYM6):
@@ -334,7 +346,7 @@ def build(shift_advec: bool = False):
                        + al * (A[i][j] * KmTh - 2.0 * AA))
     Zda = S(Zt[k] * dal[k] for k in R3)
     rhs[THETA] = (ad(THETA) + 0.5 * al * (Rzs - A2 + (2.0 / 3.0) * K * K - 2.0 * Th * K) - chi * Zda
-                  - al * P["k1_2pk2"] * Th - al * rho8 - 0.5 * al * fb * Hcal)
+                  - al * P["k1_2pk2"] * Th - al * rho8m - 0.5 * al * fb * Hcal)
     rGam = []
     for i in R3:
         s = ad(GH0 + i) - S(Gt[k] * dbe[i][k] for k in R3) + (2.0 / 3.0) * Gt[i] * divb
@@ -345,9 +357,9 @@ def build(shift_advec: bool = False):
              - (2.0 / 3.0) * S(hu[i][j] * dK[j] for j in R3))
         s = s + 2.0 * al * t - 2.0 * S(Au[i][j] * dal[j] for j in R3)
         s = s + 2.0 * S(hu[i][j] * (al * dTh[j] - Th * dal[j] - (2.0 / 3.0) * al * K * Zl[j]) for j in R3)
-        s = s - 2.0 * al * P["kappa1"] * Zt[i] - 2.0 * al * S(hu[i][j] * S8i[j] for j in R3)
+        s = s - 2.0 * al * P["kappa1"] * Zt[i] - 2.0 * al * S(hu[i][j] * S8im[j] for j in R3)
         AZ = [S(A[j][k] * Zt[k] for k in R3) for j in R3]
-        t2 = S(hu[i][j] * (Mi[j] - S8i[j] + dTh[j] - P["kappa1"] * Zl[j] - AZ[j] - K3 * Zl[j]) for j in R3)
+        t2 = S(hu[i][j] * (Mi[j] - S8im[j] + dTh[j] - P["kappa1"] * Zl[j] - AZ[j] - K3 * Zl[j]) for j in R3)
         s = s - 2.0 * al * fb * t2
         rGam.append(s)
         rhs[GH0 + i] = s

@@ -76,24 +76,27 @@ def _stage_key(name: str):
     return ("D", comp_of(name))
 
 
-def forward_code_staged(shift_advec: bool, rhs_only: bool):
+def forward_code_staged(shift_advec: bool, rhs_only: bool, decoupled: bool = False):
     """Forward right-hand side with staged inputs (see emit_staged).  Each
     right-hand-side statement also stages its Kreiss-Oliger component and, for
-    the RK4 stage modes, u0 and the accumulator of its field."""
-    b = M.build(shift_advec)
+    the RK4 stage modes, u0 and the accumulator of its field.  decoupled: the
+    decoupling limit (its constant pivot entries are not checked)."""
+    b = M.build(shift_advec, decoupled)
     g = b["graph"]
     from .expr import reachable
     rhs = b["rhs"]
-    indep = [f for f in range(M.NF) if not (reachable([rhs[f]]) & {p.idx for p in b["pivots"]})]
+    pivots = [p for p in b["pivots"] if p.op != "c"] if decoupled else b["pivots"]
+    checks = [p for p in b["pivot_check"] if p.op != "c"] if decoupled else b["pivot_check"]
+    indep = [f for f in range(M.NF) if not (reachable([rhs[f]]) & {p.idx for p in pivots})]
     dep = [f for f in range(M.NF) if f not in indep]
-    outs = [rhs[f] for f in indep] + b["pivot_check"] + [rhs[f] for f in dep]
+    outs = [rhs[f] for f in indep] + checks + [rhs[f] for f in dep]
 
     def rhs_stmt(f):
         if rhs_only:
             return (f"GRF_RHS_ST({f}, {{v}}, {{b}}, {{s0}}, 0, 0)", [("KO", f)])
         return (f"GRF_RHS_ST({f}, {{v}}, {{b}}, {{s0}}, {{s1}}, {{s2}})", [("KO", f), ("U0", f), ("ACC", f)])
 
-    stmts = ([rhs_stmt(f) for f in indep] + [("GRF_PIVCHK({v})", [])] * len(b["pivot_check"])
+    stmts = ([rhs_stmt(f) for f in indep] + [("GRF_PIVCHK({v})", [])] * len(checks)
              + [rhs_stmt(f) for f in dep])
     # heavier operand first: about a quarter less spilling in this kernel
     return emit_staged(g, outs, stmts, _stage_key, param_expr, STAGE_SLOTS, order="dfs_heavy")
@@ -121,6 +124,11 @@ def energy_code():
     code = emit(g, outs, names, input_expr, param_expr, order="dfs")
     flops, ops = count_flops(g, outs)
     return code, flops
+
+
+def _dec_flops():
+    b = M.build(False, decoupled=True)
+    return count_flops(b["graph"], b["rhs"])[0]
 
 
 def vjp_code(shift_advec: bool):
@@ -186,6 +194,7 @@ def main(outdir: str):
         f"#define GRF_FLOPS_VJP_SHIFTADV {vfl1}",
         f"#define GRF_FLOPS_CONSTRAINTS {constraints_code()[1]}",
         f"#define GRF_FLOPS_ENERGY {energy_code()[1]}",
+        f"#define GRF_FLOPS_RHS_DECOUPLED {_dec_flops()}",
         f"#define GRF_STAGE_SLOTS {STAGE_SLOTS}  // slots per buffer of the staged pointwise kernel",
         "// parameters read by the generated code (derived combinations precomputed on the host)",
         "struct grf_point_params {",
@@ -225,6 +234,20 @@ def main(outdir: str):
         fh.write(block("GRF_SHIFT_ADVEC", staged[(True, True)][0], staged[(True, False)][0]))
         fh.write("} else {\n")
         fh.write(block("GRF_SHIFT_ADVEC", staged[(False, True)][0], staged[(False, False)][0]))
+        fh.write("}\n")
+    staged_dec = {}
+    for ro in (True, False):
+        for sa in (True, False):
+            staged_dec[(ro, sa)] = forward_code_staged(sa, ro, decoupled=True)
+    with open(os.path.join(outdir, "gen_rhs_staged_dec.inc"), "w") as fh:
+        fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
+        fh.write("// decoupling limit (the scalar does not source the metric), staged as gen_rhs_staged.inc;\n")
+        fh.write("// phases (rhs only / stage, shift advection on / off): "
+                 + ", ".join(f"{v[1]}" for v in staged_dec.values()) + "\n")
+        fh.write("if constexpr (GRF_STAGE_RHS_ONLY) {\n")
+        fh.write(block("GRF_SHIFT_ADVEC", staged_dec[(True, True)][0], staged_dec[(True, False)][0]))
+        fh.write("} else {\n")
+        fh.write(block("GRF_SHIFT_ADVEC", staged_dec[(False, True)][0], staged_dec[(False, False)][0]))
         fh.write("}\n")
     con, cfl = constraints_code()
     with open(os.path.join(outdir, "gen_constraints.inc"), "w") as fh:

@@ -75,7 +75,7 @@ __device__ __forceinline__ void stage_one_st(int f, double rhs_f, double ko_f, d
 
 // The 64 cells c0 .. c0 + 63 of box b (one wave; lbuf0 / lbuf1: this wave's
 // two LDS buffers of GRF_STAGE_SLOTS items).
-template <int MODE, int SHIFTADV>
+template <int MODE, int SHIFTADV, bool DEC = false>
 __device__ __forceinline__ void staged_wave(const BoxDev& b, int64_t c0, const grf_point_params& P,
                                             const double* __restrict__ us, const double* __restrict__ D,
                                             const double* __restrict__ u0, double* __restrict__ out,
@@ -126,7 +126,11 @@ __device__ __forceinline__ void staged_wave(const BoxDev& b, int64_t c0, const g
 #define GRF_STAGE_RHS_ONLY (MODE == 0)
   // nothing of an earlier call may still read the buffers or write memory
   GRF_PHASE_SYNC();
+  if constexpr (DEC) {
+#include "gen/gen_rhs_staged_dec.inc"
+  } else {
 #include "gen/gen_rhs_staged.inc"
+  }
 #undef GRF_STAGE_RHS_ONLY
 #undef GRF_SHIFT_ADVEC
 #undef GRF_PIVCHK
@@ -145,7 +149,8 @@ __device__ __forceinline__ void staged_wave(const BoxDev& b, int64_t c0, const g
   if (flags) atomicOr(status, flags);
 }
 
-template <int MODE, int SHIFTADV>
+// DEC: the decoupling limit (the scalar does not source the metric)
+template <int MODE, int SHIFTADV, bool DEC = false>
 __global__ __launch_bounds__(kStagedThreads) void k_point_staged(BoxDev b, grf_point_params P,
                                                                  const double* __restrict__ us,
                                                                  const double* __restrict__ D,
@@ -156,8 +161,8 @@ __global__ __launch_bounds__(kStagedThreads) void k_point_staged(BoxDev b, grf_p
   __shared__ double lbuf1_[GRF_STAGE_SLOTS * 64];
   // the buffers as LDS-typed pointers, so that slot addresses are plain LDS
   // offsets (no generic-pointer conversion at each copy)
-  staged_wave<MODE, SHIFTADV>(b, (int64_t)blockIdx.x * kStagedThreads, P, us, D, u0, out, acc, sc, status,
-                              (grf_lds_double*)lbuf0_, (grf_lds_double*)lbuf1_);
+  staged_wave<MODE, SHIFTADV, DEC>(b, (int64_t)blockIdx.x * kStagedThreads, P, us, D, u0, out, acc, sc, status,
+                                   (grf_lds_double*)lbuf0_, (grf_lds_double*)lbuf1_);
 }
 
 }  // namespace grf

@@ -59,6 +59,7 @@ grf_status check_params(const grf_params* p) {
   if (p->lapse_power != 1.0) return fail(GRF_EUNSUPPORTED, "only lapse_power 1");
   if (p->a_gauge == -1.0 || p->b_gauge == -1.0) return fail(GRF_EINVAL, "a and b must differ from -1");
   if (p->enforce != 0 && p->enforce != 1) return fail(GRF_EINVAL, "enforce must be 0 or 1");
+  if (p->decoupled != 0 && p->decoupled != 1) return fail(GRF_EINVAL, "decoupled must be 0 or 1");
   if (p->enforce && !(std::isfinite(p->chi_min) && std::isfinite(p->lapse_min)))
     return fail(GRF_EINVAL, "chi_min and lapse_min must be finite");
   return GRF_OK;
@@ -232,6 +233,7 @@ int64_t grf_flops_per_cell(int which) {
     case 2: return GRF_FLOPS_VJP;
     case 3: return GRF_FLOPS_CONSTRAINTS;
     case 4: return GRF_FLOPS_ENERGY;
+    case 5: return GRF_FLOPS_RHS_DECOUPLED;
     default: return -1;
   }
 }
@@ -285,6 +287,8 @@ grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u
   unsigned* status = (unsigned*)workspace;
   double* D = (double*)((char*)workspace + kStatusBytes);
   const int sa = p->shift_advec != 0.0;
+  if (p->decoupled && g_stage_path != 2)
+    return fail(GRF_EUNSUPPORTED, "the decoupling limit runs on stage path 2 only");
   if (g_stage_path == 1) {
     prof_mark(1, stream);
     GRF_HIP_CHECK(launch_fused(0, sa, bd, pp, u, nullptr, rhs, nullptr, StageCoef{0.0}, D, p->ko_sigma, status, stream));
@@ -295,8 +299,8 @@ grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u
   GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, sa, nullptr, stream));
   prof_mark(0, stream);
   prof_mark(1, stream);
-  GRF_HIP_CHECK(
-      launch_pointwise(g_stage_path, 0, sa, bd, pp, u, D, nullptr, rhs, nullptr, StageCoef{0.0}, status, stream));
+  GRF_HIP_CHECK(launch_pointwise(g_stage_path, 0, sa | (p->decoupled ? 2 : 0), bd, pp, u, D, nullptr, rhs, nullptr,
+                                 StageCoef{0.0}, status, stream));
   prof_mark(1, stream);
   return GRF_OK;
 }
@@ -326,6 +330,8 @@ static grf_status rk4_stage_impl(const grf_params* p, const grf_box* box, int st
   unsigned* status = (unsigned*)workspace;
   double* D = (double*)((char*)workspace + kStatusBytes);
   const int sa = p->shift_advec != 0.0;
+  if (p->decoupled && g_stage_path != 2)
+    return fail(GRF_EUNSUPPORTED, "the decoupling limit runs on stage path 2 only");
   StageCoef sc;
   int mode;
   switch (stage) {
@@ -343,7 +349,8 @@ static grf_status rk4_stage_impl(const grf_params* p, const grf_box* box, int st
     GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, us, D, p->ko_sigma, sa, nullptr, stream));
     prof_mark(0, stream);
     prof_mark(1, stream);
-    GRF_HIP_CHECK(launch_pointwise(g_stage_path, mode, sa, bd, pp, us, D, u0, unext, acc, sc, status, stream));
+    GRF_HIP_CHECK(launch_pointwise(g_stage_path, mode, sa | (p->decoupled ? 2 : 0), bd, pp, us, D, u0, unext, acc,
+                                   sc, status, stream));
     prof_mark(1, stream);
   }
   if (p->enforce) GRF_HIP_CHECK(launch_enforce(bd, unext, p->chi_min, p->lapse_min, stream));
@@ -479,6 +486,7 @@ static grf_status diagnostics(int which, const grf_params* p, const grf_box* box
   grf_status s = common_checks(p, box, workspace, workspace_bytes);
   if (s != GRF_OK) return s;
   if (!u || !out) return fail(GRF_EINVAL, "u/out is null");
+  if (p->decoupled) return fail(GRF_EUNSUPPORTED, "diagnostics of the decoupling limit are not implemented");
   BoxDev bd = make_boxdev(box);
   grf_point_params pp = make_pp(p);
   double* D = (double*)((char*)workspace + kStatusBytes);
@@ -543,6 +551,7 @@ grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u,
   s = check_box(box);
   if (s != GRF_OK) return s;
   if (!u || !w || !u_bar || !theta_bar || !workspace) return fail(GRF_EINVAL, "null pointer");
+  if (p->decoupled) return fail(GRF_EUNSUPPORTED, "the adjoint of the decoupling limit is not implemented");
   if (u_bar == u || u_bar == w) return fail(GRF_EINVAL, "u_bar must not alias u or w");
   const VjpLayout L = vjp_layout(box);
   if (workspace_bytes < L.total) return fail(GRF_ENOMEM, "workspace %zu bytes < %zu", workspace_bytes, L.total);
@@ -578,6 +587,7 @@ grf_status grf_rk4_step_vjp(const grf_params* p, const grf_box* box, double dt, 
   s = check_box(box);
   if (s != GRF_OK) return s;
   if (box->bc != GRF_BC_FROZEN) return fail(GRF_EUNSUPPORTED, "the step adjoint is implemented for frozen ghosts");
+  if (p->decoupled) return fail(GRF_EUNSUPPORTED, "the adjoint of the decoupling limit is not implemented");
   if (p->enforce) return fail(GRF_EUNSUPPORTED, "the step adjoint does not differentiate the enforcement");
   if (!u || !u2 || !u3 || !u4 || !ubar_new || !ubar || !theta_bar || !workspace) return fail(GRF_EINVAL, "null pointer");
   if (ubar == ubar_new || ubar == u || ubar == u2 || ubar == u3 || ubar == u4)
@@ -701,6 +711,7 @@ grf_status grf_batch_create(const grf_params* p, const grf_box* boxes, int nboxe
   grf_status s = check_params(p);
   if (s != GRF_OK) return s;
   if (p->enforce) return fail(GRF_EUNSUPPORTED, "the batched form has no post-stage enforcement");
+  if (p->decoupled) return fail(GRF_EUNSUPPORTED, "the batched form runs the full theory only");
   if (!boxes || nboxes < 1 || !u || !dts || !out || !scratch) return fail(GRF_EINVAL, "null argument");
   for (int b = 0; b < nboxes; ++b) {
     if ((s = check_box(&boxes[b])) != GRF_OK) return s;

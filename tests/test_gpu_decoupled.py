@@ -1,0 +1,146 @@
+"""The decoupling limit of 4dST (the scalar does not source the metric) on the
+GPU against the oracle: one right-hand side, RK4 steps, sampled cells of the
+128^3 box, and the property that the metric then evolves independently of
+the scalar."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import oracle as O
+from paper_2309_06225_amd import grf as G
+from paper_2309_06225_amd import inputs as I
+from parity_util import rel_err_per_field
+
+DEV = "cuda"
+METRIC = [f for f in range(I.NF) if f not in (I.IDX["phi"], I.IDX["Pi"])]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    O.build(force=False)
+    G.lib()
+
+
+def _dec(**over):
+    return I.default_params(decoupled=1.0, **over)
+
+
+def gpu_rhs(params, u, dx, bc=G.BC_FROZEN):
+    ut = torch.from_numpy(u).to(DEV)
+    box = G.box_of(ut, dx, bc)
+    ws = G.alloc_workspace(G.workspace_bytes(box))
+    out = torch.zeros_like(ut)
+    G.rhs_eval(G.make_params(params), box, ut, out, ws)
+    code, bits = G.status_fetch(ws)
+    return out.cpu().numpy(), code, bits
+
+
+@pytest.mark.parametrize("shift_advec", [0.0, 1.0])
+def test_rhs_parity_periodic_noise(shift_advec):
+    print("case: decoupled rhs, noise 32^3, shift_advec", shift_advec, flush=True)
+    p = _dec(shift_advec=shift_advec, lambda_gb=0.3, g2=0.05)
+    u = I.flat_noise_pulse(32, 0.25, seed=0)
+    u[I.IDX["shift1"]] += 1e-3 * np.sin(np.arange(u.shape[-1]))[None, None, :]
+    u = I.wrap_ghosts(u)
+    o, fo = O.rhs(I.params_vector(p), u, 0.25)
+    g, code, bits = gpu_rhs(p, u, 0.25, G.BC_PERIODIC)
+    assert code == 0 and bits == 0 and fo == 0
+    e = rel_err_per_field(g, o)
+    assert e.max() <= 1e-12, dict(zip(I.FIELDS, e))
+
+
+def test_rhs_parity_puncture_ragged():
+    print("case: decoupled rhs, puncture 21x17x13", flush=True)
+    p = _dec(lambda_gb=0.3, g2=0.05)
+    dims, dx = (21, 17, 13), 0.3
+    u = I.puncture(dims, dx, centre=(0.4, -0.2, 0.1), phi_fn=I.shell_pulse(0.1, 2.0))
+    rng = np.random.default_rng(4)
+    u[I.IDX["K"]] += 0.01 * rng.standard_normal(u[7].shape)
+    u[I.IDX["Pi"]] += 0.01 * rng.standard_normal(u[26].shape)
+    o, _ = O.rhs(I.params_vector(p), u, dx)
+    g, code, bits = gpu_rhs(p, u, dx)
+    assert code == 0
+    e = rel_err_per_field(g, o)
+    assert e.max() <= 1e-12, dict(zip(I.FIELDS, e))
+    # the scalar's equation differs from the free one, the metric's from the full theory's
+    gf, _, _ = gpu_rhs(I.default_params(lambda_gb=0.3, g2=0.05), u, dx)
+    assert np.abs(gf[METRIC] - g[METRIC]).max() > 1e-8
+
+
+def test_rhs_parity_full_size_sampled():
+    print("case: decoupled rhs, single puncture 128^3 sampled", flush=True)
+    p = _dec(lambda_gb=0.2, g2=0.02)
+    u = I.single_puncture(128, 1.0 / 8.0)
+    g, code, bits = gpu_rhs(p, u, 1.0 / 8.0)
+    assert code == 0
+    rng = np.random.default_rng(19)
+    cells = rng.integers(0, 128, size=(2000, 3))
+    cells = np.concatenate([cells, np.array([[63, 63, 63], [64, 64, 64], [0, 0, 0], [127, 127, 127]])])
+    o, _ = O.rhs_cells(I.params_vector(p), u, 1.0 / 8.0, cells)
+    gs = g[:, cells[:, 2] + 3, cells[:, 1] + 3, cells[:, 0] + 3].T
+    num = np.abs(gs - o).max(axis=0)
+    den = np.abs(o).max(axis=0)
+    den = np.where(den > 0, den, den.max())
+    assert (num / den).max() <= 1e-12, dict(zip(I.FIELDS, num / den))
+
+
+def test_rk4_ten_steps_puncture():
+    print("case: decoupled, 10 RK4 steps 24^3 puncture", flush=True)
+    p = _dec(lambda_gb=0.3, g2=0.05)
+    u = I.single_puncture(24, 0.25)
+    o, flags = O.rk4(I.params_vector(p), u, 0.25, 0.0625, 10, periodic=False)
+    assert flags == 0
+    ut = torch.from_numpy(u).to(DEV)
+    st = G.Stepper(G.make_params(p), G.box_of(ut, 0.25), ut, 0.0625)
+    for _ in range(10):
+        st.step()
+    assert st.status() == (0, 0)
+    e = rel_err_per_field(st.u.cpu().numpy(), o, interior=False)
+    assert e.max() <= 1e-10, dict(zip(I.FIELDS, e))
+
+
+@pytest.mark.parametrize("n", [24, 128])
+def test_metric_evolves_independently_of_the_scalar(n):
+    """Without backreaction the metric's evolution does not read the scalar:
+    two runs that differ only in phi and Pi give bitwise the same metric."""
+    print("case: decoupled metric independence", n, flush=True)
+    dx = 0.25 if n < 100 else 1.0 / 8
+    p = G.make_params(_dec(lambda_gb=0.3, g2=0.05))
+    u = I.single_puncture(n, dx)
+    v = u.copy()
+    v[I.IDX["phi"]] *= -2.0
+    v[I.IDX["Pi"]] += 0.01
+    runs = []
+    for w in (u, v):
+        wt = torch.from_numpy(w).to(DEV)
+        st = G.Stepper(p, G.box_of(wt, dx), wt, 0.25 * dx)
+        for _ in range(3):
+            st.step()
+        runs.append(st.u)
+    torch.cuda.synchronize()
+    assert torch.equal(runs[0][METRIC], runs[1][METRIC])
+    assert not torch.equal(runs[0][I.IDX["Pi"]], runs[1][I.IDX["Pi"]])
+
+
+def test_unsupported_paths_are_refused():
+    p = G.make_params(_dec())
+    u = torch.from_numpy(I.single_puncture(16, 0.25)).to(DEV)
+    box = G.box_of(u, 0.25)
+    ws = G.alloc_workspace(G.workspace_bytes(box))
+    out = torch.zeros_like(u)
+    p0 = G.get_stage_path()
+    try:
+        for path in (0, 1):
+            G.set_stage_path(path)
+            with pytest.raises(G.GrfError):
+                G.rhs_eval(p, box, u, out, ws)
+    finally:
+        G.set_stage_path(p0)
+    with pytest.raises(G.GrfError):
+        G.constraints(p, box, u, ws)
+    with pytest.raises(G.GrfError):
+        G.Batch(p, [box], [u], [0.01])
