@@ -74,6 +74,7 @@ struct Params {
   double shift_gamma_coeff, shift_advec, eta;
   double ko_sigma;
   double decoupled;      // 1: decoupling limit, the scalar does not source the metric
+  int fd_order;          // 4 or 6: order of the centred finite differences
 };
 
 template <class T>
@@ -894,6 +895,7 @@ Params<T> read_params(const double* p, const double* pim) {
   P.eta = p[12];
   P.ko_sigma = p[13];
   P.decoupled = p[14];
+  P.fd_order = (int)p[15];
   (void)pim;
   return P;
 }
@@ -914,6 +916,7 @@ Params<cplx> read_params<cplx>(const double* p, const double* pim) {
   P.shift_gamma_coeff = Pd.shift_gamma_coeff;
   P.shift_advec = Pd.shift_advec;
   P.decoupled = Pd.decoupled;
+  P.fd_order = Pd.fd_order;
   P.eta = Pd.eta;
   P.ko_sigma = Pd.ko_sigma;
   return P;
@@ -922,8 +925,56 @@ Params<cplx> read_params<cplx>(const double* p, const double* pim) {
 // Gather the finite-difference inputs of one cell.  The stencils are the
 // 4th-order centred, mixed and lopsided-upwind ones of the cited CCZ4 code
 // family; Kreiss-Oliger is the 6th difference with weight sigma/(64 h).
+// Sixth-order centred differences on the same three ghost layers:
+//   d_k u   = (-u_-3 + 9 u_-2 - 45 u_-1 + 45 u_1 - 9 u_2 + u_3) / (60 h),
+//   d_k^2 u = (2 u_-3 - 27 u_-2 + 270 u_-1 - 490 u_0 + 270 u_1 - 27 u_2 + 2 u_3) / (180 h^2),
+//   d_k d_l u: the first-derivative weights applied along k and along l (49 points);
+// the advection derivative is the fifth-order stencil biased one cell towards
+// the side the shift points to (offsets -2..3 for beta >= 0, -3..2 otherwise),
+// the widest such stencil that three ghost layers hold.
 template <class T>
-void gather_point(const Box& b, const T* u, int i, int j, int k, PointIn<T>& in, T ko[NF]) {
+void gather_sixth(const Box& b, const T* u, int64_t c, PointIn<T>& in) {
+  const int64_t st[3] = {b.sx, b.sy, b.sz};
+  const double w1[7] = {-1.0, 9.0, -45.0, 0.0, 45.0, -9.0, 1.0};
+  const double w2[7] = {2.0, -27.0, 270.0, -490.0, 270.0, -27.0, 2.0};
+  const double wup[6] = {3.0, -30.0, -20.0, 60.0, -15.0, 2.0};  // offsets -2..3, over 60 h
+  for (int f = 0; f < NF; ++f) {
+    const T* uf = u + f * b.fstride;
+    for (int d = 0; d < 3; ++d) {
+      const int64_t s = st[d];
+      const double hd = b.dx[d];
+      T a1 = 0.0, a2 = 0.0;
+      for (int o = -3; o <= 3; ++o) {
+        a1 += w1[o + 3] * uf[c + o * s];
+        a2 += w2[o + 3] * uf[c + o * s];
+      }
+      in.d1[f][d] = a1 / (60.0 * hd);
+      in.d2[f][SYM[d][d]] = a2 / (180.0 * hd * hd);
+    }
+    for (int d = 0; d < 3; ++d)
+      for (int e = d + 1; e < 3; ++e) {
+        T sm = 0.0;
+        for (int pa = -3; pa <= 3; ++pa)
+          for (int pb = -3; pb <= 3; ++pb) sm += (w1[pa + 3] * w1[pb + 3]) * uf[c + pa * st[d] + pb * st[e]];
+        in.d2[f][SYM[d][e]] = sm / (3600.0 * b.dx[d] * b.dx[e]);
+      }
+  }
+  for (int d = 0; d < 3; ++d) {
+    const double bsign = re(in.u[SHIFT1 + d]);
+    const int64_t s = st[d];
+    const double hd = b.dx[d];
+    for (int f = 0; f < NF; ++f) {
+      const T* uf = u + f * b.fstride;
+      T a = 0.0;
+      // beta >= 0: offsets -2..3; beta < 0: the mirror image, offsets 2..-3 with the sign flipped
+      for (int q = 0; q < 6; ++q) a += bsign >= 0.0 ? wup[q] * uf[c + (q - 2) * s] : -wup[q] * uf[c - (q - 2) * s];
+      in.adv[f][d] = a / (60.0 * hd);
+    }
+  }
+}
+
+template <class T>
+void gather_point(const Box& b, const T* u, int i, int j, int k, PointIn<T>& in, T ko[NF], int order = 4) {
   const int64_t c = cell_index(b, i, j, k);
   const int64_t st[3] = {b.sx, b.sy, b.sz};
   const double cfd[5] = {1.0, -8.0, 0.0, 8.0, -1.0};  // first-derivative weights at -2..2
@@ -931,6 +982,9 @@ void gather_point(const Box& b, const T* u, int i, int j, int k, PointIn<T>& in,
     const T* uf = u + f * b.fstride;
     in.u[f] = uf[c];
   }
+  if (order == 6) {
+    gather_sixth(b, u, c, in);
+  } else {
   for (int f = 0; f < NF; ++f) {
     const T* uf = u + f * b.fstride;
     for (int d = 0; d < 3; ++d) {
@@ -967,6 +1021,7 @@ void gather_point(const Box& b, const T* u, int i, int j, int k, PointIn<T>& in,
                        (12.0 * hd);
     }
   }
+  }  // order 4
   for (int f = 0; f < NF; ++f) {
     const T* uf = u + f * b.fstride;
     T s = 0.0;
@@ -990,7 +1045,7 @@ int box_rhs(const Params<T>& P, const Box& b, const T* u, T* rhs, T* ham, T* mom
     T ko[NF];
     for (int j = 0; j < b.ny; ++j)
       for (int i = 0; i < b.nx; ++i) {
-        gather_point(b, u, i, j, k, in, ko);
+        gather_point(b, u, i, j, k, in, ko, P.fd_order);
         rhs_point(P, in, out);
         const int64_t c = cell_index(b, i, j, k);
         if (rhs)
@@ -1269,7 +1324,7 @@ int oracle_rhs_cells(const double* params, const int* dims, const double* spacin
     PointIn<double> in;
     PointOut<double> o;
     double ko[NF];
-    gather_point(b, u, ijk[3 * q], ijk[3 * q + 1], ijk[3 * q + 2], in, ko);
+    gather_point(b, u, ijk[3 * q], ijk[3 * q + 1], ijk[3 * q + 2], in, ko, P.fd_order);
     rhs_point(P, in, o);
     for (int f = 0; f < NF; ++f) out[q * NF + f] = o.rhs[f] + P.ko_sigma * ko[f];
     flags_all |= o.flags;
@@ -1433,7 +1488,8 @@ double oracle_gepp(int n, const double* A, const double* b, double* x) {
 
 // Finite-difference stencils of one scalar field at one cell, for polynomial pins.
 // out: d1[3], d2[6], adv_plus[3], adv_minus[3], ko (one value, sigma = 1)  -> 16 doubles
-void oracle_stencils(const int* dims, const double* spacing, const double* f, int i, int j, int k, double* out) {
+void oracle_stencils(const int* dims, const double* spacing, const double* f, int i, int j, int k, int order,
+                     double* out) {
   Box b = make_box(dims, spacing);
   // place the scalar in field 0 of a scratch state; the shift sign selects the upwind side
   std::vector<double> u(b.fstride * NF, 0.0);
@@ -1442,13 +1498,13 @@ void oracle_stencils(const int* dims, const double* spacing, const double* f, in
   double ko[NF];
   const int64_t c = cell_index(b, i, j, k);
   for (int d = 0; d < 3; ++d) u[(SHIFT1 + d) * b.fstride + c] = 1.0;
-  gather_point(b, u.data(), i, j, k, in, ko);
+  gather_point(b, u.data(), i, j, k, in, ko, order);
   int q = 0;
   for (int d = 0; d < 3; ++d) out[q++] = in.d1[0][d];
   for (int d = 0; d < 6; ++d) out[q++] = in.d2[0][d];
   for (int d = 0; d < 3; ++d) out[q++] = in.adv[0][d];
   for (int d = 0; d < 3; ++d) u[(SHIFT1 + d) * b.fstride + c] = -1.0;
-  gather_point(b, u.data(), i, j, k, in, ko);
+  gather_point(b, u.data(), i, j, k, in, ko, order);
   for (int d = 0; d < 3; ++d) out[q++] = in.adv[0][d];
   out[q++] = ko[0];
 }

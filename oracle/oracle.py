@@ -61,7 +61,7 @@ def lib():
         L.oracle_enforce.argtypes = [_ip, _dp, ctypes.c_double, ctypes.c_double]
         L.oracle_gepp.argtypes = [ctypes.c_int, _dp, _dp, _dp]
         L.oracle_gepp.restype = ctypes.c_double
-        L.oracle_stencils.argtypes = [_ip, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
+        L.oracle_stencils.argtypes = [_ip, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
         _lib = L
     return _lib
 
@@ -251,12 +251,12 @@ def gepp(A, b):
     return x, ratio
 
 
-def stencils(f, dx, i, j, k):
-    """Stencils of a scalar field f (shape (nz+6, ny+6, nx+6)) at interior cell (i,j,k):
-    dict with d1[3], d2[6], adv_plus[3], adv_minus[3], ko."""
+def stencils(f, dx, i, j, k, order=4):
+    """Stencils (centred order 4 or 6) of a scalar field f (shape (nz+6, ny+6, nx+6))
+    at interior cell (i,j,k): dict with d1[3], d2[6], adv_plus[3], adv_minus[3], ko."""
     f = _c(f)
     nz, ny, nx = (s - 2 * NG for s in f.shape)
     dims = np.array([nx, ny, nz], dtype=np.int32)
     out = np.zeros(16)
-    lib().oracle_stencils(dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(f), i, j, k, _d(out))
+    lib().oracle_stencils(dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(f), i, j, k, int(order), _d(out))
     return dict(d1=out[0:3], d2=out[3:9], adv_plus=out[9:12], adv_minus=out[12:15], ko=out[15])
