@@ -336,6 +336,17 @@ def main():
     out["decoupled"] = {"ms_per_step": c0.elapsed_time(c1) / 5, "ms_per_step_full_theory": ms_step,
                         "flops_per_cell": G.flops_per_cell(5)}
     del sd
+    # sixth-order stencils on the same box (stencil kernel 32x8x32, staged pointwise kernel)
+    s6 = G.Stepper(G.make_params(I.default_params(fd_order=6.0)), box, u.clone(), dt)
+    s6.step()
+    torch.cuda.synchronize()
+    c0.record(stream)
+    for _ in range(5):
+        s6.step()
+    c1.record(stream)
+    torch.cuda.synchronize()
+    out["sixth_order"] = {"ms_per_step": c0.elapsed_time(c1) / 5, "ms_per_step_fourth_order": ms_step}
+    del s6
     # measured peaks of this device beside the datasheet ones
     fp64_meas, copy_meas = G.measure_peaks()
     out["roofline"]["measured_peaks"] = {"fp64_tflops": fp64_meas, "copy_gbps": copy_meas,

@@ -72,7 +72,15 @@ enum { GRF_FLAG_NONFINITE = 1, GRF_FLAG_HYPERBOLIC = 2, GRF_FLAG_NONPOSITIVE = 4
  * rows of the per-cell system reduce to C_ij = Q_ij), gauge unchanged.
  * Supported by grf_rhs_eval, grf_rk4_stage and grf_rk4_stage_bc on stage path
  * 2 (the default); the other paths, the diagnostics, the batched form and the
- * adjoint return GRF_EUNSUPPORTED. */
+ * adjoint return GRF_EUNSUPPORTED.
+ * fd_order: 4 (or 0) fourth-order stencils; 6 sixth-order stencils (Key
+ * features, "Accuracy") on the same three ghost layers: centred first, second
+ * and mixed derivatives of order 6, the advection derivative of order 5 on the
+ * six points leaning one cell to the side the shift points to, the same
+ * Kreiss-Oliger operator.  Order 6 runs the z-marching 32x8x32 stencil kernel
+ * whatever grf_set_tile_variant chose, on stage paths 0 and 2, in
+ * grf_rhs_eval, grf_rk4_stage, grf_rk4_stage_bc and the diagnostics; the fused
+ * path, the batched form and the adjoint return GRF_EUNSUPPORTED. */
 typedef struct {
   double lambda_gb;
   int32_t lambda_kind;
@@ -85,6 +93,7 @@ typedef struct {
   int32_t enforce;
   double chi_min, lapse_min;
   int32_t decoupled;
+  int32_t fd_order;
 } grf_params;
 
 /* One box: nx, ny, nz interior cells, ng ghosts (must be 3), spacing dx, dy,

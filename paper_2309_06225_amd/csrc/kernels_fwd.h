@@ -23,6 +23,9 @@ struct BoxDev {
   double i12h2[3]; // 1/(12 h^2)
   double i144[3];  // 1/(144 h_x h_y), 1/(144 h_x h_z), 1/(144 h_y h_z)
   double i64h[3];  // 1/(64 h)
+  double i60h[3];    // 1/(60 h)            (sixth-order stencils)
+  double i180h2[3];  // 1/(180 h^2)
+  double i3600[3];   // 1/(3600 h_x h_y), 1/(3600 h_x h_z), 1/(3600 h_y h_z)
 };
 
 __device__ __forceinline__ bool advected(int f, int shift_adv) {
@@ -66,6 +69,41 @@ __device__ __forceinline__ double sten_mixed(const double* t, const int* pb, int
       if (bb == 0) continue;
       const int e = PAIR == 0 ? pb[3] + cxy + bb * LX + a : PAIR == 1 ? pb[bb + 3] + cxy + a : pb[bb + 3] + cxy + a * LX;
       s += (w[a + 2] * w[bb + 2]) * t[e];
+    }
+  }
+  return s;
+}
+// Sixth-order forms on the same seven points: centred first derivative
+// (-1, 9, -45, 0, 45, -9, 1)/(60 h), second derivative
+// (2, -27, 270, -490, 270, -27, 2)/(180 h^2), the 36-point mixed derivative
+// from the first-derivative weights along both axes / (3600 h_a h_b), and the
+// fifth-order advection stencil leaning one cell to the side the shift
+// points to: offsets -2..3 with (3, -30, -20, 60, -15, 2)/(60 h) for beta >= 0,
+// its mirror image for beta < 0.  All weights and their products are exact.
+__device__ __forceinline__ double sten6_d1(const double* L) {
+  return ((((-L[0] + 9.0 * L[1]) - 45.0 * L[2]) + 45.0 * L[4]) - 9.0 * L[5]) + L[6];
+}
+__device__ __forceinline__ double sten6_d2(const double* L) {
+  return (((((2.0 * L[0] - 27.0 * L[1]) + 270.0 * L[2]) - 490.0 * L[3]) + 270.0 * L[4]) - 27.0 * L[5]) + 2.0 * L[6];
+}
+__device__ __forceinline__ double sten6_up_plus(const double* L) {
+  return ((((3.0 * L[1] - 30.0 * L[2]) - 20.0 * L[3]) + 60.0 * L[4]) - 15.0 * L[5]) + 2.0 * L[6];
+}
+__device__ __forceinline__ double sten6_up_minus(const double* L) {
+  return ((((-3.0 * L[5] + 30.0 * L[4]) + 20.0 * L[3]) - 60.0 * L[2]) + 15.0 * L[1]) - 2.0 * L[0];
+}
+template <int LX, int PAIR>
+__device__ __forceinline__ double sten6_mixed(const double* t, const int* pb, int cxy) {
+  const double w[7] = {-1.0, 9.0, -45.0, 0.0, 45.0, -9.0, 1.0};
+  double s = 0.0;
+#pragma unroll
+  for (int a = -3; a <= 3; ++a) {
+    if (a == 0) continue;
+#pragma unroll
+    for (int bb = -3; bb <= 3; ++bb) {
+      if (bb == 0) continue;
+      const int e = PAIR == 0 ? pb[3] + cxy + bb * LX + a : PAIR == 1 ? pb[bb + 3] + cxy + a : pb[bb + 3] + cxy + a * LX;
+      s += (w[a + 3] * w[bb + 3]) * t[e];
     }
   }
   return s;
@@ -123,7 +161,7 @@ __device__ __forceinline__ void rec_store(double* p, double v) {
 // (pb: base of the plane at z offset dz, cxy: the cell within a plane), so the
 // same arithmetic serves a 3-D tile and a ring of z-planes.  Record layout:
 // component q of the cell lives at Dc[q * nc].
-template <int LX, bool STREAM = true>
+template <int LX, bool STREAM = true, int ORD = 4>
 __device__ __forceinline__ void compute_cell(const BoxDev& b, int i, int j, int k, int f, const double* __restrict__ u,
                                              double* __restrict__ Dc, int64_t nc, int64_t cell, double ko_sigma,
                                              int shift_adv, double* __restrict__ UP, const double* t, const int* pb,
@@ -139,17 +177,29 @@ __device__ __forceinline__ void compute_cell(const BoxDev& b, int i, int j, int 
   const int s1 = grf_d1_slot[f];
   if (s1 >= 0) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D1 + 3 * s1 + d) * nc], sten_d1(line[d]) * b.i12h[d]);
+    for (int d = 0; d < 3; ++d) {
+      const double v = ORD == 6 ? sten6_d1(line[d]) * b.i60h[d] : sten_d1(line[d]) * b.i12h[d];
+      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D1 + 3 * s1 + d) * nc], v);
+    }
   }
   const int s2 = grf_d2_slot[f];
   if (s2 >= 0) {
     const int pure[3] = {0, 3, 5};
+    if constexpr (ORD == 6) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
-      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc], sten_d2(line[d]) * b.i12h2[d]);
-    rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 1) * nc], sten_mixed<LX, 0>(t, pb, cxy) * b.i144[0]);
-    rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 2) * nc], sten_mixed<LX, 1>(t, pb, cxy) * b.i144[1]);
-    rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 4) * nc], sten_mixed<LX, 2>(t, pb, cxy) * b.i144[2]);
+      for (int d = 0; d < 3; ++d)
+        rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc], sten6_d2(line[d]) * b.i180h2[d]);
+      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 1) * nc], sten6_mixed<LX, 0>(t, pb, cxy) * b.i3600[0]);
+      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 2) * nc], sten6_mixed<LX, 1>(t, pb, cxy) * b.i3600[1]);
+      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 4) * nc], sten6_mixed<LX, 2>(t, pb, cxy) * b.i3600[2]);
+    } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc], sten_d2(line[d]) * b.i12h2[d]);
+      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 1) * nc], sten_mixed<LX, 0>(t, pb, cxy) * b.i144[0]);
+      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 2) * nc], sten_mixed<LX, 1>(t, pb, cxy) * b.i144[1]);
+      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 4) * nc], sten_mixed<LX, 2>(t, pb, cxy) * b.i144[2]);
+    }
   }
 #undef GRF_AT
   // upwinded advection: the lopsided stencil on the side the shift points to
@@ -158,7 +208,10 @@ __device__ __forceinline__ void compute_cell(const BoxDev& b, int i, int j, int 
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     beta[d] = u[(int64_t)(F_SHIFT + d) * b.fs + sc];
-    up[d] = (beta[d] >= 0.0 ? sten_up_plus(line[d]) : sten_up_minus(line[d])) * b.i12h[d];
+    if constexpr (ORD == 6)
+      up[d] = (beta[d] >= 0.0 ? sten6_up_plus(line[d]) : sten6_up_minus(line[d])) * b.i60h[d];
+    else
+      up[d] = (beta[d] >= 0.0 ? sten_up_plus(line[d]) : sten_up_minus(line[d])) * b.i12h[d];
     if (UP) UP[(int64_t)(3 * f + d) * b.ncell + cell] = up[d];
   }
   // a field whose advection sum enters only its own right-hand side, with
@@ -245,7 +298,7 @@ __host__ __device__ inline int zm_items(const BoxDev& b) {
 
 // One field of one (column, z-chunk) item: item = column x + ntx (column y +
 // nty chunk).  t: 8 * (TX+6)(TY+6) doubles of LDS.
-template <int TX, int TY, int ZC>
+template <int TX, int TY, int ZC, int ORD = 4>
 __device__ __forceinline__ void zm_column(const BoxDev& b, int item, int f, const double* __restrict__ u,
                                           double* __restrict__ D, double ko_sigma, int shift_adv,
                                           double* __restrict__ UP, double* t) {
@@ -299,12 +352,12 @@ __device__ __forceinline__ void zm_column(const BoxDev& b, int item, int f, cons
 #pragma unroll
       for (int o = 0; o < 7; ++o) pb[o] = ((k + o) & 7) * PL;
       const int64_t cell = ((int64_t)k * b.ny + j) * b.nx + i;
-      compute_cell<LX>(b, i, j, k, f, u, D + cell, b.ncell, cell, ko_sigma, shift_adv, UP, t, pb, cxy);
+      compute_cell<LX, true, ORD>(b, i, j, k, f, u, D + cell, b.ncell, cell, ko_sigma, shift_adv, UP, t, pb, cxy);
     }
   }
 }
 
-template <int TX, int TY, int ZC, bool XCDMAP>
+template <int TX, int TY, int ZC, bool XCDMAP, int ORD = 4>
 __global__ __launch_bounds__(TX* TY) void k_deriv_zm(BoxDev b, const double* __restrict__ u,
                                                       double* __restrict__ D, double ko_sigma, int shift_adv,
                                                       double* __restrict__ UP) {
@@ -319,7 +372,7 @@ __global__ __launch_bounds__(TX* TY) void k_deriv_zm(BoxDev b, const double* __r
     f = item / per_field;
     item %= per_field;
   }
-  zm_column<TX, TY, ZC>(b, item, f, u, D, ko_sigma, shift_adv, UP, t);
+  zm_column<TX, TY, ZC, ORD>(b, item, f, u, D, ko_sigma, shift_adv, UP, t);
 }
 
 // ---------------------------------------------------------------------------

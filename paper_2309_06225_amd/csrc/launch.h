@@ -23,6 +23,8 @@ constexpr int kDerivVariants = 13;    // plus z-marching shapes 5..12 (single-bo
 hipError_t launch_deriv(int variant, const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
                         hipStream_t st);
 int tiles_of_variant(int variant, const BoxDev& bd);
+// sixth-order stencil stage (the z-marching 32x8x32 form; no upwinded-derivative output)
+hipError_t launch_deriv6(const BoxDev& bd, const double* u, double* D, double sigma, int sa, hipStream_t st);
 // batched stencil stage: tiled variants 0..4 and the z-marching variant 8
 hipError_t launch_deriv_batch(int variant, int grid, const BatchBoxDev* boxes, const TileEntry* tiles, int ntiles,
                               int stage, int parity, double sigma, int sa, hipStream_t st);

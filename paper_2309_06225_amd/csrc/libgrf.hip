@@ -60,6 +60,7 @@ grf_status check_params(const grf_params* p) {
   if (p->a_gauge == -1.0 || p->b_gauge == -1.0) return fail(GRF_EINVAL, "a and b must differ from -1");
   if (p->enforce != 0 && p->enforce != 1) return fail(GRF_EINVAL, "enforce must be 0 or 1");
   if (p->decoupled != 0 && p->decoupled != 1) return fail(GRF_EINVAL, "decoupled must be 0 or 1");
+  if (p->fd_order != 0 && p->fd_order != 4 && p->fd_order != 6) return fail(GRF_EINVAL, "fd_order must be 4 or 6");
   if (p->enforce && !(std::isfinite(p->chi_min) && std::isfinite(p->lapse_min)))
     return fail(GRF_EINVAL, "chi_min and lapse_min must be finite");
   return GRF_OK;
@@ -83,6 +84,13 @@ BoxDev make_boxdev(const grf_box* b) {
   d.i144[0] = 1.0 / (144.0 * h[0] * h[1]);
   d.i144[1] = 1.0 / (144.0 * h[0] * h[2]);
   d.i144[2] = 1.0 / (144.0 * h[1] * h[2]);
+  for (int k = 0; k < 3; ++k) {
+    d.i60h[k] = 1.0 / (60.0 * h[k]);
+    d.i180h2[k] = 1.0 / (180.0 * h[k] * h[k]);
+  }
+  d.i3600[0] = 1.0 / (3600.0 * h[0] * h[1]);
+  d.i3600[1] = 1.0 / (3600.0 * h[0] * h[2]);
+  d.i3600[2] = 1.0 / (3600.0 * h[1] * h[2]);
   return d;
 }
 
@@ -276,6 +284,13 @@ static grf_status common_checks(const grf_params* p, const grf_box* box, void* w
   return GRF_OK;
 }
 
+// stencil stage of the forward paths at the parameters' finite-difference order
+static hipError_t launch_deriv_p(const grf_params* p, const BoxDev& bd, const double* u, double* D, int sa,
+                                 hipStream_t stream) {
+  if (p->fd_order == 6) return launch_deriv6(bd, u, D, p->ko_sigma, sa, stream);
+  return launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, sa, nullptr, stream);
+}
+
 grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u, double* rhs, void* workspace,
                         size_t workspace_bytes, hipStream_t stream) {
   grf_status s = common_checks(p, box, workspace, workspace_bytes);
@@ -289,6 +304,8 @@ grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u
   const int sa = p->shift_advec != 0.0;
   if (p->decoupled && g_stage_path != 2)
     return fail(GRF_EUNSUPPORTED, "the decoupling limit runs on stage path 2 only");
+  if (p->fd_order == 6 && g_stage_path == 1)
+    return fail(GRF_EUNSUPPORTED, "sixth-order stencils run on stage paths 0 and 2");
   if (g_stage_path == 1) {
     prof_mark(1, stream);
     GRF_HIP_CHECK(launch_fused(0, sa, bd, pp, u, nullptr, rhs, nullptr, StageCoef{0.0}, D, p->ko_sigma, status, stream));
@@ -296,7 +313,7 @@ grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u
     return GRF_OK;
   }
   prof_mark(0, stream);
-  GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, sa, nullptr, stream));
+  GRF_HIP_CHECK(launch_deriv_p(p, bd, u, D, sa, stream));
   prof_mark(0, stream);
   prof_mark(1, stream);
   GRF_HIP_CHECK(launch_pointwise(g_stage_path, 0, sa | (p->decoupled ? 2 : 0), bd, pp, u, D, nullptr, rhs, nullptr,
@@ -332,6 +349,8 @@ static grf_status rk4_stage_impl(const grf_params* p, const grf_box* box, int st
   const int sa = p->shift_advec != 0.0;
   if (p->decoupled && g_stage_path != 2)
     return fail(GRF_EUNSUPPORTED, "the decoupling limit runs on stage path 2 only");
+  if (p->fd_order == 6 && g_stage_path == 1)
+    return fail(GRF_EUNSUPPORTED, "sixth-order stencils run on stage paths 0 and 2");
   StageCoef sc;
   int mode;
   switch (stage) {
@@ -346,7 +365,7 @@ static grf_status rk4_stage_impl(const grf_params* p, const grf_box* box, int st
     prof_mark(1, stream);
   } else {
     prof_mark(0, stream);
-    GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, us, D, p->ko_sigma, sa, nullptr, stream));
+    GRF_HIP_CHECK(launch_deriv_p(p, bd, us, D, sa, stream));
     prof_mark(0, stream);
     prof_mark(1, stream);
     GRF_HIP_CHECK(launch_pointwise(g_stage_path, mode, sa | (p->decoupled ? 2 : 0), bd, pp, us, D, u0, unext, acc,
@@ -490,7 +509,7 @@ static grf_status diagnostics(int which, const grf_params* p, const grf_box* box
   BoxDev bd = make_boxdev(box);
   grf_point_params pp = make_pp(p);
   double* D = (double*)((char*)workspace + kStatusBytes);
-  GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, p->shift_advec != 0.0, nullptr, stream));
+  GRF_HIP_CHECK(launch_deriv_p(p, bd, u, D, p->shift_advec != 0.0, stream));
   GRF_HIP_CHECK(launch_constraints(which, bd, pp, u, D, out, stream));
   return GRF_OK;
 }
@@ -552,6 +571,7 @@ grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u,
   if (s != GRF_OK) return s;
   if (!u || !w || !u_bar || !theta_bar || !workspace) return fail(GRF_EINVAL, "null pointer");
   if (p->decoupled) return fail(GRF_EUNSUPPORTED, "the adjoint of the decoupling limit is not implemented");
+  if (p->fd_order == 6) return fail(GRF_EUNSUPPORTED, "the adjoint uses the fourth-order stencils only");
   if (u_bar == u || u_bar == w) return fail(GRF_EINVAL, "u_bar must not alias u or w");
   const VjpLayout L = vjp_layout(box);
   if (workspace_bytes < L.total) return fail(GRF_ENOMEM, "workspace %zu bytes < %zu", workspace_bytes, L.total);
@@ -588,6 +608,7 @@ grf_status grf_rk4_step_vjp(const grf_params* p, const grf_box* box, double dt, 
   if (s != GRF_OK) return s;
   if (box->bc != GRF_BC_FROZEN) return fail(GRF_EUNSUPPORTED, "the step adjoint is implemented for frozen ghosts");
   if (p->decoupled) return fail(GRF_EUNSUPPORTED, "the adjoint of the decoupling limit is not implemented");
+  if (p->fd_order == 6) return fail(GRF_EUNSUPPORTED, "the adjoint uses the fourth-order stencils only");
   if (p->enforce) return fail(GRF_EUNSUPPORTED, "the step adjoint does not differentiate the enforcement");
   if (!u || !u2 || !u3 || !u4 || !ubar_new || !ubar || !theta_bar || !workspace) return fail(GRF_EINVAL, "null pointer");
   if (ubar == ubar_new || ubar == u || ubar == u2 || ubar == u3 || ubar == u4)
@@ -712,6 +733,7 @@ grf_status grf_batch_create(const grf_params* p, const grf_box* boxes, int nboxe
   if (s != GRF_OK) return s;
   if (p->enforce) return fail(GRF_EUNSUPPORTED, "the batched form has no post-stage enforcement");
   if (p->decoupled) return fail(GRF_EUNSUPPORTED, "the batched form runs the full theory only");
+  if (p->fd_order == 6) return fail(GRF_EUNSUPPORTED, "the batched form uses the fourth-order stencils only");
   if (!boxes || nboxes < 1 || !u || !dts || !out || !scratch) return fail(GRF_EINVAL, "null argument");
   for (int b = 0; b < nboxes; ++b) {
     if ((s = check_box(&boxes[b])) != GRF_OK) return s;

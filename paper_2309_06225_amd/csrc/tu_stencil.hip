@@ -172,13 +172,17 @@ hipError_t launch_deriv_t(const BoxDev& bd, const double* u, double* D, double s
   return hipGetLastError();
 }
 
-template <int TX, int TY, int ZC, bool XCDMAP>
+template <int TX, int TY, int ZC, bool XCDMAP, int ORD = 4>
 hipError_t launch_deriv_zm_t(const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
                              hipStream_t st) {
   const int64_t items = (int64_t)((bd.nx + TX - 1) / TX) * ((bd.ny + TY - 1) / TY) * ((bd.nz + ZC - 1) / ZC) * NF;
-  hipLaunchKernelGGL((k_deriv_zm<TX, TY, ZC, XCDMAP>), dim3((unsigned)items), dim3(TX * TY), 0, st, bd, u, D, sigma,
-                     sa, UP);
+  hipLaunchKernelGGL((k_deriv_zm<TX, TY, ZC, XCDMAP, ORD>), dim3((unsigned)items), dim3(TX * TY), 0, st, bd, u, D,
+                     sigma, sa, UP);
   return hipGetLastError();
+}
+
+hipError_t launch_deriv6(const BoxDev& bd, const double* u, double* D, double sigma, int sa, hipStream_t st) {
+  return launch_deriv_zm_t<32, 8, 32, true, 6>(bd, u, D, sigma, sa, nullptr, st);
 }
 
 hipError_t launch_deriv(int variant, const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
