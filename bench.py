@@ -175,6 +175,70 @@ def batched_speedup(torch, G, I, steps=4):
             "stencil_variants": sorted(set(chosen)), "cells": ncell, "boxes": len(spec), "status": code}
 
 
+def other_rows(torch, G, I, params, box, u, st, n, dx, dt, ms_step, stream):
+    """Timings of the diagnostics, the boundary rules, the decoupling limit and
+    the sixth-order stencils on the headline box (each 5 calls after one warm-up)."""
+    out = {}
+    # constraint diagnostics (stencil stage + constraint kernel) on the same box
+    G.constraints(G.make_params(params), box, st.u, st.ws)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(5):
+        G.constraints(G.make_params(params), box, st.u, st.ws)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    out["constraints"] = {"ms_per_evaluation": c0.elapsed_time(c1) / 5,
+                          "flops_per_cell": G.flops_per_cell(3)}
+    c0.record(stream)
+    for _ in range(5):
+        G.energy_densities(G.make_params(params), box, st.u, st.ws)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    out["energy_densities"] = {"ms_per_evaluation": c0.elapsed_time(c1) / 5,
+                               "flops_per_cell": G.flops_per_cell(4)}
+    # per-face boundary rules: Sommerfeld on every face (ghosts integrated with
+    # the radiative right-hand side) against the frozen-ghost step above
+    origin = (-0.5 * n * dx + 0.5 * dx,) * 3
+    flat = I.set_flat(I.empty_state((1, 1, 1)))[:, 3, 3, 3]
+    bc = G.make_bc(["sommerfeld"] * 6, asymptote=flat)
+    sb = G.StepperBC(G.make_params(params), G.box_of(u, dx, origin=origin), u.clone(), dt, bc)
+    sb.step()
+    torch.cuda.synchronize()
+    c0.record(stream)
+    for _ in range(5):
+        sb.step()
+    c1.record(stream)
+    torch.cuda.synchronize()
+    out["boundary_rules"] = {"ms_per_step_sommerfeld_faces": c0.elapsed_time(c1) / 5,
+                             "ms_per_step_frozen": ms_step, "ghost_cells": G.bc_ghost_cells(box)}
+    del sb
+    # decoupling limit (scalar without backreaction) on the same box and path
+    sd = G.Stepper(G.make_params(I.default_params(decoupled=1.0)), box, u.clone(), dt)
+    sd.step()
+    torch.cuda.synchronize()
+    c0.record(stream)
+    for _ in range(5):
+        sd.step()
+    c1.record(stream)
+    torch.cuda.synchronize()
+    out["decoupled"] = {"ms_per_step": c0.elapsed_time(c1) / 5, "ms_per_step_full_theory": ms_step,
+                        "flops_per_cell": G.flops_per_cell(5)}
+    del sd
+    # sixth-order stencils on the same box (stencil kernel 32x8x32, staged pointwise kernel)
+    s6 = G.Stepper(G.make_params(I.default_params(fd_order=6.0)), box, u.clone(), dt)
+    s6.step()
+    torch.cuda.synchronize()
+    c0.record(stream)
+    for _ in range(5):
+        s6.step()
+    c1.record(stream)
+    torch.cuda.synchronize()
+    out["sixth_order"] = {"ms_per_step": c0.elapsed_time(c1) / 5, "ms_per_step_fourth_order": ms_step}
+    del s6
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,69 +357,13 @@ def main():
         "kernels_ms_per_step": {"stencil": deriv_ms / args.steps, "pointwise_rk4": point_ms / args.steps},
         "rhs_cells_per_s": ncell * 4 * args.steps / (ms_total * 1e-3),
     }
-    # constraint diagnostics (stencil stage + constraint kernel) on the same box
-    G.constraints(G.make_params(params), box, st.u, st.ws)
-    torch.cuda.synchronize()
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    c0.record(stream)
-    for _ in range(5):
-        G.constraints(G.make_params(params), box, st.u, st.ws)
-    c1.record(stream)
-    torch.cuda.synchronize()
-    out["constraints"] = {"ms_per_evaluation": c0.elapsed_time(c1) / 5,
-                          "flops_per_cell": G.flops_per_cell(3)}
-    c0.record(stream)
-    for _ in range(5):
-        G.energy_densities(G.make_params(params), box, st.u, st.ws)
-    c1.record(stream)
-    torch.cuda.synchronize()
-    out["energy_densities"] = {"ms_per_evaluation": c0.elapsed_time(c1) / 5,
-                               "flops_per_cell": G.flops_per_cell(4)}
-    # per-face boundary rules: Sommerfeld on every face (ghosts integrated with
-    # the radiative right-hand side) against the frozen-ghost step above
-    origin = (-0.5 * n * dx + 0.5 * dx,) * 3
-    flat = I.set_flat(I.empty_state((1, 1, 1)))[:, 3, 3, 3]
-    bc = G.make_bc(["sommerfeld"] * 6, asymptote=flat)
-    sb = G.StepperBC(G.make_params(params), G.box_of(u, dx, origin=origin), u.clone(), dt, bc)
-    sb.step()
-    torch.cuda.synchronize()
-    c0.record(stream)
-    for _ in range(5):
-        sb.step()
-    c1.record(stream)
-    torch.cuda.synchronize()
-    out["boundary_rules"] = {"ms_per_step_sommerfeld_faces": c0.elapsed_time(c1) / 5,
-                             "ms_per_step_frozen": ms_step, "ghost_cells": G.bc_ghost_cells(box)}
-    del sb
-    # decoupling limit (scalar without backreaction) on the same box and path
-    sd = G.Stepper(G.make_params(I.default_params(decoupled=1.0)), box, u.clone(), dt)
-    sd.step()
-    torch.cuda.synchronize()
-    c0.record(stream)
-    for _ in range(5):
-        sd.step()
-    c1.record(stream)
-    torch.cuda.synchronize()
-    out["decoupled"] = {"ms_per_step": c0.elapsed_time(c1) / 5, "ms_per_step_full_theory": ms_step,
-                        "flops_per_cell": G.flops_per_cell(5)}
-    del sd
-    # sixth-order stencils on the same box (stencil kernel 32x8x32, staged pointwise kernel)
-    s6 = G.Stepper(G.make_params(I.default_params(fd_order=6.0)), box, u.clone(), dt)
-    s6.step()
-    torch.cuda.synchronize()
-    c0.record(stream)
-    for _ in range(5):
-        s6.step()
-    c1.record(stream)
-    torch.cuda.synchronize()
-    out["sixth_order"] = {"ms_per_step": c0.elapsed_time(c1) / 5, "ms_per_step_fourth_order": ms_step}
-    del s6
     # measured peaks of this device beside the datasheet ones
     fp64_meas, copy_meas = G.measure_peaks()
     out["roofline"]["measured_peaks"] = {"fp64_tflops": fp64_meas, "copy_gbps": copy_meas,
                                          "frac_of_measured_copy": hbm_achieved / copy_meas,
                                          "alu_view_frac_of_measured_fp64": achieved / fp64_meas}
     if not args.no_extra:
+        out.update(other_rows(torch, G, I, params, box, u, st, n, dx, dt, ms_step, stream))
         del st
         torch.cuda.empty_cache()
         out["adjoint_forward_ratio"] = adjoint_ratio(torch, G, I)
