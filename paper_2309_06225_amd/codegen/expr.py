@@ -300,7 +300,7 @@ def dfs_order(outputs, heavy_first=False):
     return order
 
 
-def greedy_order(outputs, prio_order):
+def greedy_order(outputs, prio_order, oldest_first=False, fused=None):
     """Top-down list schedule that keeps few values live: among the nodes whose
     operands are all computed, take one that frees the most operands (its last
     remaining user) net of the value it creates; ties go to the earlier node of
@@ -317,9 +317,25 @@ def greedy_order(outputs, prio_order):
         for c in (x.a, x.b):
             if c is not None and c.idx not in nodes:
                 stack.append(c)
-    users = {i: [] for i in nodes}
+    # operands as emitted: an add or subtract fused with a product reads the
+    # product's operands; a product emitted only inside fmas is not scheduled
+    plan, skipped = fused if fused is not None else ({}, set())
+    ops_of = {}
     for i, x in nodes.items():
-        for c in {c.idx: c for c in (x.a, x.b) if c is not None}.values():
+        if i in skipped:
+            continue
+        if i in plan:
+            m_idx, k = plan[i]
+            m = nodes[m_idx]
+            other = x.b if k == 0 else x.a
+            ops_of[i] = [m.a, m.b, other]
+        else:
+            ops_of[i] = [c for c in (x.a, x.b) if c is not None]
+    nodes_all = nodes
+    nodes = {i: x for i, x in nodes.items() if i not in skipped}
+    users = {i: [] for i in nodes}
+    for i in nodes:
+        for c in {c.idx: c for c in ops_of[i]}.values():
             users[c.idx].append(i)
     is_out = {o.idx for o in outputs}
     remaining = {i: len(users[i]) for i in nodes}   # unscheduled users
@@ -330,18 +346,27 @@ def greedy_order(outputs, prio_order):
     for i, x in nodes.items():
         if i in done:
             continue
-        pending[i] = len({c.idx for c in (x.a, x.b) if c is not None and c.idx not in done})
+        pending[i] = len({c.idx for c in ops_of[i] if c.idx not in done})
 
     def delta(i):
-        x = nodes[i]
-        ops = {c.idx for c in (x.a, x.b) if c is not None and not free(c)}
-        kills = sum(1 for c in ops if remaining[c] == 1 and c not in is_out)
-        return (1 if (users[i] or i in is_out) else 0) - kills
+        # an output is stored right after it is computed: it stays live only
+        # for its other users
+        ops = {c.idx for c in ops_of[i] if not free(c)}
+        kills = sum(1 for c in ops if remaining[c] == 1)
+        return (1 if users[i] else 0) - kills
+
+    when = {}                                        # position of each computed node
+
+    def tie(i):
+        if not oldest_first:
+            return prio.get(i, 0)
+        ts = [when[c.idx] for c in ops_of[i] if c.idx in when and not free(c)]
+        return (min(ts) if ts else 1 << 30, prio.get(i, 0))
 
     heap = []
     for i, k in pending.items():
         if k == 0:
-            heapq.heappush(heap, (delta(i), prio.get(i, 0), i))
+            heapq.heappush(heap, (delta(i), tie(i), i))
     # users of a completed operand become ready; after each pick the deltas of
     # ready users of its operands may drop (a lazy heap: stale entries re-keyed)
     while heap:
@@ -350,21 +375,40 @@ def greedy_order(outputs, prio_order):
             continue
         cur = delta(i)
         if cur != d:
-            heapq.heappush(heap, (cur, prio.get(i, 0), i))
+            heapq.heappush(heap, (cur, tie(i), i))
             continue
         done.add(i)
+        when[i] = len(order)
         order.append(i)
-        x = nodes[i]
-        for c in {c.idx for c in (x.a, x.b) if c is not None}:
+        for c in {c.idx for c in ops_of[i]}:
             remaining[c] -= 1
             if remaining[c] == 1 and not free(nodes[c]):
                 for u in users[c]:
                     if u not in done and pending.get(u) == 0:
-                        heapq.heappush(heap, (delta(u), prio.get(u, 0), u))
+                        heapq.heappush(heap, (delta(u), tie(u), u))
         for u in users[i]:
             pending[u] -= 1
             if pending[u] == 0:
-                heapq.heappush(heap, (delta(u), prio.get(u, 0), u))
+                heapq.heappush(heap, (delta(u), tie(u), u))
+    # products emitted only inside fmas: anywhere before their users
+    if skipped:
+        first_use = {}
+        for k, i in enumerate(order):
+            for c in ops_of.get(i, []):
+                first_use.setdefault(c.idx, k)
+        pos_of = {}
+        for m in skipped:
+            users_m = [j for j in plan if plan[j][0] == m]
+            pos_of[m] = min(order.index(j) for j in users_m if j in set(order)) if users_m else len(order)
+        ins = sorted(skipped, key=lambda m: pos_of[m])
+        out, it = [], 0
+        for k, i in enumerate(order):
+            while it < len(ins) and pos_of[ins[it]] <= k:
+                out.append(ins[it])
+                it += 1
+            out.append(i)
+        out.extend(ins[it:])
+        order = out
     return order
 
 
@@ -490,6 +534,8 @@ def emit(g: Graph, outputs, out_names, input_expr, param_expr, indent="  ", pref
         seq = dfs_order(outputs)
     elif order == "dfs_heavy":
         seq = dfs_order(outputs, heavy_first=True)
+    elif order == "greedy":
+        seq = greedy_order(outputs, dfs_order(outputs, heavy_first=True))
     else:
         seq = sorted(reachable(outputs))
     pos = {i: k for k, i in enumerate(seq)}
@@ -546,6 +592,11 @@ def emit_staged(g: Graph, outputs, out_stmts, input_key, param_expr, slots, inde
         seq = greedy_order(outputs, dfs_order(outputs, heavy_first=True))
     elif order == "greedy_plain":
         seq = greedy_order(outputs, dfs_order(outputs))
+    elif order == "greedy_f":
+        base = dfs_order(outputs, heavy_first=True)
+        seq = greedy_order(outputs, base, fused=fusion_plan(g, base, outputs))
+    elif order == "greedy_old":
+        seq = greedy_order(outputs, dfs_order(outputs, heavy_first=True), oldest_first=True)
     elif order == "greedy_rev":
         seq = greedy_rev_order(outputs, dfs_order(outputs, heavy_first=True))
     else:
