@@ -300,10 +300,11 @@ def dfs_order(outputs, heavy_first=False):
     return order
 
 
-def greedy_order(outputs, prio_order, oldest_first=False, fused=None):
+def greedy_order(outputs, prio_order):
     """Top-down list schedule that keeps few values live: among the nodes whose
     operands are all computed, take one that frees the most operands (its last
-    remaining user) net of the value it creates; ties go to the earlier node of
+    remaining user) net of the value it creates (an output is stored at once,
+    so it stays live only for its other users); ties go to the earlier node of
     prio_order.  Constants and parameters cost nothing and come first."""
     import heapq
     prio = {i: k for k, i in enumerate(prio_order)}
@@ -317,159 +318,44 @@ def greedy_order(outputs, prio_order, oldest_first=False, fused=None):
         for c in (x.a, x.b):
             if c is not None and c.idx not in nodes:
                 stack.append(c)
-    # operands as emitted: an add or subtract fused with a product reads the
-    # product's operands; a product emitted only inside fmas is not scheduled
-    plan, skipped = fused if fused is not None else ({}, set())
-    ops_of = {}
-    for i, x in nodes.items():
-        if i in skipped:
-            continue
-        if i in plan:
-            m_idx, k = plan[i]
-            m = nodes[m_idx]
-            other = x.b if k == 0 else x.a
-            ops_of[i] = [m.a, m.b, other]
-        else:
-            ops_of[i] = [c for c in (x.a, x.b) if c is not None]
-    nodes_all = nodes
-    nodes = {i: x for i, x in nodes.items() if i not in skipped}
+    ops_of = {i: {c.idx for c in (x.a, x.b) if c is not None} for i, x in nodes.items()}
     users = {i: [] for i in nodes}
     for i in nodes:
-        for c in {c.idx: c for c in ops_of[i]}.values():
-            users[c.idx].append(i)
-    is_out = {o.idx for o in outputs}
-    remaining = {i: len(users[i]) for i in nodes}   # unscheduled users
-    free = lambda x: x.op in ("c", "p")
-    order = [i for i, x in nodes.items() if free(x)]
+        for c in ops_of[i]:
+            users[c].append(i)
+    remaining = {i: len(users[i]) for i in nodes}   # users not yet scheduled
+    free = {i for i, x in nodes.items() if x.op in ("c", "p")}
+    order = [i for i in nodes if i in free]
     done = set(order)
-    pending = {}                                     # node -> operands not yet computed
-    for i, x in nodes.items():
-        if i in done:
-            continue
-        pending[i] = len({c.idx for c in ops_of[i] if c.idx not in done})
+    pending = {i: len(ops_of[i] - done) for i in nodes if i not in done}   # operands not yet computed
 
     def delta(i):
-        # an output is stored right after it is computed: it stays live only
-        # for its other users
-        ops = {c.idx for c in ops_of[i] if not free(c)}
-        kills = sum(1 for c in ops if remaining[c] == 1)
+        kills = sum(1 for c in ops_of[i] if c not in free and remaining[c] == 1)
         return (1 if users[i] else 0) - kills
 
-    when = {}                                        # position of each computed node
-
-    def tie(i):
-        if not oldest_first:
-            return prio.get(i, 0)
-        ts = [when[c.idx] for c in ops_of[i] if c.idx in when and not free(c)]
-        return (min(ts) if ts else 1 << 30, prio.get(i, 0))
-
-    heap = []
-    for i, k in pending.items():
-        if k == 0:
-            heapq.heappush(heap, (delta(i), tie(i), i))
-    # users of a completed operand become ready; after each pick the deltas of
-    # ready users of its operands may drop (a lazy heap: stale entries re-keyed)
+    heap = [(delta(i), prio.get(i, 0), i) for i, k in pending.items() if k == 0]
+    heapq.heapify(heap)
+    # a lazy heap: an entry whose delta has dropped since it was pushed is re-keyed
     while heap:
         d, _, i = heapq.heappop(heap)
         if i in done:
             continue
         cur = delta(i)
         if cur != d:
-            heapq.heappush(heap, (cur, tie(i), i))
+            heapq.heappush(heap, (cur, prio.get(i, 0), i))
             continue
         done.add(i)
-        when[i] = len(order)
         order.append(i)
-        for c in {c.idx for c in ops_of[i]}:
+        for c in ops_of[i]:
             remaining[c] -= 1
-            if remaining[c] == 1 and not free(nodes[c]):
+            if remaining[c] == 1 and c not in free:
                 for u in users[c]:
                     if u not in done and pending.get(u) == 0:
-                        heapq.heappush(heap, (delta(u), tie(u), u))
+                        heapq.heappush(heap, (delta(u), prio.get(u, 0), u))
         for u in users[i]:
             pending[u] -= 1
             if pending[u] == 0:
-                heapq.heappush(heap, (delta(u), tie(u), u))
-    # products emitted only inside fmas: anywhere before their users
-    if skipped:
-        first_use = {}
-        for k, i in enumerate(order):
-            for c in ops_of.get(i, []):
-                first_use.setdefault(c.idx, k)
-        pos_of = {}
-        for m in skipped:
-            users_m = [j for j in plan if plan[j][0] == m]
-            pos_of[m] = min(order.index(j) for j in users_m if j in set(order)) if users_m else len(order)
-        ins = sorted(skipped, key=lambda m: pos_of[m])
-        out, it = [], 0
-        for k, i in enumerate(order):
-            while it < len(ins) and pos_of[ins[it]] <= k:
-                out.append(ins[it])
-                it += 1
-            out.append(i)
-        out.extend(ins[it:])
-        order = out
-    return order
-
-
-def greedy_rev_order(outputs, prio_order):
-    """Bottom-up list schedule (built from the outputs backwards): a node can
-    be placed once all its users are; among those, take one whose placement
-    makes the fewest new values live (its operands not yet live) net of the
-    value it ends; ties go to the later node of prio_order.  Constants and
-    parameters cost nothing."""
-    import heapq
-    prio = {i: k for k, i in enumerate(prio_order)}
-    nodes = {}
-    stack = list(outputs)
-    while stack:
-        x = stack.pop()
-        if x.idx in nodes:
-            continue
-        nodes[x.idx] = x
-        for c in (x.a, x.b):
-            if c is not None and c.idx not in nodes:
-                stack.append(c)
-    users = {i: set() for i in nodes}
-    for i, x in nodes.items():
-        for c in (x.a, x.b):
-            if c is not None:
-                users[c.idx].add(i)
-    free = lambda x: x.op in ("c", "p")
-    live = set()                      # values used by placed nodes, not yet defined
-    placed = set()
-    left = {i: len(users[i]) for i in nodes}   # users not yet placed
-    is_out = {o.idx for o in outputs}
-
-    def delta(i):
-        x = nodes[i]
-        new = {c.idx for c in (x.a, x.b) if c is not None and not free(c) and c.idx not in live}
-        return len(new) - (1 if i in live else 0)
-
-    heap = []
-    for i in nodes:
-        if left[i] == 0 and not free(nodes[i]):
-            heapq.heappush(heap, (delta(i), -prio.get(i, 0), i))
-    rev = []
-    while heap:
-        d, _, i = heapq.heappop(heap)
-        if i in placed:
-            continue
-        cur = delta(i)
-        if cur != d:
-            heapq.heappush(heap, (cur, -prio.get(i, 0), i))
-            continue
-        placed.add(i)
-        rev.append(i)
-        live.discard(i)
-        x = nodes[i]
-        for c in {c.idx for c in (x.a, x.b) if c is not None}:
-            if not free(nodes[c]):
-                live.add(c)
-            left[c] -= 1
-            if left[c] == 0 and not free(nodes[c]):
-                heapq.heappush(heap, (delta(c), -prio.get(c, 0), c))
-    order = [i for i, x in nodes.items() if free(x)] + rev[::-1]
+                heapq.heappush(heap, (delta(u), prio.get(u, 0), u))
     return order
 
 
@@ -590,15 +476,6 @@ def emit_staged(g: Graph, outputs, out_stmts, input_key, param_expr, slots, inde
     largest slot count used)."""
     if order == "greedy":
         seq = greedy_order(outputs, dfs_order(outputs, heavy_first=True))
-    elif order == "greedy_plain":
-        seq = greedy_order(outputs, dfs_order(outputs))
-    elif order == "greedy_f":
-        base = dfs_order(outputs, heavy_first=True)
-        seq = greedy_order(outputs, base, fused=fusion_plan(g, base, outputs))
-    elif order == "greedy_old":
-        seq = greedy_order(outputs, dfs_order(outputs, heavy_first=True), oldest_first=True)
-    elif order == "greedy_rev":
-        seq = greedy_rev_order(outputs, dfs_order(outputs, heavy_first=True))
     else:
         seq = dfs_order(outputs, heavy_first=(order == "dfs_heavy"))
     pos = {i: k for k, i in enumerate(seq)}
