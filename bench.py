@@ -27,10 +27,12 @@ PEAK_HBM = 8000.0  # GB/s
 
 
 def source_hash() -> str:
+    """Hash of the sources the staged pointwise kernel is compiled from (its
+    device code, the generated algebra, the layout and its launcher)."""
     h = hashlib.sha256()
     for rel in ("paper_2309_06225_amd/csrc/kernels_fwd.h", "paper_2309_06225_amd/csrc/kernels_staged.h",
-                "paper_2309_06225_amd/csrc/gen/gen_rhs.inc", "paper_2309_06225_amd/csrc/gen/gen_rhs_staged.inc",
-                "paper_2309_06225_amd/csrc/libgrf.hip"):
+                "paper_2309_06225_amd/csrc/gen/gen_rhs_staged.inc", "paper_2309_06225_amd/csrc/gen/gen_layout.h",
+                "paper_2309_06225_amd/csrc/tu_staged.hip"):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
