@@ -150,6 +150,8 @@ struct PointOut {
   T ham;          // Hamiltonian constraint  R + 2/3 K^2 - A_ij A^ij - 2 (8 pi rho)
   T mom[3];       // momentum constraint  M_i - 8 pi S_i
   T rho[3];       // energy density n^a n^b T_ab of the canonical (X), X^2 and Gauss-Bonnet terms
+  T lgb;          // Gauss-Bonnet invariant of the spacetime (with the solved C_ij)
+  T weak[2];      // weak-coupling indicators |lambda'(phi)| sqrt|L_GB| and |2 g2 X|
   T C[6];         // solved C_ij = 4R_{i n j n}
   T p;            // solved Lie_n Pi
   T sysA[49];     // the assembled 7x7 system (row-major), for solver checks
@@ -849,6 +851,22 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
   out.rho[0] = (0.5 * Pi * Pi - 0.5 * X) * inv8pi;
   out.rho[1] = g2 * (X * Pi * Pi - 0.5 * X * X) * inv8pi;
   out.rho[2] = H00 * inv8pi;
+  // The Gauss-Bonnet invariant as the scalar's row of the system reads it: its
+  // spatial part 8 M_i M^i - 4 B_ijk B^ijk plus 8 G^kl C_kl with the solved
+  // C_kl.  The weak-coupling indicators (readings; the paper plots where such
+  // conditions exceed one without defining them): the Gauss-Bonnet coupling
+  // against the curvature scale, |lambda'(phi)| sqrt|L_GB|, and the X^2 term
+  // against the X term, |2 g2 X|.
+  {
+    T gc = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) gc += Gcu[i][j] * Cs[i][j];
+    out.lgb = 8.0 * gc + 8.0 * M2 - 4.0 * B2;
+    using std::abs;
+    using std::sqrt;
+    out.weak[0] = abs(dlam) * sqrt(abs(out.lgb));
+    out.weak[1] = abs(2.0 * g2 * X);
+  }
   for (int i = 0; i < 3; ++i) out.mom[i] = Mi[i] - S8im[i];
   out.flags = flags;
 }
@@ -1036,7 +1054,8 @@ void gather_point(const Box& b, const T* u, int i, int j, int k, PointIn<T>& in,
 }
 
 template <class T>
-int box_rhs(const Params<T>& P, const Box& b, const T* u, T* rhs, T* ham, T* mom, T* rho = nullptr) {
+int box_rhs(const Params<T>& P, const Box& b, const T* u, T* rhs, T* ham, T* mom, T* rho = nullptr,
+            T* coupling = nullptr) {
   int flags_all = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : flags_all)
   for (int k = 0; k < b.nz; ++k) {
@@ -1055,6 +1074,11 @@ int box_rhs(const Params<T>& P, const Box& b, const T* u, T* rhs, T* ham, T* mom
           for (int d = 0; d < 3; ++d) mom[d * b.fstride + c] = out.mom[d];
         if (rho)
           for (int d = 0; d < 3; ++d) rho[d * b.fstride + c] = out.rho[d];
+        if (coupling) {
+          coupling[c] = out.lgb;
+          coupling[b.fstride + c] = out.weak[0];
+          coupling[2 * b.fstride + c] = out.weak[1];
+        }
         flags_all |= out.flags;
       }
   }
@@ -1384,6 +1408,13 @@ int oracle_rk4_bc(const double* params, const int* dims, const double* spacing, 
   return rk4_steps_bc(P, b, read_bc(bcv), dt, nsteps, u);
 }
 
+// Gauss-Bonnet invariant and the two weak-coupling indicators on interior cells (three fields).
+int oracle_coupling(const double* params, const int* dims, const double* spacing, const double* u, double* out) {
+  Box b = make_box(dims, spacing);
+  Params<double> P = read_params<double>(params, nullptr);
+  return box_rhs(P, b, u, (double*)nullptr, (double*)nullptr, (double*)nullptr, (double*)nullptr, out);
+}
+
 void oracle_fill_periodic(const int* dims, double* u) {
   const double sp[3] = {1.0, 1.0, 1.0};
   Box b = make_box(dims, sp);
@@ -1443,6 +1474,9 @@ int oracle_rhs_point(const double* params, const double* u, const double* d1, co
     for (int d = 0; d < 7; ++d) extra[q++] = o.sysb[d];
     extra[q++] = o.pivot_ratio;
     for (int d = 0; d < 3; ++d) extra[q++] = o.rho[d];
+    extra[q++] = o.lgb;
+    extra[q++] = o.weak[0];
+    extra[q++] = o.weak[1];
   }
   return o.flags;
 }

@@ -277,6 +277,56 @@ def test_decoupled_metric_is_vacuum_and_scalar_is_full():
     np.testing.assert_allclose(r_dec0, r_full0, rtol=1e-13, atol=1e-14)
 
 
+@pytest.mark.parametrize("case", [0, 1, 3])
+@pytest.mark.parametrize("seed", [11, 12])
+def test_gauss_bonnet_invariant_covariant_pin(case, seed):
+    """The Gauss-Bonnet invariant the oracle reports (with its solved C_ij)
+    against R_abcd R^abcd - 4 R_ab R^ab + R^2 of the covariantly solved random
+    spacetime; the weak-coupling indicators against their definitions."""
+    import covariant_ref as C
+    params = I.default_params(kappa3=1.0, a_gauge=0.0, **COV_PARAMS[case])
+    ref = C.reference_point(seed + 7 * case, params)
+    _, ex, flags = O.rhs_point(I.params_vector(params), ref["u"], ref["d1"], ref["d2"], ref["d1"])
+    assert flags == 0
+    assert ex["lgb"] == pytest.approx(ref["LGB"], rel=1e-11, abs=1e-12)
+    phi = ref["u"][IDX["phi"]]
+    assert ex["weak"][0] == pytest.approx(abs(0.5 * params["lambda_gb"] * phi) * np.sqrt(abs(ref["LGB"])),
+                                          rel=1e-10, abs=1e-300)
+
+
+def test_gauss_bonnet_invariant_on_schwarzschild():
+    """On a static Schwarzschild slice the Gauss-Bonnet invariant is the
+    Kretschmann scalar 48 M^2 / R^6 (R the areal radius): fourth-order
+    convergence of the box values to it."""
+    errs = []
+    for n in (8, 16, 32):
+        dx = 1.0 / n
+        u, r = _schwarzschild(n, dx, (2.0, 0.5, 0.25), phi0=0.3)
+        pp = I.params_vector(I.default_params(a_gauge=0.0, lambda_gb=0.0, g2=0.0))
+        lgb = O.coupling(pp, u, dx)[0]
+        ri = I.interior(r)
+        R = ri * (1 + 1 / (2 * ri)) ** 2
+        exact = 48.0 / R ** 6
+        errs.append(np.abs(lgb - exact).max() / np.abs(exact).max())
+    assert errs[-1] < 1e-5
+    assert np.log2(errs[-2] / errs[-1]) > 3.7
+
+
+def test_weak_coupling_x2_indicator_closed_form():
+    """Flat metric, phi linear, Pi constant: |2 g2 X| with X = (Pi^2 - |grad phi|^2)/2,
+    and a vanishing Gauss-Bonnet invariant."""
+    u = I.set_flat(I.empty_state((6, 5, 7)))
+    X_, Y_, Z_ = I.coords((6, 5, 7), 0.25)
+    a = np.array([0.3, -0.2, 0.5])
+    u[IDX["phi"]] = 0.1 + a[0] * X_ + a[1] * Y_ + a[2] * Z_
+    u[IDX["Pi"]] = 0.7
+    g2 = 0.3
+    c = O.coupling(I.params_vector(I.default_params(lambda_gb=0.4, g2=g2)), u, 0.25)
+    Xv = 0.5 * (0.49 - float(a @ a))
+    np.testing.assert_allclose(c[2], abs(2 * g2 * Xv), rtol=1e-13)
+    assert np.abs(c[0]).max() < 1e-13 and np.abs(c[1]).max() < 1e-6
+
+
 @pytest.mark.parametrize("case", [0, 3, 4])
 @pytest.mark.parametrize("seed", [11, 12])
 def test_energy_densities_covariant_pin(case, seed):
