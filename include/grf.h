@@ -242,7 +242,7 @@ grf_status grf_status_clear(void* workspace, hipStream_t stream);
  * of the energy densities, counted on the expression graph (add, sub, mul and
  * reciprocal each 1), stencils not included; -1 for another `which`. */
 int64_t grf_flops_per_cell(int which /* 0 rhs, 1 rhs with shift advection, 2 vjp, 3 constraints, 4 energy,
-                                         5 rhs in the decoupling limit */);
+                                         5 rhs in the decoupling limit, 6 coupling diagnostics */);
 
 /* Constraint diagnostics (Key features, "Diagnostics": constraint monitoring):
  * per interior cell the Hamiltonian constraint R + (2/3) K^2 - A_ij A^ij -
@@ -266,6 +266,19 @@ grf_status grf_constraints(const grf_params* p, const grf_box* box, const double
  *   out  device [3][nz][ny][nx]: rho_X, rho_X2, rho_GB. */
 grf_status grf_energy_densities(const grf_params* p, const grf_box* box, const double* u, double* out,
                                 void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Gauss-Bonnet invariant and weak-coupling indicators (Key features,
+ * "Diagnostics"; the regions where weak-coupling conditions exceed one).  Per
+ * interior cell: L_GB = R_abcd R^abcd - 4 R_ab R^ab + R^2 of the spacetime,
+ * evaluated as the scalar equation uses it (8 G^kl C_kl + 8 M_i M^i -
+ * 4 B_ijk B^ijk with the C_ij of the per-cell solve), then |lambda'(phi)|
+ * sqrt|L_GB| (the Gauss-Bonnet coupling against the curvature scale) and
+ * |2 g2 X| (the X^2 term against the X term); the paper does not define the
+ * conditions, these two ratios are this library's reading.  Same stencils,
+ * arguments, workspace and errors as grf_constraints;
+ *   out  device [3][nz][ny][nx]: L_GB, |lambda'| sqrt|L_GB|, |2 g2 X|. */
+grf_status grf_coupling_diagnostics(const grf_params* p, const grf_box* box, const double* u, double* out,
+                                    void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ---- Batched boxes (uneven sizes and refinement levels, frozen ghosts).
  * One RK4 step of the batch is four stages; each stage is one persistent

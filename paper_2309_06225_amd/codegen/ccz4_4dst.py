@@ -380,7 +380,19 @@ def build(shift_advec: bool = False, decoupled: bool = False):
     constraints = [Hg - 2.0 * rho8] + [Mi[i] - S8i[i] for i in R3]
     return dict(graph=g, rhs=rhs, pivots=pivots, pivot_check=pivot_check, inputs=inputs, params=P,
                 theta=[P["lambda_gb"], P["g2"]], solution=x, constraints=constraints,
-                scalar_parts=dict(X=X, Pi=Pi, GW=GW, g2=g2))
+                scalar_parts=dict(X=X, Pi=Pi, GW=GW, g2=g2, Gcu=Gcu, Cs=Cs, M2=M2, B2=B2, dlam=dlam))
+
+
+def coupling(b):
+    """Gauss-Bonnet invariant with the solved C_ij (the scalar row's reading:
+    8 G^kl C_kl + 8 M_i M^i - 4 B_ijk B^ijk) and the weak-coupling indicators
+    |lambda'(phi)| sqrt|L_GB| and |2 g2 X|, added to the graph on request."""
+    q = b["scalar_parts"]
+    g = q["X"].g
+    Gcu, Cs = q["Gcu"], q["Cs"]
+    gc = g.sum(Gcu[i][j] * Cs[i][j] for i in range(3) for j in range(3))
+    lgb = 8.0 * gc + 8.0 * q["M2"] - 4.0 * q["B2"]
+    return [lgb, g.fabs(q["dlam"]) * g.sqrt(g.fabs(lgb)), g.fabs(2.0 * q["g2"] * q["X"])]
 
 
 def energies(b):

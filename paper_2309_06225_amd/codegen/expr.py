@@ -115,6 +115,19 @@ class Graph:
             return a.a
         return self._new("neg", a)
 
+    def sqrt(self, a):
+        """Square root (diagnostics only: the reverse mode does not handle it)."""
+        return self._new("sqrt", self.lift(a))
+
+    def fabs(self, a):
+        """Absolute value (diagnostics only: the reverse mode does not handle it)."""
+        a = self.lift(a)
+        if a.op == "c":
+            return self.const(abs(a.val))
+        if a.op == "neg":
+            a = a.a
+        return self._new("abs", a)
+
     def lift(self, x):
         if isinstance(x, Node):
             return x
@@ -236,14 +249,15 @@ def _lit(v: float) -> str:
 
 
 def count_flops(g: Graph, outputs):
-    """Count of add, sub, mul and reciprocal nodes (1 flop each); negation is free."""
+    """Count of add, sub, mul, reciprocal and square-root nodes (1 flop each);
+    negation and absolute value are free."""
     need = reachable(outputs)
     c = {"+": 0, "-": 0, "*": 0, "rcp": 0, "neg": 0}
     for i in need:
         op = g.nodes[i].op
-        if op in c:
-            c[op] += 1
-    total = c["+"] + c["-"] + c["*"] + c["rcp"]
+        if op in c or op in ("sqrt", "abs"):
+            c[op] = c.get(op, 0) + 1
+    total = c["+"] + c["-"] + c["*"] + c["rcp"] + c.get("sqrt", 0)
     return total, c
 
 
@@ -408,6 +422,10 @@ def _node_expr(g, n, name_of, plan):
         return f"-{name_of(n.a)}"
     if n.op == "rcp":
         return f"1.0 / {name_of(n.a)}"
+    if n.op == "sqrt":
+        return f"sqrt({name_of(n.a)})"
+    if n.op == "abs":
+        return f"fabs({name_of(n.a)})"
     raise ValueError(n.op)
 
 

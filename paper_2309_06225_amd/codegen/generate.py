@@ -127,6 +127,18 @@ def energy_code():
     return code, flops
 
 
+def coupling_code():
+    """Gauss-Bonnet invariant and the weak-coupling indicators of one cell:
+    GRF_CON(q, v), q = 0, 1, 2."""
+    b = M.build(False)
+    g = b["graph"]
+    outs = M.coupling(b)
+    names = [f"GRF_CON({q}, {{}})" for q in range(len(outs))]
+    code = emit(g, outs, names, input_expr, param_expr, order="dfs")
+    flops, ops = count_flops(g, outs)
+    return code, flops
+
+
 def _dec_flops():
     b = M.build(False, decoupled=True)
     return count_flops(b["graph"], b["rhs"])[0]
@@ -195,6 +207,7 @@ def main(outdir: str):
         f"#define GRF_FLOPS_VJP_SHIFTADV {vfl1}",
         f"#define GRF_FLOPS_CONSTRAINTS {constraints_code()[1]}",
         f"#define GRF_FLOPS_ENERGY {energy_code()[1]}",
+        f"#define GRF_FLOPS_COUPLING {coupling_code()[1]}",
         f"#define GRF_FLOPS_RHS_DECOUPLED {_dec_flops()}",
         f"#define GRF_STAGE_SLOTS {STAGE_SLOTS}  // slots per buffer of the staged pointwise kernel",
         "// parameters read by the generated code (derived combinations precomputed on the host)",
@@ -260,6 +273,11 @@ def main(outdir: str):
         fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
         fh.write(f"// energy densities of the canonical, X^2 and Gauss-Bonnet terms: {efl} flops/cell\n")
         fh.write("{\n" + PRAGMA + en + "\n}\n")
+    cp, cpfl = coupling_code()
+    with open(os.path.join(outdir, "gen_coupling.inc"), "w") as fh:
+        fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
+        fh.write(f"// Gauss-Bonnet invariant and weak-coupling indicators: {cpfl} flops/cell\n")
+        fh.write("{\n" + PRAGMA + cp + "\n}\n")
     with open(os.path.join(outdir, "gen_vjp.inc"), "w") as fh:
         fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
         fh.write(f"// vector-Jacobian product: {vfl0} flops/cell ({vops0})\n")

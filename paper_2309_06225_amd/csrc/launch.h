@@ -32,7 +32,8 @@ int grid_deriv_batch(int variant, int64_t work);
 hipError_t launch_periodic(const BoxDev& bd, double* u, hipStream_t st);
 hipError_t launch_status_clear(unsigned* s, hipStream_t st);
 // Hamiltonian and momentum constraints of every interior cell (out: [4][ncell])
-// which: 0 Hamiltonian and momentum constraints (4 outputs), 1 energy densities (3 outputs)
+// which: 0 Hamiltonian and momentum constraints (4 outputs), 1 energy densities (3 outputs),
+// 2 Gauss-Bonnet invariant and weak-coupling indicators (3 outputs)
 hipError_t launch_constraints(int which, const BoxDev& bd, const grf_point_params& pp, const double* u,
                               const double* D, double* out, hipStream_t st);
 constexpr int kPeakChains = 8;  // independent FMA chains per thread of the FP64 peak probe

@@ -242,6 +242,7 @@ int64_t grf_flops_per_cell(int which) {
     case 3: return GRF_FLOPS_CONSTRAINTS;
     case 4: return GRF_FLOPS_ENERGY;
     case 5: return GRF_FLOPS_RHS_DECOUPLED;
+    case 6: return GRF_FLOPS_COUPLING;
     default: return -1;
   }
 }
@@ -522,6 +523,11 @@ grf_status grf_constraints(const grf_params* p, const grf_box* box, const double
 grf_status grf_energy_densities(const grf_params* p, const grf_box* box, const double* u, double* out,
                                 void* workspace, size_t workspace_bytes, hipStream_t stream) {
   return diagnostics(1, p, box, u, out, workspace, workspace_bytes, stream);
+}
+
+grf_status grf_coupling_diagnostics(const grf_params* p, const grf_box* box, const double* u, double* out,
+                                    void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  return diagnostics(2, p, box, u, out, workspace, workspace_bytes, stream);
 }
 
 grf_status grf_enforce(const grf_params* p, const grf_box* box, double* u, hipStream_t stream) {

@@ -1,7 +1,8 @@
 // Diagnostics per interior cell from the derivative record of the stencil
 // stage and the state: the Hamiltonian and momentum constraints (WHICH = 0)
-// and the energy densities of the canonical, X^2 and Gauss-Bonnet terms of the
-// action (WHICH = 1).
+// the energy densities of the canonical, X^2 and Gauss-Bonnet terms of the
+// action (WHICH = 1), and the Gauss-Bonnet invariant with the weak-coupling
+// indicators (WHICH = 2).
 #include "kernels_fwd.h"
 #include "launch.h"
 
@@ -25,8 +26,10 @@ __global__ __launch_bounds__(kPointThreads) void k_constraints(BoxDev b, grf_poi
 #define GRF_CON(q, v) out[(int64_t)(q) * b.ncell + c] = (v)
   if constexpr (WHICH == 0) {
 #include "gen/gen_constraints.inc"
-  } else {
+  } else if constexpr (WHICH == 1) {
 #include "gen/gen_energy.inc"
+  } else {
+#include "gen/gen_coupling.inc"
   }
 #undef GRF_CON
 #undef GRF_P
@@ -39,8 +42,10 @@ hipError_t launch_constraints(int which, const BoxDev& bd, const grf_point_param
   const int64_t nblk = (bd.ncell + kPointThreads - 1) / kPointThreads;
   if (which == 0)
     hipLaunchKernelGGL(k_constraints<0>, dim3((unsigned)nblk), dim3(kPointThreads), 0, st, bd, pp, u, D, out);
-  else
+  else if (which == 1)
     hipLaunchKernelGGL(k_constraints<1>, dim3((unsigned)nblk), dim3(kPointThreads), 0, st, bd, pp, u, D, out);
+  else
+    hipLaunchKernelGGL(k_constraints<2>, dim3((unsigned)nblk), dim3(kPointThreads), 0, st, bd, pp, u, D, out);
   return hipGetLastError();
 }
 

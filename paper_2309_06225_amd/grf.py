@@ -68,6 +68,8 @@ def lib():
         L.grf_constraints.restype = ctypes.c_int
         L.grf_energy_densities.argtypes = [P, B, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.grf_energy_densities.restype = ctypes.c_int
+        L.grf_coupling_diagnostics.argtypes = [P, B, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.grf_coupling_diagnostics.restype = ctypes.c_int
         L.grf_rk4_stage.argtypes = [P, B, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.grf_fill_periodic.argtypes = [B, _vp, _vp]
         L.grf_enforce.argtypes = [P, B, _vp, _vp]
@@ -246,6 +248,15 @@ def rk4_stage_bc(params: Params, box: Box, bc: BC, stage, dt, u0, us, unext, acc
     _check(lib().grf_rk4_stage_bc(ctypes.byref(params), ctypes.byref(box), ctypes.byref(bc), int(stage), float(dt),
                                   _ptr(u0), _ptr(us), _ptr(unext), _ptr(acc), _ptr(gacc), _ptr(ws), ws.numel() * 8,
                                   _stream(stream)))
+
+
+def coupling_diagnostics(params: Params, box: Box, u, ws, stream=None):
+    """-> (3, nz, ny, nx): the Gauss-Bonnet invariant and the weak-coupling
+    indicators |lambda'(phi)| sqrt|L_GB| and |2 g2 X| on the interior."""
+    out = torch.empty((3, box.nz, box.ny, box.nx), dtype=torch.float64, device=u.device)
+    _check(lib().grf_coupling_diagnostics(ctypes.byref(params), ctypes.byref(box), _ptr(u), _ptr(out), _ptr(ws),
+                                          ws.numel() * 8, _stream(stream)))
+    return out
 
 
 def enforce(params: Params, box: Box, u, stream=None):

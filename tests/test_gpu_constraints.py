@@ -117,3 +117,36 @@ def test_energy_densities_match_oracle(case):
     for q in range(3):
         assert np.abs(ro[q]).max() > 0.0, q
         assert _rel(rg[q], ro[q]) <= 1e-12, (q, _rel(rg[q], ro[q]))
+
+
+def gpu_coupling(p, u, dx, bc=G.BC_FROZEN):
+    ut = torch.from_numpy(u).to(DEV)
+    box = G.box_of(ut, dx, bc)
+    ws = G.alloc_workspace(G.workspace_bytes(box))
+    return G.coupling_diagnostics(G.make_params(p), box, ut, ws).cpu().numpy()
+
+
+@pytest.mark.parametrize("case", ["noise32", "puncture_ragged"])
+def test_coupling_diagnostics_match_oracle(case):
+    print("case: Gauss-Bonnet invariant and weak-coupling indicators", case, flush=True)
+    p = I.default_params(lambda_gb=0.3, g2=0.05)
+    u, dx, bc = _case(case)
+    co = O.coupling(I.params_vector(p), u, dx)
+    cg = gpu_coupling(p, u, dx, bc)
+    for q in range(3):
+        assert np.abs(co[q]).max() > 0.0, q
+        assert _rel(cg[q], co[q]) <= 1e-12, (q, _rel(cg[q], co[q]))
+
+
+def test_coupling_diagnostics_full_size_sampled():
+    """128^3 single puncture: GPU values at every cell, the oracle's at sampled
+    cells (its box routine on a 3-cell-thick slab around each sampled plane)."""
+    print("case: coupling diagnostics 128^3 sampled planes", flush=True)
+    p = I.default_params(lambda_gb=0.2, g2=0.02)
+    u = I.single_puncture(128, 1.0 / 8.0)
+    cg = gpu_coupling(p, u, 1.0 / 8.0)
+    for k in (0, 40, 64, 127):
+        slab = u[:, k:k + 7, :, :]   # interior plane k and its 3 ghost planes either side
+        co = O.coupling(I.params_vector(p), slab, 1.0 / 8.0)[:, 0]
+        for q in range(3):
+            assert _rel(cg[q, k], co[q]) <= 1e-12, (k, q, _rel(cg[q, k], co[q]))
