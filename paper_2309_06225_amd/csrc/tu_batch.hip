@@ -1,4 +1,4 @@
-// Batched persistent pointwise kernel of libgrf for one stage mode
+// Batched pointwise kernel of libgrf for one stage mode
 // (compiled once per mode with -DGRF_TU_MODE=1, 2 or 4).
 #include "kernels_batch.h"
 #include "launch.h"
@@ -18,13 +18,11 @@ hipError_t launch_point_batch_m<GRF_TU_MODE>(int sa, int grid, const BatchBoxDev
   return hipGetLastError();
 }
 
+// one workgroup per entry
 template <>
 int grid_point_batch_m<GRF_TU_MODE>(int sa, int64_t work) {
-  int per = 1;
-  hipError_t e = sa ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_point_batch<GRF_TU_MODE, 1>, kStagedThreads, 0)
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_point_batch<GRF_TU_MODE, 0>, kStagedThreads, 0);
-  if (e != hipSuccess) per = 1;
-  return persistent_grid_from(per, work);
+  (void)sa;
+  return (int)(work < 1 ? 1 : work);
 }
 
 }  // namespace grf
