@@ -282,9 +282,10 @@ grf_status grf_coupling_diagnostics(const grf_params* p, const grf_box* box, con
 
 /* ---- Batched boxes (uneven sizes and refinement levels, frozen ghosts).
  * One RK4 step of the batch is four stages; each stage is one persistent
- * stencil launch per stencil variant in use and one persistent pointwise
- * launch, covering every box (work lists of (box, tile or column chunk) and
- * (box, 64-cell wave) entries, fixed assignment to workgroups, no atomics).
+ * stencil launch per stencil variant in use and one pointwise launch,
+ * covering every box (work lists of (box, tile or column chunk) entries,
+ * fixed assignment to workgroups, and (box, 64-cell wave) entries, one per
+ * workgroup; no atomics).
  * Per cell the device code is the one of grf_rk4_stage, so results are
  * bitwise identical to per-box launches (grf_batch_step_perbox runs that
  * reference form on the same buffers).  Boxes use stencil variant 8 (the
