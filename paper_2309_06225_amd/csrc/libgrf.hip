@@ -146,7 +146,7 @@ size_t deriv_bytes(const grf_box* b) {
 constexpr int kTileVariantsMax = kDerivVariants;
 // stencil variants the batched form can run (tiled shapes, z-marching 16x8x32, 32x8x32, 16x16x32)
 constexpr int kBatchVariants[] = {0, 1, 2, 3, 4, 5, 6, 8};
-int g_tile_variant = 6;  // z-marching 32x8 columns, 32-plane chunks
+int g_tile_variant = 17;  // z-marching 128x8 columns, 32-plane chunks
 
 // Optional per-kernel timing with HIP events recorded on the launch stream
 // around each stencil-stage and pointwise launch (enabled by grf_prof_begin).
