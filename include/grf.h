@@ -352,7 +352,7 @@ int grf_get_tile_variant(void);
  * 2 (default) = as 0, but the pointwise kernel copies its inputs (record
  *     components, state, u0, accumulator) phase by phase into LDS with
  *     LDS-direct loads, one phase ahead of the arithmetic.
- * On a 128^3 box one stage takes about 3.5 ms (0), 9.4 ms (1) and 2.5 ms (2).
+ * On a 128^3 box one stage takes about 3.4 ms (0), 9.4 ms (1) and 2.3 ms (2).
  * Results are bitwise identical.  GRF_EINVAL outside 0..2. */
 grf_status grf_set_stage_path(int path);
 int grf_get_stage_path(void);
