@@ -150,3 +150,30 @@ def test_coupling_diagnostics_full_size_sampled():
         co = O.coupling(I.params_vector(p), slab, 1.0 / 8.0)[:, 0]
         for q in range(3):
             assert _rel(cg[q, k], co[q]) <= 1e-12, (k, q, _rel(cg[q, k], co[q]))
+
+
+def test_constraints_and_energy_full_size_sampled():
+    """128^3 single puncture: GPU constraints and energy densities at every
+    cell against the oracle on four planes (each a 1-cell-thick box with its
+    three neighbour planes either side as ghosts)."""
+    print("case: constraints and energy densities 128^3 sampled planes", flush=True)
+    p = I.default_params(lambda_gb=0.2, g2=0.02)
+    dx = 1.0 / 8.0
+    u = I.single_puncture(128, dx)
+    ut = torch.from_numpy(u).to(DEV)
+    box = G.box_of(ut, dx)
+    ws = G.alloc_workspace(G.workspace_bytes(box))
+    P = G.make_params(p)
+    ham, mom = G.constraints(P, box, ut, ws)
+    rho = G.energy_densities(P, box, ut, ws)
+    ham, mom, rho = ham.cpu().numpy(), mom.cpu().numpy(), rho.cpu().numpy()
+    for k in (0, 40, 64, 127):
+        slab = u[:, k:k + 7, :, :]
+        ho, mo = O.constraints(I.params_vector(p), slab, dx)
+        ro = O.energy_densities(I.params_vector(p), slab, dx)
+        assert _rel(ham[k], ho[0]) <= 1e-12, (k, _rel(ham[k], ho[0]))
+        for d in range(3):
+            assert _rel(mom[d, k], mo[d, 0]) <= 1e-12, (k, d)
+        for q in range(3):
+            if np.abs(ro[q, 0]).max() > 0:
+                assert _rel(rho[q, k], ro[q, 0]) <= 1e-12, (k, q, _rel(rho[q, k], ro[q, 0]))
