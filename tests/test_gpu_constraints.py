@@ -167,13 +167,18 @@ def test_constraints_and_energy_full_size_sampled():
     ham, mom = G.constraints(P, box, ut, ws)
     rho = G.energy_densities(P, box, ut, ws)
     ham, mom, rho = ham.cpu().numpy(), mom.cpu().numpy(), rho.cpu().numpy()
+    # relative per field: the error over the field's largest value in the box
+    # (far from the puncture the constraints are ~1e-11, the result of
+    # cancellation among much larger terms, so a plane's own maximum is no scale)
+    s_ham = np.abs(ham).max()
+    s_mom = np.abs(mom).max(axis=(1, 2, 3))
+    s_rho = np.abs(rho).max(axis=(1, 2, 3))
     for k in (0, 40, 64, 127):
         slab = u[:, k:k + 7, :, :]
         ho, mo = O.constraints(I.params_vector(p), slab, dx)
         ro = O.energy_densities(I.params_vector(p), slab, dx)
-        assert _rel(ham[k], ho[0]) <= 1e-12, (k, _rel(ham[k], ho[0]))
+        assert np.abs(ham[k] - ho[0]).max() <= 1e-12 * s_ham, k
         for d in range(3):
-            assert _rel(mom[d, k], mo[d, 0]) <= 1e-12, (k, d)
+            assert np.abs(mom[d, k] - mo[d, 0]).max() <= 1e-12 * s_mom[d], (k, d)
         for q in range(3):
-            if np.abs(ro[q, 0]).max() > 0:
-                assert _rel(rho[q, k], ro[q, 0]) <= 1e-12, (k, q, _rel(rho[q, k], ro[q, 0]))
+            assert np.abs(rho[q, k] - ro[q, 0]).max() <= 1e-12 * max(s_rho[q], 1e-300), (k, q)
