@@ -102,8 +102,9 @@ void inv3(const T m[3][3], T out[3][3]) {
 // solver will do for the oracle).  Returns the smallest |pivot| / (max-norm of
 // its row) seen, so the caller can flag near-singular systems.
 template <class T>
-double gepp_solve(int n, T* A /* n*n row-major, destroyed */, T* b /* n, destroyed */, T* x) {
+double gepp_solve(int n, T* A /* n*n row-major, destroyed */, T* b /* n, destroyed */, T* x, T* det = nullptr) {
   double worst = 1e300;
+  int swaps = 0;
   std::vector<int> perm(n);
   for (int i = 0; i < n; ++i) perm[i] = i;
   for (int k = 0; k < n; ++k) {
@@ -116,6 +117,7 @@ double gepp_solve(int n, T* A /* n*n row-major, destroyed */, T* b /* n, destroy
     if (p != k) {
       for (int j = 0; j < n; ++j) std::swap(A[k * n + j], A[p * n + j]);
       std::swap(b[k], b[p]);
+      ++swaps;
     }
     double rownorm = 0.0;
     for (int j = k; j < n; ++j) rownorm = std::max(rownorm, std::abs(re(A[k * n + j])));
@@ -131,6 +133,11 @@ double gepp_solve(int n, T* A /* n*n row-major, destroyed */, T* b /* n, destroy
     T s = b[i];
     for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * x[j];
     x[i] = s / A[i * n + i];
+  }
+  if (det) {  // determinant: product of the pivots, sign of the row exchanges
+    T d = (swaps % 2) ? T(-1.0) : T(1.0);
+    for (int k = 0; k < n; ++k) d *= A[k * n + k];
+    *det = d;
   }
   return worst;
 }
@@ -152,6 +159,7 @@ struct PointOut {
   T rho[3];       // energy density n^a n^b T_ab of the canonical (X), X^2 and Gauss-Bonnet terms
   T lgb;          // Gauss-Bonnet invariant of the spacetime (with the solved C_ij)
   T weak[2];      // weak-coupling indicators |lambda'(phi)| sqrt|L_GB| and |2 g2 X|
+  T detA;         // determinant of the per-cell system (zero where the time derivatives cannot be solved for)
   T C[6];         // solved C_ij = 4R_{i n j n}
   T p;            // solved Lie_n Pi
   T sysA[49];     // the assembled 7x7 system (row-major), for solver checks
@@ -722,7 +730,9 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
   T Awork[49], bwork[7], xs[7];
   for (int q = 0; q < 49; ++q) Awork[q] = Amat[q];
   for (int q = 0; q < 7; ++q) bwork[q] = bvec[q];
-  const double pr = gepp_solve(7, Awork, bwork, xs);
+  T detA;
+  const double pr = gepp_solve(7, Awork, bwork, xs, &detA);
+  out.detA = detA;
   out.pivot_ratio = pr;
   if (!(pr >= 1e-12)) flags |= FLAG_HYPERBOLIC;
   T Cs[3][3];
@@ -1078,6 +1088,7 @@ int box_rhs(const Params<T>& P, const Box& b, const T* u, T* rhs, T* ham, T* mom
           coupling[c] = out.lgb;
           coupling[b.fstride + c] = out.weak[0];
           coupling[2 * b.fstride + c] = out.weak[1];
+          coupling[3 * b.fstride + c] = out.detA;
         }
         flags_all |= out.flags;
       }
@@ -1408,7 +1419,8 @@ int oracle_rk4_bc(const double* params, const int* dims, const double* spacing, 
   return rk4_steps_bc(P, b, read_bc(bcv), dt, nsteps, u);
 }
 
-// Gauss-Bonnet invariant and the two weak-coupling indicators on interior cells (three fields).
+// Gauss-Bonnet invariant, the two weak-coupling indicators and the determinant of the
+// per-cell system on interior cells (four fields).
 int oracle_coupling(const double* params, const int* dims, const double* spacing, const double* u, double* out) {
   Box b = make_box(dims, spacing);
   Params<double> P = read_params<double>(params, nullptr);
@@ -1477,6 +1489,7 @@ int oracle_rhs_point(const double* params, const double* u, const double* d1, co
     extra[q++] = o.lgb;
     extra[q++] = o.weak[0];
     extra[q++] = o.weak[1];
+    extra[q++] = o.detA;
   }
   return o.flags;
 }

@@ -164,15 +164,16 @@ def pack_bc(bc):
 
 
 def coupling(params, u, dx):
-    """(3,nz,ny,nx) on the interior: the Gauss-Bonnet invariant and the
-    weak-coupling indicators |lambda'(phi)| sqrt|L_GB| and |2 g2 X|."""
+    """(4,nz,ny,nx) on the interior: the Gauss-Bonnet invariant, the
+    weak-coupling indicators |lambda'(phi)| sqrt|L_GB| and |2 g2 X|, and the
+    determinant of the per-cell system."""
     u = _c(u)
-    out = np.zeros((NF,) + u.shape[1:])  # only the first 3 fields are written
+    out = np.zeros((NF,) + u.shape[1:])  # only the first 4 fields are written
     p = _c(params)
     dims = _dims(u)
     lib().oracle_coupling(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(u), _d(out))
     s = (slice(NG, -NG),) * 3
-    return out[(slice(0, 3),) + s]
+    return out[(slice(0, 4),) + s]
 
 
 def fill_bc(u, dx, bc):
@@ -241,11 +242,11 @@ def rhs_point(params, u, d1, d2, adv):
     d2 = _c(d2)
     adv = _c(adv)
     out = np.zeros(NF)
-    extra = np.zeros(74)
+    extra = np.zeros(75)
     flags = lib().oracle_rhs_point(_d(p), _d(u), _d(d1), _d(d2), _d(adv), _d(out), _d(extra))
     ex = dict(ham=extra[0], mom=extra[1:4], C=extra[4:10], p=extra[10],
               A=extra[11:60].reshape(7, 7), b=extra[60:67], pivot_ratio=extra[67], rho=extra[68:71],
-              lgb=extra[71], weak=extra[72:74])
+              lgb=extra[71], weak=extra[72:74], detA=extra[74])
     return out, ex, flags
 
 

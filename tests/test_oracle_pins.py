@@ -294,6 +294,27 @@ def test_gauss_bonnet_invariant_covariant_pin(case, seed):
                                           rel=1e-10, abs=1e-300)
 
 
+def test_system_determinant():
+    """The determinant the oracle reports is that of its assembled per-cell
+    matrix (checked with numpy on random spacetimes, whose matrices the
+    covariant pin fixes); without the Gauss-Bonnet coupling the matrix is the
+    identity except for D_Pi = 1 + 3 g2 Pi^2 - g2 |grad phi|^2, its determinant."""
+    import covariant_ref as C
+    for case in (0, 3):
+        params = I.default_params(kappa3=1.0, a_gauge=0.0, **COV_PARAMS[case])
+        ref = C.reference_point(21 + case, params)
+        _, ex, _ = O.rhs_point(I.params_vector(params), ref["u"], ref["d1"], ref["d2"], ref["d1"])
+        assert ex["detA"] == pytest.approx(np.linalg.det(ex["A"]), rel=1e-12)
+    u = I.set_flat(I.empty_state((6, 5, 7)))
+    X_, Y_, Z_ = I.coords((6, 5, 7), 0.25)
+    a = np.array([0.3, -0.2, 0.5])
+    u[IDX["phi"]] = 0.1 + a[0] * X_ + a[1] * Y_ + a[2] * Z_
+    u[IDX["Pi"]] = 0.7
+    g2 = 0.3
+    det = O.coupling(I.params_vector(I.default_params(lambda_gb=0.0, g2=g2)), u, 0.25)[3]
+    np.testing.assert_allclose(det, 1 + 3 * g2 * 0.49 - g2 * float(a @ a), rtol=1e-13)
+
+
 def test_gauss_bonnet_invariant_on_schwarzschild():
     """On a static Schwarzschild slice the Gauss-Bonnet invariant is the
     Kretschmann scalar 48 M^2 / R^6 (R the areal radius): fourth-order
