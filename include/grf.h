@@ -274,9 +274,13 @@ grf_status grf_energy_densities(const grf_params* p, const grf_box* box, const d
  * 4 B_ijk B^ijk with the C_ij of the per-cell solve), then |lambda'(phi)|
  * sqrt|L_GB| (the Gauss-Bonnet coupling against the curvature scale) and
  * |2 g2 X| (the X^2 term against the X term); the paper does not define the
- * conditions, these two ratios are this library's reading.  Same stencils,
- * arguments, workspace and errors as grf_constraints;
- *   out  device [3][nz][ny][nx]: L_GB, |lambda'| sqrt|L_GB|, |2 g2 X|. */
+ * conditions, these two ratios are this library's reading.  Fourth, the
+ * determinant of the per-cell 7x7 system (the product of its elimination
+ * pivots): it vanishes where the mixed time derivatives can no longer be
+ * solved for, this library's on-path stand-in for the effective-metric
+ * determinant the paper plots.  Same stencils, arguments, workspace and
+ * errors as grf_constraints;
+ *   out  device [4][nz][ny][nx]: L_GB, |lambda'| sqrt|L_GB|, |2 g2 X|, det. */
 grf_status grf_coupling_diagnostics(const grf_params* p, const grf_box* box, const double* u, double* out,
                                     void* workspace, size_t workspace_bytes, hipStream_t stream);
 

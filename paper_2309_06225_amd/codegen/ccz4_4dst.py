@@ -385,14 +385,18 @@ def build(shift_advec: bool = False, decoupled: bool = False):
 
 def coupling(b):
     """Gauss-Bonnet invariant with the solved C_ij (the scalar row's reading:
-    8 G^kl C_kl + 8 M_i M^i - 4 B_ijk B^ijk) and the weak-coupling indicators
-    |lambda'(phi)| sqrt|L_GB| and |2 g2 X|, added to the graph on request."""
+    8 G^kl C_kl + 8 M_i M^i - 4 B_ijk B^ijk), the weak-coupling indicators
+    |lambda'(phi)| sqrt|L_GB| and |2 g2 X|, and the determinant of the
+    per-cell system, added to the graph on request."""
     q = b["scalar_parts"]
     g = q["X"].g
     Gcu, Cs = q["Gcu"], q["Cs"]
     gc = g.sum(Gcu[i][j] * Cs[i][j] for i in range(3) for j in range(3))
     lgb = 8.0 * gc + 8.0 * q["M2"] - 4.0 * q["B2"]
-    return [lgb, g.fabs(q["dlam"]) * g.sqrt(g.fabs(lgb)), g.fabs(2.0 * q["g2"] * q["X"])]
+    det = b["pivots"][0]
+    for pv in b["pivots"][1:]:
+        det = det * pv  # the elimination has no row exchanges: det = product of the pivots
+    return [lgb, g.fabs(q["dlam"]) * g.sqrt(g.fabs(lgb)), g.fabs(2.0 * q["g2"] * q["X"]), det]
 
 
 def energies(b):

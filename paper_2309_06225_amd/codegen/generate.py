@@ -128,8 +128,8 @@ def energy_code():
 
 
 def coupling_code():
-    """Gauss-Bonnet invariant and the weak-coupling indicators of one cell:
-    GRF_CON(q, v), q = 0, 1, 2."""
+    """Gauss-Bonnet invariant, the weak-coupling indicators and the
+    determinant of the per-cell system of one cell: GRF_CON(q, v), q = 0..3."""
     b = M.build(False)
     g = b["graph"]
     outs = M.coupling(b)
@@ -276,7 +276,7 @@ def main(outdir: str):
     cp, cpfl = coupling_code()
     with open(os.path.join(outdir, "gen_coupling.inc"), "w") as fh:
         fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
-        fh.write(f"// Gauss-Bonnet invariant and weak-coupling indicators: {cpfl} flops/cell\n")
+        fh.write(f"// Gauss-Bonnet invariant, weak-coupling indicators, system determinant: {cpfl} flops/cell\n")
         fh.write("{\n" + PRAGMA + cp + "\n}\n")
     with open(os.path.join(outdir, "gen_vjp.inc"), "w") as fh:
         fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")

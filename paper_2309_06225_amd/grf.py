@@ -251,9 +251,10 @@ def rk4_stage_bc(params: Params, box: Box, bc: BC, stage, dt, u0, us, unext, acc
 
 
 def coupling_diagnostics(params: Params, box: Box, u, ws, stream=None):
-    """-> (3, nz, ny, nx): the Gauss-Bonnet invariant and the weak-coupling
-    indicators |lambda'(phi)| sqrt|L_GB| and |2 g2 X| on the interior."""
-    out = torch.empty((3, box.nz, box.ny, box.nx), dtype=torch.float64, device=u.device)
+    """-> (4, nz, ny, nx): the Gauss-Bonnet invariant, the weak-coupling
+    indicators |lambda'(phi)| sqrt|L_GB| and |2 g2 X|, and the determinant of
+    the per-cell system, on the interior."""
+    out = torch.empty((4, box.nz, box.ny, box.nx), dtype=torch.float64, device=u.device)
     _check(lib().grf_coupling_diagnostics(ctypes.byref(params), ctypes.byref(box), _ptr(u), _ptr(out), _ptr(ws),
                                           ws.numel() * 8, _stream(stream)))
     return out

@@ -133,7 +133,7 @@ def test_coupling_diagnostics_match_oracle(case):
     u, dx, bc = _case(case)
     co = O.coupling(I.params_vector(p), u, dx)
     cg = gpu_coupling(p, u, dx, bc)
-    for q in range(3):
+    for q in range(4):
         assert np.abs(co[q]).max() > 0.0, q
         assert _rel(cg[q], co[q]) <= 1e-12, (q, _rel(cg[q], co[q]))
 
@@ -148,7 +148,7 @@ def test_coupling_diagnostics_full_size_sampled():
     for k in (0, 40, 64, 127):
         slab = u[:, k:k + 7, :, :]   # interior plane k and its 3 ghost planes either side
         co = O.coupling(I.params_vector(p), slab, 1.0 / 8.0)[:, 0]
-        for q in range(3):
+        for q in range(4):
             assert _rel(cg[q, k], co[q]) <= 1e-12, (k, q, _rel(cg[q, k], co[q]))
 
 
