@@ -173,7 +173,7 @@ def field_equations(st: RandomSpacetime, params: dict, x0=None):
     phi = st.phi(x0)
     dphi = jacfwd(st.phi)(x0)
     ddphi = jacfwd(jacfwd(st.phi))(x0)
-    dlam = 0.5 * lam_gb * phi
+    dlam = params.get("lambda_lin", 0.0) + 0.5 * lam_gb * phi
     ddlam = 0.5 * lam_gb
     dl = dlam * dphi
     ddl = ddlam * torch.outer(dphi, dphi) + dlam * ddphi

@@ -204,6 +204,8 @@ COV_PARAMS = [
     dict(lambda_gb=0.0, g2=0.0, b_gauge=0.7, kappa1=0.2, kappa2=0.5),   # b-terms, no coupling
     dict(lambda_gb=0.5, g2=0.0, b_gauge=0.0, kappa1=0.0, kappa2=0.0),   # Gauss-Bonnet only
     dict(lambda_gb=0.0, g2=0.4, b_gauge=0.2, kappa1=0.1, kappa2=0.1),   # X^2 only
+    dict(lambda_gb=0.0, lambda_lin=0.4, g2=0.1, b_gauge=0.3, kappa1=0.1),  # shift-symmetric coupling
+    dict(lambda_gb=0.3, lambda_lin=-0.2, g2=0.0, b_gauge=0.0, kappa1=0.1),  # linear + quadratic
 ]
 
 
