@@ -45,7 +45,7 @@ def merged_adv(shift_advec: bool):
 
 PARAMS = ("lambda_gb", "g2", "kappa1", "kappa3", "k1_1pk2", "k1_2pk2", "k1k2",
           "lapse_coeff", "lapse_advec", "shift_gamma_coeff", "shift_advec", "eta",
-          "inv1pa", "a_1pa", "fb", "cfac", "b4")
+          "inv1pa", "a_1pa", "fb", "cfac", "b4", "lambda_lin")
 
 
 def _eps(a, b, c):
@@ -202,7 +202,7 @@ def build(shift_advec: bool = False, decoupled: bool = False):
     FX = 1.0 + 2.0 * g2 * X
     F = X + g2 * X * X
     lam = P["lambda_gb"]
-    dlam = 0.5 * lam * phi
+    dlam = P["lambda_lin"] + 0.5 * lam * phi
     ddlam = 0.5 * lam
     DDphi = symfill(lambda i, j: ddphi[i][j] - S(chrp[k][i][j] * dphi[k] for k in R3))
     ial = 1.0 / al

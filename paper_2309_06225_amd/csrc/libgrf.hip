@@ -114,6 +114,7 @@ grf_point_params make_pp(const grf_params* p) {
   q.fb = b / (1.0 + b);
   q.cfac = 1.0 / (1.0 + b);
   q.b4 = b / (4.0 * (1.0 + b));
+  q.lambda_lin = p->lambda_lin;
   return q;
 }
 

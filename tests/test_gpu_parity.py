@@ -334,3 +334,29 @@ def test_enforcement_matches_oracle_and_stage_applies_it():
     G.rk4_stage(G.make_params(p0), box, 1, 0.1, u0, u0, b2, acc, ws)
     G.enforce(G.make_params(p), box, b2)
     assert torch.equal(a, b2)
+
+
+def test_shift_symmetric_coupling_parity():
+    """lambda(phi) = lambda_lin phi + lambda_gb phi^2 / 4: the linear
+    (shift-symmetric) term alone and with the quadratic one, one right-hand
+    side at 1e-12 and four RK4 steps at 1e-10 against the oracle."""
+    print("case: shift-symmetric coupling, puncture 21x17x13", flush=True)
+    dims, dx = (21, 17, 13), 0.3
+    u = I.puncture(dims, dx, centre=(0.4, -0.2, 0.1), phi_fn=I.shell_pulse(0.1, 2.0))
+    rng = np.random.default_rng(5)
+    u[I.IDX["K"]] += 0.01 * rng.standard_normal(u[7].shape)
+    u[I.IDX["Pi"]] += 0.01 * rng.standard_normal(u[26].shape)
+    for over in (dict(lambda_gb=0.0, lambda_lin=0.3), dict(lambda_gb=0.2, lambda_lin=-0.15)):
+        p = I.default_params(**over)
+        o, _ = O.rhs(I.params_vector(p), u, dx)
+        g, code, _ = gpu_rhs(p, u, dx)
+        assert code == 0
+        e = rel_err_per_field(g, o)
+        assert e.max() <= 1e-12, (over, dict(zip(I.FIELDS, e)))
+        o4, _ = O.rk4(I.params_vector(p), u, dx, 0.25 * dx, 4, periodic=False)
+        ut = torch.from_numpy(u).to(DEV)
+        st = G.Stepper(G.make_params(p), G.box_of(ut, dx), ut, 0.25 * dx)
+        for _ in range(4):
+            st.step()
+        e4 = rel_err_per_field(st.u.cpu().numpy(), o4, interior=False)
+        assert e4.max() <= 1e-10, (over, dict(zip(I.FIELDS, e4)))
