@@ -63,11 +63,13 @@ def input_names(shift_advec: bool):
     return names
 
 
-def build(shift_advec: bool = False, decoupled: bool = False):
+def build(shift_advec: bool = False, decoupled: bool = False, shift_symmetric: bool = True):
     """decoupled: the decoupling limit of 4dST (the scalar moves on the metric
     without sourcing it): the metric equations see no energy, momentum,
     stress or Gauss-Bonnet tensor and their rows of the per-cell system reduce
-    to C_ij = Q_ij; the scalar's row is unchanged."""
+    to C_ij = Q_ij; the scalar's row is unchanged.  shift_symmetric: include
+    the linear term lambda_lin phi of lambda(phi) (without it the graph is
+    the purely quadratic coupling's, for the default staged kernel)."""
     g = Graph()
     S = g.sum
     P = {n: g.param(n) for n in PARAMS}
@@ -202,7 +204,7 @@ def build(shift_advec: bool = False, decoupled: bool = False):
     FX = 1.0 + 2.0 * g2 * X
     F = X + g2 * X * X
     lam = P["lambda_gb"]
-    dlam = P["lambda_lin"] + 0.5 * lam * phi
+    dlam = P["lambda_lin"] + 0.5 * lam * phi if shift_symmetric else 0.5 * lam * phi
     ddlam = 0.5 * lam
     DDphi = symfill(lambda i, j: ddphi[i][j] - S(chrp[k][i][j] * dphi[k] for k in R3))
     ial = 1.0 / al

@@ -75,7 +75,7 @@ __device__ __forceinline__ void stage_one_st(int f, double rhs_f, double ko_f, d
 
 // The 64 cells c0 .. c0 + 63 of box b (one wave; lbuf0 / lbuf1: this wave's
 // two LDS buffers of GRF_STAGE_SLOTS items).
-template <int MODE, int SHIFTADV, bool DEC = false>
+template <int MODE, int SHIFTADV, int VAR = 0>
 __device__ __forceinline__ void staged_wave(const BoxDev& b, int64_t c0, const grf_point_params& P,
                                             const double* __restrict__ us, const double* __restrict__ D,
                                             const double* __restrict__ u0, double* __restrict__ out,
@@ -126,8 +126,10 @@ __device__ __forceinline__ void staged_wave(const BoxDev& b, int64_t c0, const g
 #define GRF_STAGE_RHS_ONLY (MODE == 0)
   // nothing of an earlier call may still read the buffers or write memory
   GRF_PHASE_SYNC();
-  if constexpr (DEC) {
+  if constexpr (VAR == 1) {
 #include "gen/gen_rhs_staged_dec.inc"
+  } else if constexpr (VAR == 2) {
+#include "gen/gen_rhs_staged_lin.inc"
   } else {
 #include "gen/gen_rhs_staged.inc"
   }
@@ -149,8 +151,10 @@ __device__ __forceinline__ void staged_wave(const BoxDev& b, int64_t c0, const g
   if (flags) atomicOr(status, flags);
 }
 
-// DEC: the decoupling limit (the scalar does not source the metric)
-template <int MODE, int SHIFTADV, bool DEC = false>
+// VAR 0: the full theory with the quadratic coupling; 1: the decoupling limit
+// (the scalar does not source the metric); 2: the full theory with the linear
+// (shift-symmetric) term of the coupling as well
+template <int MODE, int SHIFTADV, int VAR = 0>
 __global__ __launch_bounds__(kStagedThreads) void k_point_staged(BoxDev b, grf_point_params P,
                                                                  const double* __restrict__ us,
                                                                  const double* __restrict__ D,
@@ -161,7 +165,7 @@ __global__ __launch_bounds__(kStagedThreads) void k_point_staged(BoxDev b, grf_p
   __shared__ double lbuf1_[GRF_STAGE_SLOTS * 64];
   // the buffers as LDS-typed pointers, so that slot addresses are plain LDS
   // offsets (no generic-pointer conversion at each copy)
-  staged_wave<MODE, SHIFTADV, DEC>(b, (int64_t)blockIdx.x * kStagedThreads, P, us, D, u0, out, acc, sc, status,
+  staged_wave<MODE, SHIFTADV, VAR>(b, (int64_t)blockIdx.x * kStagedThreads, P, us, D, u0, out, acc, sc, status,
                                    (grf_lds_double*)lbuf0_, (grf_lds_double*)lbuf1_);
 }
 

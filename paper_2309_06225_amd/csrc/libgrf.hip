@@ -209,7 +209,9 @@ hipError_t launch_pointwise(int path, int mode, int sa, const BoxDev& bd, const 
                             const double* us, const double* D, const double* u0, double* out, double* acc,
                             StageCoef sc, unsigned* status, hipStream_t st) {
   if (path == 2) return launch_staged(mode, sa, bd, pp, us, D, u0, out, acc, sc, status, st);
-  return launch_point(mode, sa, bd, pp, us, D, u0, out, acc, sc, status, st);
+  // the plain kernel's code always carries the linear coupling term; only the
+  // shift-advection bit selects its instance
+  return launch_point(mode, sa & 1, bd, pp, us, D, u0, out, acc, sc, status, st);
 }
 
 hipError_t launch_point_batch(int mode, int sa, int grid, const BatchBoxDev* boxes, const CellEntry* cells,
@@ -286,6 +288,15 @@ static grf_status common_checks(const grf_params* p, const grf_box* box, void* w
   return GRF_OK;
 }
 
+// variant code of the staged pointwise kernel: bit 0 shift advection, then
+// 2 the decoupling limit (its code carries the linear coupling term), 4 the
+// full theory with the linear coupling term (the default code has the
+// quadratic coupling alone)
+static int staged_variant(const grf_params* p, int sa) {
+  if (p->decoupled) return sa | 2;
+  return sa | (p->lambda_lin != 0.0 ? 4 : 0);
+}
+
 // stencil stage of the forward paths at the parameters' finite-difference order
 static hipError_t launch_deriv_p(const grf_params* p, const BoxDev& bd, const double* u, double* D, int sa,
                                  hipStream_t stream) {
@@ -318,7 +329,7 @@ grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u
   GRF_HIP_CHECK(launch_deriv_p(p, bd, u, D, sa, stream));
   prof_mark(0, stream);
   prof_mark(1, stream);
-  GRF_HIP_CHECK(launch_pointwise(g_stage_path, 0, sa | (p->decoupled ? 2 : 0), bd, pp, u, D, nullptr, rhs, nullptr,
+  GRF_HIP_CHECK(launch_pointwise(g_stage_path, 0, staged_variant(p, sa), bd, pp, u, D, nullptr, rhs, nullptr,
                                  StageCoef{0.0}, status, stream));
   prof_mark(1, stream);
   return GRF_OK;
@@ -370,7 +381,7 @@ static grf_status rk4_stage_impl(const grf_params* p, const grf_box* box, int st
     GRF_HIP_CHECK(launch_deriv_p(p, bd, us, D, sa, stream));
     prof_mark(0, stream);
     prof_mark(1, stream);
-    GRF_HIP_CHECK(launch_pointwise(g_stage_path, mode, sa | (p->decoupled ? 2 : 0), bd, pp, us, D, u0, unext, acc,
+    GRF_HIP_CHECK(launch_pointwise(g_stage_path, mode, staged_variant(p, sa), bd, pp, us, D, u0, unext, acc,
                                    sc, status, stream));
     prof_mark(1, stream);
   }
@@ -740,6 +751,7 @@ grf_status grf_batch_create(const grf_params* p, const grf_box* boxes, int nboxe
   if (s != GRF_OK) return s;
   if (p->enforce) return fail(GRF_EUNSUPPORTED, "the batched form has no post-stage enforcement");
   if (p->decoupled) return fail(GRF_EUNSUPPORTED, "the batched form runs the full theory only");
+  if (p->lambda_lin != 0.0) return fail(GRF_EUNSUPPORTED, "the batched form has the quadratic coupling only");
   if (p->fd_order == 6) return fail(GRF_EUNSUPPORTED, "the batched form uses the fourth-order stencils only");
   if (!boxes || nboxes < 1 || !u || !dts || !out || !scratch) return fail(GRF_EINVAL, "null argument");
   for (int b = 0; b < nboxes; ++b) {

@@ -349,10 +349,11 @@ def test_shift_symmetric_coupling_parity():
     for over in (dict(lambda_gb=0.0, lambda_lin=0.3), dict(lambda_gb=0.2, lambda_lin=-0.15)):
         p = I.default_params(**over)
         o, _ = O.rhs(I.params_vector(p), u, dx)
-        g, code, _ = gpu_rhs(p, u, dx)
-        assert code == 0
-        e = rel_err_per_field(g, o)
-        assert e.max() <= 1e-12, (over, dict(zip(I.FIELDS, e)))
+        for path in (2, 0, 1):  # staged (its own variant), plain and fused kernels
+            g, code, _ = gpu_rhs(p, u, dx, path=path)
+            assert code == 0
+            e = rel_err_per_field(g, o)
+            assert e.max() <= 1e-12, (over, path, dict(zip(I.FIELDS, e)))
         o4, _ = O.rk4(I.params_vector(p), u, dx, 0.25 * dx, 4, periodic=False)
         ut = torch.from_numpy(u).to(DEV)
         st = G.Stepper(G.make_params(p), G.box_of(ut, dx), ut, 0.25 * dx)
@@ -360,3 +361,6 @@ def test_shift_symmetric_coupling_parity():
             st.step()
         e4 = rel_err_per_field(st.u.cpu().numpy(), o4, interior=False)
         assert e4.max() <= 1e-10, (over, dict(zip(I.FIELDS, e4)))
+        # the batched form has the quadratic coupling only
+        with pytest.raises(G.GrfError):
+            G.Batch(G.make_params(p), [G.box_of(ut, dx)], [ut], [0.25 * dx])
