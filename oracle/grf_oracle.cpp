@@ -13,8 +13,9 @@
 // prints no equations, so the equation set below is the covariant 4dST theory
 // with backreaction written in 3+1 form):
 //   * action (1/16pi) int sqrt(-g) [R + X + lambda(phi) L_GB + g2 X^2],
-//     X = -1/2 (d phi)^2, lambda(phi) = lambda_lin phi + lambda_gb phi^2 / 4
-//     (the linear term: the shift-symmetric coupling), V = 0;
+//     X = -1/2 (d phi)^2, lambda(phi) = lambda_lin phi + lambda_gb (1 -
+//     exp(-beta phi^2)) / (4 beta) (the linear term: the shift-symmetric
+//     coupling; beta = 0: lambda_gb phi^2 / 4), V = 0;
 //   * CCZ4 with damping kappa1, kappa2, kappa3, the Z4 trace reversal done with
 //     hat g^{mu nu} = g^{mu nu} - b n^mu n^nu (modified gauge function b);
 //   * modified puncture gauge: 1+log lapse and B-form Gamma-driver, divided by
@@ -77,6 +78,7 @@ struct Params {
   double decoupled;      // 1: decoupling limit, the scalar does not source the metric
   int fd_order;          // 4 or 6: order of the centred finite differences
   double lambda_lin;     // linear (shift-symmetric) part of lambda(phi)
+  double beta;           // exponential form of the even part of lambda(phi) (0: quadratic)
 };
 
 template <class T>
@@ -473,8 +475,11 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
   const T g2 = P.g2;
   const T FX = 1.0 + 2.0 * g2 * X;
   const T F = X + g2 * X * X;               // V = 0
-  const T dlam = P.lambda_lin + 0.5 * P.lambda_gb * phi;   // lambda'(phi)
-  const T ddlam = 0.5 * P.lambda_gb;        // lambda''(phi)
+  // lambda(phi) = lambda_lin phi + lambda_gb (1 - exp(-beta phi^2)) / (4 beta)
+  // (beta -> 0: lambda_gb phi^2 / 4); only its first two derivatives enter
+  const T ex = std::exp(-P.beta * phi * phi);
+  const T dlam = P.lambda_lin + 0.5 * P.lambda_gb * phi * ex;               // lambda'(phi)
+  const T ddlam = 0.5 * P.lambda_gb * (1.0 - 2.0 * P.beta * phi * phi) * ex;  // lambda''(phi)
   T DDphi[3][3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
@@ -927,6 +932,7 @@ Params<T> read_params(const double* p, const double* pim) {
   P.decoupled = p[14];
   P.fd_order = (int)p[15];
   P.lambda_lin = p[16];
+  P.beta = p[17];
   (void)pim;
   return P;
 }
@@ -949,6 +955,7 @@ Params<cplx> read_params<cplx>(const double* p, const double* pim) {
   P.decoupled = Pd.decoupled;
   P.fd_order = Pd.fd_order;
   P.lambda_lin = Pd.lambda_lin;
+  P.beta = Pd.beta;
   P.eta = Pd.eta;
   P.ko_sigma = Pd.ko_sigma;
   return P;

@@ -29,7 +29,7 @@ IDX = {n: i for i, n in enumerate(FIELDS)}
 PARAM_NAMES = (
     "lambda_gb", "g2", "a_gauge", "b_gauge", "kappa1", "kappa2", "kappa3",
     "lapse_coeff", "lapse_power", "lapse_advec",
-    "shift_gamma_coeff", "shift_advec", "eta", "ko_sigma", "decoupled", "fd_order", "lambda_lin",
+    "shift_gamma_coeff", "shift_advec", "eta", "ko_sigma", "decoupled", "fd_order", "lambda_lin", "beta",
 )
 
 
@@ -40,7 +40,8 @@ def default_params(**over) -> dict:
     p = dict(lambda_gb=0.1, g2=0.01, a_gauge=0.2, b_gauge=0.4,
              kappa1=0.1, kappa2=0.0, kappa3=1.0,
              lapse_coeff=2.0, lapse_power=1.0, lapse_advec=1.0,
-             shift_gamma_coeff=0.75, shift_advec=0.0, eta=1.0, ko_sigma=0.3, decoupled=0.0, fd_order=4.0, lambda_lin=0.0)
+             shift_gamma_coeff=0.75, shift_advec=0.0, eta=1.0, ko_sigma=0.3, decoupled=0.0, fd_order=4.0, lambda_lin=0.0,
+             beta=0.0)
     for k, v in over.items():
         if k not in p:
             raise KeyError(k)

@@ -173,8 +173,10 @@ def field_equations(st: RandomSpacetime, params: dict, x0=None):
     phi = st.phi(x0)
     dphi = jacfwd(st.phi)(x0)
     ddphi = jacfwd(jacfwd(st.phi))(x0)
-    dlam = params.get("lambda_lin", 0.0) + 0.5 * lam_gb * phi
-    ddlam = 0.5 * lam_gb
+    beta = params.get("beta", 0.0)
+    ex = torch.exp(-beta * phi * phi)
+    dlam = params.get("lambda_lin", 0.0) + 0.5 * lam_gb * phi * ex
+    ddlam = 0.5 * lam_gb * (1.0 - 2.0 * beta * phi * phi) * ex
     dl = dlam * dphi
     ddl = ddlam * torch.outer(dphi, dphi) + dlam * ddphi
     nnl = ddl - torch.einsum("rmn,r->mn", Gam, dl)  # nabla_m nabla_n lambda

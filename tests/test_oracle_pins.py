@@ -206,6 +206,7 @@ COV_PARAMS = [
     dict(lambda_gb=0.0, g2=0.4, b_gauge=0.2, kappa1=0.1, kappa2=0.1),   # X^2 only
     dict(lambda_gb=0.0, lambda_lin=0.4, g2=0.1, b_gauge=0.3, kappa1=0.1),  # shift-symmetric coupling
     dict(lambda_gb=0.3, lambda_lin=-0.2, g2=0.0, b_gauge=0.0, kappa1=0.1),  # linear + quadratic
+    dict(lambda_gb=0.6, beta=3.0, g2=0.05, b_gauge=0.2, kappa1=0.1),     # exponential coupling
 ]
 
 
@@ -455,6 +456,24 @@ def test_schwarzschild_static_fourth_order():
     # fields whose exact and discrete right-hand sides both vanish identically
     for f in ("h11", "h12", "Gam1", "shift1", "B1", "phi", "Pi"):
         assert errs[:, IDX[f]].max() == 0.0
+
+
+def test_exponential_coupling_source_on_schwarzschild():
+    """With phi = phi0 constant and Pi = 0 the scalar source is lambda'(phi0)
+    L_GB, lambda'(phi0) = (lambda_gb/2) phi0 exp(-beta phi0^2) for the
+    exponential coupling: d p / d lambda_gb at lambda_gb = 0 by complex step
+    against (phi0/2) exp(-beta phi0^2) 48 M^2 / R^6."""
+    phi0, beta, h = 0.7, 1.3, 1e-20
+    n = 32
+    dx = 1.0 / n
+    u, r = _schwarzschild(n, dx, (2.0, 0.5, 0.25), phi0=phi0)
+    pp = I.params_vector(I.default_params(a_gauge=0.0, lambda_gb=0.0, beta=beta))
+    _, rim = O.rhs_cs(pp, np.array([h, 0.0]), u, None, dx)
+    dp = I.interior(rim[IDX["Pi"]]) / h / I.interior(u[IDX["lapse"]])
+    ri = I.interior(r)
+    R = ri * (1 + 1 / (2 * ri)) ** 2
+    exact = 0.5 * phi0 * np.exp(-beta * phi0 ** 2) * 48.0 / R ** 6
+    assert np.abs(dp - exact).max() / np.abs(exact).max() < 1e-6
 
 
 def test_gauss_bonnet_source_on_schwarzschild():
