@@ -56,8 +56,11 @@ enum { GRF_LAMBDA_QUADRATIC = 0 };
 /* device status bits (grf_status_fetch's *bits) */
 enum { GRF_FLAG_NONFINITE = 1, GRF_FLAG_HYPERBOLIC = 2, GRF_FLAG_NONPOSITIVE = 4 };
 
-/* Couplings and gauge.  lambda(phi) = lambda_lin phi + lambda_gb phi^2 / 4
- * (lambda_kind 0 only; lambda_lin alone is the shift-symmetric coupling),
+/* Couplings and gauge.  lambda(phi) = lambda_lin phi + lambda_gb (1 -
+ * exp(-beta phi^2)) / (4 beta), which is lambda_gb phi^2 / 4 at beta = 0
+ * (lambda_kind 0 only; lambda_lin alone is the shift-symmetric coupling,
+ * beta > 0 the exponential coupling of spin-induced scalarisation studies;
+ * the batched form takes lambda_lin = beta = 0 only),
  * g2 constant, V = 0.  a_gauge, b_gauge: the modified-gauge functions a(x), b(x)
  * (constants).  lapse: d_t alpha = lapse_advec beta.d alpha
  *   - lapse_coeff alpha^lapse_power (K - 2 Theta) / (1 + a)   (lapse_power 1 only);
@@ -96,6 +99,7 @@ typedef struct {
   int32_t decoupled;
   int32_t fd_order;
   double lambda_lin;
+  double beta;
 } grf_params;
 
 /* One box: nx, ny, nz interior cells, ng ghosts (must be 3), spacing dx, dy,

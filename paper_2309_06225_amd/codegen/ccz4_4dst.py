@@ -45,7 +45,7 @@ def merged_adv(shift_advec: bool):
 
 PARAMS = ("lambda_gb", "g2", "kappa1", "kappa3", "k1_1pk2", "k1_2pk2", "k1k2",
           "lapse_coeff", "lapse_advec", "shift_gamma_coeff", "shift_advec", "eta",
-          "inv1pa", "a_1pa", "fb", "cfac", "b4", "lambda_lin")
+          "inv1pa", "a_1pa", "fb", "cfac", "b4", "lambda_lin", "beta")
 
 
 def _eps(a, b, c):
@@ -63,13 +63,14 @@ def input_names(shift_advec: bool):
     return names
 
 
-def build(shift_advec: bool = False, decoupled: bool = False, shift_symmetric: bool = True):
+def build(shift_advec: bool = False, decoupled: bool = False, general_coupling: bool = True):
     """decoupled: the decoupling limit of 4dST (the scalar moves on the metric
     without sourcing it): the metric equations see no energy, momentum,
     stress or Gauss-Bonnet tensor and their rows of the per-cell system reduce
-    to C_ij = Q_ij; the scalar's row is unchanged.  shift_symmetric: include
-    the linear term lambda_lin phi of lambda(phi) (without it the graph is
-    the purely quadratic coupling's, for the default staged kernel)."""
+    to C_ij = Q_ij; the scalar's row is unchanged.  general_coupling:
+    lambda(phi) = lambda_lin phi + lambda_gb (1 - exp(-beta phi^2))/(4 beta)
+    (beta = 0: lambda_gb phi^2 / 4); without it the graph is the purely
+    quadratic coupling's, for the default staged kernel."""
     g = Graph()
     S = g.sum
     P = {n: g.param(n) for n in PARAMS}
@@ -204,8 +205,14 @@ def build(shift_advec: bool = False, decoupled: bool = False, shift_symmetric: b
     FX = 1.0 + 2.0 * g2 * X
     F = X + g2 * X * X
     lam = P["lambda_gb"]
-    dlam = P["lambda_lin"] + 0.5 * lam * phi if shift_symmetric else 0.5 * lam * phi
-    ddlam = 0.5 * lam
+    if general_coupling:
+        bphi2 = P["beta"] * phi * phi
+        ex = g.exp(-bphi2)
+        dlam = P["lambda_lin"] + 0.5 * lam * phi * ex
+        ddlam = 0.5 * lam * (1.0 - 2.0 * bphi2) * ex
+    else:
+        dlam = 0.5 * lam * phi
+        ddlam = 0.5 * lam
     DDphi = symfill(lambda i, j: ddphi[i][j] - S(chrp[k][i][j] * dphi[k] for k in R3))
     ial = 1.0 / al
     adphi = ial * S(dal[k] * dphiu[k] for k in R3)                       # a^k d_k phi

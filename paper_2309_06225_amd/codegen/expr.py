@@ -115,6 +115,12 @@ class Graph:
             return a.a
         return self._new("neg", a)
 
+    def exp(self, a):
+        a = self.lift(a)
+        if a.op == "c":
+            return self.const(math.exp(a.val))
+        return self._new("exp", a)
+
     def sqrt(self, a):
         """Square root (diagnostics only: the reverse mode does not handle it)."""
         return self._new("sqrt", self.lift(a))
@@ -234,6 +240,8 @@ def vjp(g: Graph, outputs, cotangents, wrt):
             acc(n.a, g.neg(a))
         elif n.op == "rcp":  # d(1/x) = -1/x^2
             acc(n.a, g.neg(g.mul(a, g.mul(n, n))))
+        elif n.op == "exp":  # d exp(x) = exp(x)
+            acc(n.a, g.mul(a, n))
         else:
             raise ValueError(n.op)
     return [adj.get(w.idx, g.const(0.0)) for w in wrt]
@@ -249,15 +257,15 @@ def _lit(v: float) -> str:
 
 
 def count_flops(g: Graph, outputs):
-    """Count of add, sub, mul, reciprocal and square-root nodes (1 flop each);
-    negation and absolute value are free."""
+    """Count of add, sub, mul, reciprocal, square-root and exponential nodes
+    (1 flop each); negation and absolute value are free."""
     need = reachable(outputs)
     c = {"+": 0, "-": 0, "*": 0, "rcp": 0, "neg": 0}
     for i in need:
         op = g.nodes[i].op
-        if op in c or op in ("sqrt", "abs"):
+        if op in c or op in ("sqrt", "abs", "exp"):
             c[op] = c.get(op, 0) + 1
-    total = c["+"] + c["-"] + c["*"] + c["rcp"] + c.get("sqrt", 0)
+    total = c["+"] + c["-"] + c["*"] + c["rcp"] + c.get("sqrt", 0) + c.get("exp", 0)
     return total, c
 
 
@@ -424,6 +432,8 @@ def _node_expr(g, n, name_of, plan):
         return f"1.0 / {name_of(n.a)}"
     if n.op == "sqrt":
         return f"sqrt({name_of(n.a)})"
+    if n.op == "exp":
+        return f"exp({name_of(n.a)})"
     if n.op == "abs":
         return f"fabs({name_of(n.a)})"
     raise ValueError(n.op)

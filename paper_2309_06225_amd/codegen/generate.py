@@ -76,12 +76,12 @@ def _stage_key(name: str):
     return ("D", comp_of(name))
 
 
-def forward_code_staged(shift_advec: bool, rhs_only: bool, decoupled: bool = False, shift_symmetric: bool = True):
+def forward_code_staged(shift_advec: bool, rhs_only: bool, decoupled: bool = False, general_coupling: bool = True):
     """Forward right-hand side with staged inputs (see emit_staged).  Each
     right-hand-side statement also stages its Kreiss-Oliger component and, for
     the RK4 stage modes, u0 and the accumulator of its field.  decoupled: the
     decoupling limit (its constant pivot entries are not checked)."""
-    b = M.build(shift_advec, decoupled, shift_symmetric)
+    b = M.build(shift_advec, decoupled, general_coupling)
     g = b["graph"]
     from .expr import reachable
     rhs = b["rhs"]
@@ -235,13 +235,13 @@ def main(outdir: str):
         fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
         fh.write(f"// forward right-hand side: {fl0} flops/cell ({ops0})\n")
         fh.write(block("GRF_SHIFT_ADVEC", fw1, fw0))
-    # the default staged kernel: the quadratic coupling alone (one parameter
-    # node fewer lets the schedule keep its measured spill count); the linear
-    # term has its own staged variant below
+    # the default staged kernel: the quadratic coupling alone (without the
+    # general coupling's nodes the schedule keeps its measured spill count);
+    # the general coupling has its own staged variant below
     staged = {}
     for ro in (True, False):
         for sa in (True, False):
-            staged[(ro, sa)] = forward_code_staged(sa, ro, shift_symmetric=False)
+            staged[(ro, sa)] = forward_code_staged(sa, ro, general_coupling=False)
     with open(os.path.join(outdir, "gen_rhs_staged.inc"), "w") as fh:
         fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
         fh.write(f"// forward right-hand side with inputs staged through two buffers of {STAGE_SLOTS} slots;\n")
@@ -255,10 +255,10 @@ def main(outdir: str):
     staged_lin = {}
     for ro in (True, False):
         for sa in (True, False):
-            staged_lin[(ro, sa)] = forward_code_staged(sa, ro, shift_symmetric=True)
+            staged_lin[(ro, sa)] = forward_code_staged(sa, ro, general_coupling=True)
     with open(os.path.join(outdir, "gen_rhs_staged_lin.inc"), "w") as fh:
         fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
-        fh.write("// with the linear (shift-symmetric) term of the coupling, staged as gen_rhs_staged.inc;\n")
+        fh.write("// with the general coupling (linear and exponential terms), staged as gen_rhs_staged.inc;\n")
         fh.write("// phases (rhs only / stage, shift advection on / off): "
                  + ", ".join(f"{v[1]}" for v in staged_lin.values()) + "\n")
         fh.write("if constexpr (GRF_STAGE_RHS_ONLY) {\n")

@@ -152,8 +152,8 @@ __device__ __forceinline__ void staged_wave(const BoxDev& b, int64_t c0, const g
 }
 
 // VAR 0: the full theory with the quadratic coupling; 1: the decoupling limit
-// (the scalar does not source the metric); 2: the full theory with the linear
-// (shift-symmetric) term of the coupling as well
+// (the scalar does not source the metric); 2: the full theory with the
+// general coupling (linear and exponential terms)
 template <int MODE, int SHIFTADV, int VAR = 0>
 __global__ __launch_bounds__(kStagedThreads) void k_point_staged(BoxDev b, grf_point_params P,
                                                                  const double* __restrict__ us,

@@ -61,6 +61,7 @@ grf_status check_params(const grf_params* p) {
   if (p->enforce != 0 && p->enforce != 1) return fail(GRF_EINVAL, "enforce must be 0 or 1");
   if (p->decoupled != 0 && p->decoupled != 1) return fail(GRF_EINVAL, "decoupled must be 0 or 1");
   if (p->fd_order != 0 && p->fd_order != 4 && p->fd_order != 6) return fail(GRF_EINVAL, "fd_order must be 4 or 6");
+  if (!std::isfinite(p->lambda_lin) || !std::isfinite(p->beta)) return fail(GRF_EINVAL, "lambda_lin/beta not finite");
   if (p->enforce && !(std::isfinite(p->chi_min) && std::isfinite(p->lapse_min)))
     return fail(GRF_EINVAL, "chi_min and lapse_min must be finite");
   return GRF_OK;
@@ -115,6 +116,7 @@ grf_point_params make_pp(const grf_params* p) {
   q.cfac = 1.0 / (1.0 + b);
   q.b4 = b / (4.0 * (1.0 + b));
   q.lambda_lin = p->lambda_lin;
+  q.beta = p->beta;
   return q;
 }
 
@@ -209,7 +211,7 @@ hipError_t launch_pointwise(int path, int mode, int sa, const BoxDev& bd, const 
                             const double* us, const double* D, const double* u0, double* out, double* acc,
                             StageCoef sc, unsigned* status, hipStream_t st) {
   if (path == 2) return launch_staged(mode, sa, bd, pp, us, D, u0, out, acc, sc, status, st);
-  // the plain kernel's code always carries the linear coupling term; only the
+  // the plain kernel's code always carries the general coupling; only the
   // shift-advection bit selects its instance
   return launch_point(mode, sa & 1, bd, pp, us, D, u0, out, acc, sc, status, st);
 }
@@ -289,12 +291,12 @@ static grf_status common_checks(const grf_params* p, const grf_box* box, void* w
 }
 
 // variant code of the staged pointwise kernel: bit 0 shift advection, then
-// 2 the decoupling limit (its code carries the linear coupling term), 4 the
-// full theory with the linear coupling term (the default code has the
-// quadratic coupling alone)
+// 2 the decoupling limit (its code carries the general coupling), 4 the full
+// theory with the general coupling (linear and exponential terms; the
+// default code has the quadratic coupling alone)
 static int staged_variant(const grf_params* p, int sa) {
   if (p->decoupled) return sa | 2;
-  return sa | (p->lambda_lin != 0.0 ? 4 : 0);
+  return sa | (p->lambda_lin != 0.0 || p->beta != 0.0 ? 4 : 0);
 }
 
 // stencil stage of the forward paths at the parameters' finite-difference order
@@ -751,7 +753,8 @@ grf_status grf_batch_create(const grf_params* p, const grf_box* boxes, int nboxe
   if (s != GRF_OK) return s;
   if (p->enforce) return fail(GRF_EUNSUPPORTED, "the batched form has no post-stage enforcement");
   if (p->decoupled) return fail(GRF_EUNSUPPORTED, "the batched form runs the full theory only");
-  if (p->lambda_lin != 0.0) return fail(GRF_EUNSUPPORTED, "the batched form has the quadratic coupling only");
+  if (p->lambda_lin != 0.0 || p->beta != 0.0)
+    return fail(GRF_EUNSUPPORTED, "the batched form has the quadratic coupling only");
   if (p->fd_order == 6) return fail(GRF_EUNSUPPORTED, "the batched form uses the fourth-order stencils only");
   if (!boxes || nboxes < 1 || !u || !dts || !out || !scratch) return fail(GRF_EINVAL, "null argument");
   for (int b = 0; b < nboxes; ++b) {

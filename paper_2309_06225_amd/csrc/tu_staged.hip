@@ -1,7 +1,7 @@
 // Pointwise right-hand side + RK4 stage with staged inputs, for one stage mode
 // (compiled once per mode with -DGRF_TU_MODE=0, 1, 2 or 4), with and without
 // shift advection, full theory, decoupling limit and full theory with the
-// linear coupling term.
+// general coupling.
 #include "kernels_staged.h"
 #include "launch.h"
 
@@ -12,7 +12,7 @@ hipError_t launch_staged_m<GRF_TU_MODE>(int sa, const BoxDev& bd, const grf_poin
                                         const double* D, const double* u0, double* out, double* acc,
                                         const StageCoef& sc, unsigned* status, hipStream_t st) {
   // sa: bit 0 shift advection; bits 1-2 the variant (0 full theory, 1 the
-  // decoupling limit, 2 the full theory with the linear coupling term)
+  // decoupling limit, 2 the full theory with the general coupling)
   const int64_t nblk = (bd.ncell + kStagedThreads - 1) / kStagedThreads;
   const dim3 grid((unsigned)nblk), block(kStagedThreads);
 #define GRF_LAUNCH_STAGED(S, V) \

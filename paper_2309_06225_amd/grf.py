@@ -38,7 +38,7 @@ class Params(ctypes.Structure):
                 ("shift_gamma_coeff", ctypes.c_double), ("shift_advec", ctypes.c_double), ("eta", ctypes.c_double),
                 ("ko_sigma", ctypes.c_double), ("enforce", ctypes.c_int32), ("chi_min", ctypes.c_double),
                 ("lapse_min", ctypes.c_double), ("decoupled", ctypes.c_int32), ("fd_order", ctypes.c_int32),
-                ("lambda_lin", ctypes.c_double)]
+                ("lambda_lin", ctypes.c_double), ("beta", ctypes.c_double)]
 
 
 class Box(ctypes.Structure):
@@ -138,7 +138,8 @@ def make_params(p: dict | None = None, **over) -> Params:
                   shift_gamma_coeff=d["shift_gamma_coeff"], shift_advec=d["shift_advec"], eta=d["eta"],
                   ko_sigma=d["ko_sigma"], enforce=int(d.get("enforce", 0)), chi_min=d.get("chi_min", 0.0),
                   lapse_min=d.get("lapse_min", 0.0), decoupled=int(d.get("decoupled", 0)),
-                  fd_order=int(d.get("fd_order", 4)), lambda_lin=float(d.get("lambda_lin", 0.0)))
+                  fd_order=int(d.get("fd_order", 4)), lambda_lin=float(d.get("lambda_lin", 0.0)),
+                  beta=float(d.get("beta", 0.0)))
 
 
 def make_box(dims, dx, bc=BC_FROZEN, origin=(0.0, 0.0, 0.0)) -> Box:

@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "_host_point.so")
 _dp = ctypes.POINTER(ctypes.c_double)
 PARAMS = ("lambda_gb", "g2", "kappa1", "kappa3", "k1_1pk2", "k1_2pk2", "k1k2",
           "lapse_coeff", "lapse_advec", "shift_gamma_coeff", "shift_advec", "eta",
-          "inv1pa", "a_1pa", "fb", "cfac", "b4", "lambda_lin")
+          "inv1pa", "a_1pa", "fb", "cfac", "b4", "lambda_lin", "beta")
 _lib = None
 
 
@@ -35,7 +35,7 @@ def point_params(p: dict) -> np.ndarray:
              k1_2pk2=k1 * (2 + k2), k1k2=k1 * k2, lapse_coeff=p["lapse_coeff"], lapse_advec=p["lapse_advec"],
              shift_gamma_coeff=p["shift_gamma_coeff"], shift_advec=p["shift_advec"], eta=p["eta"],
              inv1pa=1 / (1 + a), a_1pa=a / (1 + a), fb=b / (1 + b), cfac=1 / (1 + b), b4=b / (4 * (1 + b)),
-             lambda_lin=p.get("lambda_lin", 0.0))
+             lambda_lin=p.get("lambda_lin", 0.0), beta=p.get("beta", 0.0))
     return np.array([d[n] for n in PARAMS])
 
 

@@ -41,7 +41,7 @@ def _record(u, d1, d2, adv, sa):
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_generated_rhs_matches_oracle_point(sa, seed):
     rng = np.random.default_rng(seed)
-    p = I.default_params(shift_advec=float(sa), lambda_gb=0.3, g2=0.05, lambda_lin=0.15)
+    p = I.default_params(shift_advec=float(sa), lambda_gb=0.3, g2=0.05, lambda_lin=0.15, beta=1.5)
     u, d1, d2, adv = _point(rng)
     if not sa:
         adv[19:25] = 0.0  # the oracle multiplies them by shift_advec = 0 anyway
@@ -58,7 +58,7 @@ def test_generated_rhs_matches_oracle_point(sa, seed):
 @pytest.mark.parametrize("sa", [0, 1])
 def test_generated_vjp_matches_central_differences(sa):
     rng = np.random.default_rng(7 + sa)
-    p = I.default_params(shift_advec=float(sa), lambda_gb=0.3, g2=0.05, lambda_lin=0.15)
+    p = I.default_params(shift_advec=float(sa), lambda_gb=0.3, g2=0.05, lambda_lin=0.15, beta=1.5)
     pp = H.point_params(p)
     u, d1, d2, adv = _point(rng)
     D = _record(u, d1, d2, adv, sa)

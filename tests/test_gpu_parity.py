@@ -336,17 +336,19 @@ def test_enforcement_matches_oracle_and_stage_applies_it():
     assert torch.equal(a, b2)
 
 
-def test_shift_symmetric_coupling_parity():
-    """lambda(phi) = lambda_lin phi + lambda_gb phi^2 / 4: the linear
-    (shift-symmetric) term alone and with the quadratic one, one right-hand
-    side at 1e-12 and four RK4 steps at 1e-10 against the oracle."""
-    print("case: shift-symmetric coupling, puncture 21x17x13", flush=True)
+def test_general_coupling_parity():
+    """lambda(phi) = lambda_lin phi + lambda_gb (1 - exp(-beta phi^2))/(4 beta):
+    the linear (shift-symmetric) term alone, with the quadratic one, and the
+    exponential form; one right-hand side at 1e-12 on the staged, plain and
+    fused kernels and four RK4 steps at 1e-10 against the oracle."""
+    print("case: general coupling, puncture 21x17x13", flush=True)
     dims, dx = (21, 17, 13), 0.3
     u = I.puncture(dims, dx, centre=(0.4, -0.2, 0.1), phi_fn=I.shell_pulse(0.1, 2.0))
     rng = np.random.default_rng(5)
     u[I.IDX["K"]] += 0.01 * rng.standard_normal(u[7].shape)
     u[I.IDX["Pi"]] += 0.01 * rng.standard_normal(u[26].shape)
-    for over in (dict(lambda_gb=0.0, lambda_lin=0.3), dict(lambda_gb=0.2, lambda_lin=-0.15)):
+    for over in (dict(lambda_gb=0.0, lambda_lin=0.3), dict(lambda_gb=0.2, lambda_lin=-0.15),
+                 dict(lambda_gb=0.5, beta=2.0, g2=0.05)):
         p = I.default_params(**over)
         o, _ = O.rhs(I.params_vector(p), u, dx)
         for path in (2, 0, 1):  # staged (its own variant), plain and fused kernels
