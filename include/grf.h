@@ -4,8 +4,10 @@
  * to a scalar field with the four-derivative scalar-tensor terms, with
  * Kreiss-Oliger dissipation, and the classic RK4 stage update, on 3-D boxes with
  * three ghost cells (the method named in the paper's Summary and Key features:
- * 4dST theory, modified moving-puncture gauge, 4th-order finite differences,
- * RK4, periodic boundaries).
+ * 4dST theory, modified moving-puncture gauge, 4th- and 6th-order finite
+ * differences, RK4, periodic and per-face boundary rules, the decoupling
+ * limit, constraint, energy and weak-coupling diagnostics), a batched form for
+ * many boxes and the adjoint of the right-hand side and of an RK4 step.
  *
  * Conventions shared by every call
  *  - State layout: 27 FP64 fields, field-major; field f of a box starts at
