@@ -45,6 +45,37 @@ FILL_CASES = {
 }
 
 
+def test_thin_boxes_fill_and_radiative_rhs():
+    """Boxes one or two cells thick along an axis: periodic and order-0
+    extrapolating faces there (the rules such a box allows), Sommerfeld on the
+    others; fills bitwise and the radiative right-hand side at 1e-13 against
+    the oracle; a reflective face on a thin axis is refused."""
+    print("case: thin boxes", flush=True)
+    for dims in ((1, 6, 5), (7, 2, 4), (3, 4, 1)):
+        u = _random_state(dims, 9)
+        thin = [a for a in range(3) if dims[a] <= 2][0]
+        rules = ["sommerfeld"] * 6
+        rules[2 * thin] = rules[2 * thin + 1] = "periodic"
+        h = 0.25
+        origin = (1.0, 2.0, -3.0)
+        bc = dict(rules=rules, centre=(0.1, 0.2, 0.3), origin=origin, asymptote=np.zeros(NF))
+        ut = _dev(u)
+        box = G.box_of(ut, h, origin=origin)
+        G.bc_fill(G.make_bc(**bc), box, ut)
+        assert np.array_equal(ut.cpu().numpy(), O.fill_bc(u, h, bc)), dims
+        want = O.ghost_rhs(u, h, bc)
+        got = G.bc_ghost_rhs(G.make_bc(**bc), box, _dev(u)).cpu().numpy()
+        assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max(), dims
+        ex = dict(rules=["extrapolating"] * 6, extrap_order=0)
+        ut = _dev(u)
+        G.bc_fill(G.make_bc(**ex), box, ut)
+        assert np.array_equal(ut.cpu().numpy(), O.fill_bc(u, h, ex)), dims
+        refl = ["frozen"] * 6
+        refl[2 * thin] = "reflective"
+        with pytest.raises(G.GrfError):
+            G.bc_fill(G.make_bc(refl), box, ut)
+
+
 @pytest.mark.parametrize("dims", [(5, 7, 3), (16, 9, 11)])
 @pytest.mark.parametrize("case", sorted(FILL_CASES))
 def test_fill_bitwise_against_oracle(case, dims):
