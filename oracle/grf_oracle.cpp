@@ -23,7 +23,10 @@
 //   * the 4dST stress depends on C_ij = 4R_{i n j n} and on p = Lie_n Pi, which
 //     enter the equations linearly: a 7x7 linear system per cell;
 //   * 4th-order centred, mixed and lopsided-upwind finite differences, Kreiss-
-//     Oliger dissipation sigma/(64 h) times the 6th difference, classic RK4.
+//     Oliger dissipation sigma/(64 h) times the 6th difference, classic RK4;
+//     sixth-order forms of the stencils on boxes with three ghost layers, and
+//     on boxes with four ghost layers a sixth-order advection stencil and the
+//     dissipation -sigma/(256 h) times the 8th difference.
 // Readings taken where the paper is silent are marked "reading:" in the code.
 //
 // Conventions: 27 fields in the order
@@ -49,7 +52,6 @@ enum {
   CHI = 0, H11 = 1, KTR = 7, A11 = 8, THETA = 14, GH1 = 15, LAPSE = 18, SHIFT1 = 19,
   BB1 = 22, PHI = 25, PI_ = 26, NF = 27
 };
-const int NG = 3;
 // symmetric 3x3 index -> packed position (xx, xy, xz, yy, yz, zz)
 const int SYM[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
 
@@ -891,25 +893,28 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
 // ---------------------------------------------------------------- box level
 struct Box {
   int nx, ny, nz;       // interior cells
+  int ng;               // ghost layers on every side (3; 4 for the sixth-order scheme with its own dissipation)
   double dx[3];         // spacing along x, y, z
   int64_t sx, sy, sz;   // strides (x is contiguous)
   int64_t fstride;      // elements per field
 };
 
+// dims: nx, ny, nz, ghost layers
 Box make_box(const int* dims, const double* spacing) {
   Box b;
   b.nx = dims[0];
   b.ny = dims[1];
   b.nz = dims[2];
+  b.ng = dims[3];
   for (int d = 0; d < 3; ++d) b.dx[d] = spacing[d];
   b.sx = 1;
-  b.sy = b.nx + 2 * NG;
-  b.sz = int64_t(b.nx + 2 * NG) * (b.ny + 2 * NG);
-  b.fstride = b.sz * (b.nz + 2 * NG);
+  b.sy = b.nx + 2 * b.ng;
+  b.sz = int64_t(b.nx + 2 * b.ng) * (b.ny + 2 * b.ng);
+  b.fstride = b.sz * (b.nz + 2 * b.ng);
   return b;
 }
 inline int64_t cell_index(const Box& b, int i, int j, int k) {
-  return int64_t(k + NG) * b.sz + int64_t(j + NG) * b.sy + (i + NG);
+  return int64_t(k + b.ng) * b.sz + int64_t(j + b.ng) * b.sy + (i + b.ng);
 }
 
 template <class T>
@@ -968,15 +973,20 @@ Params<cplx> read_params<cplx>(const double* p, const double* pim) {
 //   d_k u   = (-u_-3 + 9 u_-2 - 45 u_-1 + 45 u_1 - 9 u_2 + u_3) / (60 h),
 //   d_k^2 u = (2 u_-3 - 27 u_-2 + 270 u_-1 - 490 u_0 + 270 u_1 - 27 u_2 + 2 u_3) / (180 h^2),
 //   d_k d_l u: the first-derivative weights applied along k and along l (49 points);
-// the advection derivative is the fifth-order stencil biased one cell towards
-// the side the shift points to (offsets -2..3 for beta >= 0, -3..2 otherwise),
-// the widest such stencil that three ghost layers hold.
+// the advection derivative, on a box with three ghost layers, is the
+// fifth-order stencil biased one cell towards the side the shift points to
+// (offsets -2..3 for beta >= 0, -3..2 otherwise), the widest such stencil
+// that three layers hold; with four ghost layers it is the sixth-order
+// stencil on offsets -2..4 (beta >= 0) or -4..2,
+//   (2 u_-2 - 24 u_-1 - 35 u_0 + 80 u_1 - 30 u_2 + 8 u_3 - u_4) / (60 h),
+// which is exact on polynomials of degree 6.
 template <class T>
 void gather_sixth(const Box& b, const T* u, int64_t c, PointIn<T>& in) {
   const int64_t st[3] = {b.sx, b.sy, b.sz};
   const double w1[7] = {-1.0, 9.0, -45.0, 0.0, 45.0, -9.0, 1.0};
   const double w2[7] = {2.0, -27.0, 270.0, -490.0, 270.0, -27.0, 2.0};
-  const double wup[6] = {3.0, -30.0, -20.0, 60.0, -15.0, 2.0};  // offsets -2..3, over 60 h
+  const double wup[6] = {3.0, -30.0, -20.0, 60.0, -15.0, 2.0};          // offsets -2..3, over 60 h
+  const double wup7[7] = {2.0, -24.0, -35.0, 80.0, -30.0, 8.0, -1.0};    // offsets -2..4, over 60 h
   for (int f = 0; f < NF; ++f) {
     const T* uf = u + f * b.fstride;
     for (int d = 0; d < 3; ++d) {
@@ -1005,8 +1015,11 @@ void gather_sixth(const Box& b, const T* u, int64_t c, PointIn<T>& in) {
     for (int f = 0; f < NF; ++f) {
       const T* uf = u + f * b.fstride;
       T a = 0.0;
-      // beta >= 0: offsets -2..3; beta < 0: the mirror image, offsets 2..-3 with the sign flipped
-      for (int q = 0; q < 6; ++q) a += bsign >= 0.0 ? wup[q] * uf[c + (q - 2) * s] : -wup[q] * uf[c - (q - 2) * s];
+      // beta >= 0: offsets -2..3 (-2..4); beta < 0: the mirror image with the sign flipped
+      if (b.ng >= 4)
+        for (int q = 0; q < 7; ++q) a += bsign >= 0.0 ? wup7[q] * uf[c + (q - 2) * s] : -wup7[q] * uf[c - (q - 2) * s];
+      else
+        for (int q = 0; q < 6; ++q) a += bsign >= 0.0 ? wup[q] * uf[c + (q - 2) * s] : -wup[q] * uf[c - (q - 2) * s];
       in.adv[f][d] = a / (60.0 * hd);
     }
   }
@@ -1061,14 +1074,25 @@ void gather_point(const Box& b, const T* u, int i, int j, int k, PointIn<T>& in,
     }
   }
   }  // order 4
+  // Kreiss-Oliger: with four ghost layers and the sixth-order scheme, minus
+  // the eighth difference over 256 h (an O(h^7) term, below the scheme's
+  // truncation error); otherwise the sixth difference over 64 h.  Either
+  // multiplies the highest grid mode by -1/h.
+  const bool ko8 = order == 6 && b.ng >= 4;
   for (int f = 0; f < NF; ++f) {
     const T* uf = u + f * b.fstride;
     T s = 0.0;
     for (int d = 0; d < 3; ++d) {
       const int64_t q = st[d];
-      T six = uf[c - 3 * q] - 6.0 * uf[c - 2 * q] + 15.0 * uf[c - q] - 20.0 * uf[c] + 15.0 * uf[c + q] -
-              6.0 * uf[c + 2 * q] + uf[c + 3 * q];
-      s += six / (64.0 * b.dx[d]);
+      if (ko8) {
+        T eight = uf[c - 4 * q] - 8.0 * uf[c - 3 * q] + 28.0 * uf[c - 2 * q] - 56.0 * uf[c - q] + 70.0 * uf[c] -
+                  56.0 * uf[c + q] + 28.0 * uf[c + 2 * q] - 8.0 * uf[c + 3 * q] + uf[c + 4 * q];
+        s += -eight / (256.0 * b.dx[d]);
+      } else {
+        T six = uf[c - 3 * q] - 6.0 * uf[c - 2 * q] + 15.0 * uf[c - q] - 20.0 * uf[c] + 15.0 * uf[c + q] -
+                6.0 * uf[c + 2 * q] + uf[c + 3 * q];
+        s += six / (64.0 * b.dx[d]);
+      }
     }
     ko[f] = s;
   }
@@ -1113,9 +1137,9 @@ template <class T>
 void fill_periodic(const Box& b, T* u) {
   const int n[3] = {b.nx, b.ny, b.nz};
 #pragma omp parallel for
-  for (int k = -NG; k < b.nz + NG; ++k)
-    for (int j = -NG; j < b.ny + NG; ++j)
-      for (int i = -NG; i < b.nx + NG; ++i) {
+  for (int k = -b.ng; k < b.nz + b.ng; ++k)
+    for (int j = -b.ng; j < b.ny + b.ng; ++j)
+      for (int i = -b.ng; i < b.nx + b.ng; ++i) {
         if (i >= 0 && i < n[0] && j >= 0 && j < n[1] && k >= 0 && k < n[2]) continue;
         const int si = ((i % n[0]) + n[0]) % n[0];
         const int sj = ((j % n[1]) + n[1]) % n[1];
@@ -1231,9 +1255,9 @@ template <class T>
 void fill_faces(const Box& b, const BcSpec& bc, T* u) {
   const int n[3] = {b.nx, b.ny, b.nz};
   for (int axis = 2; axis >= 0; --axis) {
-    for (int k = -NG; k < b.nz + NG; ++k)
-      for (int j = -NG; j < b.ny + NG; ++j)
-        for (int i = -NG; i < b.nx + NG; ++i) {
+    for (int k = -b.ng; k < b.nz + b.ng; ++k)
+      for (int j = -b.ng; j < b.ny + b.ng; ++j)
+        for (int i = -b.ng; i < b.nx + b.ng; ++i) {
           const int face = owner_face(b, i, j, k);
           if (face < 0 || face / 2 != axis) continue;
           const int rule = bc.rule[face];
@@ -1304,9 +1328,9 @@ T sommerfeld_rhs(const Box& b, const BcSpec& bc, const T* u, int f, int i, int j
 // right-hand side in the ghost cells: radiative on Sommerfeld faces, 0 elsewhere
 template <class T>
 void ghost_rhs(const Box& b, const BcSpec& bc, const T* u, T* rhs) {
-  for (int k = -NG; k < b.nz + NG; ++k)
-    for (int j = -NG; j < b.ny + NG; ++j)
-      for (int i = -NG; i < b.nx + NG; ++i) {
+  for (int k = -b.ng; k < b.nz + b.ng; ++k)
+    for (int j = -b.ng; j < b.ny + b.ng; ++j)
+      for (int i = -b.ng; i < b.nx + b.ng; ++i) {
         const int face = owner_face(b, i, j, k);
         if (face < 0) continue;
         const int64_t c = cell_index(b, i, j, k);

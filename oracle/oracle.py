@@ -76,9 +76,10 @@ def _c(a):
     return a
 
 
-def _dims(u):
-    nz, ny, nx = (s - 2 * NG for s in u.shape[1:])
-    return np.array([nx, ny, nz], dtype=np.int32)
+def _dims(u, ng=NG):
+    """nx, ny, nz and the ghost count, as the oracle's box reads them."""
+    nz, ny, nx = (s - 2 * ng for s in u.shape[1:])
+    return np.array([nx, ny, nz, ng], dtype=np.int32)
 
 
 def _spacing(dx):
@@ -87,23 +88,24 @@ def _spacing(dx):
     return np.array(dx, dtype=np.float64)
 
 
-def rhs(params, u, dx):
-    """Right-hand side (incl. Kreiss-Oliger) on interior cells; ghosts of the result are 0."""
+def rhs(params, u, dx, ng=NG):
+    """Right-hand side (incl. Kreiss-Oliger) on interior cells; ghosts of the result are 0.
+    ng: ghost layers of u (4 only with the sixth-order scheme)."""
     u = _c(u)
     out = np.zeros_like(u)
     p = _c(params)
-    dims = _dims(u)
+    dims = _dims(u, ng)
     flags = lib().oracle_rhs(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(u), _d(out))
     return out, flags
 
 
-def rhs_cells(params, u, dx, cells):
+def rhs_cells(params, u, dx, cells, ng=NG):
     """Right-hand side at interior cells given as an (n, 3) array of (i, j, k)."""
     u = _c(u)
     cells = np.ascontiguousarray(cells, dtype=np.int32)
     out = np.zeros((cells.shape[0], NF))
     p = _c(params)
-    dims = _dims(u)
+    dims = _dims(u, ng)
     flags = lib().oracle_rhs_cells(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(u), cells.shape[0],
                                    cells.ctypes.data_as(_ip), _d(out))
     return out, flags
@@ -123,15 +125,15 @@ def rhs_cs(params, theta_im, u_re, u_im, dx):
     return r_re, r_im
 
 
-def constraints(params, u, dx):
+def constraints(params, u, dx, ng=NG):
     """Hamiltonian (nz,ny,nx) and momentum (3,nz,ny,nx) constraints on the interior."""
     u = _c(u)
     ham = np.zeros(u.shape[1:])
     mom = np.zeros((NF,) + u.shape[1:])  # only the first 3 fields are written
     p = _c(params)
-    dims = _dims(u)
+    dims = _dims(u, ng)
     lib().oracle_constraints(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(u), _d(ham), _d(mom))
-    s = (slice(NG, -NG),) * 3
+    s = (slice(ng, -ng),) * 3
     return ham[s], mom[(slice(0, 3),) + s]
 
 
@@ -204,18 +206,18 @@ def rk4_bc(params, u, dx, dt, nsteps, bc):
     return u, flags
 
 
-def fill_periodic(u):
+def fill_periodic(u, ng=NG):
     u = _c(u).copy()
-    dims = _dims(u)
+    dims = _dims(u, ng)
     lib().oracle_fill_periodic(dims.ctypes.data_as(_ip), _d(u))
     return u
 
 
-def rk4(params, u, dx, dt, nsteps, periodic):
+def rk4(params, u, dx, dt, nsteps, periodic, ng=NG):
     """nsteps classic RK4 steps; returns (new state, flags)."""
     u = _c(u).copy()
     p = _c(params)
-    dims = _dims(u)
+    dims = _dims(u, ng)
     flags = lib().oracle_rk4(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), 1 if periodic else 0,
                              float(dt), int(nsteps), _d(u))
     return u, flags
@@ -266,12 +268,12 @@ def gepp(A, b):
     return x, ratio
 
 
-def stencils(f, dx, i, j, k, order=4):
-    """Stencils (centred order 4 or 6) of a scalar field f (shape (nz+6, ny+6, nx+6))
+def stencils(f, dx, i, j, k, order=4, ng=NG):
+    """Stencils (centred order 4 or 6) of a scalar field f (shape (nz+2ng, ny+2ng, nx+2ng))
     at interior cell (i,j,k): dict with d1[3], d2[6], adv_plus[3], adv_minus[3], ko."""
     f = _c(f)
-    nz, ny, nx = (s - 2 * NG for s in f.shape)
-    dims = np.array([nx, ny, nz], dtype=np.int32)
+    nz, ny, nx = (s - 2 * ng for s in f.shape)
+    dims = np.array([nx, ny, nz, ng], dtype=np.int32)
     out = np.zeros(16)
     lib().oracle_stencils(dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(f), i, j, k, int(order), _d(out))
     return dict(d1=out[0:3], d2=out[3:9], adv_plus=out[9:12], adv_minus=out[12:15], ko=out[15])

@@ -53,21 +53,21 @@ def params_vector(p: dict) -> np.ndarray:
     return np.array([p[n] for n in PARAM_NAMES], dtype=np.float64)
 
 
-def coords(dims, dx, centre=(0.0, 0.0, 0.0)):
-    """Cell-centre coordinate arrays (z, y, x order, including ghosts)."""
+def coords(dims, dx, centre=(0.0, 0.0, 0.0), ng=NG):
+    """Cell-centre coordinate arrays (z, y, x order, including ng ghost layers)."""
     nx, ny, nz = dims
     axes = []
     for n, c in zip((nx, ny, nz), centre):
-        i = np.arange(-NG, n + NG, dtype=np.float64)
+        i = np.arange(-ng, n + ng, dtype=np.float64)
         axes.append(c - 0.5 * n * dx + (i + 0.5) * dx)
     x, y, z = axes
     Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
     return X, Y, Z
 
 
-def empty_state(dims):
+def empty_state(dims, ng=NG):
     nx, ny, nz = dims
-    return np.zeros((NF, nz + 2 * NG, ny + 2 * NG, nx + 2 * NG), dtype=np.float64)
+    return np.zeros((NF, nz + 2 * ng, ny + 2 * ng, nx + 2 * ng), dtype=np.float64)
 
 
 def set_flat(u):
@@ -78,36 +78,36 @@ def set_flat(u):
     return u
 
 
-def wrap_ghosts(u):
+def wrap_ghosts(u, ng=NG):
     """Periodic ghost fill of an input state (each ghost copies the interior cell
     congruent to it modulo the box size)."""
-    inner = u[:, NG:-NG, NG:-NG, NG:-NG]
-    return np.pad(inner, ((0, 0), (NG, NG), (NG, NG), (NG, NG)), mode="wrap")
+    inner = u[:, ng:-ng, ng:-ng, ng:-ng]
+    return np.pad(inner, ((0, 0), (ng, ng), (ng, ng), (ng, ng)), mode="wrap")
 
 
-def flat_noise_pulse(n=32, dx=0.25, seed=0, noise=1e-6, pulse=0.01, width2=4.0):
+def flat_noise_pulse(n=32, dx=0.25, seed=0, noise=1e-6, pulse=0.01, width2=4.0, ng=NG):
     """Periodic flat space + uniform noise on every field + Gaussian scalar pulse
-    phi += pulse * exp(-r^2 / width2)."""
+    phi += pulse * exp(-r^2 / width2) (the interior does not depend on ng)."""
     dims = (n, n, n)
-    u = set_flat(empty_state(dims))
+    u = set_flat(empty_state(dims, ng))
     rng = np.random.default_rng(seed)
-    inner = (slice(NG, -NG),) * 3
+    inner = (slice(ng, -ng),) * 3
     for f in range(NF):
         u[(f,) + inner] += rng.uniform(-noise, noise, size=(n, n, n))
-    X, Y, Z = coords(dims, dx)
+    X, Y, Z = coords(dims, dx, ng=ng)
     r2 = X * X + Y * Y + Z * Z
     u[(IDX["phi"],) + inner] += pulse * np.exp(-r2[inner] / width2)
-    return wrap_ghosts(u)
+    return wrap_ghosts(u, ng)
 
 
 def puncture(dims, dx, centre=(0.0, 0.0, 0.0), masses=((1.0, (0.0, 0.0, 0.0)),),
-             phi_fn=None):
+             phi_fn=None, ng=NG):
     """Conformally flat (superposed) puncture data, frozen ghosts included:
     chi^(-1/4) = 1 + sum_A m_A / (2 r_A) with r_A floored at dx/2; h = delta;
     A = K = Theta = Gamma = shift = B = 0; pre-collapsed lapse alpha = sqrt(chi);
     phi from phi_fn(X, Y, Z), Pi = 0."""
-    u = empty_state(dims)
-    X, Y, Z = coords(dims, dx, centre)
+    u = empty_state(dims, ng)
+    X, Y, Z = coords(dims, dx, centre, ng)
     psi = np.ones_like(X)
     for m, (cx, cy, cz) in masses:
         r = np.sqrt((X - cx) ** 2 + (Y - cy) ** 2 + (Z - cz) ** 2)
@@ -136,9 +136,9 @@ def gaussian_pulse(amp=0.05, width2=25.0):
     return f
 
 
-def single_puncture(n=128, dx=1.0 / 8.0):
+def single_puncture(n=128, dx=1.0 / 8.0, ng=NG):
     """One non-spinning puncture of mass 1 plus phi = 0.1 exp(-(r-4)^2)."""
-    return puncture((n, n, n), dx, phi_fn=shell_pulse())
+    return puncture((n, n, n), dx, phi_fn=shell_pulse(), ng=ng)
 
 
 def two_punctures(n=256, dx=1.0 / 16.0):
@@ -175,8 +175,8 @@ def shell_mask(dims, dx, r_in=8.0, r_out=10.0, centre=(0.0, 0.0, 0.0)):
     return (r > r_in) & (r < r_out)
 
 
-def interior(u):
-    return u[..., NG:-NG, NG:-NG, NG:-NG]
+def interior(u, ng=NG):
+    return u[..., ng:-ng, ng:-ng, ng:-ng]
 
 
 def amr_states(boxes):

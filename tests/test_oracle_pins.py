@@ -31,9 +31,9 @@ def _build():
 
 
 # ------------------------------------------------------------------ stencils
-def _poly_field(n, dx, coeffs, degree):
+def _poly_field(n, dx, coeffs, degree, ng=3):
     """sum c_{abc} x^a y^b z^c over a+b+c <= degree on the grid (incl. ghosts)."""
-    X, Y, Z = I.coords((n, n, n), dx)
+    X, Y, Z = I.coords((n, n, n), dx, ng=ng)
     f = np.zeros_like(X)
     derivs = {}
     for (a, b, c), cf in coeffs.items():
@@ -139,12 +139,78 @@ def test_sixth_order_stencils_not_exact_beyond_their_degree():
     assert abs(s6["adv_plus"][0] - s6["adv_minus"][0]) > 1e-6
 
 
-def _smooth_periodic_2d(n, L, shift):
+@pytest.mark.parametrize("degree", [4, 6, 7])
+def test_sixth_order_four_ghost_stencils_exact_on_polynomials(degree):
+    """With four ghost layers the sixth-order scheme's advection stencils
+    (offsets -2..4 and their mirror) are exact up to degree 6 and its
+    Kreiss-Oliger operator (the eighth difference) vanishes up to degree 7;
+    the centred stencils are those of three ghost layers."""
+    rng = np.random.default_rng(30 + degree)
+    n, dx, ng = 8, 2.0 ** -2, 4
+    terms = [(a, b, c) for a in range(degree + 1) for b in range(degree + 1) for c in range(degree + 1)
+             if a + b + c <= degree]
+    coeffs = {t: float(rng.integers(-3, 4)) for t in terms}
+    f, X, Y, Z = _poly_field(n, dx, coeffs, degree, ng=ng)
+    f3 = f[1:-1, 1:-1, 1:-1]
+    for (i, j, k) in [(0, 0, 0), (3, 4, 5), (7, 7, 7)]:
+        s = O.stencils(f, dx, i, j, k, order=6, ng=ng)
+        x, y, z = X[k + ng, j + ng, i + ng], Y[k + ng, j + ng, i + ng], Z[k + ng, j + ng, i + ng]
+
+        def d(px, py, pz):
+            tot = 0.0
+            for (a, b, c), cf in coeffs.items():
+                if a < px or b < py or c < pz:
+                    continue
+                fa = np.prod(range(a - px + 1, a + 1)) if px else 1
+                fb = np.prod(range(b - py + 1, b + 1)) if py else 1
+                fc = np.prod(range(c - pz + 1, c + 1)) if pz else 1
+                tot += cf * fa * fb * fc * x ** (a - px) * y ** (b - py) * z ** (c - pz)
+            return tot
+
+        scale = max(1.0, np.abs(f).max())
+        exact_d1 = [d(1, 0, 0), d(0, 1, 0), d(0, 0, 1)]
+        if degree <= 6:
+            np.testing.assert_allclose(s["adv_plus"], exact_d1, rtol=0, atol=1e-11 * scale / dx)
+            np.testing.assert_allclose(s["adv_minus"], exact_d1, rtol=0, atol=1e-11 * scale / dx)
+        assert abs(s["ko"]) <= 1e-11 * scale / dx
+        # centred stencils: the same values as on the box with three ghost layers
+        s3 = O.stencils(f3, dx, i, j, k, order=6)
+        assert np.array_equal(s["d1"], s3["d1"]) and np.array_equal(s["d2"], s3["d2"])
+
+
+def test_sixth_order_four_ghost_stencils_not_exact_beyond_their_degree():
+    n, dx, ng = 8, 0.25, 4
+    X, Y, Z = I.coords((n, n, n), dx, ng=ng)
+    x = X[7, 7, 7]
+    s7 = O.stencils(X ** 7, dx, 3, 3, 3, order=6, ng=ng)
+    assert abs(s7["adv_plus"][0] - 7 * x ** 6) > 1e-6 and abs(s7["adv_minus"][0] - 7 * x ** 6) > 1e-6
+    # the eighth difference of x^8 is 8! h^8, so KO = -8! h^8 / (256 h)
+    s8 = O.stencils(X ** 8, dx, 3, 3, 3, order=6, ng=ng)
+    # the two biased stencils differ (their errors on x^8 differ in the h^7 term)
+    assert abs(s8["adv_plus"][0] - s8["adv_minus"][0]) > 1e-6
+    assert s8["ko"] == pytest.approx(-40320 * dx ** 8 / (256 * dx), rel=1e-9)
+
+
+@pytest.mark.parametrize("order,ng", [(4, 3), (6, 3), (6, 4)])
+def test_kreiss_oliger_damps_the_grid_mode_at_rate_one_over_h(order, ng):
+    """Both dissipation operators take the highest grid mode (-1)^(i+j+k) to
+    -1/h times itself per axis: the same damping, whatever the scheme."""
+    n, dx = 8, 0.5
+    X, Y, Z = I.coords((n, n, n), dx, ng=ng)
+    idx = np.indices(X.shape).sum(axis=0)
+    f = np.where(idx % 2 == 0, 1.0, -1.0)
+    for (i, j, k) in [(0, 0, 0), (2, 5, 3)]:
+        s = O.stencils(f, dx, i, j, k, order=order, ng=ng)
+        v = f[k + ng, j + ng, i + ng]
+        assert s["ko"] == pytest.approx(-3.0 * v / dx, rel=1e-14)
+
+
+def _smooth_periodic_2d(n, L, shift, ng=3):
     """Smooth data periodic in x and y (4 cells along z), every field varying."""
     dims = (n, n, 4)
     dx = L / n
-    u = I.set_flat(I.empty_state(dims))
-    X, Y, Z = I.coords(dims, dx)
+    u = I.set_flat(I.empty_state(dims, ng))
+    X, Y, Z = I.coords(dims, dx, ng=ng)
     k = 2 * np.pi / L
     rng = np.random.default_rng(3)
     for f in range(27):
@@ -152,28 +218,33 @@ def _smooth_periodic_2d(n, L, shift):
         u[f] += a * np.sin(k * X + 2 * k * Y + b) + c * np.cos(2 * k * X - k * Y)
     for f in ("shift1", "shift2", "shift3", "B1", "B2", "B3"):
         u[IDX[f]] *= 1.0 if shift else 0.0
-    return I.wrap_ghosts(u), dx
+    return I.wrap_ghosts(u, ng), dx
 
 
-@pytest.mark.parametrize("order,shift,expect", [(4, False, (3.6, 4.4)), (6, False, (5.6, 6.4)),
-                                                (6, True, (4.8, 6.2))])
-def test_rhs_spatial_convergence_order(order, shift, expect):
+@pytest.mark.parametrize("order,shift,expect,sigma,ng", [
+    (4, False, (3.6, 4.4), 0.0, 3), (6, False, (5.6, 6.4), 0.0, 3), (6, True, (4.8, 6.2), 0.0, 3),
+    (6, False, (5.6, 6.4), 0.3, 4), (6, True, (5.6, 6.4), 0.3, 4), (6, False, (4.6, 5.4), 0.3, 3)])
+def test_rhs_spatial_convergence_order(order, shift, expect, sigma, ng):
     """The right-hand side of smooth periodic data converges at the order of
     its stencils: compared through low Fourier modes of every field at 16, 32
-    and 64 cells per period (Kreiss-Oliger off).  With a nonzero shift the
+    and 64 cells per period.  With three ghost layers and a nonzero shift the
     fifth-order advection stencil of the sixth-order scheme enters: the
-    measured order lies between 5 and 6 (about 5.3 to 5.9 per field here)."""
+    measured order lies between 5 and 6 (about 5.3 to 5.9 per field here);
+    with dissipation on, its sixth difference over 64 h is an O(h^5) term and
+    the order drops to 5.  With four ghost layers (sixth-order advection,
+    eighth-difference dissipation) the order is 6 with the shift and the
+    dissipation on."""
     L = 8.0
-    p = I.params_vector(I.default_params(ko_sigma=0.0, lambda_gb=0.2, g2=0.05, fd_order=float(order)))
+    p = I.params_vector(I.default_params(ko_sigma=sigma, lambda_gb=0.2, g2=0.05, fd_order=float(order)))
     modes = [(0, 0), (1, 0), (1, 2), (2, -1)]
     coefs = []
     for n in (16, 32, 64):
-        u, dx = _smooth_periodic_2d(n, L, shift)
-        r, flags = O.rhs(p, u, dx)
+        u, dx = _smooth_periodic_2d(n, L, shift, ng)
+        r, flags = O.rhs(p, u, dx, ng=ng)
         assert flags == 0
-        X, Y, _ = I.coords((n, n, 4), dx)
-        x, y = I.interior(X[None])[0], I.interior(Y[None])[0]
-        ri = I.interior(r)
+        X, Y, _ = I.coords((n, n, 4), dx, ng=ng)
+        x, y = I.interior(X[None], ng)[0], I.interior(Y[None], ng)[0]
+        ri = I.interior(r, ng)
         kk = 2 * np.pi / L
         coefs.append(np.array([[np.mean(ri[f] * np.exp(-1j * kk * (m * x + l * y))) for (m, l) in modes]
                                for f in range(27)]))
