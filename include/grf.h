@@ -3,7 +3,7 @@
  * the pointwise right-hand side of CCZ4 in the modified puncture gauge coupled
  * to a scalar field with the four-derivative scalar-tensor terms, with
  * Kreiss-Oliger dissipation, and the classic RK4 stage update, on 3-D boxes with
- * three ghost cells (the method named in the paper's Summary and Key features:
+ * three (or, for the sixth-order scheme, four) ghost cells (the method named in the paper's Summary and Key features:
  * 4dST theory, modified moving-puncture gauge, 4th- and 6th-order finite
  * differences, RK4, periodic and per-face boundary rules, the decoupling
  * limit, constraint, energy and weak-coupling diagnostics), a batched form for
@@ -12,7 +12,8 @@
  * Conventions shared by every call
  *  - State layout: 27 FP64 fields, field-major; field f of a box starts at
  *    f * field_stride; within a field, cells are [z][y][x] with x fastest over
- *    (nx+6) x (ny+6) x (nz+6) cells (3 ghost cells on every side).  Field order:
+ *    (nx+2g) x (ny+2g) x (nz+2g) cells (g = 3 ghost cells on every side, or
+ *    g = 4 for the sixth-order scheme described at fd_order).  Field order:
  *      chi, h11 h12 h13 h22 h23 h33, K, A11 A12 A13 A22 A23 A33, Theta,
  *      Gam1 Gam2 Gam3, lapse, shift1 shift2 shift3, B1 B2 B3, phi, Pi.
  *  - Interior arrays ("compact"): 27 fields, field-major, nx*ny*nz cells each,
@@ -80,13 +81,18 @@ enum { GRF_FLAG_NONFINITE = 1, GRF_FLAG_HYPERBOLIC = 2, GRF_FLAG_NONPOSITIVE = 4
  * 2 (the default); the other paths, the diagnostics, the batched form and the
  * adjoint return GRF_EUNSUPPORTED.
  * fd_order: 4 (or 0) fourth-order stencils; 6 sixth-order stencils (Key
- * features, "Accuracy") on the same three ghost layers: centred first, second
- * and mixed derivatives of order 6, the advection derivative of order 5 on the
- * six points leaning one cell to the side the shift points to, the same
- * Kreiss-Oliger operator.  Order 6 runs the z-marching 32x8x32 stencil kernel
- * whatever grf_set_tile_variant chose, on stage paths 0 and 2, in
- * grf_rhs_eval, grf_rk4_stage, grf_rk4_stage_bc and the diagnostics; the fused
- * path, the batched form and the adjoint return GRF_EUNSUPPORTED. */
+ * features, "Accuracy").  On a box with three ghost layers: centred first,
+ * second and mixed derivatives of order 6, the advection derivative of order
+ * 5 on the six points leaning one cell to the side the shift points to, the
+ * same Kreiss-Oliger operator (an O(h^5) term).  On a box with four ghost
+ * layers (grf_box.ng = 4): the same centred derivatives, the advection
+ * derivative of order 6 on offsets -2..4 (mirrored for a negative shift) and
+ * the dissipation -sigma/(256 h) times the eighth difference, so the scheme
+ * keeps order 6 with dissipation on.  Order 6 runs the z-marching 32x8x32
+ * stencil kernel whatever grf_set_tile_variant chose, on stage paths 0 and 2,
+ * in grf_rhs_eval, grf_rk4_stage, grf_rk4_stage_bc (three ghost layers) and
+ * the diagnostics; the fused path, the batched form and the adjoint return
+ * GRF_EUNSUPPORTED. */
 typedef struct {
   double lambda_gb;
   int32_t lambda_kind;
@@ -104,10 +110,15 @@ typedef struct {
   double beta;
 } grf_params;
 
-/* One box: nx, ny, nz interior cells, ng ghosts (must be 3), spacing dx, dy,
- * dz, coordinates x0, y0, z0 of the centre of interior cell (0,0,0) (read by
- * the radiative boundary rule only),
- * field_stride >= (nx+6)(ny+6)(nz+6), boundary rule bc. */
+/* One box: nx, ny, nz interior cells, ng ghosts, spacing dx, dy, dz,
+ * coordinates x0, y0, z0 of the centre of interior cell (0,0,0) (read by the
+ * radiative boundary rule only), field_stride >= (nx+2ng)(ny+2ng)(nz+2ng),
+ * boundary rule bc.  ng is 3, or 4 with fd_order 6 (GRF_EUNSUPPORTED with
+ * fd_order 4); four ghost layers are accepted by grf_rhs_eval, grf_rk4_stage,
+ * grf_fill_periodic, grf_enforce, grf_constraints, grf_energy_densities and
+ * grf_coupling_diagnostics, and refused with GRF_EUNSUPPORTED by the boundary
+ * rules, the batched form and the adjoint (whose size queries return 0);
+ * GRF_ESHAPE for any other ng. */
 typedef struct {
   int32_t nx, ny, nz, ng;
   double dx, dy, dz;

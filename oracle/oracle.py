@@ -252,10 +252,10 @@ def rhs_point(params, u, d1, d2, adv):
     return out, ex, flags
 
 
-def enforce(u, chi_min, lapse_min):
+def enforce(u, chi_min, lapse_min, ng=NG):
     """Post-stage enforcement on the interior cells (returns a new state)."""
     u = _c(u).copy()
-    dims = _dims(u)
+    dims = _dims(u, ng)
     lib().oracle_enforce(dims.ctypes.data_as(_ip), _d(u), float(chi_min), float(lapse_min))
     return u
 

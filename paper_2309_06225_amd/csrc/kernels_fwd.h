@@ -15,8 +15,9 @@ constexpr int F_CHI = 0, F_LAPSE = 18, F_SHIFT = 19, F_B = 22;
 // Geometry of one box as the kernels see it.
 struct BoxDev {
   int nx, ny, nz;
-  int sy;          // state stride in y (nx + 6)
-  int64_t sz;      // state stride in z ((nx+6)(ny+6))
+  int ng;          // ghost layers (3; 4 for the sixth-order scheme with eighth-difference dissipation)
+  int sy;          // state stride in y (nx + 2 ng)
+  int64_t sz;      // state stride in z ((nx + 2 ng)(ny + 2 ng))
   int64_t fs;      // field stride of the state
   int64_t ncell;   // nx*ny*nz
   double i12h[3];  // 1/(12 h)
@@ -26,6 +27,7 @@ struct BoxDev {
   double i60h[3];    // 1/(60 h)            (sixth-order stencils)
   double i180h2[3];  // 1/(180 h^2)
   double i3600[3];   // 1/(3600 h_x h_y), 1/(3600 h_x h_z), 1/(3600 h_y h_z)
+  double i256h[3];   // 1/(256 h)           (eighth-difference dissipation)
 };
 
 __device__ __forceinline__ bool advected(int f, int shift_adv) {
@@ -92,7 +94,8 @@ __device__ __forceinline__ double sten6_up_plus(const double* L) {
 __device__ __forceinline__ double sten6_up_minus(const double* L) {
   return ((((-3.0 * L[5] + 30.0 * L[4]) + 20.0 * L[3]) - 60.0 * L[2]) + 15.0 * L[1]) - 2.0 * L[0];
 }
-template <int LX, int PAIR>
+// (H: the staged halo, 3 or 4; pb[dz + H] is the plane at z offset dz)
+template <int LX, int PAIR, int H = 3>
 __device__ __forceinline__ double sten6_mixed(const double* t, const int* pb, int cxy) {
   const double w[7] = {-1.0, 9.0, -45.0, 0.0, 45.0, -9.0, 1.0};
   double s = 0.0;
@@ -102,11 +105,27 @@ __device__ __forceinline__ double sten6_mixed(const double* t, const int* pb, in
 #pragma unroll
     for (int bb = -3; bb <= 3; ++bb) {
       if (bb == 0) continue;
-      const int e = PAIR == 0 ? pb[3] + cxy + bb * LX + a : PAIR == 1 ? pb[bb + 3] + cxy + a : pb[bb + 3] + cxy + a * LX;
+      const int e = PAIR == 0 ? pb[H] + cxy + bb * LX + a : PAIR == 1 ? pb[bb + H] + cxy + a : pb[bb + H] + cxy + a * LX;
       s += (w[a + 3] * w[bb + 3]) * t[e];
     }
   }
   return s;
+}
+// With four ghost layers, on a line L[0..8] = u at offsets -4..4: the
+// sixth-order advection stencil leaning one cell to the side the shift points
+// to, offsets -2..4 with (2, -24, -35, 80, -30, 8, -1)/(60 h) for beta >= 0 and
+// its mirror image for beta < 0, and the eighth difference
+// (1, -8, 28, -56, 70, -56, 28, -8, 1), which the dissipation takes with
+// weight -sigma/(256 h).
+__device__ __forceinline__ double sten6_up7_plus(const double* L) {
+  return (((((2.0 * L[2] - 24.0 * L[3]) - 35.0 * L[4]) + 80.0 * L[5]) - 30.0 * L[6]) + 8.0 * L[7]) - L[8];
+}
+__device__ __forceinline__ double sten6_up7_minus(const double* L) {
+  return (((((-2.0 * L[6] + 24.0 * L[5]) + 35.0 * L[4]) - 80.0 * L[3]) + 30.0 * L[2]) - 8.0 * L[1]) + L[0];
+}
+__device__ __forceinline__ double sten_ko8(const double* L) {
+  return (((((((L[0] - 8.0 * L[1]) + 28.0 * L[2]) - 56.0 * L[3]) + 70.0 * L[4]) - 56.0 * L[5]) + 28.0 * L[6]) -
+          8.0 * L[7]) + L[8];
 }
 #pragma clang fp contract(fast)
 
@@ -161,24 +180,29 @@ __device__ __forceinline__ void rec_store(double* p, double v) {
 // (pb: base of the plane at z offset dz, cxy: the cell within a plane), so the
 // same arithmetic serves a 3-D tile and a ring of z-planes.  Record layout:
 // component q of the cell lives at Dc[q * nc].
-template <int LX, bool STREAM = true, int ORD = 4>
+// H: the staged halo (3, or 4 for the sixth-order scheme with four ghost
+// layers: sixth-order advection and eighth-difference dissipation).
+template <int LX, bool STREAM = true, int ORD = 4, int H = 3>
 __device__ __forceinline__ void compute_cell(const BoxDev& b, int i, int j, int k, int f, const double* __restrict__ u,
                                              double* __restrict__ Dc, int64_t nc, int64_t cell, double ko_sigma,
                                              int shift_adv, double* __restrict__ UP, const double* t, const int* pb,
                                              int cxy) {
-#define GRF_AT(dx, dy, dz) t[pb[(dz) + 3] + cxy + (dy) * LX + (dx)]
-  double line[3][7];
+  static_assert(H == 3 || (H == 4 && ORD == 6), "four ghost layers only with the sixth-order scheme");
+#define GRF_AT(dx, dy, dz) t[pb[(dz) + H] + cxy + (dy) * LX + (dx)]
+  double line[3][2 * H + 1];
 #pragma unroll
-  for (int o = -3; o <= 3; ++o) {
-    line[0][o + 3] = GRF_AT(o, 0, 0);
-    line[1][o + 3] = GRF_AT(0, o, 0);
-    line[2][o + 3] = GRF_AT(0, 0, o);
+  for (int o = -H; o <= H; ++o) {
+    line[0][o + H] = GRF_AT(o, 0, 0);
+    line[1][o + H] = GRF_AT(0, o, 0);
+    line[2][o + H] = GRF_AT(0, 0, o);
   }
+  // the seven points -3..3 of each line
+  const double* l7[3] = {line[0] + (H - 3), line[1] + (H - 3), line[2] + (H - 3)};
   const int s1 = grf_d1_slot[f];
   if (s1 >= 0) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const double v = ORD == 6 ? sten6_d1(line[d]) * b.i60h[d] : sten_d1(line[d]) * b.i12h[d];
+      const double v = ORD == 6 ? sten6_d1(l7[d]) * b.i60h[d] : sten_d1(l7[d]) * b.i12h[d];
       rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D1 + 3 * s1 + d) * nc], v);
     }
   }
@@ -188,14 +212,14 @@ __device__ __forceinline__ void compute_cell(const BoxDev& b, int i, int j, int 
     if constexpr (ORD == 6) {
 #pragma unroll
       for (int d = 0; d < 3; ++d)
-        rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc], sten6_d2(line[d]) * b.i180h2[d]);
-      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 1) * nc], sten6_mixed<LX, 0>(t, pb, cxy) * b.i3600[0]);
-      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 2) * nc], sten6_mixed<LX, 1>(t, pb, cxy) * b.i3600[1]);
-      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 4) * nc], sten6_mixed<LX, 2>(t, pb, cxy) * b.i3600[2]);
+        rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc], sten6_d2(l7[d]) * b.i180h2[d]);
+      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 1) * nc], sten6_mixed<LX, 0, H>(t, pb, cxy) * b.i3600[0]);
+      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 2) * nc], sten6_mixed<LX, 1, H>(t, pb, cxy) * b.i3600[1]);
+      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 4) * nc], sten6_mixed<LX, 2, H>(t, pb, cxy) * b.i3600[2]);
     } else {
 #pragma unroll
       for (int d = 0; d < 3; ++d)
-        rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc], sten_d2(line[d]) * b.i12h2[d]);
+        rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc], sten_d2(l7[d]) * b.i12h2[d]);
       rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 1) * nc], sten_mixed<LX, 0>(t, pb, cxy) * b.i144[0]);
       rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 2) * nc], sten_mixed<LX, 1>(t, pb, cxy) * b.i144[1]);
       rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 4) * nc], sten_mixed<LX, 2>(t, pb, cxy) * b.i144[2]);
@@ -203,15 +227,17 @@ __device__ __forceinline__ void compute_cell(const BoxDev& b, int i, int j, int 
   }
 #undef GRF_AT
   // upwinded advection: the lopsided stencil on the side the shift points to
-  const int64_t sc = (int64_t)(k + 3) * b.sz + (int64_t)(j + 3) * b.sy + (i + 3);
+  const int64_t sc = (int64_t)(k + H) * b.sz + (int64_t)(j + H) * b.sy + (i + H);
   double beta[3], up[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     beta[d] = u[(int64_t)(F_SHIFT + d) * b.fs + sc];
-    if constexpr (ORD == 6)
-      up[d] = (beta[d] >= 0.0 ? sten6_up_plus(line[d]) : sten6_up_minus(line[d])) * b.i60h[d];
+    if constexpr (H == 4)
+      up[d] = (beta[d] >= 0.0 ? sten6_up7_plus(line[d]) : sten6_up7_minus(line[d])) * b.i60h[d];
+    else if constexpr (ORD == 6)
+      up[d] = (beta[d] >= 0.0 ? sten6_up_plus(l7[d]) : sten6_up_minus(l7[d])) * b.i60h[d];
     else
-      up[d] = (beta[d] >= 0.0 ? sten_up_plus(line[d]) : sten_up_minus(line[d])) * b.i12h[d];
+      up[d] = (beta[d] >= 0.0 ? sten_up_plus(l7[d]) : sten_up_minus(l7[d])) * b.i12h[d];
     if (UP) UP[(int64_t)(3 * f + d) * b.ncell + cell] = up[d];
   }
   // a field whose advection sum enters only its own right-hand side, with
@@ -224,7 +250,12 @@ __device__ __forceinline__ void compute_cell(const BoxDev& b, int i, int j, int 
   }
   double ko = 0.0;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) ko += sten_ko(line[d]) * b.i64h[d];
+  for (int d = 0; d < 3; ++d) {
+    if constexpr (H == 4)
+      ko += (-sten_ko8(line[d])) * b.i256h[d];
+    else
+      ko += sten_ko(l7[d]) * b.i64h[d];
+  }
   rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_KO + f) * nc], merged ? adv + ko_sigma * ko : ko_sigma * ko);
 }
 
@@ -297,12 +328,16 @@ __host__ __device__ inline int zm_items(const BoxDev& b) {
 }
 
 // One field of one (column, z-chunk) item: item = column x + ntx (column y +
-// nty chunk).  t: 8 * (TX+6)(TY+6) doubles of LDS.
-template <int TX, int TY, int ZC, int ORD = 4>
+// nty chunk).  t: zm_ring(H) * (TX+2H)(TY+2H) doubles of LDS, H the halo.
+// A ring of 2H + 2 planes for a (2H + 1)-plane stencil needs one barrier per
+// step (the slot a step writes is never one the previous step reads).
+__host__ __device__ constexpr int zm_ring(int h) { return 2 * h + 2; }
+
+template <int TX, int TY, int ZC, int ORD = 4, int H = 3>
 __device__ __forceinline__ void zm_column(const BoxDev& b, int item, int f, const double* __restrict__ u,
                                           double* __restrict__ D, double ko_sigma, int shift_adv,
                                           double* __restrict__ UP, double* t) {
-  constexpr int LX = TX + 6, LY = TY + 6, PL = LX * LY, NT = TX * TY;
+  constexpr int LX = TX + 2 * H, LY = TY + 2 * H, PL = LX * LY, NT = TX * TY, R = zm_ring(H);
   const int ntx = (b.nx + TX - 1) / TX, nty = (b.ny + TY - 1) / TY;
   const int tx0 = (item % ntx) * TX;
   item /= ntx;
@@ -313,9 +348,9 @@ __device__ __forceinline__ void zm_column(const BoxDev& b, int item, int f, cons
   const int ix = threadIdx.x % TX, iy = threadIdx.x / TX;
   const int i = tx0 + ix, j = ty0 + iy;
   const bool inside = i < b.nx && j < b.ny;
-  const int cxy = (iy + 3) * LX + (ix + 3);
+  const int cxy = (iy + H) * LX + (ix + H);
   // a plane of the column (ghost-inclusive z = gz) is fetched into registers,
-  // PER values per thread, and later written to its ring slot gz mod 8; the
+  // PER values per thread, and later written to its ring slot gz mod R; the
   // fetch of the next plane is issued before the current plane is computed
   constexpr int PER = (PL + NT - 1) / NT;
   double pre[PER];
@@ -326,11 +361,11 @@ __device__ __forceinline__ void zm_column(const BoxDev& b, int item, int f, cons
       const int e = threadIdx.x + q * NT;
       const int lx = e % LX, ly = e / LX;
       const int gx = tx0 + lx, gy = ty0 + ly;
-      pre[q] = (e < PL && gx < b.nx + 6 && gy < b.ny + 6) ? up[(int64_t)gy * b.sy + gx] : 0.0;
+      pre[q] = (e < PL && gx < b.nx + 2 * H && gy < b.ny + 2 * H) ? up[(int64_t)gy * b.sy + gx] : 0.0;
     }
   };
   auto store_plane = [&](int gz) {
-    double* tp = t + (gz & 7) * PL;
+    double* tp = t + ((unsigned)gz % R) * PL;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = threadIdx.x + q * NT;
@@ -338,30 +373,31 @@ __device__ __forceinline__ void zm_column(const BoxDev& b, int item, int f, cons
     }
   };
   __syncthreads();  // an earlier item of this workgroup is done with t
-  for (int gz = z0; gz < z0 + 6; ++gz) {
+  for (int gz = z0; gz < z0 + 2 * H; ++gz) {
     fetch_plane(gz);
     store_plane(gz);
   }
-  fetch_plane(z0 + 6);
+  fetch_plane(z0 + 2 * H);
   for (int k = z0; k < z1; ++k) {
-    store_plane(k + 6);
+    store_plane(k + 2 * H);
     __syncthreads();
-    if (k + 1 < z1) fetch_plane(k + 7);
+    if (k + 1 < z1) fetch_plane(k + 2 * H + 1);
     if (inside) {
-      int pb[7];
+      int pb[2 * H + 1];
 #pragma unroll
-      for (int o = 0; o < 7; ++o) pb[o] = ((k + o) & 7) * PL;
+      for (int o = 0; o < 2 * H + 1; ++o) pb[o] = ((unsigned)(k + o) % R) * PL;
       const int64_t cell = ((int64_t)k * b.ny + j) * b.nx + i;
-      compute_cell<LX, true, ORD>(b, i, j, k, f, u, D + cell, b.ncell, cell, ko_sigma, shift_adv, UP, t, pb, cxy);
+      compute_cell<LX, true, ORD, H>(b, i, j, k, f, u, D + cell, b.ncell, cell, ko_sigma, shift_adv, UP, t, pb,
+                                     cxy);
     }
   }
 }
 
-template <int TX, int TY, int ZC, bool XCDMAP, int ORD = 4>
+template <int TX, int TY, int ZC, bool XCDMAP, int ORD = 4, int H = 3>
 __global__ __launch_bounds__(TX* TY) void k_deriv_zm(BoxDev b, const double* __restrict__ u,
                                                       double* __restrict__ D, double ko_sigma, int shift_adv,
                                                       double* __restrict__ UP) {
-  __shared__ double t[8 * (TX + 6) * (TY + 6)];
+  __shared__ double t[zm_ring(H) * (TX + 2 * H) * (TY + 2 * H)];
   int item = blockIdx.x, f;
   if (XCDMAP) {
     item = xcd_item(item, (int)gridDim.x);
@@ -372,7 +408,7 @@ __global__ __launch_bounds__(TX* TY) void k_deriv_zm(BoxDev b, const double* __r
     f = item / per_field;
     item %= per_field;
   }
-  zm_column<TX, TY, ZC, ORD>(b, item, f, u, D, ko_sigma, shift_adv, UP, t);
+  zm_column<TX, TY, ZC, ORD, H>(b, item, f, u, D, ko_sigma, shift_adv, UP, t);
 }
 
 // ---------------------------------------------------------------------------

@@ -42,14 +42,25 @@ constexpr size_t kStatusBytes = 256;
 
 grf_status check_box(const grf_box* b) {
   if (!b) return fail(GRF_EINVAL, "box is null");
-  if (b->ng != NG) return fail(GRF_ESHAPE, "ng must be 3 (got %d)", b->ng);
+  if (b->ng != 3 && b->ng != 4) return fail(GRF_ESHAPE, "ng must be 3 or 4 (got %d)", b->ng);
   if (b->nx < 1 || b->ny < 1 || b->nz < 1) return fail(GRF_ESHAPE, "box dims must be >= 1");
-  if ((int64_t)b->nx + 6 > (1 << 20) || (int64_t)b->ny + 6 > (1 << 20) || (int64_t)b->nz + 6 > (1 << 20))
+  const int e = 2 * b->ng;
+  if ((int64_t)b->nx + e > (1 << 20) || (int64_t)b->ny + e > (1 << 20) || (int64_t)b->nz + e > (1 << 20))
     return fail(GRF_ESHAPE, "box too large");
-  const int64_t need = (int64_t)(b->nx + 6) * (b->ny + 6) * (b->nz + 6);
+  const int64_t need = (int64_t)(b->nx + e) * (b->ny + e) * (b->nz + e);
   if (b->field_stride < need) return fail(GRF_ESHAPE, "field_stride %lld < %lld", (long long)b->field_stride, (long long)need);
   if (!(b->dx > 0.0) || !(b->dy > 0.0) || !(b->dz > 0.0)) return fail(GRF_EINVAL, "spacing must be > 0");
   if (b->bc != GRF_BC_FROZEN && b->bc != GRF_BC_PERIODIC) return fail(GRF_EINVAL, "unknown bc %d", b->bc);
+  return GRF_OK;
+}
+
+// entry points whose kernels assume three ghost layers
+grf_status check_box3(const grf_box* b) {
+  grf_status s = check_box(b);
+  if (s != GRF_OK) return s;
+  if (b->ng != 3)
+    return fail(GRF_EUNSUPPORTED, "four ghost layers are supported by grf_rhs_eval, grf_rk4_stage, "
+                                  "grf_fill_periodic, grf_enforce and the diagnostics only");
   return GRF_OK;
 }
 
@@ -72,8 +83,9 @@ BoxDev make_boxdev(const grf_box* b) {
   d.nx = b->nx;
   d.ny = b->ny;
   d.nz = b->nz;
-  d.sy = b->nx + 6;
-  d.sz = (int64_t)(b->nx + 6) * (b->ny + 6);
+  d.ng = b->ng;
+  d.sy = b->nx + 2 * b->ng;
+  d.sz = (int64_t)(b->nx + 2 * b->ng) * (b->ny + 2 * b->ng);
   d.fs = b->field_stride;
   d.ncell = (int64_t)b->nx * b->ny * b->nz;
   const double h[3] = {b->dx, b->dy, b->dz};
@@ -92,8 +104,15 @@ BoxDev make_boxdev(const grf_box* b) {
   d.i3600[0] = 1.0 / (3600.0 * h[0] * h[1]);
   d.i3600[1] = 1.0 / (3600.0 * h[0] * h[2]);
   d.i3600[2] = 1.0 / (3600.0 * h[1] * h[2]);
+  for (int k = 0; k < 3; ++k) d.i256h[k] = 1.0 / (256.0 * h[k]);
   return d;
 }
+
+// The pointwise, enforcement and diagnostic kernels address interior cell
+// (i, j, k) at (k+3) sz + (j+3) sy + (i+3) of the state they are given; on a
+// box with four ghost layers they are given the state moved by one cell
+// along each axis (same strides), which puts that address at (k+4, j+4, i+4).
+int64_t interior_shift(const BoxDev& bd) { return (int64_t)(bd.ng - 3) * (bd.sz + bd.sy + 1); }
 
 grf_point_params make_pp(const grf_params* p) {
   grf_point_params q;
@@ -284,6 +303,7 @@ static grf_status common_checks(const grf_params* p, const grf_box* box, void* w
   if (s != GRF_OK) return s;
   s = check_box(box);
   if (s != GRF_OK) return s;
+  if (box->ng == 4 && p->fd_order != 6) return fail(GRF_EUNSUPPORTED, "four ghost layers only with fd_order 6");
   if (!ws) return fail(GRF_EINVAL, "workspace is null");
   if (ws_bytes < kStatusBytes + deriv_bytes(box))
     return fail(GRF_ENOMEM, "workspace %zu bytes < %zu", ws_bytes, kStatusBytes + deriv_bytes(box));
@@ -327,12 +347,13 @@ grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u
     prof_mark(1, stream);
     return GRF_OK;
   }
+  const int64_t sh = interior_shift(bd);
   prof_mark(0, stream);
   GRF_HIP_CHECK(launch_deriv_p(p, bd, u, D, sa, stream));
   prof_mark(0, stream);
   prof_mark(1, stream);
-  GRF_HIP_CHECK(launch_pointwise(g_stage_path, 0, staged_variant(p, sa), bd, pp, u, D, nullptr, rhs, nullptr,
-                                 StageCoef{0.0}, status, stream));
+  GRF_HIP_CHECK(launch_pointwise(g_stage_path, 0, staged_variant(p, sa), bd, pp, u + sh, D, nullptr, rhs + sh,
+                                 nullptr, StageCoef{0.0}, status, stream));
   prof_mark(1, stream);
   return GRF_OK;
 }
@@ -379,15 +400,17 @@ static grf_status rk4_stage_impl(const grf_params* p, const grf_box* box, int st
     GRF_HIP_CHECK(launch_fused(mode, sa, bd, pp, us, u0, unext, acc, sc, D, p->ko_sigma, status, stream));
     prof_mark(1, stream);
   } else {
+    const int64_t sh = interior_shift(bd);
     prof_mark(0, stream);
     GRF_HIP_CHECK(launch_deriv_p(p, bd, us, D, sa, stream));
     prof_mark(0, stream);
     prof_mark(1, stream);
-    GRF_HIP_CHECK(launch_pointwise(g_stage_path, mode, staged_variant(p, sa), bd, pp, us, D, u0, unext, acc,
-                                   sc, status, stream));
+    GRF_HIP_CHECK(launch_pointwise(g_stage_path, mode, staged_variant(p, sa), bd, pp, us + sh, D, u0 + sh,
+                                   unext + sh, acc, sc, status, stream));
     prof_mark(1, stream);
   }
-  if (p->enforce) GRF_HIP_CHECK(launch_enforce(bd, unext, p->chi_min, p->lapse_min, stream));
+  if (p->enforce)
+    GRF_HIP_CHECK(launch_enforce(bd, unext + interior_shift(bd), p->chi_min, p->lapse_min, stream));
   if (box_ghosts && box->bc == GRF_BC_PERIODIC) GRF_HIP_CHECK(launch_periodic(bd, unext, stream));
   return GRF_OK;
 }
@@ -458,12 +481,12 @@ static grf_status make_bcdev(const grf_bc* bc, const grf_box* box, bool radiativ
 }
 
 int64_t grf_bc_ghost_cells(const grf_box* box) {
-  if (check_box(box) != GRF_OK) return 0;
+  if (check_box3(box) != GRF_OK) return 0;
   return ghost_cells(make_boxdev(box));
 }
 
 grf_status grf_bc_fill(const grf_bc* bc, const grf_box* box, double* u, hipStream_t stream) {
-  grf_status s = check_box(box);
+  grf_status s = check_box3(box);
   if (s != GRF_OK) return s;
   if (!u) return fail(GRF_EINVAL, "u is null");
   BcDev d;
@@ -474,7 +497,7 @@ grf_status grf_bc_fill(const grf_bc* bc, const grf_box* box, double* u, hipStrea
 
 grf_status grf_bc_ghost_rhs(const grf_bc* bc, const grf_box* box, const double* u, double* rhs,
                             hipStream_t stream) {
-  grf_status s = check_box(box);
+  grf_status s = check_box3(box);
   if (s != GRF_OK) return s;
   if (!u || !rhs) return fail(GRF_EINVAL, "u/rhs is null");
   if (u == rhs) return fail(GRF_EINVAL, "rhs must not alias u");
@@ -487,7 +510,7 @@ grf_status grf_bc_ghost_rhs(const grf_bc* bc, const grf_box* box, const double* 
 grf_status grf_rk4_stage_bc(const grf_params* p, const grf_box* box, const grf_bc* bc, int stage, double dt,
                             const double* u0, const double* us, double* unext, double* acc, double* gacc,
                             void* workspace, size_t workspace_bytes, hipStream_t stream) {
-  grf_status s = check_box(box);
+  grf_status s = check_box3(box);
   if (s != GRF_OK) return s;
   BcDev d;
   if ((s = make_bcdev(bc, box, true, d)) != GRF_OK) return s;
@@ -525,7 +548,7 @@ static grf_status diagnostics(int which, const grf_params* p, const grf_box* box
   grf_point_params pp = make_pp(p);
   double* D = (double*)((char*)workspace + kStatusBytes);
   GRF_HIP_CHECK(launch_deriv_p(p, bd, u, D, p->shift_advec != 0.0, stream));
-  GRF_HIP_CHECK(launch_constraints(which, bd, pp, u, D, out, stream));
+  GRF_HIP_CHECK(launch_constraints(which, bd, pp, u + interior_shift(bd), D, out, stream));
   return GRF_OK;
 }
 
@@ -550,7 +573,7 @@ grf_status grf_enforce(const grf_params* p, const grf_box* box, double* u, hipSt
   if ((s = check_box(box)) != GRF_OK) return s;
   if (!u) return fail(GRF_EINVAL, "u is null");
   BoxDev bd = make_boxdev(box);
-  GRF_HIP_CHECK(launch_enforce(bd, u, p->chi_min, p->lapse_min, stream));
+  GRF_HIP_CHECK(launch_enforce(bd, u + interior_shift(bd), p->chi_min, p->lapse_min, stream));
   return GRF_OK;
 }
 
@@ -579,7 +602,7 @@ VjpLayout vjp_layout(const grf_box* b) {
 extern "C" {
 
 size_t grf_vjp_workspace_bytes(const grf_box* box) {
-  if (check_box(box) != GRF_OK) return 0;
+  if (check_box3(box) != GRF_OK) return 0;
   return vjp_layout(box).total;
 }
 
@@ -587,7 +610,7 @@ grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u,
                        double* theta_bar, void* workspace, size_t workspace_bytes, hipStream_t stream) {
   grf_status s = check_params(p);
   if (s != GRF_OK) return s;
-  s = check_box(box);
+  s = check_box3(box);
   if (s != GRF_OK) return s;
   if (!u || !w || !u_bar || !theta_bar || !workspace) return fail(GRF_EINVAL, "null pointer");
   if (p->decoupled) return fail(GRF_EUNSUPPORTED, "the adjoint of the decoupling limit is not implemented");
@@ -614,7 +637,7 @@ grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u,
 }
 
 size_t grf_rk4_step_vjp_workspace_bytes(const grf_box* box) {
-  if (check_box(box) != GRF_OK) return 0;
+  if (check_box3(box) != GRF_OK) return 0;
   const size_t state = (size_t)NF * box->field_stride * 8;
   return vjp_layout(box).total + 2 * ((state + 255) / 256 * 256);
 }
@@ -624,7 +647,7 @@ grf_status grf_rk4_step_vjp(const grf_params* p, const grf_box* box, double dt, 
                             double* theta_bar, void* workspace, size_t workspace_bytes, hipStream_t stream) {
   grf_status s = check_params(p);
   if (s != GRF_OK) return s;
-  s = check_box(box);
+  s = check_box3(box);
   if (s != GRF_OK) return s;
   if (box->bc != GRF_BC_FROZEN) return fail(GRF_EUNSUPPORTED, "the step adjoint is implemented for frozen ghosts");
   if (p->decoupled) return fail(GRF_EUNSUPPORTED, "the adjoint of the decoupling limit is not implemented");
@@ -738,7 +761,7 @@ size_t grf_batch_scratch_bytes(const grf_box* boxes, int nboxes) {
   if (!boxes || nboxes < 1) return 0;
   size_t tot = 0;
   for (int b = 0; b < nboxes; ++b) {
-    if (check_box(&boxes[b]) != GRF_OK) return 0;
+    if (check_box3(&boxes[b]) != GRF_OK) return 0;
     const size_t n = (size_t)boxes[b].nx * boxes[b].ny * boxes[b].nz;
     const size_t state = (size_t)NF * boxes[b].field_stride * 8;
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };
@@ -758,7 +781,7 @@ grf_status grf_batch_create(const grf_params* p, const grf_box* boxes, int nboxe
   if (p->fd_order == 6) return fail(GRF_EUNSUPPORTED, "the batched form uses the fourth-order stencils only");
   if (!boxes || nboxes < 1 || !u || !dts || !out || !scratch) return fail(GRF_EINVAL, "null argument");
   for (int b = 0; b < nboxes; ++b) {
-    if ((s = check_box(&boxes[b])) != GRF_OK) return s;
+    if ((s = check_box3(&boxes[b])) != GRF_OK) return s;
     if (boxes[b].bc != GRF_BC_FROZEN) return fail(GRF_EUNSUPPORTED, "batched boxes use frozen ghosts");
     if (!u[b]) return fail(GRF_EINVAL, "null state of box %d", b);
     if (!std::isfinite(dts[b])) return fail(GRF_EINVAL, "dt of box %d not finite", b);

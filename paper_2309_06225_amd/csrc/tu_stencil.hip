@@ -13,18 +13,19 @@ namespace grf {
 // everything), so that edges and corners end up congruent to interior cells.
 __global__ void k_periodic(BoxDev b, double* __restrict__ u, int axis) {
   const int n[3] = {b.nx, b.ny, b.nz};
+  const int g = b.ng;
   // extents of the ghost slab of this axis in state coordinates
   int ext[3], off[3];
   for (int d = 0; d < 3; ++d) {
     if (d == axis) {
-      ext[d] = 6;
+      ext[d] = 2 * g;
       off[d] = 0;
     } else if (d < axis) {
-      ext[d] = n[d] + 6;
+      ext[d] = n[d] + 2 * g;
       off[d] = 0;
     } else {
       ext[d] = n[d];
-      off[d] = 3;
+      off[d] = g;
     }
   }
   const int64_t total = (int64_t)ext[0] * ext[1] * ext[2];
@@ -41,9 +42,9 @@ __global__ void k_periodic(BoxDev b, double* __restrict__ u, int axis) {
   for (int d = 0; d < 3; ++d) {
     int v = x[d] + off[d];
     if (d == axis) {
-      const int g = x[d];                 // 0..5
-      v = g < 3 ? g : n[d] + g;           // ghost state coordinate
-      src[d] = (((v - 3) % n[d]) + n[d]) % n[d] + 3;  // congruent interior cell
+      const int q = x[d];                 // 0 .. 2g-1
+      v = q < g ? q : n[d] + q;           // ghost state coordinate
+      src[d] = (((v - g) % n[d]) + n[d]) % n[d] + g;  // congruent interior cell
       x[d] = v;
     } else {
       x[d] = v;
@@ -172,17 +173,18 @@ hipError_t launch_deriv_t(const BoxDev& bd, const double* u, double* D, double s
   return hipGetLastError();
 }
 
-template <int TX, int TY, int ZC, bool XCDMAP, int ORD = 4>
+template <int TX, int TY, int ZC, bool XCDMAP, int ORD = 4, int H = 3>
 hipError_t launch_deriv_zm_t(const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
                              hipStream_t st) {
   const int64_t items = (int64_t)((bd.nx + TX - 1) / TX) * ((bd.ny + TY - 1) / TY) * ((bd.nz + ZC - 1) / ZC) * NF;
-  hipLaunchKernelGGL((k_deriv_zm<TX, TY, ZC, XCDMAP, ORD>), dim3((unsigned)items), dim3(TX * TY), 0, st, bd, u, D,
-                     sigma, sa, UP);
+  hipLaunchKernelGGL((k_deriv_zm<TX, TY, ZC, XCDMAP, ORD, H>), dim3((unsigned)items), dim3(TX * TY), 0, st, bd, u,
+                     D, sigma, sa, UP);
   return hipGetLastError();
 }
 
 hipError_t launch_deriv6(const BoxDev& bd, const double* u, double* D, double sigma, int sa, hipStream_t st) {
   // the 128x8 column measured slower here (11.9 against 10.1 ms per 128^3 step)
+  if (bd.ng == 4) return launch_deriv_zm_t<32, 8, 32, true, 6, 4>(bd, u, D, sigma, sa, nullptr, st);
   return launch_deriv_zm_t<32, 8, 32, true, 6>(bd, u, D, sigma, sa, nullptr, st);
 }
 
@@ -285,9 +287,9 @@ hipError_t launch_deriv_batch(int variant, int grid, const BatchBoxDev* boxes, c
 hipError_t launch_periodic(const BoxDev& bd, double* u, hipStream_t st) {
   const int n[3] = {bd.nx, bd.ny, bd.nz};
   for (int axis = 0; axis < 3; ++axis) {
-    int64_t cells = 6;
+    int64_t cells = 2 * bd.ng;
     for (int d = 0; d < 3; ++d)
-      if (d != axis) cells *= (d < axis) ? (n[d] + 6) : n[d];
+      if (d != axis) cells *= (d < axis) ? (n[d] + 2 * bd.ng) : n[d];
     const int64_t total = cells * NF;
     hipLaunchKernelGGL(k_periodic, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, bd, u, axis);
     hipError_t e = hipGetLastError();

@@ -142,17 +142,20 @@ def make_params(p: dict | None = None, **over) -> Params:
                   beta=float(d.get("beta", 0.0)))
 
 
-def make_box(dims, dx, bc=BC_FROZEN, origin=(0.0, 0.0, 0.0)) -> Box:
+def make_box(dims, dx, bc=BC_FROZEN, origin=(0.0, 0.0, 0.0), ng=NG) -> Box:
+    """ng: ghost layers, 3, or 4 for the sixth-order scheme with its
+    eighth-difference dissipation."""
     nx, ny, nz = dims
     if not isinstance(dx, (tuple, list)):
         dx = (dx, dx, dx)
-    return Box(nx=nx, ny=ny, nz=nz, ng=NG, dx=dx[0], dy=dx[1], dz=dx[2], x0=origin[0], y0=origin[1],
-               z0=origin[2], field_stride=(nx + 6) * (ny + 6) * (nz + 6), bc=bc)
+    e = 2 * ng
+    return Box(nx=nx, ny=ny, nz=nz, ng=ng, dx=dx[0], dy=dx[1], dz=dx[2], x0=origin[0], y0=origin[1],
+               z0=origin[2], field_stride=(nx + e) * (ny + e) * (nz + e), bc=bc)
 
 
-def box_of(u: torch.Tensor, dx, bc=BC_FROZEN, origin=(0.0, 0.0, 0.0)) -> Box:
-    nz, ny, nx = (s - 2 * NG for s in u.shape[1:])
-    return make_box((nx, ny, nz), dx, bc, origin)
+def box_of(u: torch.Tensor, dx, bc=BC_FROZEN, origin=(0.0, 0.0, 0.0), ng=NG) -> Box:
+    nz, ny, nx = (s - 2 * ng for s in u.shape[1:])
+    return make_box((nx, ny, nz), dx, bc, origin, ng)
 
 
 class BC(ctypes.Structure):

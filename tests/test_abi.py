@@ -38,6 +38,17 @@ def test_host_side_validation_without_device():
     assert code != 0
     assert b"null" in L.grf_last_error() or b"workspace" in L.grf_last_error()
     assert L.grf_flops_per_cell(0) > 1000
+    # four ghost layers: a valid shape, but only for the sixth-order scheme
+    box4 = G.make_box((8, 8, 8), 0.25, ng=4)
+    assert L.grf_workspace_bytes(ctypes.byref(box4)) == L.grf_workspace_bytes(ctypes.byref(box))
+    assert L.grf_vjp_workspace_bytes(ctypes.byref(box4)) == 0
+    code = L.grf_rhs_eval(ctypes.byref(p), ctypes.byref(box4), None, None, None, 0, None)
+    assert code == 7 and b"fd_order 6" in L.grf_last_error()
+    bad.ng = 5
+    assert L.grf_workspace_bytes(ctypes.byref(bad)) == 0
+    short = G.make_box((8, 8, 8), 0.25, ng=4)
+    short.field_stride = 14 ** 3
+    assert L.grf_workspace_bytes(ctypes.byref(short)) == 0
 
 
 def test_boundary_rules_rejected_on_the_host():

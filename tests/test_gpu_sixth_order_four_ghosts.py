@@ -1,0 +1,223 @@
+"""The sixth-order scheme on boxes with four ghost layers on the GPU against
+the oracle: there the advection stencil is of order 6 (offsets -2..4 and
+mirror) and the Kreiss-Oliger term is the eighth difference, so the scheme
+keeps order 6 with dissipation on.  One right-hand side on both split paths,
+sampled cells of the 128^3 box, RK4 steps with periodic and frozen ghosts,
+constraints, enforcement, the measured order, and the refused paths."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import oracle as O
+from paper_2309_06225_amd import grf as G
+from paper_2309_06225_amd import inputs as I
+from parity_util import rel_err_per_field
+from test_oracle_pins import _smooth_periodic_2d
+
+DEV = "cuda"
+NG4 = 4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    O.build(force=False)
+    G.lib()
+
+
+def _p6(**over):
+    return I.default_params(fd_order=6.0, **over)
+
+
+def gpu_rhs(params, u, dx, bc=G.BC_FROZEN, path=None):
+    ut = torch.from_numpy(u).to(DEV)
+    box = G.box_of(ut, dx, bc, ng=NG4)
+    ws = G.alloc_workspace(G.workspace_bytes(box))
+    out = torch.zeros_like(ut)
+    p0 = G.get_stage_path()
+    if path is not None:
+        G.set_stage_path(path)
+    try:
+        G.rhs_eval(G.make_params(params), box, ut, out, ws)
+        code, bits = G.status_fetch(ws)
+    finally:
+        G.set_stage_path(p0)
+    return out.cpu().numpy(), code, bits
+
+
+def _err(g, o):
+    return rel_err_per_field(g, o, ng=NG4)
+
+
+@pytest.mark.parametrize("shift_advec", [0.0, 1.0])
+def test_rhs_parity_periodic_noise(shift_advec):
+    print("case: sixth order, four ghosts, rhs noise 32^3, shift_advec", shift_advec, flush=True)
+    p = _p6(shift_advec=shift_advec, lambda_gb=0.3, g2=0.05)
+    u = I.flat_noise_pulse(32, 0.25, seed=0, ng=NG4)
+    u[I.IDX["shift1"]] += 1e-3 * np.sin(np.arange(u.shape[-1]))[None, None, :]
+    u[I.IDX["shift2"]] -= 1e-3 * np.cos(np.arange(u.shape[-2]))[None, :, None]
+    u = I.wrap_ghosts(u, NG4)
+    o, fo = O.rhs(I.params_vector(p), u, 0.25, ng=NG4)
+    assert fo == 0
+    for path in (0, 2):
+        g, code, bits = gpu_rhs(p, u, 0.25, G.BC_PERIODIC, path)
+        assert code == 0 and bits == 0
+        e = _err(g, o)
+        assert e.max() <= 1e-12, (path, dict(zip(I.FIELDS, e)))
+        # the ghosts of the result are not written
+        assert np.all(g[:, :NG4] == 0.0) and np.all(g[..., -NG4:] == 0.0)
+
+
+def test_rhs_parity_puncture_ragged():
+    print("case: sixth order, four ghosts, rhs puncture 21x17x13", flush=True)
+    p = _p6(lambda_gb=0.3, g2=0.05)
+    dims, dx = (21, 17, 13), 0.3
+    u = I.puncture(dims, dx, centre=(0.4, -0.2, 0.1), phi_fn=I.shell_pulse(0.1, 2.0), ng=NG4)
+    rng = np.random.default_rng(4)
+    u[I.IDX["shift1"]:I.IDX["shift3"] + 1] += 0.01 * rng.standard_normal(u[19:22].shape)
+    u[I.IDX["K"]] += 0.01 * rng.standard_normal(u[7].shape)
+    o, _ = O.rhs(I.params_vector(p), u, dx, ng=NG4)
+    g, code, _ = gpu_rhs(p, u, dx)
+    assert code == 0
+    e = _err(g, o)
+    assert e.max() <= 1e-12, dict(zip(I.FIELDS, e))
+    # the same interior on three ghost layers gives another result (advection
+    # and dissipation differ)
+    u3 = u[:, 1:-1, 1:-1, 1:-1].copy()
+    ut3 = torch.from_numpy(u3).to(DEV)
+    box3 = G.box_of(ut3, dx)
+    ws3 = G.alloc_workspace(G.workspace_bytes(box3))
+    out3 = torch.zeros_like(ut3)
+    G.rhs_eval(G.make_params(p), box3, ut3, out3, ws3)
+    g3 = out3.cpu().numpy()
+    assert np.abs(I.interior(g3) - I.interior(g, NG4)).max() > 1e-8
+
+
+def test_rhs_parity_full_size_sampled():
+    print("case: sixth order, four ghosts, rhs single puncture 128^3 sampled", flush=True)
+    p = _p6(shift_advec=1.0)
+    u = I.single_puncture(128, 1.0 / 8.0, ng=NG4)
+    rng = np.random.default_rng(31)
+    u[I.IDX["shift1"]:I.IDX["shift3"] + 1] += 0.01 * rng.standard_normal(u[19:22].shape)
+    g, code, _ = gpu_rhs(p, u, 1.0 / 8.0)
+    assert code == 0
+    cells = rng.integers(0, 128, size=(2000, 3))
+    cells = np.concatenate([cells, np.array([[63, 63, 63], [64, 64, 64], [0, 0, 0], [127, 127, 127]])])
+    o, _ = O.rhs_cells(I.params_vector(p), u, 1.0 / 8.0, cells, ng=NG4)
+    gs = g[:, cells[:, 2] + NG4, cells[:, 1] + NG4, cells[:, 0] + NG4].T
+    num = np.abs(gs - o).max(axis=0)
+    den = np.abs(o).max(axis=0)
+    den = np.where(den > 0, den, den.max())
+    assert (num / den).max() <= 1e-12, dict(zip(I.FIELDS, num / den))
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_rk4_ten_steps(periodic):
+    print("case: sixth order, four ghosts, 10 RK4 steps 24^3, periodic", periodic, flush=True)
+    p = _p6(lambda_gb=0.2, g2=0.02, shift_advec=1.0)
+    if periodic:
+        u = I.flat_noise_pulse(24, 0.25, seed=2, noise=1e-4, ng=NG4)
+        bc = G.BC_PERIODIC
+    else:
+        u = I.single_puncture(24, 0.25, ng=NG4)
+        bc = G.BC_FROZEN
+    o, flags = O.rk4(I.params_vector(p), u, 0.25, 0.0625, 10, periodic=periodic, ng=NG4)
+    assert flags == 0
+    ut = torch.from_numpy(u).to(DEV)
+    st = G.Stepper(G.make_params(p), G.box_of(ut, 0.25, bc, ng=NG4), ut, 0.0625)
+    for _ in range(10):
+        st.step()
+    assert st.status() == (0, 0)
+    e = rel_err_per_field(st.u.cpu().numpy(), o, interior=False)
+    assert e.max() <= 1e-10, dict(zip(I.FIELDS, e))
+
+
+def test_fill_periodic_four_layers():
+    u = I.flat_noise_pulse(9, 0.5, seed=3, noise=1e-3, ng=NG4)
+    u[:, :NG4] = 0.0
+    u[..., -NG4:] = 0.0
+    ut = torch.from_numpy(u).to(DEV)
+    G.fill_periodic(G.box_of(ut, 0.5, G.BC_PERIODIC, ng=NG4), ut)
+    assert np.array_equal(ut.cpu().numpy(), I.wrap_ghosts(u, NG4))
+
+
+def test_constraints_and_enforcement():
+    print("case: sixth order, four ghosts, constraints and enforcement", flush=True)
+    p = _p6(lambda_gb=0.3, g2=0.05)
+    dx = 0.3
+    u = I.puncture((21, 17, 13), dx, centre=(0.4, -0.2, 0.1), phi_fn=I.shell_pulse(0.1, 2.0), ng=NG4)
+    ho, mo = O.constraints(I.params_vector(p), u, dx, ng=NG4)
+    ut = torch.from_numpy(u).to(DEV)
+    box = G.box_of(ut, dx, ng=NG4)
+    ws = G.alloc_workspace(G.workspace_bytes(box))
+    hg, mg = G.constraints(G.make_params(p), box, ut, ws)
+    hg, mg = hg.cpu().numpy(), mg.cpu().numpy()
+    assert np.abs(hg - ho).max() <= 1e-12 * np.abs(ho).max()
+    for d in range(3):
+        assert np.abs(mg[d] - mo[d]).max() <= 1e-12 * np.abs(mo[d]).max()
+    rng = np.random.default_rng(8)
+    v = u.copy()
+    v[1:14] += 0.05 * rng.standard_normal(v[1:14].shape)
+    v[0] -= 0.5
+    q = dict(p, enforce=1, chi_min=1e-4, lapse_min=1e-3)
+    oe = O.enforce(v, 1e-4, 1e-3, ng=NG4)
+    vt = torch.from_numpy(v).to(DEV)
+    G.enforce(G.make_params(q), G.box_of(vt, dx, ng=NG4), vt)
+    e = rel_err_per_field(vt.cpu().numpy(), oe, interior=False)
+    assert e.max() <= 1e-14, dict(zip(I.FIELDS, e))
+    # ghosts untouched
+    assert np.array_equal(vt.cpu().numpy()[:, :NG4], v[:, :NG4])
+
+
+def test_gpu_rhs_converges_at_sixth_order_with_dissipation():
+    """With four ghost layers the GPU right-hand side of smooth periodic data
+    converges at sixth order with the shift and the dissipation on."""
+    print("case: sixth order, four ghosts, spatial convergence on the GPU", flush=True)
+    L = 8.0
+    p = _p6(ko_sigma=0.3, lambda_gb=0.2, g2=0.05)
+    modes = [(0, 0), (1, 0), (1, 2), (2, -1)]
+    coefs = []
+    for n in (16, 32, 64):
+        u, dx = _smooth_periodic_2d(n, L, True, NG4)
+        r, code, _ = gpu_rhs(p, u, dx, G.BC_PERIODIC)
+        assert code == 0
+        X, Y, _ = I.coords((n, n, 4), dx, ng=NG4)
+        x, y = I.interior(X[None], NG4)[0], I.interior(Y[None], NG4)[0]
+        ri = I.interior(r, NG4)
+        kk = 2 * np.pi / L
+        coefs.append(np.array([[np.mean(ri[f] * np.exp(-1j * kk * (m * x + l * y))) for (m, l) in modes]
+                               for f in range(27)]))
+    c = np.array(coefs)
+    d1 = np.abs(c[0] - c[1]).max(axis=1)
+    d2 = np.abs(c[1] - c[2]).max(axis=1)
+    live = d2 > 1e-12 * np.abs(c[2]).max()
+    order_f = np.log2(d1[live] / d2[live])
+    assert 5.6 < np.median(order_f) < 6.4, order_f
+
+
+def test_four_ghost_layers_refused_elsewhere():
+    u = torch.from_numpy(I.single_puncture(12, 0.25, ng=NG4)).to(DEV)
+    box = G.box_of(u, 0.25, ng=NG4)
+    ws = G.alloc_workspace(G.workspace_bytes(box))
+    out = torch.zeros_like(u)
+    # the fourth-order scheme
+    with pytest.raises(G.GrfError) as e:
+        G.rhs_eval(G.make_params(I.default_params()), box, u, out, ws)
+    assert e.value.code == 7
+    p = G.make_params(_p6())
+    p0 = G.get_stage_path()
+    try:
+        G.set_stage_path(1)
+        with pytest.raises(G.GrfError):
+            G.rhs_eval(p, box, u, out, ws)
+    finally:
+        G.set_stage_path(p0)
+    with pytest.raises((G.GrfError, ValueError)):
+        G.Batch(p, [box], [u], [0.01])
+    with pytest.raises(G.GrfError) as e:
+        G.bc_fill(G.make_bc(["periodic"] * 6), box, u)
+    assert e.value.code == 7
+    assert G.vjp_workspace_bytes(box) == 0
