@@ -137,15 +137,15 @@ def constraints(params, u, dx, ng=NG):
     return ham[s], mom[(slice(0, 3),) + s]
 
 
-def energy_densities(params, u, dx):
+def energy_densities(params, u, dx, ng=NG):
     """Energy densities (3,nz,ny,nx) of the canonical, X^2 and Gauss-Bonnet
     terms of the action on the interior."""
     u = _c(u)
     rho = np.zeros((NF,) + u.shape[1:])  # only the first 3 fields are written
     p = _c(params)
-    dims = _dims(u)
+    dims = _dims(u, ng)
     lib().oracle_energy_densities(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(u), _d(rho))
-    s = (slice(NG, -NG),) * 3
+    s = (slice(ng, -ng),) * 3
     return rho[(slice(0, 3),) + s]
 
 
@@ -165,16 +165,16 @@ def pack_bc(bc):
     return np.array(v)
 
 
-def coupling(params, u, dx):
+def coupling(params, u, dx, ng=NG):
     """(4,nz,ny,nx) on the interior: the Gauss-Bonnet invariant, the
     weak-coupling indicators |lambda'(phi)| sqrt|L_GB| and |2 g2 X|, and the
     determinant of the per-cell system."""
     u = _c(u)
     out = np.zeros((NF,) + u.shape[1:])  # only the first 4 fields are written
     p = _c(params)
-    dims = _dims(u)
+    dims = _dims(u, ng)
     lib().oracle_coupling(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(u), _d(out))
-    s = (slice(NG, -NG),) * 3
+    s = (slice(ng, -ng),) * 3
     return out[(slice(0, 4),) + s]
 
 

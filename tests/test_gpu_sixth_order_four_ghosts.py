@@ -172,6 +172,40 @@ def test_constraints_and_enforcement():
     assert np.array_equal(vt.cpu().numpy()[:, :NG4], v[:, :NG4])
 
 
+@pytest.mark.parametrize("variant", ["decoupled", "general_coupling"])
+def test_rhs_parity_other_theories(variant):
+    """The decoupling limit and the general coupling run their own pointwise
+    code; on four ghost layers they take the same moved state."""
+    print("case: sixth order, four ghosts, rhs", variant, flush=True)
+    over = dict(decoupled=1.0) if variant == "decoupled" else dict(lambda_lin=0.15, beta=1.5)
+    p = _p6(lambda_gb=0.3, g2=0.05, shift_advec=1.0, **over)
+    dims, dx = (19, 13, 11), 0.3
+    u = I.puncture(dims, dx, centre=(0.2, 0.1, -0.3), phi_fn=I.shell_pulse(0.1, 2.0), ng=NG4)
+    rng = np.random.default_rng(12)
+    u[I.IDX["shift1"]:I.IDX["shift3"] + 1] += 0.01 * rng.standard_normal(u[19:22].shape)
+    o, _ = O.rhs(I.params_vector(p), u, dx, ng=NG4)
+    g, code, _ = gpu_rhs(p, u, dx)
+    assert code == 0
+    e = _err(g, o)
+    assert e.max() <= 1e-12, dict(zip(I.FIELDS, e))
+
+
+def test_energy_and_coupling_diagnostics():
+    print("case: sixth order, four ghosts, energy and coupling diagnostics", flush=True)
+    p = _p6(lambda_gb=0.3, g2=0.05)
+    dx = 0.3
+    u = I.puncture((17, 15, 13), dx, centre=(0.4, -0.2, 0.1), phi_fn=I.shell_pulse(0.1, 2.0), ng=NG4)
+    u[I.IDX["Pi"]] += 0.02
+    ut = torch.from_numpy(u).to(DEV)
+    box = G.box_of(ut, dx, ng=NG4)
+    ws = G.alloc_workspace(G.workspace_bytes(box))
+    for got, want in ((G.energy_densities(G.make_params(p), box, ut, ws), O.energy_densities(I.params_vector(p), u, dx, ng=NG4)),
+                      (G.coupling_diagnostics(G.make_params(p), box, ut, ws), O.coupling(I.params_vector(p), u, dx, ng=NG4))):
+        got = got.cpu().numpy()
+        for q in range(want.shape[0]):
+            assert np.abs(got[q] - want[q]).max() <= 1e-12 * max(np.abs(want[q]).max(), 1e-300), q
+
+
 def test_gpu_rhs_converges_at_sixth_order_with_dissipation():
     """With four ghost layers the GPU right-hand side of smooth periodic data
     converges at sixth order with the shift and the dissipation on."""
