@@ -114,11 +114,9 @@ typedef struct {
  * coordinates x0, y0, z0 of the centre of interior cell (0,0,0) (read by the
  * radiative boundary rule only), field_stride >= (nx+2ng)(ny+2ng)(nz+2ng),
  * boundary rule bc.  ng is 3, or 4 with fd_order 6 (GRF_EUNSUPPORTED with
- * fd_order 4); four ghost layers are accepted by grf_rhs_eval, grf_rk4_stage,
- * grf_fill_periodic, grf_enforce, grf_constraints, grf_energy_densities and
- * grf_coupling_diagnostics, and refused with GRF_EUNSUPPORTED by the boundary
- * rules, the batched form and the adjoint (whose size queries return 0);
- * GRF_ESHAPE for any other ng. */
+ * fd_order 4); the batched form and the adjoint refuse four ghost layers with
+ * GRF_EUNSUPPORTED (their size queries return 0), every other call takes
+ * them; GRF_ESHAPE for any other ng. */
 typedef struct {
   int32_t nx, ny, nz, ng;
   double dx, dy, dz;
@@ -196,7 +194,7 @@ typedef struct {
   double asymptote[27];    /* f_inf per field (finite) */
 } grf_bc;
 
-/* Number of ghost cells of a box ((nx+6)(ny+6)(nz+6) - nx ny nz); the ghost
+/* Number of ghost cells of a box ((nx+2ng)(ny+2ng)(nz+2ng) - nx ny nz); the ghost
  * accumulator of grf_rk4_stage_bc holds 27 times as many doubles.  0 for an
  * invalid box. */
 int64_t grf_bc_ghost_cells(const grf_box* box);
@@ -205,8 +203,8 @@ int64_t grf_bc_ghost_cells(const grf_box* box);
  * (device, state layout) from u; other ghosts and the interior untouched.
  * Errors: GRF_EINVAL for an invalid rule, an unpaired periodic face, an
  * extrapolation order other than 0/1, a parity other than +-1, a reflective
- * face on an axis with fewer than 3 cells or an order-1 extrapolating face on
- * one with fewer than 2. */
+ * face on an axis with fewer cells than ghost layers or an order-1
+ * extrapolating face on one with fewer than 2. */
 grf_status grf_bc_fill(const grf_bc* bc, const grf_box* box, double* u, hipStream_t stream);
 
 /* Ghost right-hand side: every ghost cell of rhs (device, state layout) gets

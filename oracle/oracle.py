@@ -178,29 +178,29 @@ def coupling(params, u, dx, ng=NG):
     return out[(slice(0, 4),) + s]
 
 
-def fill_bc(u, dx, bc):
+def fill_bc(u, dx, bc, ng=NG):
     """Ghosts of periodic, reflective and extrapolating faces refilled (new state)."""
     u = _c(u).copy()
-    dims = _dims(u)
+    dims = _dims(u, ng)
     lib().oracle_fill_bc(dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(pack_bc(bc)), _d(u))
     return u
 
 
-def ghost_rhs(u, dx, bc):
+def ghost_rhs(u, dx, bc, ng=NG):
     """Right-hand side in the ghost cells (radiative on Sommerfeld faces, 0 on
     the others); interior cells are 0."""
     u = _c(u)
     r = np.zeros_like(u)
-    dims = _dims(u)
+    dims = _dims(u, ng)
     lib().oracle_ghost_rhs(dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(pack_bc(bc)), _d(u), _d(r))
     return r
 
 
-def rk4_bc(params, u, dx, dt, nsteps, bc):
+def rk4_bc(params, u, dx, dt, nsteps, bc, ng=NG):
     """nsteps classic RK4 steps with per-face boundary rules; (state, flags)."""
     u = _c(u).copy()
     p = _c(params)
-    dims = _dims(u)
+    dims = _dims(u, ng)
     flags = lib().oracle_rk4_bc(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(pack_bc(bc)), float(dt),
                                 int(nsteps), _d(u))
     return u, flags

@@ -59,8 +59,7 @@ grf_status check_box3(const grf_box* b) {
   grf_status s = check_box(b);
   if (s != GRF_OK) return s;
   if (b->ng != 3)
-    return fail(GRF_EUNSUPPORTED, "four ghost layers are supported by grf_rhs_eval, grf_rk4_stage, "
-                                  "grf_fill_periodic, grf_enforce and the diagnostics only");
+    return fail(GRF_EUNSUPPORTED, "four ghost layers are not supported by the batched form and the adjoint");
   return GRF_OK;
 }
 
@@ -438,7 +437,8 @@ static grf_status make_bcdev(const grf_bc* bc, const grf_box* box, bool radiativ
     const int axis = f / 2;
     if (r == GRF_FACE_PERIODIC && bc->rule[f ^ 1] != GRF_FACE_PERIODIC)
       return fail(GRF_EINVAL, "face %d: periodic faces come in pairs", f);
-    if (r == GRF_FACE_REFLECTIVE && n[axis] < 3) return fail(GRF_EINVAL, "face %d: reflective needs >= 3 cells", f);
+    if (r == GRF_FACE_REFLECTIVE && n[axis] < box->ng)
+      return fail(GRF_EINVAL, "face %d: reflective needs >= %d cells (the ghost count)", f, box->ng);
     if (r == GRF_FACE_EXTRAPOLATING && bc->extrap_order == 1 && n[axis] < 2)
       return fail(GRF_EINVAL, "face %d: linear extrapolation needs >= 2 cells", f);
     d.rule[f] = r;
@@ -472,7 +472,7 @@ static grf_status make_bcdev(const grf_bc* bc, const grf_box* box, bool radiativ
     for (int a = 0; a < 3; ++a) {
       const double t = (bc->centre[a] - origin[a]) / h[a];
       const double m = std::nearbyint(t);
-      on_cell &= std::fabs(t - m) < 1e-9 && m >= -3.0 && m <= n[a] + 2.0;
+      on_cell &= std::fabs(t - m) < 1e-9 && m >= -(double)box->ng && m <= n[a] + box->ng - 1.0;
       ghost |= m < 0.0 || m >= n[a];
     }
     if (on_cell && ghost) return fail(GRF_EINVAL, "the radiative centre is a ghost cell centre");
@@ -481,12 +481,12 @@ static grf_status make_bcdev(const grf_bc* bc, const grf_box* box, bool radiativ
 }
 
 int64_t grf_bc_ghost_cells(const grf_box* box) {
-  if (check_box3(box) != GRF_OK) return 0;
+  if (check_box(box) != GRF_OK) return 0;
   return ghost_cells(make_boxdev(box));
 }
 
 grf_status grf_bc_fill(const grf_bc* bc, const grf_box* box, double* u, hipStream_t stream) {
-  grf_status s = check_box3(box);
+  grf_status s = check_box(box);
   if (s != GRF_OK) return s;
   if (!u) return fail(GRF_EINVAL, "u is null");
   BcDev d;
@@ -497,7 +497,7 @@ grf_status grf_bc_fill(const grf_bc* bc, const grf_box* box, double* u, hipStrea
 
 grf_status grf_bc_ghost_rhs(const grf_bc* bc, const grf_box* box, const double* u, double* rhs,
                             hipStream_t stream) {
-  grf_status s = check_box3(box);
+  grf_status s = check_box(box);
   if (s != GRF_OK) return s;
   if (!u || !rhs) return fail(GRF_EINVAL, "u/rhs is null");
   if (u == rhs) return fail(GRF_EINVAL, "rhs must not alias u");
@@ -510,7 +510,7 @@ grf_status grf_bc_ghost_rhs(const grf_bc* bc, const grf_box* box, const double* 
 grf_status grf_rk4_stage_bc(const grf_params* p, const grf_box* box, const grf_bc* bc, int stage, double dt,
                             const double* u0, const double* us, double* unext, double* acc, double* gacc,
                             void* workspace, size_t workspace_bytes, hipStream_t stream) {
-  grf_status s = check_box3(box);
+  grf_status s = check_box(box);
   if (s != GRF_OK) return s;
   BcDev d;
   if ((s = make_bcdev(bc, box, true, d)) != GRF_OK) return s;

@@ -16,34 +16,36 @@ namespace grf {
 #pragma clang fp contract(off)
 
 // Ghost region of one axis's two faces in state coordinates (cell offsets from
-// the first ghost): the axis itself spans its 6 ghost layers; lower axes (which
-// own their own ghosts) span only the interior, higher axes span everything.
+// the first ghost): the axis itself spans its 2 ng ghost layers; lower axes
+// (which own their own ghosts) span only the interior, higher axes span
+// everything.
 struct Slab {
   int ext[3];  // extents along x, y, z
-  int off[3];  // first coordinate (0 = outermost ghost, 3 = first interior cell)
+  int off[3];  // first coordinate (0 = outermost ghost, ng = first interior cell)
   __host__ __device__ int64_t count() const { return (int64_t)ext[0] * ext[1] * ext[2]; }
 };
 
 __host__ __device__ inline Slab slab_of(const BoxDev& b, int axis) {
   const int n[3] = {b.nx, b.ny, b.nz};
+  const int g = b.ng;
   Slab s;
   for (int d = 0; d < 3; ++d) {
     if (d == axis) {
-      s.ext[d] = 6;
+      s.ext[d] = 2 * g;
       s.off[d] = 0;
     } else if (d < axis) {
       s.ext[d] = n[d];
-      s.off[d] = 3;
+      s.off[d] = g;
     } else {
-      s.ext[d] = n[d] + 6;
+      s.ext[d] = n[d] + 2 * g;
       s.off[d] = 0;
     }
   }
   return s;
 }
 
-// state coordinates (0 .. n+5) of element e of the slab; the axis's ghost
-// layers 0..5 map to 0,1,2 (low face) and n+3..n+5 (high face)
+// state coordinates (0 .. n+2ng-1) of element e of the slab; the axis's ghost
+// layers 0..2ng-1 map to 0..ng-1 (low face) and n+ng..n+2ng-1 (high face)
 __device__ __forceinline__ void slab_cell(const BoxDev& b, const Slab& s, int axis, int64_t e, int x[3]) {
   const int n[3] = {b.nx, b.ny, b.nz};
   int64_t r = e;
@@ -51,7 +53,7 @@ __device__ __forceinline__ void slab_cell(const BoxDev& b, const Slab& s, int ax
     const int v = (int)(r % s.ext[d]);
     r /= s.ext[d];
     x[d] = s.off[d] + v;
-    if (d == axis && v >= 3) x[d] = n[d] + v;  // 3,4,5 -> n+3, n+4, n+5
+    if (d == axis && v >= b.ng) x[d] = n[d] + v;  // ng .. 2ng-1 -> n+ng .. n+2ng-1
   }
 }
 
@@ -69,7 +71,7 @@ __global__ __launch_bounds__(256) void k_bc_fill(BoxDev b, BcDev bc, int axis, d
   int x[3];
   slab_cell(b, s, axis, e, x);
   const int n = axis == 0 ? b.nx : axis == 1 ? b.ny : b.nz;
-  const int m = x[axis] - 3;  // interior index along the axis (negative on the low face)
+  const int m = x[axis] - b.ng;  // interior index along the axis (negative on the low face)
   const bool low = m < 0;
   const int rule = bc.rule[2 * axis + (low ? 0 : 1)];
   if (rule != GRF_FACE_PERIODIC && rule != GRF_FACE_REFLECTIVE && rule != GRF_FACE_EXTRAPOLATING) return;
@@ -112,13 +114,13 @@ __device__ __forceinline__ void sommerfeld_cell(const BoxDev& b, const BcDev& bc
   double rel[3];
   double r2 = 0.0;
   for (int a = 0; a < 3; ++a) {
-    rel[a] = bc.origin[a] + (double)(x[a] - 3) * bc.h[a] - bc.centre[a];
+    rel[a] = bc.origin[a] + (double)(x[a] - b.ng) * bc.h[a] - bc.centre[a];
     r2 += rel[a] * rel[a];
   }
   const double inv_r = 1.0 / sqrt(r2);
   // per axis: stencil kind and weights on (c, c + dir step, c + 2 dir step)
   int kind[3];
-  for (int a = 0; a < 3; ++a) kind[a] = x[a] < 3 ? -1 : (x[a] >= n[a] + 3 ? 1 : 0);
+  for (int a = 0; a < 3; ++a) kind[a] = x[a] < b.ng ? -1 : (x[a] >= n[a] + b.ng ? 1 : 0);
   for (int f = 0; f < NF; ++f) {
     const double* uf = us + (int64_t)f * b.fs;
     const double val = uf[c];
@@ -178,7 +180,7 @@ __global__ __launch_bounds__(256) void k_bc_ghost(BoxDev b, BcDev bc, const doub
   }
   int x[3];
   slab_cell(b, axis == 0 ? s0 : axis == 1 ? s1 : s2, axis, e, x);
-  const bool low = x[axis] < 3;
+  const bool low = x[axis] < b.ng;
   const int rule = bc.rule[2 * axis + (low ? 0 : 1)];
   if (rule == GRF_FACE_SOMMERFELD) {
     sommerfeld_cell<MODE>(b, bc, x, g, nghost, us, u0, out, gacc, sc);

@@ -3,7 +3,8 @@ the oracle: there the advection stencil is of order 6 (offsets -2..4 and
 mirror) and the Kreiss-Oliger term is the eighth difference, so the scheme
 keeps order 6 with dissipation on.  One right-hand side on both split paths,
 sampled cells of the 128^3 box, RK4 steps with periodic and frozen ghosts,
-constraints, enforcement, the measured order, and the refused paths."""
+constraints, enforcement, the per-face boundary rules, the measured order,
+and the refused paths."""
 import numpy as np
 import pytest
 
@@ -15,6 +16,7 @@ from paper_2309_06225_amd import grf as G
 from paper_2309_06225_amd import inputs as I
 from parity_util import rel_err_per_field
 from test_oracle_pins import _smooth_periodic_2d
+from test_gpu_bc import FILL_CASES, FLAT, STEP_CASES
 
 DEV = "cuda"
 NG4 = 4
@@ -232,6 +234,60 @@ def test_gpu_rhs_converges_at_sixth_order_with_dissipation():
     assert 5.6 < np.median(order_f) < 6.4, order_f
 
 
+@pytest.mark.parametrize("dims", [(5, 7, 4), (16, 9, 11)])
+@pytest.mark.parametrize("case", sorted(FILL_CASES))
+def test_bc_fill_bitwise_against_oracle(case, dims):
+    print("case: four ghosts, fill", case, dims, flush=True)
+    bc = FILL_CASES[case]
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal((I.NF, dims[2] + 2 * NG4, dims[1] + 2 * NG4, dims[0] + 2 * NG4))
+    want = O.fill_bc(u, 0.25, bc, ng=NG4)
+    ut = torch.from_numpy(u).to(DEV)
+    G.bc_fill(G.make_bc(**bc), G.box_of(ut, 0.25, ng=NG4), ut)
+    assert np.array_equal(ut.cpu().numpy(), want)
+
+
+def test_bc_ghost_rhs_against_oracle():
+    print("case: four ghosts, radiative ghost rhs", flush=True)
+    dims, h = (12, 9, 7), 0.25
+    origin = (-0.5 * dims[0] * h + 0.5 * h, -0.5 * dims[1] * h + 0.5 * h + 0.1, -0.5 * dims[2] * h + 0.5 * h)
+    X, Y, Z = I.coords(dims, h, ng=NG4)
+    rng = np.random.default_rng(2)
+    u = I.set_flat(I.empty_state(dims, NG4))
+    for f in range(I.NF):
+        a = 0.1 * rng.standard_normal(4)
+        u[f] += a[0] * np.sin(0.3 * X + a[1]) * np.cos(0.2 * Y - a[2]) + a[3] * np.exp(-0.01 * (X * X + Z * Z))
+    bc = dict(rules=["sommerfeld", "sommerfeld", "reflective", "sommerfeld", "frozen", "sommerfeld"],
+              centre=(0.05, -0.02, 0.01), speed=0.5 + rng.random(I.NF), asymptote=FLAT, origin=origin)
+    want = O.ghost_rhs(u, h, bc, ng=NG4)
+    ut = torch.from_numpy(u).to(DEV)
+    got = G.bc_ghost_rhs(G.make_bc(**bc), G.box_of(ut, h, origin=origin, ng=NG4), ut).cpu().numpy()
+    scale = np.abs(want).max(axis=(1, 2, 3))
+    err = np.abs(got - want).max(axis=(1, 2, 3)) / scale
+    assert err.max() <= 1e-13, err
+
+
+@pytest.mark.parametrize("case", sorted(STEP_CASES))
+def test_rk4_steps_with_faces_against_oracle(case):
+    print("case: four ghosts, RK4 with faces", case, flush=True)
+    dims, h, dt, nsteps = (14, 12, 10), 0.3, 0.075, 3
+    origin = (-0.5 * dims[0] * h + 0.5 * h, -0.5 * dims[1] * h + 0.5 * h, -0.5 * dims[2] * h + 0.5 * h)
+    u = I.puncture(dims, h, centre=(0.0, 0.0, 0.0), phi_fn=I.shell_pulse(0.1, 1.5), ng=NG4)
+    bc = dict(STEP_CASES[case], centre=(0.01, 0.02, -0.03), speed=np.where(np.arange(I.NF) == 18, 2 ** 0.5, 1.0),
+              asymptote=FLAT, origin=origin)
+    p = _p6(lambda_gb=0.2, g2=0.05)
+    u = O.fill_bc(u, h, bc, ng=NG4)
+    want, flags = O.rk4_bc(I.params_vector(p), u, h, dt, nsteps, bc, ng=NG4)
+    assert flags == 0
+    ut = torch.from_numpy(u).to(DEV)
+    st = G.StepperBC(G.make_params(p), G.box_of(ut, h, origin=origin, ng=NG4), ut, dt, G.make_bc(**bc))
+    for _ in range(nsteps):
+        st.step()
+    assert st.status() == (0, 0)
+    e = rel_err_per_field(st.u.cpu().numpy(), want, interior=False)
+    assert e.max() <= 1e-10, dict(zip(I.FIELDS, e))
+
+
 def test_four_ghost_layers_refused_elsewhere():
     u = torch.from_numpy(I.single_puncture(12, 0.25, ng=NG4)).to(DEV)
     box = G.box_of(u, 0.25, ng=NG4)
@@ -251,7 +307,9 @@ def test_four_ghost_layers_refused_elsewhere():
         G.set_stage_path(p0)
     with pytest.raises((G.GrfError, ValueError)):
         G.Batch(p, [box], [u], [0.01])
-    with pytest.raises(G.GrfError) as e:
-        G.bc_fill(G.make_bc(["periodic"] * 6), box, u)
-    assert e.value.code == 7
     assert G.vjp_workspace_bytes(box) == 0
+    # a reflective face needs as many interior cells as there are ghost layers
+    thin = torch.from_numpy(I.single_puncture(3, 0.25, ng=NG4)).to(DEV)
+    with pytest.raises(G.GrfError) as e:
+        G.bc_fill(G.make_bc(["reflective"] * 6), G.box_of(thin, 0.25, ng=NG4), thin)
+    assert e.value.code == 1

@@ -287,3 +287,63 @@ def test_rk4_bc_sommerfeld_ghosts_follow_the_radiative_rule():
     som = _face_mask(dims, "x-") | _face_mask(dims, "x+")
     assert np.abs(got[IDX["phi"]][som] - u[IDX["phi"]][som]).max() > 1e-6   # the radiative ghosts moved
     assert np.array_equal(got[:, _face_mask(dims, "z+")], u[:, _face_mask(dims, "z+")])  # frozen face
+
+
+# ------------------------------------------------------------------ four ghost layers
+def _grid_ng(dims, h, origin, ng):
+    x, y, z = [origin[a] + h * np.arange(-ng, dims[a] + ng, dtype=np.float64) for a in range(3)]
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    return X, Y, Z
+
+
+def test_four_ghost_layers_periodic_and_linear_extrapolation():
+    """On a box with four ghost layers: periodic faces are numpy's wrap, and
+    first-order extrapolation is exact on linear functions in every layer."""
+    ng, dims, h = 4, (5, 6, 4), 0.5
+    rng = np.random.default_rng(12)
+    u = rng.standard_normal((NF, dims[2] + 2 * ng, dims[1] + 2 * ng, dims[0] + 2 * ng))
+    got = O.fill_bc(u, h, _bc(["periodic"] * 6), ng=ng)
+    inner = u[:, ng:-ng, ng:-ng, ng:-ng]
+    assert np.array_equal(got, np.pad(inner, ((0, 0), (ng, ng), (ng, ng), (ng, ng)), mode="wrap"))
+    X, Y, Z = _grid_ng(dims, h, (0.1, -0.2, 0.3), ng)
+    lin = np.empty_like(u)
+    for f in range(NF):
+        a = rng.standard_normal(4)
+        lin[f] = a[0] + a[1] * X + a[2] * Y + a[3] * Z
+    junk = lin.copy()
+    ghost = np.ones(X.shape, bool)
+    ghost[ng:-ng, ng:-ng, ng:-ng] = False
+    junk[:, ghost] = -7.0
+    got = O.fill_bc(junk, h, _bc(["extrapolating"] * 6, extrap_order=1), ng=ng)
+    np.testing.assert_allclose(got, lin, rtol=0, atol=1e-12)
+
+
+def test_four_ghost_layers_sommerfeld_exact_on_quadratics():
+    """The radiative right-hand side takes its closed form on quadratics in
+    all four ghost layers."""
+    ng, dims, h = 4, (6, 5, 7), 0.25
+    origin, centre = (1.0, -2.0, 0.5), (-3.0, 1.0, -4.0)
+    X, Y, Z = _grid_ng(dims, h, origin, ng)
+    rng = np.random.default_rng(14)
+    u = np.zeros((NF,) + X.shape)
+    want = np.zeros_like(u)
+    speed = 0.5 + rng.random(NF)
+    asym = rng.standard_normal(NF)
+    xr, yr, zr = X - centre[0], Y - centre[1], Z - centre[2]
+    r = np.sqrt(xr * xr + yr * yr + zr * zr)
+    for f in range(NF):
+        c = rng.standard_normal(10)
+        q = (c[0] + c[1] * X + c[2] * Y + c[3] * Z + c[4] * X * X + c[5] * Y * Y + c[6] * Z * Z
+             + c[7] * X * Y + c[8] * Y * Z + c[9] * X * Z)
+        gx = c[1] + 2 * c[4] * X + c[7] * Y + c[9] * Z
+        gy = c[2] + 2 * c[5] * Y + c[7] * X + c[8] * Z
+        gz = c[3] + 2 * c[6] * Z + c[8] * Y + c[9] * X
+        u[f] = q
+        want[f] = -speed[f] * (xr * gx + yr * gy + zr * gz) / r - speed[f] * (q - asym[f]) / r
+    bc = _bc(["sommerfeld"] * 6, origin=origin, centre=centre, speed=speed, asymptote=asym)
+    got = O.ghost_rhs(u, h, bc, ng=ng)
+    g = np.ones(X.shape, bool)
+    g[ng:-ng, ng:-ng, ng:-ng] = False
+    scale = np.abs(want[:, g]).max()
+    np.testing.assert_allclose(got[:, g], want[:, g], rtol=0, atol=1e-12 * scale)
+    assert np.all(got[:, ~g] == 0.0)
