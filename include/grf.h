@@ -90,9 +90,9 @@ enum { GRF_FLAG_NONFINITE = 1, GRF_FLAG_HYPERBOLIC = 2, GRF_FLAG_NONPOSITIVE = 4
  * the dissipation -sigma/(256 h) times the eighth difference, so the scheme
  * keeps order 6 with dissipation on.  Order 6 runs the z-marching 32x8x32
  * stencil kernel whatever grf_set_tile_variant chose, on stage paths 0 and 2,
- * in grf_rhs_eval, grf_rk4_stage, grf_rk4_stage_bc (three ghost layers) and
- * the diagnostics; the fused path, the batched form and the adjoint return
- * GRF_EUNSUPPORTED. */
+ * in grf_rhs_eval, grf_rk4_stage, grf_rk4_stage_bc and the diagnostics, and
+ * in the adjoint on three ghost layers (the transposes of the same stencils);
+ * the fused path and the batched form return GRF_EUNSUPPORTED. */
 typedef struct {
   double lambda_gb;
   int32_t lambda_kind;

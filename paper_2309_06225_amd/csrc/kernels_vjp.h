@@ -76,7 +76,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 // u_bar[f] += sum over the field's stencils of their transposes applied to the
 // cotangent record (the upwind split by the sign of the shift at the source
 // cell) and the Kreiss-Oliger transpose applied to w.  (An LDS-tiled form of
-// the same sums measured 1.30 against 1.10 ms at 64^3.)
+// the same sums measured 1.30 against 1.10 ms at 64^3.)  ORD 6: the transposes
+// of the sixth-order stencils of the three-ghost box (centred derivatives on
+// seven points, the fifth-order biased advection stencils), the same
+// Kreiss-Oliger operator.
 __device__ __forceinline__ double src_at(const BoxDev& b, const double* __restrict__ comp, int X, int Y, int Z) {
   const int ix = X - 3, iy = Y - 3, iz = Z - 3;
   if (ix < 0 || ix >= b.nx || iy < 0 || iy >= b.ny || iz < 0 || iz >= b.nz) return 0.0;
@@ -85,7 +88,7 @@ __device__ __forceinline__ double src_at(const BoxDev& b, const double* __restri
 
 constexpr int kGatherThreads = 256;
 
-template <int NT>
+template <int NT, int ORD = 4>
 __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __restrict__ u,
                                                                const double* __restrict__ w,
                                                                const double* __restrict__ Dbar, double ko_sigma,
@@ -103,6 +106,47 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
   };
   double acc = 0.0;
   const int s1 = grf_d1_slot[f];
+  const int s2 = grf_d2_slot[f];
+  if constexpr (ORD == 6) {
+    const double w1[7] = {-1.0, 9.0, -45.0, 0.0, 45.0, -9.0, 1.0};
+    const double w2[7] = {2.0, -27.0, 270.0, -490.0, 270.0, -27.0, 2.0};
+    if (s1 >= 0) {
+      for (int d = 0; d < 3; ++d) {
+        const double* comp = Dbar + (int64_t)(GRF_OFF_D1 + 3 * s1 + d) * nc;
+        double s = 0.0;
+#pragma unroll
+        for (int o = -3; o <= 3; ++o)
+          if (o != 0) s += w1[o + 3] * at(comp, d, o);
+        acc += s * b.i60h[d];
+      }
+    }
+    if (s2 >= 0) {
+      const int pure[3] = {0, 3, 5};
+      for (int d = 0; d < 3; ++d) {
+        const double* comp = Dbar + (int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc;
+        double s = 0.0;
+#pragma unroll
+        for (int o = -3; o <= 3; ++o) s += w2[o + 3] * at(comp, d, o);
+        acc += s * b.i180h2[d];
+      }
+      const int pd[3] = {0, 0, 1}, pe[3] = {1, 2, 2}, pq[3] = {1, 2, 4};
+      for (int m = 0; m < 3; ++m) {
+        const double* comp = Dbar + (int64_t)(GRF_OFF_D2 + 6 * s2 + pq[m]) * nc;
+        double s = 0.0;
+#pragma unroll
+        for (int a = -3; a <= 3; ++a)
+#pragma unroll
+          for (int bb = -3; bb <= 3; ++bb)
+            if (a != 0 && bb != 0) {
+              int dx[3] = {0, 0, 0};
+              dx[pd[m]] += a;
+              dx[pe[m]] += bb;
+              s += (w1[a + 3] * w1[bb + 3]) * src_at(b, comp, X - dx[0], Y - dx[1], Z - dx[2]);
+            }
+        acc += s * b.i3600[m];
+      }
+    }
+  } else {
   if (s1 >= 0) {
     const double w1[5] = {1.0, -8.0, 0.0, 8.0, -1.0};
     for (int d = 0; d < 3; ++d) {
@@ -114,7 +158,6 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
       acc += s * b.i12h[d];
     }
   }
-  const int s2 = grf_d2_slot[f];
   if (s2 >= 0) {
     const double w1[5] = {1.0, -8.0, 0.0, 8.0, -1.0};
     const double w2[5] = {-1.0, 16.0, -30.0, 16.0, -1.0};
@@ -143,9 +186,14 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
       acc += s * b.i144[m];
     }
   }
+  }  // ORD 4
   if (advected(f, shift_adv)) {
+    // forward weights of the biased stencils at offsets -3..3 from the source
+    // cell, for a nonnegative and a negative shift there
     const double wp[7] = {0.0, 0.0, -3.0, -10.0, 18.0, -6.0, 1.0};
     const double wm[7] = {-1.0, 6.0, -18.0, 10.0, 3.0, 0.0, 0.0};
+    const double wp6[7] = {0.0, 3.0, -30.0, -20.0, 60.0, -15.0, 2.0};
+    const double wm6[7] = {-2.0, 15.0, -60.0, 20.0, 30.0, -3.0, 0.0};
     const double* comp = Dbar + (int64_t)(GRF_OFF_ADV + f) * nc;
     // the advection sum's cotangent: w_f where the sum rides in the
     // Kreiss-Oliger slot, else the cotangent record
@@ -168,9 +216,12 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
           else
             vm = a * bd;
         }
-        s += wp[o + 3] * vp + wm[o + 3] * vm;
+        if constexpr (ORD == 6)
+          s += wp6[o + 3] * vp + wm6[o + 3] * vm;
+        else
+          s += wp[o + 3] * vp + wm[o + 3] * vm;
       }
-      acc += s * b.i12h[d];
+      acc += s * (ORD == 6 ? b.i60h[d] : b.i12h[d]);
     }
   }
   {

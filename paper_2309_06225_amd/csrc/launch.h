@@ -24,7 +24,8 @@ hipError_t launch_deriv(int variant, const BoxDev& bd, const double* u, double* 
                         hipStream_t st);
 int tiles_of_variant(int variant, const BoxDev& bd);
 // sixth-order stencil stage (the z-marching 32x8x32 form; no upwinded-derivative output)
-hipError_t launch_deriv6(const BoxDev& bd, const double* u, double* D, double sigma, int sa, hipStream_t st);
+hipError_t launch_deriv6(const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
+                         hipStream_t st);
 // batched stencil stage: tiled variants 0..4 and the z-marching variant 8
 hipError_t launch_deriv_batch(int variant, int grid, const BatchBoxDev* boxes, const TileEntry* tiles, int ntiles,
                               int stage, int parity, double sigma, int sa, hipStream_t st);
@@ -132,7 +133,7 @@ hipError_t launch_vjp_point(int sa, const BoxDev& bd, const grf_point_params& pp
                             const double* UP, const double* w, double* ubar, double* Dbar, double* TH,
                             hipStream_t st);
 hipError_t launch_vjp_transpose(const BoxDev& bd, const double* u, const double* w, const double* Dbar, double sigma,
-                                int sa, double* ubar, hipStream_t st);
+                                int sa, int order, double* ubar, hipStream_t st);
 hipError_t launch_reduce(const double* TH, int64_t n, int64_t chunk, int nparts, double* part, double* theta_bar,
                          hipStream_t st);
 hipError_t launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* out,

@@ -321,7 +321,7 @@ static int staged_variant(const grf_params* p, int sa) {
 // stencil stage of the forward paths at the parameters' finite-difference order
 static hipError_t launch_deriv_p(const grf_params* p, const BoxDev& bd, const double* u, double* D, int sa,
                                  hipStream_t stream) {
-  if (p->fd_order == 6) return launch_deriv6(bd, u, D, p->ko_sigma, sa, stream);
+  if (p->fd_order == 6) return launch_deriv6(bd, u, D, p->ko_sigma, sa, nullptr, stream);
   return launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, sa, nullptr, stream);
 }
 
@@ -614,7 +614,6 @@ grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u,
   if (s != GRF_OK) return s;
   if (!u || !w || !u_bar || !theta_bar || !workspace) return fail(GRF_EINVAL, "null pointer");
   if (p->decoupled) return fail(GRF_EUNSUPPORTED, "the adjoint of the decoupling limit is not implemented");
-  if (p->fd_order == 6) return fail(GRF_EUNSUPPORTED, "the adjoint uses the fourth-order stencils only");
   if (u_bar == u || u_bar == w) return fail(GRF_EINVAL, "u_bar must not alias u or w");
   const VjpLayout L = vjp_layout(box);
   if (workspace_bytes < L.total) return fail(GRF_ENOMEM, "workspace %zu bytes < %zu", workspace_bytes, L.total);
@@ -628,9 +627,13 @@ grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u,
   double* part = (double*)(ws + L.off_part);
   const int sa = p->shift_advec != 0.0;
   prof_mark(2, stream);
-  GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, sa, UP, stream));
+  const int order = p->fd_order == 6 ? 6 : 4;
+  if (order == 6)
+    GRF_HIP_CHECK(launch_deriv6(bd, u, D, p->ko_sigma, sa, UP, stream));
+  else
+    GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, sa, UP, stream));
   GRF_HIP_CHECK(launch_vjp_point(sa, bd, pp, u, D, UP, w, u_bar, Dbar, TH, stream));
-  GRF_HIP_CHECK(launch_vjp_transpose(bd, u, w, Dbar, p->ko_sigma, sa, u_bar, stream));
+  GRF_HIP_CHECK(launch_vjp_transpose(bd, u, w, Dbar, p->ko_sigma, sa, order, u_bar, stream));
   GRF_HIP_CHECK(launch_reduce(TH, bd.ncell, kRedChunk, L.nparts, part, theta_bar, stream));
   prof_mark(2, stream);
   return GRF_OK;
@@ -651,7 +654,6 @@ grf_status grf_rk4_step_vjp(const grf_params* p, const grf_box* box, double dt, 
   if (s != GRF_OK) return s;
   if (box->bc != GRF_BC_FROZEN) return fail(GRF_EUNSUPPORTED, "the step adjoint is implemented for frozen ghosts");
   if (p->decoupled) return fail(GRF_EUNSUPPORTED, "the adjoint of the decoupling limit is not implemented");
-  if (p->fd_order == 6) return fail(GRF_EUNSUPPORTED, "the adjoint uses the fourth-order stencils only");
   if (p->enforce) return fail(GRF_EUNSUPPORTED, "the step adjoint does not differentiate the enforcement");
   if (!u || !u2 || !u3 || !u4 || !ubar_new || !ubar || !theta_bar || !workspace) return fail(GRF_EINVAL, "null pointer");
   if (ubar == ubar_new || ubar == u || ubar == u2 || ubar == u3 || ubar == u4)

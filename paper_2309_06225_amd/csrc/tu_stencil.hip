@@ -182,10 +182,11 @@ hipError_t launch_deriv_zm_t(const BoxDev& bd, const double* u, double* D, doubl
   return hipGetLastError();
 }
 
-hipError_t launch_deriv6(const BoxDev& bd, const double* u, double* D, double sigma, int sa, hipStream_t st) {
+hipError_t launch_deriv6(const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
+                         hipStream_t st) {
   // the 128x8 column measured slower here (11.9 against 10.1 ms per 128^3 step)
-  if (bd.ng == 4) return launch_deriv_zm_t<32, 8, 32, true, 6, 4>(bd, u, D, sigma, sa, nullptr, st);
-  return launch_deriv_zm_t<32, 8, 32, true, 6>(bd, u, D, sigma, sa, nullptr, st);
+  if (bd.ng == 4) return launch_deriv_zm_t<32, 8, 32, true, 6, 4>(bd, u, D, sigma, sa, UP, st);
+  return launch_deriv_zm_t<32, 8, 32, true, 6>(bd, u, D, sigma, sa, UP, st);
 }
 
 hipError_t launch_deriv(int variant, const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
@@ -342,10 +343,15 @@ hipError_t launch_status_clear(unsigned* s, hipStream_t st) {
 }
 
 hipError_t launch_vjp_transpose(const BoxDev& bd, const double* u, const double* w, const double* Dbar, double sigma,
-                                int sa, double* ubar, hipStream_t st) {
+                                int sa, int order, double* ubar, hipStream_t st) {
   const int64_t n = (int64_t)(bd.nx + 6) * (bd.ny + 6) * (bd.nz + 6);
-  hipLaunchKernelGGL(k_vjp_gather<kGatherThreads>, dim3((unsigned)((n + kGatherThreads - 1) / kGatherThreads), NF),
-                     dim3(kGatherThreads), 0, st, bd, u, w, Dbar, sigma, sa, ubar);
+  const dim3 grid((unsigned)((n + kGatherThreads - 1) / kGatherThreads), NF);
+  if (order == 6)
+    hipLaunchKernelGGL((k_vjp_gather<kGatherThreads, 6>), grid, dim3(kGatherThreads), 0, st, bd, u, w, Dbar, sigma, sa,
+                       ubar);
+  else
+    hipLaunchKernelGGL((k_vjp_gather<kGatherThreads, 4>), grid, dim3(kGatherThreads), 0, st, bd, u, w, Dbar, sigma, sa,
+                       ubar);
   return hipGetLastError();
 }
 

@@ -38,10 +38,11 @@ def _interior_mask(shape):
     return m
 
 
+@pytest.mark.parametrize("fd_order", [4.0, 6.0])
 @pytest.mark.parametrize("shift_advec", [0.0, 1.0])
-def test_rhs_vjp_dot_product_vs_oracle_tangent(shift_advec):
-    print("case: RHS VJP 11x9x7 shift_advec", shift_advec, flush=True)
-    p = I.default_params(shift_advec=shift_advec, lambda_gb=0.3, g2=0.05)
+def test_rhs_vjp_dot_product_vs_oracle_tangent(shift_advec, fd_order):
+    print("case: RHS VJP 11x9x7 shift_advec", shift_advec, "fd_order", fd_order, flush=True)
+    p = I.default_params(shift_advec=shift_advec, lambda_gb=0.3, g2=0.05, fd_order=fd_order)
     dims, dx = (11, 9, 7), 0.4
     u = _state(dims, dx, 1)
     rng = np.random.default_rng(2)
@@ -98,9 +99,10 @@ def test_rhs_vjp_reaches_ghosts():
     assert np.abs(ub[:, 3, 3, 7:]).max() == 0   # beyond the stencil reach
 
 
-def test_rk4_step_vjp_vs_oracle_tangent():
-    print("case: RK4 step VJP 10x8x9", flush=True)
-    p = I.default_params(lambda_gb=0.3, g2=0.05)
+@pytest.mark.parametrize("fd_order", [4.0, 6.0])
+def test_rk4_step_vjp_vs_oracle_tangent(fd_order):
+    print("case: RK4 step VJP 10x8x9 fd_order", fd_order, flush=True)
+    p = I.default_params(lambda_gb=0.3, g2=0.05, shift_advec=1.0 if fd_order == 6.0 else 0.0, fd_order=fd_order)
     dims, dx, dt = (10, 8, 9), 0.4, 0.1
     u = _state(dims, dx, 5, amp=0.01)
     rng = np.random.default_rng(6)
@@ -256,11 +258,13 @@ def test_trajectory_gradient_vs_oracle_tangent_cfg3_box():
     assert float(theta.grad[0]) == pytest.approx(tangent, rel=1e-8)
 
 
-def test_trajectory_gradient_vs_oracle_tangent():
+@pytest.mark.parametrize("fd_order", [4.0, 6.0])
+def test_trajectory_gradient_vs_oracle_tangent(fd_order):
     """Small box: the adjoint's dJ/dtheta and dJ/dphi0 . v against the oracle's
-    complex-step tangent through the same RK4 steps."""
-    print("case: trajectory 16^3 x 6 steps vs oracle tangent", flush=True)
-    p = I.default_params(lambda_gb=0.5, g2=0.05)
+    complex-step tangent through the same RK4 steps (fourth- and sixth-order
+    stencils)."""
+    print("case: trajectory 16^3 x 6 steps vs oracle tangent, fd_order", fd_order, flush=True)
+    p = I.default_params(lambda_gb=0.5, g2=0.05, fd_order=fd_order)
     n, dx, nsteps = 16, 0.5, 6
     dt = 0.25 * dx
     u0 = I.puncture((n, n, n), dx, phi_fn=I.shell_pulse(0.3, 2.0))
