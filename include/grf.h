@@ -90,9 +90,9 @@ enum { GRF_FLAG_NONFINITE = 1, GRF_FLAG_HYPERBOLIC = 2, GRF_FLAG_NONPOSITIVE = 4
  * the dissipation -sigma/(256 h) times the eighth difference, so the scheme
  * keeps order 6 with dissipation on.  Order 6 runs the z-marching 32x8x32
  * stencil kernel whatever grf_set_tile_variant chose, on stage paths 0 and 2,
- * in grf_rhs_eval, grf_rk4_stage, grf_rk4_stage_bc and the diagnostics, and
- * in the adjoint on three ghost layers (the transposes of the same stencils);
- * the fused path and the batched form return GRF_EUNSUPPORTED. */
+ * in grf_rhs_eval, grf_rk4_stage, grf_rk4_stage_bc, the diagnostics and the
+ * adjoint (the transposes of the same stencils); the fused path and the
+ * batched form return GRF_EUNSUPPORTED. */
 typedef struct {
   double lambda_gb;
   int32_t lambda_kind;
@@ -114,9 +114,9 @@ typedef struct {
  * coordinates x0, y0, z0 of the centre of interior cell (0,0,0) (read by the
  * radiative boundary rule only), field_stride >= (nx+2ng)(ny+2ng)(nz+2ng),
  * boundary rule bc.  ng is 3, or 4 with fd_order 6 (GRF_EUNSUPPORTED with
- * fd_order 4); the batched form and the adjoint refuse four ghost layers with
- * GRF_EUNSUPPORTED (their size queries return 0), every other call takes
- * them; GRF_ESHAPE for any other ng. */
+ * fd_order 4); the batched form refuses four ghost layers with
+ * GRF_EUNSUPPORTED (its size query returns 0), every other call takes them;
+ * GRF_ESHAPE for any other ng. */
 typedef struct {
   int32_t nx, ny, nz, ng;
   double dx, dy, dz;

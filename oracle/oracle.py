@@ -111,7 +111,7 @@ def rhs_cells(params, u, dx, cells, ng=NG):
     return out, flags
 
 
-def rhs_cs(params, theta_im, u_re, u_im, dx):
+def rhs_cs(params, theta_im, u_re, u_im, dx, ng=NG):
     """Complex-step right-hand side. Returns (real part, imaginary part)."""
     u_re = _c(u_re)
     u_im = _c(u_im) if u_im is not None else np.zeros_like(u_re)
@@ -119,7 +119,7 @@ def rhs_cs(params, theta_im, u_re, u_im, dx):
     r_im = np.zeros_like(u_re)
     p = _c(params)
     ti = _c(theta_im)
-    dims = _dims(u_re)
+    dims = _dims(u_re, ng)
     lib().oracle_rhs_cs(_d(p), _d(ti), dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(u_re), _d(u_im),
                         _d(r_re), _d(r_im))
     return r_re, r_im
@@ -223,13 +223,13 @@ def rk4(params, u, dx, dt, nsteps, periodic, ng=NG):
     return u, flags
 
 
-def rk4_cs(params, theta_im, u_re, u_im, dx, dt, nsteps, periodic):
+def rk4_cs(params, theta_im, u_re, u_im, dx, dt, nsteps, periodic, ng=NG):
     """Complex-step RK4: returns (real state, imaginary state)."""
     u_re = _c(u_re).copy()
     u_im = _c(u_im).copy()
     p = _c(params)
     ti = _c(theta_im)
-    dims = _dims(u_re)
+    dims = _dims(u_re, ng)
     lib().oracle_rk4_cs(_d(p), _d(ti), dims.ctypes.data_as(_ip), _d(_spacing(dx)), 1 if periodic else 0,
                         float(dt), int(nsteps), _d(u_re), _d(u_im))
     return u_re, u_im

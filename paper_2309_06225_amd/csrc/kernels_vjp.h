@@ -79,22 +79,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 // the same sums measured 1.30 against 1.10 ms at 64^3.)  ORD 6: the transposes
 // of the sixth-order stencils of the three-ghost box (centred derivatives on
 // seven points, the fifth-order biased advection stencils), the same
-// Kreiss-Oliger operator.
+// Kreiss-Oliger operator; with H = 4 (four ghost layers) the sixth-order
+// biased stencils on seven points and the eighth difference.
+// (X, Y, Z: state coordinates on a box with H ghost layers)
+template <int H = 3>
 __device__ __forceinline__ double src_at(const BoxDev& b, const double* __restrict__ comp, int X, int Y, int Z) {
-  const int ix = X - 3, iy = Y - 3, iz = Z - 3;
+  const int ix = X - H, iy = Y - H, iz = Z - H;
   if (ix < 0 || ix >= b.nx || iy < 0 || iy >= b.ny || iz < 0 || iz >= b.nz) return 0.0;
   return comp[((int64_t)iz * b.ny + iy) * b.nx + ix];
 }
 
 constexpr int kGatherThreads = 256;
 
-template <int NT, int ORD = 4>
+template <int NT, int ORD = 4, int H = 3>
 __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __restrict__ u,
                                                                const double* __restrict__ w,
                                                                const double* __restrict__ Dbar, double ko_sigma,
                                                                int shift_adv, double* __restrict__ ubar) {
+  static_assert(H == 3 || (H == 4 && ORD == 6), "four ghost layers only with the sixth-order scheme");
   const int f = blockIdx.y;
-  const int NX = b.nx + 6, NY = b.ny + 6, NZ = b.nz + 6;
+  const int NX = b.nx + 2 * H, NY = b.ny + 2 * H, NZ = b.nz + 2 * H;
   const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (e >= (int64_t)NX * NY * NZ) return;
   const int X = (int)(e % NX);
@@ -102,7 +106,7 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
   const int Y = (int)(r % NY), Z = (int)(r / NY);
   const int64_t nc = b.ncell;
   auto at = [&](const double* comp, int d, int o) {  // comp at the target moved by -o along d
-    return src_at(b, comp, X - (d == 0 ? o : 0), Y - (d == 1 ? o : 0), Z - (d == 2 ? o : 0));
+    return src_at<H>(b, comp, X - (d == 0 ? o : 0), Y - (d == 1 ? o : 0), Z - (d == 2 ? o : 0));
   };
   double acc = 0.0;
   const int s1 = grf_d1_slot[f];
@@ -141,7 +145,7 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
               int dx[3] = {0, 0, 0};
               dx[pd[m]] += a;
               dx[pe[m]] += bb;
-              s += (w1[a + 3] * w1[bb + 3]) * src_at(b, comp, X - dx[0], Y - dx[1], Z - dx[2]);
+              s += (w1[a + 3] * w1[bb + 3]) * src_at<H>(b, comp, X - dx[0], Y - dx[1], Z - dx[2]);
             }
         acc += s * b.i3600[m];
       }
@@ -188,12 +192,22 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
   }
   }  // ORD 4
   if (advected(f, shift_adv)) {
-    // forward weights of the biased stencils at offsets -3..3 from the source
-    // cell, for a nonnegative and a negative shift there
-    const double wp[7] = {0.0, 0.0, -3.0, -10.0, 18.0, -6.0, 1.0};
-    const double wm[7] = {-1.0, 6.0, -18.0, 10.0, 3.0, 0.0, 0.0};
-    const double wp6[7] = {0.0, 3.0, -30.0, -20.0, 60.0, -15.0, 2.0};
-    const double wm6[7] = {-2.0, 15.0, -60.0, 20.0, 30.0, -3.0, 0.0};
+    // forward weights of the biased stencils at offsets -H..H from the source
+    // cell, for a nonnegative (wp) and a negative (wm) shift there
+    double wp[2 * H + 1], wm[2 * H + 1];
+    if constexpr (H == 4) {
+      const double p7[9] = {0.0, 0.0, 2.0, -24.0, -35.0, 80.0, -30.0, 8.0, -1.0};
+      const double m7[9] = {1.0, -8.0, 30.0, -80.0, 35.0, 24.0, -2.0, 0.0, 0.0};
+      for (int q = 0; q < 9; ++q) wp[q] = p7[q], wm[q] = m7[q];
+    } else if constexpr (ORD == 6) {
+      const double p6[7] = {0.0, 3.0, -30.0, -20.0, 60.0, -15.0, 2.0};
+      const double m6[7] = {-2.0, 15.0, -60.0, 20.0, 30.0, -3.0, 0.0};
+      for (int q = 0; q < 7; ++q) wp[q] = p6[q], wm[q] = m6[q];
+    } else {
+      const double p4[7] = {0.0, 0.0, -3.0, -10.0, 18.0, -6.0, 1.0};
+      const double m4[7] = {-1.0, 6.0, -18.0, 10.0, 3.0, 0.0, 0.0};
+      for (int q = 0; q < 7; ++q) wp[q] = p4[q], wm[q] = m4[q];
+    }
     const double* comp = Dbar + (int64_t)(GRF_OFF_ADV + f) * nc;
     // the advection sum's cotangent: w_f where the sum rides in the
     // Kreiss-Oliger slot, else the cotangent record
@@ -203,10 +217,10 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
       const double* beta = u + (int64_t)(F_SHIFT + d) * b.fs;
       double s = 0.0;
 #pragma unroll
-      for (int o = -3; o <= 3; ++o) {
+      for (int o = -H; o <= H; ++o) {
         const int sx = X - (d == 0 ? o : 0), sy = Y - (d == 1 ? o : 0), sz = Z - (d == 2 ? o : 0);
         double vp = 0.0, vm = 0.0;
-        const int ix = sx - 3, iy = sy - 3, iz = sz - 3;
+        const int ix = sx - H, iy = sy - H, iz = sz - H;
         if (ix >= 0 && ix < b.nx && iy >= 0 && iy < b.ny && iz >= 0 && iz < b.nz) {
           const double a = merged ? wf_adv[(int64_t)sz * b.sz + (int64_t)sy * b.sy + sx]
                                   : comp[((int64_t)iz * b.ny + iy) * b.nx + ix];
@@ -216,30 +230,36 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
           else
             vm = a * bd;
         }
-        if constexpr (ORD == 6)
-          s += wp6[o + 3] * vp + wm6[o + 3] * vm;
-        else
-          s += wp[o + 3] * vp + wm[o + 3] * vm;
+        s += wp[o + H] * vp + wm[o + H] * vm;
       }
       acc += s * (ORD == 6 ? b.i60h[d] : b.i12h[d]);
     }
   }
   {
-    const double wk[7] = {1.0, -6.0, 15.0, -20.0, 15.0, -6.0, 1.0};
+    // Kreiss-Oliger (symmetric): the sixth difference over 64 h, or with four
+    // ghost layers minus the eighth difference over 256 h
+    double wk[2 * H + 1];
+    if constexpr (H == 4) {
+      const double k8[9] = {1.0, -8.0, 28.0, -56.0, 70.0, -56.0, 28.0, -8.0, 1.0};
+      for (int q = 0; q < 9; ++q) wk[q] = k8[q];
+    } else {
+      const double k6[7] = {1.0, -6.0, 15.0, -20.0, 15.0, -6.0, 1.0};
+      for (int q = 0; q < 7; ++q) wk[q] = k6[q];
+    }
     const double* wf = w + (int64_t)f * b.fs;
     double s = 0.0;
     for (int d = 0; d < 3; ++d) {
       double sd = 0.0;
 #pragma unroll
-      for (int o = -3; o <= 3; ++o) {
+      for (int o = -H; o <= H; ++o) {
         const int sx = X - (d == 0 ? o : 0), sy = Y - (d == 1 ? o : 0), sz = Z - (d == 2 ? o : 0);
-        const int ix = sx - 3, iy = sy - 3, iz = sz - 3;
+        const int ix = sx - H, iy = sy - H, iz = sz - H;
         double v = 0.0;
         if (ix >= 0 && ix < b.nx && iy >= 0 && iy < b.ny && iz >= 0 && iz < b.nz)
           v = wf[(int64_t)sz * b.sz + (int64_t)sy * b.sy + sx];
-        sd += wk[o + 3] * v;
+        sd += wk[o + H] * v;
       }
-      s += sd * b.i64h[d];
+      s += sd * (H == 4 ? -b.i256h[d] : b.i64h[d]);
     }
     acc += ko_sigma * s;
   }

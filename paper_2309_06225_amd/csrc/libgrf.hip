@@ -59,7 +59,7 @@ grf_status check_box3(const grf_box* b) {
   grf_status s = check_box(b);
   if (s != GRF_OK) return s;
   if (b->ng != 3)
-    return fail(GRF_EUNSUPPORTED, "four ghost layers are not supported by the batched form and the adjoint");
+    return fail(GRF_EUNSUPPORTED, "four ghost layers are not supported by the batched form");
   return GRF_OK;
 }
 
@@ -602,7 +602,7 @@ VjpLayout vjp_layout(const grf_box* b) {
 extern "C" {
 
 size_t grf_vjp_workspace_bytes(const grf_box* box) {
-  if (check_box3(box) != GRF_OK) return 0;
+  if (check_box(box) != GRF_OK) return 0;
   return vjp_layout(box).total;
 }
 
@@ -610,10 +610,11 @@ grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u,
                        double* theta_bar, void* workspace, size_t workspace_bytes, hipStream_t stream) {
   grf_status s = check_params(p);
   if (s != GRF_OK) return s;
-  s = check_box3(box);
+  s = check_box(box);
   if (s != GRF_OK) return s;
   if (!u || !w || !u_bar || !theta_bar || !workspace) return fail(GRF_EINVAL, "null pointer");
   if (p->decoupled) return fail(GRF_EUNSUPPORTED, "the adjoint of the decoupling limit is not implemented");
+  if (box->ng == 4 && p->fd_order != 6) return fail(GRF_EUNSUPPORTED, "four ghost layers only with fd_order 6");
   if (u_bar == u || u_bar == w) return fail(GRF_EINVAL, "u_bar must not alias u or w");
   const VjpLayout L = vjp_layout(box);
   if (workspace_bytes < L.total) return fail(GRF_ENOMEM, "workspace %zu bytes < %zu", workspace_bytes, L.total);
@@ -632,7 +633,8 @@ grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u,
     GRF_HIP_CHECK(launch_deriv6(bd, u, D, p->ko_sigma, sa, UP, stream));
   else
     GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, sa, UP, stream));
-  GRF_HIP_CHECK(launch_vjp_point(sa, bd, pp, u, D, UP, w, u_bar, Dbar, TH, stream));
+  const int64_t sh = interior_shift(bd);
+  GRF_HIP_CHECK(launch_vjp_point(sa, bd, pp, u + sh, D, UP, w + sh, u_bar + sh, Dbar, TH, stream));
   GRF_HIP_CHECK(launch_vjp_transpose(bd, u, w, Dbar, p->ko_sigma, sa, order, u_bar, stream));
   GRF_HIP_CHECK(launch_reduce(TH, bd.ncell, kRedChunk, L.nparts, part, theta_bar, stream));
   prof_mark(2, stream);
@@ -640,7 +642,7 @@ grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u,
 }
 
 size_t grf_rk4_step_vjp_workspace_bytes(const grf_box* box) {
-  if (check_box3(box) != GRF_OK) return 0;
+  if (check_box(box) != GRF_OK) return 0;
   const size_t state = (size_t)NF * box->field_stride * 8;
   return vjp_layout(box).total + 2 * ((state + 255) / 256 * 256);
 }
@@ -650,10 +652,11 @@ grf_status grf_rk4_step_vjp(const grf_params* p, const grf_box* box, double dt, 
                             double* theta_bar, void* workspace, size_t workspace_bytes, hipStream_t stream) {
   grf_status s = check_params(p);
   if (s != GRF_OK) return s;
-  s = check_box3(box);
+  s = check_box(box);
   if (s != GRF_OK) return s;
   if (box->bc != GRF_BC_FROZEN) return fail(GRF_EUNSUPPORTED, "the step adjoint is implemented for frozen ghosts");
   if (p->decoupled) return fail(GRF_EUNSUPPORTED, "the adjoint of the decoupling limit is not implemented");
+  if (box->ng == 4 && p->fd_order != 6) return fail(GRF_EUNSUPPORTED, "four ghost layers only with fd_order 6");
   if (p->enforce) return fail(GRF_EUNSUPPORTED, "the step adjoint does not differentiate the enforcement");
   if (!u || !u2 || !u3 || !u4 || !ubar_new || !ubar || !theta_bar || !workspace) return fail(GRF_EINVAL, "null pointer");
   if (ubar == ubar_new || ubar == u || ubar == u2 || ubar == u3 || ubar == u4)

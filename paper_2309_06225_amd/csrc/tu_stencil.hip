@@ -344,9 +344,13 @@ hipError_t launch_status_clear(unsigned* s, hipStream_t st) {
 
 hipError_t launch_vjp_transpose(const BoxDev& bd, const double* u, const double* w, const double* Dbar, double sigma,
                                 int sa, int order, double* ubar, hipStream_t st) {
-  const int64_t n = (int64_t)(bd.nx + 6) * (bd.ny + 6) * (bd.nz + 6);
+  const int e = 2 * bd.ng;
+  const int64_t n = (int64_t)(bd.nx + e) * (bd.ny + e) * (bd.nz + e);
   const dim3 grid((unsigned)((n + kGatherThreads - 1) / kGatherThreads), NF);
-  if (order == 6)
+  if (bd.ng == 4)
+    hipLaunchKernelGGL((k_vjp_gather<kGatherThreads, 6, 4>), grid, dim3(kGatherThreads), 0, st, bd, u, w, Dbar, sigma,
+                       sa, ubar);
+  else if (order == 6)
     hipLaunchKernelGGL((k_vjp_gather<kGatherThreads, 6>), grid, dim3(kGatherThreads), 0, st, bd, u, w, Dbar, sigma, sa,
                        ubar);
   else

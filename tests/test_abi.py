@@ -41,7 +41,7 @@ def test_host_side_validation_without_device():
     # four ghost layers: a valid shape, but only for the sixth-order scheme
     box4 = G.make_box((8, 8, 8), 0.25, ng=4)
     assert L.grf_workspace_bytes(ctypes.byref(box4)) == L.grf_workspace_bytes(ctypes.byref(box))
-    assert L.grf_vjp_workspace_bytes(ctypes.byref(box4)) == 0
+    assert L.grf_vjp_workspace_bytes(ctypes.byref(box4)) == L.grf_vjp_workspace_bytes(ctypes.byref(box))
     code = L.grf_rhs_eval(ctypes.byref(p), ctypes.byref(box4), None, None, None, 0, None)
     assert code == 7 and b"fd_order 6" in L.grf_last_error()
     bad.ng = 5

@@ -288,6 +288,78 @@ def test_rk4_steps_with_faces_against_oracle(case):
     assert e.max() <= 1e-10, dict(zip(I.FIELDS, e))
 
 
+H_CS = 1e-30
+
+
+def _vjp_state(dims, dx, seed, amp=0.02):
+    u = I.puncture(dims, dx, centre=(0.7, -0.4, 0.3), phi_fn=I.shell_pulse(0.2, 1.5), ng=NG4)
+    rng = np.random.default_rng(seed)
+    u += amp * rng.standard_normal(u.shape) * (np.abs(u) + 0.1)
+    u[I.IDX["lapse"]] = np.abs(u[I.IDX["lapse"]]) + 0.2
+    u[I.IDX["chi"]] = np.abs(u[I.IDX["chi"]]) + 0.1
+    return u
+
+
+@pytest.mark.parametrize("shift_advec", [0.0, 1.0])
+def test_rhs_vjp_dot_product_vs_oracle_tangent(shift_advec):
+    """<w, J v + J_theta dth> from the oracle's complex step equals
+    <J^T w, v> + <J_theta^T w, dth> from the GPU adjoint, on four ghost layers
+    (the transposes of the seven-point biased stencils and the eighth
+    difference)."""
+    print("case: four ghosts, RHS VJP 11x9x7 shift_advec", shift_advec, flush=True)
+    p = _p6(shift_advec=shift_advec, lambda_gb=0.3, g2=0.05)
+    dims, dx = (11, 9, 7), 0.4
+    u = _vjp_state(dims, dx, 1)
+    rng = np.random.default_rng(2)
+    v = rng.standard_normal(u.shape)
+    dth = np.array([0.7, -0.4])
+    inner = np.zeros(u.shape, bool)
+    inner[:, NG4:-NG4, NG4:-NG4, NG4:-NG4] = True
+    w = rng.standard_normal(u.shape) * inner
+    _, jim = O.rhs_cs(I.params_vector(p), H_CS * dth, u, H_CS * v, dx, ng=NG4)
+    lhs = np.sum(w * jim / H_CS * inner)
+    ut = torch.from_numpy(u).to(DEV)
+    wt = torch.from_numpy(w).to(DEV)
+    ubar = torch.zeros_like(ut)
+    tbar = torch.zeros(2, dtype=torch.float64, device=DEV)
+    box = G.box_of(ut, dx, ng=NG4)
+    G.rhs_vjp(G.make_params(p), box, ut, wt, ubar, tbar, G.alloc_workspace(G.vjp_workspace_bytes(box)))
+    ub = ubar.cpu().numpy()
+    rhs = float(np.sum(ub * v) + tbar.cpu().numpy() @ dth)
+    assert abs(lhs - rhs) <= 1e-11 * max(abs(lhs), 1.0), (lhs, rhs)
+    # cotangents reach the fourth ghost layer (the eighth difference and the
+    # biased stencils read it) and nothing beyond the stencils' reach
+    assert np.abs(ub[:, 0, NG4:-NG4, NG4:-NG4]).max() > 0
+
+
+def test_rk4_step_vjp_vs_oracle_tangent():
+    print("case: four ghosts, RK4 step VJP 10x8x9", flush=True)
+    p = _p6(lambda_gb=0.3, g2=0.05, shift_advec=1.0)
+    dims, dx, dt = (10, 8, 9), 0.4, 0.1
+    u = _vjp_state(dims, dx, 5, amp=0.01)
+    rng = np.random.default_rng(6)
+    v = rng.standard_normal(u.shape)
+    dth = np.array([-0.3, 0.9])
+    w = rng.standard_normal(u.shape)
+    _, uim = O.rk4_cs(I.params_vector(p), H_CS * dth, u, H_CS * v, dx, dt, 1, periodic=False, ng=NG4)
+    lhs = np.sum(w * uim / H_CS)
+    ut = torch.from_numpy(u).to(DEV)
+    box = G.box_of(ut, dx, ng=NG4)
+    P = G.make_params(p)
+    acc = torch.zeros((I.NF, box.nx * box.ny * box.nz), dtype=torch.float64, device=DEV)
+    ws = G.alloc_workspace(G.workspace_bytes(box))
+    u2, u3, u4, un = (ut.clone() for _ in range(4))
+    G.rk4_stage(P, box, 1, dt, ut, ut, u2, acc, ws)
+    G.rk4_stage(P, box, 2, dt, ut, u2, u3, acc, ws)
+    G.rk4_stage(P, box, 3, dt, ut, u3, u4, acc, ws)
+    ubar = torch.empty_like(ut)
+    tbar = torch.zeros(2, dtype=torch.float64, device=DEV)
+    wsv = G.alloc_workspace(G.step_vjp_workspace_bytes(box))
+    G.rk4_step_vjp(P, box, dt, ut, u2, u3, u4, torch.from_numpy(w).to(DEV), ubar, tbar, wsv)
+    rhs = float(np.sum(ubar.cpu().numpy() * v) + tbar.cpu().numpy() @ dth)
+    assert abs(lhs - rhs) <= 1e-11 * max(abs(lhs), 1.0), (lhs, rhs)
+
+
 def test_four_ghost_layers_refused_elsewhere():
     u = torch.from_numpy(I.single_puncture(12, 0.25, ng=NG4)).to(DEV)
     box = G.box_of(u, 0.25, ng=NG4)
@@ -307,7 +379,12 @@ def test_four_ghost_layers_refused_elsewhere():
         G.set_stage_path(p0)
     with pytest.raises((G.GrfError, ValueError)):
         G.Batch(p, [box], [u], [0.01])
-    assert G.vjp_workspace_bytes(box) == 0
+    # the adjoint of the fourth-order scheme
+    tbar = torch.zeros(2, dtype=torch.float64, device=DEV)
+    with pytest.raises(G.GrfError) as e:
+        G.rhs_vjp(G.make_params(I.default_params()), box, u, torch.zeros_like(u), torch.zeros_like(u), tbar,
+                  G.alloc_workspace(G.vjp_workspace_bytes(box)))
+    assert e.value.code == 7
     # a reflective face needs as many interior cells as there are ghost layers
     thin = torch.from_numpy(I.single_puncture(3, 0.25, ng=NG4)).to(DEV)
     with pytest.raises(G.GrfError) as e:
