@@ -21,6 +21,7 @@ HIPCC_FLAGS = [
 
 # (source, object name, extra defines)
 UNITS = [("libgrf.hip", "api", []), ("tu_stencil.hip", "stencil", []), ("tu_vjp.hip", "vjp", []),
+         ("tu_vjp.hip", "vjp_dec", ["-DGRF_VJP_DEC=1"]),
          ("tu_constraints.hip", "constraints", []), ("tu_bc.hip", "bc", [])]
 UNITS += [("tu_point.hip", f"point_m{m}", [f"-DGRF_TU_MODE={m}"]) for m in (0, 1, 2, 4)]
 UNITS += [("tu_batch.hip", f"batch_m{m}", [f"-DGRF_TU_MODE={m}"]) for m in (1, 2, 4)]

@@ -150,8 +150,8 @@ def _dec_flops():
     return count_flops(b["graph"], b["rhs"])[0]
 
 
-def vjp_code(shift_advec: bool):
-    b = M.build(shift_advec)
+def vjp_code(shift_advec: bool, decoupled: bool = False):
+    b = M.build(shift_advec, decoupled=decoupled)
     g = b["graph"]
     w = [g.input(f"w{f}") for f in range(M.NF)]
     leaves = [n for n in g.nodes if n.op == "in" and not n.name.startswith("w")]
@@ -307,6 +307,12 @@ def main(outdir: str):
         fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
         fh.write(f"// vector-Jacobian product: {vfl0} flops/cell ({vops0})\n")
         fh.write(block("GRF_SHIFT_ADVEC", vj1, vj0))
+    vd0, vdfl0, vdops0 = vjp_code(False, decoupled=True)
+    vd1, _, _ = vjp_code(True, decoupled=True)
+    with open(os.path.join(outdir, "gen_vjp_dec.inc"), "w") as fh:
+        fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
+        fh.write(f"// vector-Jacobian product in the decoupling limit: {vdfl0} flops/cell ({vdops0})\n")
+        fh.write(block("GRF_SHIFT_ADVEC", vd1, vd0))
     return dict(flops_rhs=fl0, flops_rhs_shiftadv=fl1, flops_vjp=vfl0, ops=ops0, vops=vops0)
 
 

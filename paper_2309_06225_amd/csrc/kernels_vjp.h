@@ -23,7 +23,8 @@ constexpr int NCOMP_BAR = GRF_OFF_KO;
 // Two waves per SIMD (256 registers each): the kernel spills ~12 KB per lane
 // either way, and the second wave hides part of that traffic's latency
 // (3.86 -> 3.04 ms at 64^3; three or four waves per SIMD measured slower).
-template <int SHIFTADV>
+// DEC: the decoupling limit (the scalar does not source the metric).
+template <int SHIFTADV, int DEC = 0>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_vjp_point(BoxDev b, grf_point_params P, const double* __restrict__ us,
                                                   const double* __restrict__ D, const double* __restrict__ UP,
                                                   const double* __restrict__ w, double* __restrict__ ubar,
@@ -45,7 +46,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 #define GRF_BAR_D(cc, v) Dbar[(int64_t)(cc) * nc + c] = (v)
 #define GRF_BAR_TH(q, v) TH[(int64_t)(q) * nc + c] = (v)
 #define GRF_SHIFT_ADVEC (SHIFTADV != 0)
+  if constexpr (DEC != 0) {
+#include "gen/gen_vjp_dec.inc"
+  } else {
 #include "gen/gen_vjp.inc"
+  }
 #undef GRF_SHIFT_ADVEC
 #undef GRF_BAR_U
 #undef GRF_BAR_D

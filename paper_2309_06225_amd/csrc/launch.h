@@ -132,6 +132,10 @@ template <> int fused_blocks_per_cu_m<4>(int);
 hipError_t launch_vjp_point(int sa, const BoxDev& bd, const grf_point_params& pp, const double* u, const double* D,
                             const double* UP, const double* w, double* ubar, double* Dbar, double* TH,
                             hipStream_t st);
+// the same in the decoupling limit
+hipError_t launch_vjp_point_dec(int sa, const BoxDev& bd, const grf_point_params& pp, const double* u, const double* D,
+                            const double* UP, const double* w, double* ubar, double* Dbar, double* TH,
+                            hipStream_t st);
 hipError_t launch_vjp_transpose(const BoxDev& bd, const double* u, const double* w, const double* Dbar, double sigma,
                                 int sa, int order, double* ubar, hipStream_t st);
 hipError_t launch_reduce(const double* TH, int64_t n, int64_t chunk, int nparts, double* part, double* theta_bar,

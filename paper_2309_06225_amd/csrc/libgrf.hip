@@ -613,7 +613,6 @@ grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u,
   s = check_box(box);
   if (s != GRF_OK) return s;
   if (!u || !w || !u_bar || !theta_bar || !workspace) return fail(GRF_EINVAL, "null pointer");
-  if (p->decoupled) return fail(GRF_EUNSUPPORTED, "the adjoint of the decoupling limit is not implemented");
   if (box->ng == 4 && p->fd_order != 6) return fail(GRF_EUNSUPPORTED, "four ghost layers only with fd_order 6");
   if (u_bar == u || u_bar == w) return fail(GRF_EINVAL, "u_bar must not alias u or w");
   const VjpLayout L = vjp_layout(box);
@@ -634,7 +633,10 @@ grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u,
   else
     GRF_HIP_CHECK(launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, sa, UP, stream));
   const int64_t sh = interior_shift(bd);
-  GRF_HIP_CHECK(launch_vjp_point(sa, bd, pp, u + sh, D, UP, w + sh, u_bar + sh, Dbar, TH, stream));
+  if (p->decoupled)
+    GRF_HIP_CHECK(launch_vjp_point_dec(sa, bd, pp, u + sh, D, UP, w + sh, u_bar + sh, Dbar, TH, stream));
+  else
+    GRF_HIP_CHECK(launch_vjp_point(sa, bd, pp, u + sh, D, UP, w + sh, u_bar + sh, Dbar, TH, stream));
   GRF_HIP_CHECK(launch_vjp_transpose(bd, u, w, Dbar, p->ko_sigma, sa, order, u_bar, stream));
   GRF_HIP_CHECK(launch_reduce(TH, bd.ncell, kRedChunk, L.nparts, part, theta_bar, stream));
   prof_mark(2, stream);
@@ -655,7 +657,6 @@ grf_status grf_rk4_step_vjp(const grf_params* p, const grf_box* box, double dt, 
   s = check_box(box);
   if (s != GRF_OK) return s;
   if (box->bc != GRF_BC_FROZEN) return fail(GRF_EUNSUPPORTED, "the step adjoint is implemented for frozen ghosts");
-  if (p->decoupled) return fail(GRF_EUNSUPPORTED, "the adjoint of the decoupling limit is not implemented");
   if (box->ng == 4 && p->fd_order != 6) return fail(GRF_EUNSUPPORTED, "four ghost layers only with fd_order 6");
   if (p->enforce) return fail(GRF_EUNSUPPORTED, "the step adjoint does not differentiate the enforcement");
   if (!u || !u2 || !u3 || !u4 || !ubar_new || !ubar || !theta_bar || !workspace) return fail(GRF_EINVAL, "null pointer");

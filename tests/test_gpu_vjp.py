@@ -288,3 +288,48 @@ def test_trajectory_gradient_vs_oracle_tangent(fd_order):
     assert adj == pytest.approx(tangent, rel=1e-9)
     # the forward J matches the oracle's too
     assert float(J.detach()) == pytest.approx(float(np.sum((phi_re ** 2)[maskn])), rel=1e-10)
+
+
+@pytest.mark.parametrize("shift_advec", [0.0, 1.0])
+def test_decoupled_vjp_dot_products_vs_oracle_tangent(shift_advec):
+    """The decoupling limit (the scalar does not source the metric) has its
+    own generated reverse: the right-hand side's and the RK4 step's VJPs
+    against the oracle's complex-step tangent."""
+    print("case: decoupled VJPs, shift_advec", shift_advec, flush=True)
+    p = I.default_params(shift_advec=shift_advec, lambda_gb=0.3, g2=0.05, decoupled=1.0)
+    dims, dx, dt = (11, 9, 7), 0.4, 0.1
+    u = _state(dims, dx, 7)
+    rng = np.random.default_rng(8)
+    v = rng.standard_normal(u.shape)
+    dth = np.array([0.5, -0.8])
+    w = rng.standard_normal(u.shape) * _interior_mask(u.shape)
+    _, jim = O.rhs_cs(I.params_vector(p), H_CS * dth, u, H_CS * v, dx)
+    lhs = np.sum(w * jim / H_CS * _interior_mask(u.shape))
+    ut = torch.from_numpy(u).to(DEV)
+    ubar = torch.zeros_like(ut)
+    tbar = torch.zeros(2, dtype=torch.float64, device=DEV)
+    box = G.box_of(ut, dx)
+    G.rhs_vjp(G.make_params(p), box, ut, torch.from_numpy(w).to(DEV), ubar, tbar,
+              G.alloc_workspace(G.vjp_workspace_bytes(box)))
+    rhs = float(np.sum(ubar.cpu().numpy() * v) + tbar.cpu().numpy() @ dth)
+    assert abs(lhs - rhs) <= 1e-11 * max(abs(lhs), 1.0), (lhs, rhs)
+    # and it is not the full theory's reverse
+    ub_full = torch.zeros_like(ut)
+    G.rhs_vjp(G.make_params(dict(p, decoupled=0.0)), box, ut, torch.from_numpy(w).to(DEV), ub_full,
+              torch.zeros(2, dtype=torch.float64, device=DEV), G.alloc_workspace(G.vjp_workspace_bytes(box)))
+    assert not torch.equal(ub_full, ubar)
+    # one RK4 step
+    w2 = rng.standard_normal(u.shape)
+    _, uim = O.rk4_cs(I.params_vector(p), H_CS * dth, u, H_CS * v, dx, dt, 1, periodic=False)
+    lhs2 = np.sum(w2 * uim / H_CS)
+    traj = A.Trajectory(p, box, dt, 1)
+    P = traj._params([p["lambda_gb"], p["g2"]])
+    bufs = [ut.clone() for _ in range(4)]
+    traj.step(P, ut, traj._accbuf(ut.device), bufs)
+    u2, u3, u4 = bufs[:3]
+    ub2 = torch.empty_like(ut)
+    tb2 = torch.zeros(2, dtype=torch.float64, device=DEV)
+    G.rk4_step_vjp(P, box, dt, ut, u2, u3, u4, torch.from_numpy(w2).to(DEV), ub2, tb2,
+                   G.alloc_workspace(G.step_vjp_workspace_bytes(box)))
+    rhs2 = float(np.sum(ub2.cpu().numpy() * v) + tb2.cpu().numpy() @ dth)
+    assert abs(lhs2 - rhs2) <= 1e-11 * max(abs(lhs2), 1.0), (lhs2, rhs2)
