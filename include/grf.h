@@ -78,8 +78,9 @@ enum { GRF_FLAG_NONFINITE = 1, GRF_FLAG_HYPERBOLIC = 2, GRF_FLAG_NONPOSITIVE = 4
  * momentum, stress or Gauss-Bonnet tensor in the metric equations; the metric
  * rows of the per-cell system reduce to C_ij = Q_ij), gauge unchanged.
  * Supported by grf_rhs_eval, grf_rk4_stage and grf_rk4_stage_bc on stage path
- * 2 (the default) and by the adjoint (its own generated reverse); the other
- * paths, the diagnostics and the batched form return GRF_EUNSUPPORTED.
+ * 2 (the default), by grf_constraints (without scalar sources) and by the
+ * adjoint (its own generated reverse); the other paths, the energy and
+ * coupling diagnostics and the batched form return GRF_EUNSUPPORTED.
  * fd_order: 4 (or 0) fourth-order stencils; 6 sixth-order stencils (Key
  * features, "Accuracy").  On a box with three ghost layers: centred first,
  * second and mixed derivatives of order 6, the advection derivative of order

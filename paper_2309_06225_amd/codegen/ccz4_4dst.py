@@ -386,7 +386,8 @@ def build(shift_advec: bool = False, decoupled: bool = False, general_coupling: 
     inputs = {n.name: n for n in g.nodes if n.op == "in"}
     # constraint diagnostics: Hamiltonian R + 2/3 K^2 - A_ij A^ij - 2 (8 pi rho)
     # (with the pure Ricci scalar) and momentum M_i - 8 pi S_i
-    constraints = [Hg - 2.0 * rho8] + [Mi[i] - S8i[i] for i in R3]
+    # in the decoupling limit the metric constraints carry no scalar sources
+    constraints = [Hg - 2.0 * rho8m] + [Mi[i] - S8im[i] for i in R3]
     return dict(graph=g, rhs=rhs, pivots=pivots, pivot_check=pivot_check, inputs=inputs, params=P,
                 theta=[P["lambda_gb"], P["g2"]], solution=x, constraints=constraints,
                 scalar_parts=dict(X=X, Pi=Pi, GW=GW, g2=g2, Gcu=Gcu, Cs=Cs, M2=M2, B2=B2, dlam=dlam))

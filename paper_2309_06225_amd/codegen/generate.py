@@ -103,10 +103,11 @@ def forward_code_staged(shift_advec: bool, rhs_only: bool, decoupled: bool = Fal
     return emit_staged(g, outs, stmts, _stage_key, param_expr, STAGE_SLOTS, order="greedy")
 
 
-def constraints_code():
+def constraints_code(decoupled: bool = False):
     """Hamiltonian and momentum constraints of one cell: GRF_CON(q, v), q = 0
-    Hamiltonian, 1..3 momentum (they do not involve the advection sums)."""
-    b = M.build(False)
+    Hamiltonian, 1..3 momentum (they do not involve the advection sums); in
+    the decoupling limit without the scalar's sources."""
+    b = M.build(False, decoupled=decoupled)
     g = b["graph"]
     outs = b["constraints"]
     names = [f"GRF_CON({q}, {{}})" for q in range(len(outs))]
@@ -293,6 +294,11 @@ def main(outdir: str):
         fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
         fh.write(f"// Hamiltonian and momentum constraints: {cfl} flops/cell\n")
         fh.write("{\n" + PRAGMA + con + "\n}\n")
+    cond, cdfl = constraints_code(decoupled=True)
+    with open(os.path.join(outdir, "gen_constraints_dec.inc"), "w") as fh:
+        fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")
+        fh.write(f"// Hamiltonian and momentum constraints in the decoupling limit: {cdfl} flops/cell\n")
+        fh.write("{\n" + PRAGMA + cond + "\n}\n")
     en, efl = energy_code()
     with open(os.path.join(outdir, "gen_energy.inc"), "w") as fh:
         fh.write("// Generated by paper_2309_06225_amd/codegen/generate.py -- do not edit.\n")

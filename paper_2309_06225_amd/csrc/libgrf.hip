@@ -543,12 +543,13 @@ static grf_status diagnostics(int which, const grf_params* p, const grf_box* box
   grf_status s = common_checks(p, box, workspace, workspace_bytes);
   if (s != GRF_OK) return s;
   if (!u || !out) return fail(GRF_EINVAL, "u/out is null");
-  if (p->decoupled) return fail(GRF_EUNSUPPORTED, "diagnostics of the decoupling limit are not implemented");
+  if (p->decoupled && which != 0)
+    return fail(GRF_EUNSUPPORTED, "in the decoupling limit only the constraints are implemented");
   BoxDev bd = make_boxdev(box);
   grf_point_params pp = make_pp(p);
   double* D = (double*)((char*)workspace + kStatusBytes);
   GRF_HIP_CHECK(launch_deriv_p(p, bd, u, D, p->shift_advec != 0.0, stream));
-  GRF_HIP_CHECK(launch_constraints(which, bd, pp, u + interior_shift(bd), D, out, stream));
+  GRF_HIP_CHECK(launch_constraints(p->decoupled ? 3 : which, bd, pp, u + interior_shift(bd), D, out, stream));
   return GRF_OK;
 }
 

@@ -2,7 +2,8 @@
 // stage and the state: the Hamiltonian and momentum constraints (WHICH = 0)
 // the energy densities of the canonical, X^2 and Gauss-Bonnet terms of the
 // action (WHICH = 1), and the Gauss-Bonnet invariant with the weak-coupling
-// indicators (WHICH = 2).
+// indicators (WHICH = 2); WHICH = 3: the constraints in the decoupling limit
+// (no scalar sources).
 #include "kernels_fwd.h"
 #include "launch.h"
 
@@ -26,6 +27,8 @@ __global__ __launch_bounds__(kPointThreads) void k_constraints(BoxDev b, grf_poi
 #define GRF_CON(q, v) out[(int64_t)(q) * b.ncell + c] = (v)
   if constexpr (WHICH == 0) {
 #include "gen/gen_constraints.inc"
+  } else if constexpr (WHICH == 3) {
+#include "gen/gen_constraints_dec.inc"
   } else if constexpr (WHICH == 1) {
 #include "gen/gen_energy.inc"
   } else {
@@ -42,6 +45,8 @@ hipError_t launch_constraints(int which, const BoxDev& bd, const grf_point_param
   const int64_t nblk = (bd.ncell + kPointThreads - 1) / kPointThreads;
   if (which == 0)
     hipLaunchKernelGGL(k_constraints<0>, dim3((unsigned)nblk), dim3(kPointThreads), 0, st, bd, pp, u, D, out);
+  else if (which == 3)
+    hipLaunchKernelGGL(k_constraints<3>, dim3((unsigned)nblk), dim3(kPointThreads), 0, st, bd, pp, u, D, out);
   else if (which == 1)
     hipLaunchKernelGGL(k_constraints<1>, dim3((unsigned)nblk), dim3(kPointThreads), 0, st, bd, pp, u, D, out);
   else

@@ -141,6 +141,27 @@ def test_unsupported_paths_are_refused():
     finally:
         G.set_stage_path(p0)
     with pytest.raises(G.GrfError):
-        G.constraints(p, box, u, ws)
+        G.energy_densities(p, box, u, ws)
     with pytest.raises(G.GrfError):
         G.Batch(p, [box], [u], [0.01])
+
+
+def test_constraints_parity():
+    """In the decoupling limit the constraints carry no scalar sources: the
+    GPU's against the oracle's, and different from the full theory's."""
+    print("case: decoupled constraints 21x17x13", flush=True)
+    p = _dec(lambda_gb=0.3, g2=0.05)
+    dx = 0.3
+    u = I.puncture((21, 17, 13), dx, centre=(0.4, -0.2, 0.1), phi_fn=I.shell_pulse(0.1, 2.0))
+    u[I.IDX["Pi"]] += 0.05
+    ho, mo = O.constraints(I.params_vector(p), u, dx)
+    ut = torch.from_numpy(u).to(DEV)
+    box = G.box_of(ut, dx)
+    ws = G.alloc_workspace(G.workspace_bytes(box))
+    hg, mg = G.constraints(G.make_params(p), box, ut, ws)
+    hg, mg = hg.cpu().numpy(), mg.cpu().numpy()
+    assert np.abs(hg - ho).max() <= 1e-12 * np.abs(ho).max()
+    for d in range(3):
+        assert np.abs(mg[d] - mo[d]).max() <= 1e-12 * np.abs(mo[d]).max()
+    hf, _ = G.constraints(G.make_params(I.default_params(lambda_gb=0.3, g2=0.05)), box, ut, ws)
+    assert np.abs(hf.cpu().numpy() - hg).max() > 1e-8
