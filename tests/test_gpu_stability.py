@@ -2,10 +2,13 @@
 cannot reach: flat space with 1e-6 noise on every field, periodic, 64^3 at
 dx = 1/8, 2,000 RK4 steps, with the growth criteria the oracle's pin uses on
 8^3 to 16^3 (bounded Hamiltonian constraint, at most linear drift from flat
-space).  Gauge functions with a >= b pass; with b > a (a = 0.2, b = 0.4) the
-noise grows exponentially at this resolution unless the Kreiss-Oliger
-coefficient is raised (0.5 suffices): a property of the modified gauge as
-written here, shared by the oracle's equations, not of the kernels."""
+space).  The equations are strongly hyperbolic for the modified gauge
+(a = 0.2, b = 0.4), but with b > a the fourth-order stencils carry a grid mode
+whose growth rate scales as 1/dx unless the Kreiss-Oliger coefficient is at
+least about 0.9 (the spectrum of the oracle's discrete operator shows it; the
+same holds for these kernels, which match the oracle).  The configured gauge
+therefore runs here with sigma = 1, beside the standard gauge and a > b at the
+default sigma = 0.3."""
 import numpy as np
 import pytest
 
@@ -27,7 +30,7 @@ def _setup():
 
 GAUGES = {"standard": dict(a_gauge=0.0, b_gauge=0.0),
           "a_above_b": dict(a_gauge=0.4, b_gauge=0.2),
-          "b_above_a_more_dissipation": dict(a_gauge=0.2, b_gauge=0.4, ko_sigma=0.5)}
+          "configured_gauge_sigma_one": dict(a_gauge=0.2, b_gauge=0.4, ko_sigma=1.0)}
 
 
 @pytest.mark.parametrize("gauge", sorted(GAUGES))

@@ -296,6 +296,40 @@ def test_covariant_pointwise_pin(case, seed):
     assert ex["p"] == pytest.approx(ref["p"], abs=1e-12 * max(1.0, abs(ref["p"])))
 
 
+@pytest.mark.parametrize("case", [0, 2])
+@pytest.mark.parametrize("a,shift_advec", [(0.0, 0.0), (0.3, 0.0), (0.3, 1.0)])
+def test_gauge_rows_against_covariant_gamma(case, a, shift_advec):
+    """The modified gauge (a) enters the lapse, shift and B rows only: the other
+    time derivatives still equal the covariant ones for a != 0 and with shift
+    advection.  The B row is the Gamma-driver in co-moving form,
+    (d_t - beta.d) B = (d_t - beta.d) Gam / (1 + a) - eta B, with d_t Gam taken
+    from the covariant reference (not from the oracle's Gam row), and the
+    shift row gains beta.d beta exactly when shift advection is on (the
+    advection inputs are the exact first derivatives here)."""
+    import covariant_ref as C
+    params = I.default_params(kappa3=1.0, a_gauge=a, shift_advec=shift_advec, eta=0.7, **COV_PARAMS[case])
+    ref = C.reference_point(31 + 7 * case, params)
+    assert ref["residual"] < 1e-12
+    u, d1 = ref["u"], ref["d1"]
+    rhs, _, flags = O.rhs_point(I.params_vector(params), u, d1, ref["d2"], d1)
+    assert flags == 0
+    scale = np.abs(ref["dt"][NONGAUGE]).max()
+    np.testing.assert_allclose(rhs[NONGAUGE], ref["dt"][NONGAUGE], rtol=0, atol=1e-12 * scale)
+    beta = u[19:22]
+    for i in range(3):
+        gam_dt = ref["dt"][15 + i]
+        adv_b = beta @ d1[22 + i]
+        adv_g = beta @ d1[15 + i]
+        want = (gam_dt - shift_advec * adv_g) / (1.0 + a) - 0.7 * u[22 + i] + shift_advec * adv_b
+        assert rhs[22 + i] == pytest.approx(want, abs=1e-12 * max(1.0, abs(gam_dt)))
+    # shift advection adds beta.d beta to the shift rows and nothing else to them
+    other = I.default_params(kappa3=1.0, a_gauge=a, shift_advec=1.0 - shift_advec, eta=0.7, **COV_PARAMS[case])
+    rhs2, _, _ = O.rhs_point(I.params_vector(other), u, d1, ref["d2"], d1)
+    sgn = 1.0 if shift_advec else -1.0
+    for i in range(3):
+        assert rhs[19 + i] - rhs2[19 + i] == pytest.approx(sgn * (beta @ d1[19 + i]), abs=1e-14)
+
+
 @pytest.mark.parametrize("case", [0, 3, 4])
 @pytest.mark.parametrize("seed", [11, 12])
 def test_decoupled_covariant_pin(case, seed):
