@@ -379,6 +379,15 @@ int grf_get_tile_variant(void);
 grf_status grf_set_stage_path(int path);
 int grf_get_stage_path(void);
 
+/* Interior z-planes per slab of the split stage paths of grf_rhs_eval,
+ * grf_rk4_stage: 0 (default) = the whole box in one
+ * stencil launch and one pointwise launch; n > 0 = slabs of n planes, each a
+ * stencil launch writing the slab's derivative records and a pointwise launch
+ * reading them (so the records held between the two launches are slab-sized).
+ * Results are bitwise identical.  GRF_EINVAL for n < 0. */
+grf_status grf_set_slab_planes(int planes);
+int grf_get_slab_planes(void);
+
 /* Kernel timing with HIP events recorded on the launch stream around each
  * launch, for up to max_launches launches per kernel class; grf_prof_end waits
  * for the events and returns per class (0 stencil stage, 1 pointwise + RK4,

@@ -20,6 +20,8 @@ struct BoxDev {
   int64_t sz;      // state stride in z ((nx + 2 ng)(ny + 2 ng))
   int64_t fs;      // field stride of the state
   int64_t ncell;   // nx*ny*nz
+  int64_t as;      // field stride of the compact accumulator: ncell, or the
+                   // whole box's cell count when a z-slab of it is processed
   double i12h[3];  // 1/(12 h)
   double i12h2[3]; // 1/(12 h^2)
   double i144[3];  // 1/(144 h_x h_y), 1/(144 h_x h_z), 1/(144 h_y h_z)
@@ -429,11 +431,10 @@ template <int MODE>
 __device__ __forceinline__ void stage_one(int f, double rhs_f, double ko_f, const BoxDev& b, int64_t c, int64_t s,
                                           const double* __restrict__ u0, double* __restrict__ out,
                                           double* __restrict__ acc, StageCoef sc, unsigned& flags) {
-  const int64_t nc = b.ncell;
   const double kf = rhs_f + ko_f;
   if (!isfinite(kf)) flags |= 1u;
   const int64_t q = (int64_t)f * b.fs + s;
-  const int64_t qa = (int64_t)f * nc + c;
+  const int64_t qa = (int64_t)f * b.as + c;
   if constexpr (MODE == 0) {
     out[q] = kf;
   } else if constexpr (MODE == 1) {

@@ -58,7 +58,7 @@ __device__ __forceinline__ void stage_one_st(int f, double rhs_f, double ko_f, d
   const double kf = rhs_f + ko_f;
   if (!isfinite(kf)) flags |= 1u;
   const int64_t q = (int64_t)f * b.fs + s;
-  const int64_t qa = (int64_t)f * b.ncell + c;
+  const int64_t qa = (int64_t)f * b.as + c;
   if constexpr (MODE == 0) {
     out[q] = kf;
   } else if constexpr (MODE == 1) {
@@ -110,7 +110,7 @@ __device__ __forceinline__ void staged_wave(const BoxDev& b, int64_t c0, const g
 #define GRF_STAGE_ACC(bb, slot, f)                                                                         \
   do {                                                                                                     \
     if constexpr (MODE == 2 || MODE == 4)                                                                  \
-      stage_item(acc + (int64_t)(f) * nc + vc0, acc + (int64_t)(f) * nc + vc1, wb, &GRF_BUF(bb)[(slot) * 64]); \
+      stage_item(acc + (int64_t)(f) * b.as + vc0, acc + (int64_t)(f) * b.as + vc1, wb, &GRF_BUF(bb)[(slot) * 64]); \
   } while (0)
 #define GRF_PHASE_SYNC()                        \
   do {                                          \

@@ -87,6 +87,7 @@ BoxDev make_boxdev(const grf_box* b) {
   d.sz = (int64_t)(b->nx + 2 * b->ng) * (b->ny + 2 * b->ng);
   d.fs = b->field_stride;
   d.ncell = (int64_t)b->nx * b->ny * b->nz;
+  d.as = d.ncell;
   const double h[3] = {b->dx, b->dy, b->dz};
   for (int k = 0; k < 3; ++k) {
     d.i12h[k] = 1.0 / (12.0 * h[k]);
@@ -325,6 +326,49 @@ static hipError_t launch_deriv_p(const grf_params* p, const BoxDev& bd, const do
   return launch_deriv(g_tile_variant, bd, u, D, p->ko_sigma, sa, nullptr, stream);
 }
 
+// Interior planes per z-slab of the split stage paths: 0 = the whole box in
+// one stencil launch and one pointwise launch (record of the whole box);
+// n > 0 = slabs of n planes, each a stencil launch writing the slab's record
+// and a pointwise launch reading it, so that the record held between the two
+// is slab-sized.
+static int g_slab_planes = 0;
+
+// Stencil stage + pointwise stage (mode 0: right-hand side into out; 1, 2, 4:
+// RK4 stage) of the split paths over z-slabs of at most `planes` interior
+// planes.  Each slab is a sub-box: the state pointers move to its first plane
+// (its ghost planes are the neighbouring planes of the box, or the box's own
+// ghosts at the ends), its record in D is compact over the slab, and the
+// accumulator keeps the whole box's field stride.  Per cell the arithmetic is
+// that of the whole-box launches, so results are bitwise identical.
+static hipError_t split_stage(const grf_params* p, const BoxDev& bd, int planes, int mode, StageCoef sc,
+                              const double* us, const double* u0, double* out, double* acc, double* D,
+                              unsigned* status, hipStream_t stream) {
+  const grf_point_params pp = make_pp(p);
+  const int sa = p->shift_advec != 0.0;
+  const int var = staged_variant(p, sa);
+  const int path = g_stage_path == 0 ? 0 : 2;
+  const int64_t sh = interior_shift(bd);
+  const int64_t plane = (int64_t)bd.nx * bd.ny;
+  if (planes <= 0 || planes > bd.nz) planes = bd.nz;
+  for (int z0 = 0; z0 < bd.nz; z0 += planes) {
+    BoxDev sb = bd;
+    sb.nz = planes < bd.nz - z0 ? planes : bd.nz - z0;
+    sb.ncell = plane * sb.nz;
+    sb.as = bd.ncell;
+    const int64_t so = (int64_t)z0 * bd.sz;
+    prof_mark(0, stream);
+    hipError_t e = launch_deriv_p(p, sb, us + so, D, sa, stream);
+    if (e != hipSuccess) return e;
+    prof_mark(0, stream);
+    prof_mark(1, stream);
+    e = launch_pointwise(path, mode, var, sb, pp, us + so + sh, D, u0 ? u0 + so + sh : nullptr, out + so + sh,
+                         acc ? acc + (int64_t)z0 * plane : nullptr, sc, status, stream);
+    if (e != hipSuccess) return e;
+    prof_mark(1, stream);
+  }
+  return hipSuccess;
+}
+
 grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u, double* rhs, void* workspace,
                         size_t workspace_bytes, hipStream_t stream) {
   grf_status s = common_checks(p, box, workspace, workspace_bytes);
@@ -346,14 +390,7 @@ grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u
     prof_mark(1, stream);
     return GRF_OK;
   }
-  const int64_t sh = interior_shift(bd);
-  prof_mark(0, stream);
-  GRF_HIP_CHECK(launch_deriv_p(p, bd, u, D, sa, stream));
-  prof_mark(0, stream);
-  prof_mark(1, stream);
-  GRF_HIP_CHECK(launch_pointwise(g_stage_path, 0, staged_variant(p, sa), bd, pp, u + sh, D, nullptr, rhs + sh,
-                                 nullptr, StageCoef{0.0}, status, stream));
-  prof_mark(1, stream);
+  GRF_HIP_CHECK(split_stage(p, bd, g_slab_planes, 0, StageCoef{0.0}, u, nullptr, rhs, nullptr, D, status, stream));
   return GRF_OK;
 }
 
@@ -399,14 +436,7 @@ static grf_status rk4_stage_impl(const grf_params* p, const grf_box* box, int st
     GRF_HIP_CHECK(launch_fused(mode, sa, bd, pp, us, u0, unext, acc, sc, D, p->ko_sigma, status, stream));
     prof_mark(1, stream);
   } else {
-    const int64_t sh = interior_shift(bd);
-    prof_mark(0, stream);
-    GRF_HIP_CHECK(launch_deriv_p(p, bd, us, D, sa, stream));
-    prof_mark(0, stream);
-    prof_mark(1, stream);
-    GRF_HIP_CHECK(launch_pointwise(g_stage_path, mode, staged_variant(p, sa), bd, pp, us + sh, D, u0 + sh,
-                                   unext + sh, acc, sc, status, stream));
-    prof_mark(1, stream);
+    GRF_HIP_CHECK(split_stage(p, bd, g_slab_planes, mode, sc, us, u0, unext, acc, D, status, stream));
   }
   if (p->enforce)
     GRF_HIP_CHECK(launch_enforce(bd, unext + interior_shift(bd), p->chi_min, p->lapse_min, stream));
@@ -1125,5 +1155,13 @@ grf_status grf_set_tile_variant(int variant) {
   g_tile_variant = variant;
   return GRF_OK;
 }
+
+// Interior planes per z-slab of the split stage paths (0 = whole box).
+grf_status grf_set_slab_planes(int planes) {
+  if (planes < 0) return fail(GRF_EINVAL, "slab planes must be >= 0");
+  g_slab_planes = planes;
+  return GRF_OK;
+}
+int grf_get_slab_planes(void) { return g_slab_planes; }
 
 }  // extern "C"

@@ -108,13 +108,15 @@ def lib():
         L.grf_last_error.restype = ctypes.c_char_p
         L.grf_set_tile_variant.argtypes = [ctypes.c_int]
         L.grf_set_stage_path.argtypes = [ctypes.c_int]
+        L.grf_set_slab_planes.argtypes = [ctypes.c_int]
         L.grf_prof_begin.argtypes = [ctypes.c_int]
         L.grf_measure_peaks.argtypes = [_vp, ctypes.c_size_t, _vp, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]
         L.grf_measure_peaks.restype = ctypes.c_int
         L.grf_prof_end.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         for name in ("grf_rhs_eval", "grf_rk4_stage", "grf_fill_periodic", "grf_rhs_vjp", "grf_status_fetch",
-                     "grf_status_clear", "grf_set_tile_variant", "grf_set_stage_path", "grf_prof_begin", "grf_prof_end",
+                     "grf_status_clear", "grf_set_tile_variant", "grf_set_stage_path", "grf_set_slab_planes",
+                     "grf_prof_begin", "grf_prof_end",
                      "grf_rk4_step_vjp", "grf_enforce", "grf_batch_create", "grf_batch_step", "grf_batch_step_perbox",
                      "grf_batch_autotune", "grf_batch_capture", "grf_batch_state", "grf_batch_tile_variant",
                      "grf_batch_set_tile_variant",
@@ -306,6 +308,15 @@ def set_stage_path(path: int):
     """0: stencil kernel + pointwise kernel; 1: fused per-tile stage kernel;
     2 (default): stencil kernel + pointwise kernel with LDS-staged inputs."""
     _check(lib().grf_set_stage_path(int(path)))
+
+
+def set_slab_planes(planes: int):
+    """Interior z-planes per slab of the split stage paths (0: the whole box)."""
+    _check(lib().grf_set_slab_planes(int(planes)))
+
+
+def get_slab_planes() -> int:
+    return int(lib().grf_get_slab_planes())
 
 
 def get_stage_path() -> int:
