@@ -150,6 +150,29 @@ grf_status grf_rk4_stage(const grf_params* p, const grf_box* box, int stage, dou
                          const double* us, double* unext, double* acc, void* workspace, size_t workspace_bytes,
                          hipStream_t stream);
 
+/* RK4 stage that allocates nothing and takes no workspace, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, arithmetic,
+ * results (bitwise) and ghost handling as grf_rk4_stage, except:
+ *  - the derivative records live in a device array of the library, 128 MiB
+ *    on each GPU it runs on, held until the process ends; the box is swept in
+ *    z-slabs of as many interior planes as fit (1584 bytes per cell), so one
+ *    plane of nx * ny cells may hold at most 84,733 cells: larger planes are
+ *    refused with GRF_ENOMEM before anything runs;
+ *  - device conditions are OR-ed into *status, a caller-owned device word
+ *    (read it with grf_status_fetch(status, ...), clear it with
+ *    grf_status_clear(status, ...)); the call does not clear it;
+ *  - it always runs the split path with staged pointwise inputs.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (every slab's record is written before it is read, so nothing needs
+ * clearing); calls that overlap in time on one GPU, from any stream or host
+ * thread, race on it and give undefined results.  No hipMalloc, hipFree or
+ * allocating library call is made; the device address of the array is looked
+ * up once per device on the first call there. */
+grf_status grf_rk4_stage_static(const grf_params* p, const grf_box* box, int stage, double dt, const double* u0,
+                                const double* us, double* unext, double* acc, uint32_t* status,
+                                hipStream_t stream);
+
 /* Algebraic enforcement on the interior cells of a state, in place:
  * h_ij <- h_ij det(h)^(-1/3) (unit determinant), A_ij <- A_ij - 1/3 h_ij h^kl A_kl
  * with the corrected h, chi <- max(chi, chi_min), lapse <- max(lapse, lapse_min).
@@ -380,7 +403,7 @@ grf_status grf_set_stage_path(int path);
 int grf_get_stage_path(void);
 
 /* Interior z-planes per slab of the split stage paths of grf_rhs_eval,
- * grf_rk4_stage: 0 (default) = the whole box in one
+ * grf_rk4_stage and grf_rk4_stage_static: 0 (default) = the whole box in one
  * stencil launch and one pointwise launch; n > 0 = slabs of n planes, each a
  * stencil launch writing the slab's derivative records and a pointwise launch
  * reading them (so the records held between the two launches are slab-sized).

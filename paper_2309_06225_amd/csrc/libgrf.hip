@@ -16,6 +16,7 @@
 #include "launch.h"
 
 #include <map>
+#include <mutex>
 #include <tuple>
 
 namespace grf {
@@ -441,6 +442,78 @@ static grf_status rk4_stage_impl(const grf_params* p, const grf_box* box, int st
   if (p->enforce)
     GRF_HIP_CHECK(launch_enforce(bd, unext + interior_shift(bd), p->chi_min, p->lapse_min, stream));
   if (box_ghosts && box->bc == GRF_BC_PERIODIC) GRF_HIP_CHECK(launch_periodic(bd, unext, stream));
+  return GRF_OK;
+}
+
+// ---- RK4 stage without allocation or workspace
+//
+// The derivative records of grf_rk4_stage_static live in this file-scope
+// device array, one copy per GPU, held until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it only stands for the
+// symbol); its device address is looked up once per device with
+// hipGetSymbolAddress and kept in g_scratch_ptr.
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (the current device's copy).
+static grf_status static_scratch(double** out) {
+  int dev = -1;
+  GRF_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(GRF_EUNSUPPORTED, "device index %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    GRF_HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(GRF_EHIP, "hipGetSymbolAddress returned a null address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = (double*)g_scratch_ptr[dev];
+  return GRF_OK;
+}
+
+extern "C" grf_status grf_rk4_stage_static(const grf_params* p, const grf_box* box, int stage, double dt,
+                                           const double* u0, const double* us, double* unext, double* acc,
+                                           uint32_t* status, hipStream_t stream) {
+  grf_status s = check_params(p);
+  if (s != GRF_OK) return s;
+  s = check_box(box);
+  if (s != GRF_OK) return s;
+  if (box->ng == 4 && p->fd_order != 6) return fail(GRF_EUNSUPPORTED, "four ghost layers only with fd_order 6");
+  if (stage < 1 || stage > 4) return fail(GRF_EINVAL, "stage must be 1..4 (got %d)", stage);
+  if (!u0 || !us || !unext || !acc || !status) return fail(GRF_EINVAL, "null pointer argument");
+  if (unext == us || unext == u0) return fail(GRF_EINVAL, "unext must not alias us or u0");
+  if (!std::isfinite(dt)) return fail(GRF_EINVAL, "dt not finite");
+  const int64_t plane = (int64_t)box->nx * box->ny;
+  const int64_t cap = (int64_t)(kStaticScratchBytes / (GRF_NCOMP * sizeof(double)));
+  if (plane > cap)
+    return fail(GRF_ENOMEM, "one z-plane of %lld cells exceeds the static scratch (%lld cells, %zu bytes)",
+                (long long)plane, (long long)cap, kStaticScratchBytes);
+  double* D = nullptr;
+  s = static_scratch(&D);
+  if (s != GRF_OK) return s;
+  BoxDev bd = make_boxdev(box);
+  int planes = (int)(cap / plane < box->nz ? cap / plane : box->nz);
+  if (g_slab_planes > 0 && g_slab_planes < planes) planes = g_slab_planes;
+  StageCoef sc;
+  int mode;
+  switch (stage) {
+    case 1: mode = 1; sc = StageCoef{0.5 * dt}; break;
+    case 2: mode = 2; sc = StageCoef{0.5 * dt}; break;
+    case 3: mode = 2; sc = StageCoef{1.0 * dt}; break;
+    default: mode = 4; sc = StageCoef{dt / 6.0}; break;
+  }
+  const int keep = g_stage_path;
+  g_stage_path = 2;  // the split path with staged pointwise inputs
+  const hipError_t e = split_stage(p, bd, planes, mode, sc, us, u0, unext, acc, D, (unsigned*)status, stream);
+  g_stage_path = keep;
+  if (e != hipSuccess) return fail(GRF_EHIP, "grf_rk4_stage_static: %s", hipGetErrorString(e));
+  if (p->enforce)
+    GRF_HIP_CHECK(launch_enforce(bd, unext + interior_shift(bd), p->chi_min, p->lapse_min, stream));
+  if (box->bc == GRF_BC_PERIODIC) GRF_HIP_CHECK(launch_periodic(bd, unext, stream));
   return GRF_OK;
 }
 

@@ -109,13 +109,14 @@ def lib():
         L.grf_set_tile_variant.argtypes = [ctypes.c_int]
         L.grf_set_stage_path.argtypes = [ctypes.c_int]
         L.grf_set_slab_planes.argtypes = [ctypes.c_int]
+        L.grf_rk4_stage_static.argtypes = [P, B, ctypes.c_int, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, _vp]
         L.grf_prof_begin.argtypes = [ctypes.c_int]
         L.grf_measure_peaks.argtypes = [_vp, ctypes.c_size_t, _vp, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]
         L.grf_measure_peaks.restype = ctypes.c_int
         L.grf_prof_end.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         for name in ("grf_rhs_eval", "grf_rk4_stage", "grf_fill_periodic", "grf_rhs_vjp", "grf_status_fetch",
-                     "grf_status_clear", "grf_set_tile_variant", "grf_set_stage_path", "grf_set_slab_planes",
+                     "grf_status_clear", "grf_set_tile_variant", "grf_set_stage_path", "grf_set_slab_planes", "grf_rk4_stage_static",
                      "grf_prof_begin", "grf_prof_end",
                      "grf_rk4_step_vjp", "grf_enforce", "grf_batch_create", "grf_batch_step", "grf_batch_step_perbox",
                      "grf_batch_autotune", "grf_batch_capture", "grf_batch_state", "grf_batch_tile_variant",
@@ -217,6 +218,14 @@ def rhs_eval(params: Params, box: Box, u, rhs, ws, stream=None):
 def rk4_stage(params: Params, box: Box, stage, dt, u0, us, unext, acc, ws, stream=None):
     _check(lib().grf_rk4_stage(ctypes.byref(params), ctypes.byref(box), int(stage), float(dt), _ptr(u0), _ptr(us),
                                _ptr(unext), _ptr(acc), _ptr(ws), ws.numel() * 8, _stream(stream)))
+
+
+def rk4_stage_static(params: Params, box: Box, stage, dt, u0, us, unext, acc, status, stream=None):
+    """grf_rk4_stage without a workspace: the derivative records live in the
+    library's own device scratch; ``status`` is a float64 device tensor whose
+    first 4 bytes are the status word into which device conditions are OR-ed."""
+    _check(lib().grf_rk4_stage_static(ctypes.byref(params), ctypes.byref(box), int(stage), float(dt), _ptr(u0),
+                                      _ptr(us), _ptr(unext), _ptr(acc), _ptr(status), _stream(stream)))
 
 
 def constraints(params: Params, box: Box, u, ws, stream=None):

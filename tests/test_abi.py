@@ -76,3 +76,19 @@ def test_boundary_rules_rejected_on_the_host():
     nan_speed = G.make_bc(["sommerfeld"] * 6, centre=(50.0, 0.0, 0.0), speed=[float("nan")] * 27)
     assert L.grf_bc_ghost_rhs(ctypes.byref(nan_speed), ctypes.byref(box), dummy, ctypes.c_void_p(16), None) == 1
     assert L.grf_bc_ghost_cells(ctypes.byref(box)) == 14 * 8 * 14 - 8 * 2 * 8
+
+
+def test_static_stage_refuses_oversized_planes_on_the_host():
+    """grf_rk4_stage_static checks a z-plane against its 128 MiB scratch before
+    any device work (the pointers below are never dereferenced)."""
+    from paper_2309_06225_amd import grf as G
+    L = G.lib()
+    p = G.make_params()
+    box = G.make_box((300, 300, 4), 0.25)   # 90,000 cells per plane > 84,733
+    ptr = [ctypes.c_void_p(8 * (k + 1)) for k in range(5)]
+    code = L.grf_rk4_stage_static(ctypes.byref(p), ctypes.byref(box), 1, 0.1, ptr[0], ptr[1], ptr[2], ptr[3],
+                                  ptr[4], None)
+    assert code == 6 and b"static scratch" in L.grf_last_error()
+    code = L.grf_rk4_stage_static(ctypes.byref(p), ctypes.byref(box), 1, 0.1, ptr[0], ptr[1], ptr[2], ptr[3],
+                                  None, None)
+    assert code == 1
