@@ -36,6 +36,7 @@
 
 #include <cmath>
 #include <complex>
+#include <omp.h>
 #include <cstdint>
 #include <cstring>
 #include <vector>
@@ -47,6 +48,113 @@ inline double re(double x) { return x; }
 inline double re(const cplx& x) { return x.real(); }
 inline bool finite_val(double x) { return std::isfinite(x); }
 inline bool finite_val(const cplx& x) { return std::isfinite(x.real()) && std::isfinite(x.imag()); }
+
+// ---------------------------------------------------------------- flop counting
+// A scalar that records its own arithmetic on a tape, run through the same
+// templated code to give the algorithmic flop count per cell used by roofline
+// fractions.  One count each for +, -, *, / and for sqrt, cbrt, exp, pow;
+// nothing for comparisons, negation, copies, abs and selects.  A value built
+// from constants alone (literals, the double-typed parameters) is a constant:
+// operations between constants are folded, as are additions of a constant 0
+// and multiplications or divisions by a constant 0 or +-1, which are no
+// arithmetic in any implementation.  Inputs (state values, couplings) are
+// variables.  Only the operations that the requested outputs depend on are
+// counted (values this code computes and never uses, such as second
+// derivatives of fields that appear only with first derivatives, are not
+// algorithmic work).
+struct Flop {
+  double v = 0.0;
+  int32_t id = -1;  // -1 constant, -2 input variable, >= 0 tape node
+  Flop() = default;
+  Flop(double x) : v(x), id(-1) {}
+  static Flop var(double x) {
+    Flop f(x);
+    f.id = -2;
+    return f;
+  }
+};
+struct FlopNode {
+  int32_t a, b;
+};
+std::vector<FlopNode> g_tape;
+inline Flop flop_node(double v, const Flop& a, const Flop& b) {
+  Flop r(v);
+  r.id = (int32_t)g_tape.size();
+  g_tape.push_back(FlopNode{a.id, b.id});
+  return r;
+}
+inline bool konst(const Flop& a) { return a.id == -1; }
+inline bool unit(const Flop& a) { return konst(a) && (a.v == 1.0 || a.v == -1.0); }
+inline Flop operator-(const Flop& a) {
+  Flop r = a;
+  r.v = -a.v;
+  return r;
+}
+inline Flop operator+(const Flop& a, const Flop& b) {
+  if (konst(a) && konst(b)) return Flop(a.v + b.v);
+  if (konst(a) && a.v == 0.0) return b;
+  if (konst(b) && b.v == 0.0) return a;
+  return flop_node(a.v + b.v, a, b);
+}
+inline Flop operator-(const Flop& a, const Flop& b) {
+  if (konst(a) && konst(b)) return Flop(a.v - b.v);
+  if (konst(b) && b.v == 0.0) return a;
+  if (konst(a) && a.v == 0.0) return -b;
+  return flop_node(a.v - b.v, a, b);
+}
+inline Flop operator*(const Flop& a, const Flop& b) {
+  if (konst(a) && konst(b)) return Flop(a.v * b.v);
+  if ((konst(a) && a.v == 0.0) || (konst(b) && b.v == 0.0)) return Flop(0.0);
+  if (unit(a)) return a.v > 0 ? b : -b;
+  if (unit(b)) return b.v > 0 ? a : -a;
+  return flop_node(a.v * b.v, a, b);
+}
+inline Flop operator/(const Flop& a, const Flop& b) {
+  if (konst(a) && konst(b)) return Flop(a.v / b.v);
+  if (konst(a) && a.v == 0.0) return Flop(0.0);
+  if (unit(b)) return b.v > 0 ? a : -a;
+  return flop_node(a.v / b.v, a, b);
+}
+inline Flop& operator+=(Flop& a, const Flop& b) { return a = a + b; }
+inline Flop& operator-=(Flop& a, const Flop& b) { return a = a - b; }
+inline Flop& operator*=(Flop& a, const Flop& b) { return a = a * b; }
+inline Flop& operator/=(Flop& a, const Flop& b) { return a = a / b; }
+#define GRF_FLOP_MIXED(op)                                                        \
+  inline Flop operator op(const Flop& a, double b) { return a op Flop(b); }      \
+  inline Flop operator op(double a, const Flop& b) { return Flop(a) op b; }      \
+  inline Flop operator op(const Flop& a, int b) { return a op Flop(double(b)); } \
+  inline Flop operator op(int a, const Flop& b) { return Flop(double(a)) op b; }
+GRF_FLOP_MIXED(+)
+GRF_FLOP_MIXED(-)
+GRF_FLOP_MIXED(*)
+GRF_FLOP_MIXED(/)
+#undef GRF_FLOP_MIXED
+inline Flop flop_fn(double v, const Flop& a) { return konst(a) ? Flop(v) : flop_node(v, a, Flop()); }
+inline Flop sqrt(const Flop& a) { return flop_fn(std::sqrt(a.v), a); }
+inline Flop cbrt(const Flop& a) { return flop_fn(std::cbrt(a.v), a); }
+inline Flop exp(const Flop& a) { return flop_fn(std::exp(a.v), a); }
+inline Flop pow(const Flop& a, double e) { return flop_fn(std::pow(a.v, e), a); }
+inline Flop abs(const Flop& a) {
+  Flop r = a;
+  r.v = std::fabs(a.v);
+  return r;
+}
+inline double re(const Flop& x) { return x.v; }
+inline bool finite_val(const Flop& x) { return std::isfinite(x.v); }
+// Number of tape operations that the given outputs depend on.
+int64_t flop_count_live(const std::vector<int32_t>& outputs) {
+  std::vector<char> live(g_tape.size(), 0);
+  for (int32_t o : outputs)
+    if (o >= 0) live[o] = 1;
+  int64_t n = 0;
+  for (int64_t q = (int64_t)g_tape.size() - 1; q >= 0; --q) {
+    if (!live[q]) continue;
+    ++n;
+    if (g_tape[q].a >= 0) live[g_tape[q].a] = 1;
+    if (g_tape[q].b >= 0) live[g_tape[q].b] = 1;
+  }
+  return n;
+}
 
 enum {
   CHI = 0, H11 = 1, KTR = 7, A11 = 8, THETA = 14, GH1 = 15, LAPSE = 18, SHIFT1 = 19,
@@ -479,7 +587,8 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
   const T F = X + g2 * X * X;               // V = 0
   // lambda(phi) = lambda_lin phi + lambda_gb (1 - exp(-beta phi^2)) / (4 beta)
   // (beta -> 0: lambda_gb phi^2 / 4); only its first two derivatives enter
-  const T ex = std::exp(-P.beta * phi * phi);
+  using std::exp;
+  const T ex = exp(-P.beta * phi * phi);
   const T dlam = P.lambda_lin + 0.5 * P.lambda_gb * phi * ex;               // lambda'(phi)
   const T ddlam = 0.5 * P.lambda_gb * (1.0 - 2.0 * P.beta * phi * phi) * ex;  // lambda''(phi)
   T DDphi[3][3];
@@ -848,7 +957,8 @@ void rhs_point(const Params<T>& P, const PointIn<T>& in, PointOut<T>& out) {
     rGam[i] = s;
     r[GH1 + i] = s;
   }
-  const T apow = (P.lapse_power == 1.0) ? alpha : T(std::pow(alpha, P.lapse_power));
+  using std::pow;
+  const T apow = (P.lapse_power == 1.0) ? alpha : T(pow(alpha, P.lapse_power));
   // reading: the a-modification divides the lapse source and the B source by (1 + a)
   r[LAPSE] = P.lapse_advec * adv[LAPSE] - P.lapse_coeff * apow * (K - 2.0 * Th) / (1.0 + aa);
   for (int i = 0; i < 3; ++i) {
@@ -1370,8 +1480,9 @@ int rk4_steps_bc(const Params<T>& P, const Box& b, const BcSpec& bc, double dt, 
 }  // namespace
 
 // ---------------------------------------------------------------- C ABI
-// Parameter array (14 doubles): lambda_gb, g2, a, b, kappa1, kappa2, kappa3,
-// lapse_coeff, lapse_power, lapse_advec, shift_gamma_coeff, shift_advec, eta, ko_sigma.
+// Parameter array (18 doubles): lambda_gb, g2, a, b, kappa1, kappa2, kappa3,
+// lapse_coeff, lapse_power, lapse_advec, shift_gamma_coeff, shift_advec, eta, ko_sigma,
+// decoupled, fd_order, lambda_lin, beta.
 extern "C" {
 
 int oracle_nfields() { return NF; }
@@ -1469,6 +1580,88 @@ void oracle_fill_periodic(const int* dims, double* u) {
 }
 
 // nsteps RK4 steps in place.  bc: 0 frozen ghosts, 1 periodic.
+// Algorithmic flops per interior cell (the convention of the Flop type above),
+// counted by running this file's own code on Flop values: the state u (state
+// layout, ghosts filled) and the two couplings variable, everything else
+// constant.  Single-threaded while counting.
+//   out[0]  one right-hand side (Kreiss-Oliger included) at an interior cell,
+//           mean over the interior cells;
+//   out[1]  the part of out[0] in the stencils and the Kreiss-Oliger sum;
+//   out[2]  one classic RK4 step per interior cell (four right-hand sides and
+//           the stage updates), the box taken as periodic.
+int oracle_flops_per_cell(const double* params, const int* dims, const double* spacing, const double* u,
+                          double* out) {
+  Box b = make_box(dims, spacing);
+  Params<double> Pd = read_params<double>(params, nullptr);
+  Params<Flop> P;
+  P.lambda_gb = Flop::var(Pd.lambda_gb);
+  P.g2 = Flop::var(Pd.g2);
+  P.a = Pd.a;
+  P.b = Pd.b;
+  P.kappa1 = Pd.kappa1;
+  P.kappa2 = Pd.kappa2;
+  P.kappa3 = Pd.kappa3;
+  P.lapse_coeff = Pd.lapse_coeff;
+  P.lapse_power = Pd.lapse_power;
+  P.lapse_advec = Pd.lapse_advec;
+  P.shift_gamma_coeff = Pd.shift_gamma_coeff;
+  P.shift_advec = Pd.shift_advec;
+  P.eta = Pd.eta;
+  P.ko_sigma = Pd.ko_sigma;
+  P.decoupled = Pd.decoupled;
+  P.fd_order = Pd.fd_order;
+  P.lambda_lin = Pd.lambda_lin;
+  P.beta = Pd.beta;
+  const int64_t ntot = b.fstride * NF;
+  std::vector<Flop> uf(ntot);
+  for (int64_t q = 0; q < ntot; ++q) uf[q] = Flop::var(u[q]);
+  const int keep = omp_get_max_threads();
+  omp_set_num_threads(1);
+  const int64_t ncell = (int64_t)b.nx * b.ny * b.nz;
+  int64_t rhs_ops = 0, gather_ops = 0;
+  int flags = 0;
+  for (int k = 0; k < b.nz; ++k)
+    for (int j = 0; j < b.ny; ++j)
+      for (int i = 0; i < b.nx; ++i) {
+        PointIn<Flop> in;
+        PointOut<Flop> o;
+        Flop ko[NF];
+        g_tape.clear();
+        gather_point(b, uf.data(), i, j, k, in, ko, P.fd_order);
+        const int32_t gathered = (int32_t)g_tape.size();
+        rhs_point(P, in, o);
+        std::vector<int32_t> outs;
+        for (int f = 0; f < NF; ++f) outs.push_back((o.rhs[f] + P.ko_sigma * ko[f]).id);
+        // the stencil part: live operations recorded by the gather
+        std::vector<char> live(g_tape.size(), 0);
+        for (int32_t q : outs)
+          if (q >= 0) live[q] = 1;
+        for (int64_t q = (int64_t)g_tape.size() - 1; q >= 0; --q) {
+          if (!live[q]) continue;
+          ++rhs_ops;
+          if (q < gathered) ++gather_ops;
+          if (g_tape[q].a >= 0) live[g_tape[q].a] = 1;
+          if (g_tape[q].b >= 0) live[g_tape[q].b] = 1;
+        }
+        flags |= o.flags;
+      }
+  g_tape.clear();
+  flags |= rk4_steps(P, b, 1, 0.01, 1, uf.data());
+  std::vector<int32_t> outs;
+  for (int f = 0; f < NF; ++f)
+    for (int k = 0; k < b.nz; ++k)
+      for (int j = 0; j < b.ny; ++j)
+        for (int i = 0; i < b.nx; ++i) outs.push_back(uf[f * b.fstride + cell_index(b, i, j, k)].id);
+  const int64_t step_ops = flop_count_live(outs);
+  g_tape.clear();
+  g_tape.shrink_to_fit();
+  omp_set_num_threads(keep);
+  out[0] = double(rhs_ops) / double(ncell);
+  out[1] = double(gather_ops) / double(ncell);
+  out[2] = double(step_ops) / double(ncell);
+  return flags;
+}
+
 int oracle_rk4(const double* params, const int* dims, const double* spacing, int bc, double dt, int nsteps,
                double* u) {
   Box b = make_box(dims, spacing);

@@ -5,9 +5,9 @@ of the benchmark load this module; the GPU library never does, and this module
 imports nothing from the GPU package.
 
 States are numpy float64 arrays of shape (27, nz+6, ny+6, nx+6).  Parameters
-are the 14-double vector (lambda_gb, g2, a, b, kappa1, kappa2, kappa3,
+are the 18-double vector (lambda_gb, g2, a, b, kappa1, kappa2, kappa3,
 lapse_coeff, lapse_power, lapse_advec, shift_gamma_coeff, shift_advec, eta,
-ko_sigma).
+ko_sigma, decoupled, fd_order, lambda_lin, beta).
 """
 from __future__ import annotations
 
@@ -63,6 +63,7 @@ def lib():
         L.oracle_gepp.argtypes = [ctypes.c_int, _dp, _dp, _dp]
         L.oracle_gepp.restype = ctypes.c_double
         L.oracle_stencils.argtypes = [_ip, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
+        L.oracle_flops_per_cell.argtypes = [_dp, _ip, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -277,3 +278,18 @@ def stencils(f, dx, i, j, k, order=4, ng=NG):
     out = np.zeros(16)
     lib().oracle_stencils(dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(f), i, j, k, int(order), _d(out))
     return dict(d1=out[0:3], d2=out[3:9], adv_plus=out[9:12], adv_minus=out[12:15], ko=out[15])
+
+
+def flops_per_cell(params, u, dx, ng=NG):
+    """Algorithmic flops per interior cell counted on the oracle's own code
+    (add, sub, mul, div, sqrt, cbrt, exp, pow 1 each; constants folded; only
+    operations the outputs depend on): dict with `rhs` (one right-hand side,
+    Kreiss-Oliger included), `stencils` (its stencil and Kreiss-Oliger part)
+    and `rk4_step` (one RK4 step, four right-hand sides and the updates, the
+    box taken as periodic).  u: a small box of generic (non-degenerate) data."""
+    u = _c(u)
+    out = np.zeros(3)
+    p = _c(params)
+    dims = _dims(u, ng)
+    lib().oracle_flops_per_cell(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), _d(u), _d(out))
+    return dict(rhs=out[0], stencils=out[1], rk4_step=out[2])

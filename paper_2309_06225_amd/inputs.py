@@ -24,7 +24,7 @@ FIELDS = (
 NF = len(FIELDS)
 IDX = {n: i for i, n in enumerate(FIELDS)}
 
-# Parameter order of the flat 14-double parameter vector used by the oracle
+# Parameter order of the flat 18-double parameter vector used by the oracle
 # and by the GPU binding's marshalling.
 PARAM_NAMES = (
     "lambda_gb", "g2", "a_gauge", "b_gauge", "kappa1", "kappa2", "kappa3",

@@ -872,3 +872,22 @@ def test_enforcement_definition():
     ghost = np.ones(u.shape[1:], bool)
     ghost[inner] = False
     assert np.array_equal(e[:, ghost], u[:, ghost])
+
+
+# ------------------------------------------------------------------ flop count
+def test_flop_count_convention_and_stored_counts():
+    """The op-counting scalar run through the oracle: one RK4 step costs four
+    right-hand sides plus the stage updates, whose count has a closed form per
+    field (three stage states u + (c dt) k: 2 each; the new state
+    u + (dt/6)(k1 + 2 k2 + 2 k3 + k4): 7), and the counts stored in
+    profiles/flops_per_cell.json (read by the benchmark) are the oracle's."""
+    import json
+    import os
+    from oracle import flop_count as FC
+    got = FC.counts()
+    for name, c in got.items():
+        assert c["rk4_step"] - 4 * c["rhs"] == 27 * (3 * 2 + 7), name
+        assert 0 < c["stencils"] < c["rhs"]
+    stored = json.load(open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
+                                         "flops_per_cell.json")))["per_cell"]
+    assert stored == got
