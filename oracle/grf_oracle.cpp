@@ -48,6 +48,10 @@ inline double re(double x) { return x; }
 inline double re(const cplx& x) { return x.real(); }
 inline bool finite_val(double x) { return std::isfinite(x); }
 inline bool finite_val(const cplx& x) { return std::isfinite(x.real()) && std::isfinite(x.imag()); }
+// extended precision (x87 80-bit: 64-bit significand), the reference that the
+// double-precision results are measured against on ill-conditioned data
+inline double re(long double x) { return (double)x; }
+inline bool finite_val(long double x) { return std::isfinite(x); }
 
 // ---------------------------------------------------------------- flop counting
 // A scalar that records its own arithmetic on a tape, run through the same
@@ -1659,6 +1663,20 @@ int oracle_flops_per_cell(const double* params, const int* dims, const double* s
   out[0] = double(rhs_ops) / double(ncell);
   out[1] = double(gather_ops) / double(ncell);
   out[2] = double(step_ops) / double(ncell);
+  return flags;
+}
+
+// The same RK4 steps carried out in long double throughout (state, stencils,
+// algebra, the per-cell solve); u is read and the result written back rounded
+// to double.
+int oracle_rk4_ld(const double* params, const int* dims, const double* spacing, int bc, double dt, int nsteps,
+                  double* u) {
+  Box b = make_box(dims, spacing);
+  Params<long double> P = read_params<long double>(params, nullptr);
+  const int64_t ntot = b.fstride * NF;
+  std::vector<long double> ul(u, u + ntot);
+  const int flags = rk4_steps(P, b, bc, (long double)dt, nsteps, ul.data());
+  for (int64_t q = 0; q < ntot; ++q) u[q] = (double)ul[q];
   return flags;
 }
 

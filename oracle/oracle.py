@@ -57,6 +57,7 @@ def lib():
         L.oracle_ghost_rhs.argtypes = [_ip, _dp, _dp, _dp, _dp]
         L.oracle_rk4_bc.argtypes = [_dp, _ip, _dp, _dp, ctypes.c_double, ctypes.c_int, _dp]
         L.oracle_rk4.argtypes = [_dp, _ip, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp]
+        L.oracle_rk4_ld.argtypes = [_dp, _ip, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp]
         L.oracle_rk4_cs.argtypes = [_dp, _dp, _ip, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp, _dp]
         L.oracle_rhs_point.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, _dp]
         L.oracle_enforce.argtypes = [_ip, _dp, ctypes.c_double, ctypes.c_double]
@@ -221,6 +222,18 @@ def rk4(params, u, dx, dt, nsteps, periodic, ng=NG):
     dims = _dims(u, ng)
     flags = lib().oracle_rk4(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), 1 if periodic else 0,
                              float(dt), int(nsteps), _d(u))
+    return u, flags
+
+
+def rk4_ld(params, u, dx, dt, nsteps, periodic, ng=NG):
+    """nsteps classic RK4 steps carried out in long double (x87 extended
+    precision) throughout, the result rounded to double: a reference for the
+    double-precision results; returns (new state, flags)."""
+    u = _c(u).copy()
+    p = _c(params)
+    dims = _dims(u, ng)
+    flags = lib().oracle_rk4_ld(_d(p), dims.ctypes.data_as(_ip), _d(_spacing(dx)), 1 if periodic else 0,
+                                float(dt), int(nsteps), _d(u))
     return u, flags
 
 

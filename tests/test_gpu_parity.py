@@ -136,21 +136,6 @@ def test_rhs_parity_full_size_sampled():
     assert (num / den).max() <= 1e-12, dict(zip(I.FIELDS, num / den))
 
 
-def _ulp_floor(p, u, dx, dt, nsteps, periodic, seeds=(0, 1)):
-    """The oracle's own sensitivity: relative per-field change of the nsteps
-    result when every input value is moved by one unit in the last place."""
-    a, _ = O.rk4(I.params_vector(p), u, dx, dt, nsteps, periodic=periodic)
-    worst = 0.0
-    for sd in seeds:
-        rng = np.random.default_rng(sd)
-        up = u * (1 + np.finfo(float).eps * rng.choice([-1.0, 1.0], size=u.shape))
-        if periodic:
-            up = I.wrap_ghosts(up)
-        b, _ = O.rk4(I.params_vector(p), up, dx, dt, nsteps, periodic=periodic)
-        worst = max(worst, rel_err_per_field(b, a, interior=False).max())
-    return a, worst
-
-
 def test_rhs_parity_two_punctures_256_sampled():
     """256^3 two-puncture box at dx = M/16 with lambda_gb = 0.2, g2 = 0.02 (the
     large single-box workload): GPU right-hand side at every cell, oracle at
@@ -177,26 +162,56 @@ def test_rhs_parity_two_punctures_256_sampled():
 
 
 def test_rk4_ten_steps_periodic():
-    """Flat space + 1e-6 noise + pulse, 32^3 periodic, 10 steps.  With O(1)
-    fields carrying 1e-6 perturbations the map is ill-conditioned: a one-ulp
-    change of the input moves the oracle's own result by ~7e-10 relative.  The
-    GPU (whose stencil sums round exactly as the oracle's) must stay within
-    1e-10 or that floor, whichever is larger."""
-    print("case: 10 RK4 steps 32^3 periodic", flush=True)
+    """Flat space + 1e-6 noise + pulse, 32^3 periodic, 10 steps (the plain
+    small workload).  With O(1) fields carrying 1e-6 perturbations the map is
+    ill-conditioned: the double-precision oracle itself is off the
+    extended-precision result (the same oracle run in long double) by up to
+    about 4e-10 relative per field.  Each field of the GPU result must be
+    within max(1e-10, 1.5 x the double oracle's own error) of that reference."""
+    print("case: 10 RK4 steps 32^3 periodic against the long-double reference", flush=True)
     p = I.default_params()
     u = I.flat_noise_pulse(32, 0.25, seed=0)
     dt = 0.0625
-    o, floor = _ulp_floor(p, u, 0.25, dt, 10, True)
+    pv = I.params_vector(p)
+    ref, fl = O.rk4_ld(pv, u, 0.25, dt, 10, periodic=True)
+    o, fo = O.rk4(pv, u, 0.25, dt, 10, periodic=True)
+    assert fl == 0 and fo == 0
     ut = torch.from_numpy(u).to(DEV)
     st = G.Stepper(G.make_params(p), G.box_of(ut, 0.25, G.BC_PERIODIC), ut, dt)
     for _ in range(10):
         st.step()
     code, bits = st.status()
-    g = st.u.cpu().numpy()
     assert code == 0
+    g = st.u.cpu().numpy()
+    e_gpu = rel_err_per_field(g, ref, interior=False)
+    e_orc = rel_err_per_field(o, ref, interior=False)
+    bound = np.maximum(1e-10, 1.5 * e_orc)
+    print(f"10 steps: GPU vs long double {e_gpu.max():.3e}, double oracle vs long double {e_orc.max():.3e}",
+          flush=True)
+    assert np.all(e_gpu <= bound), {f: (e_gpu[i], bound[i]) for i, f in enumerate(I.FIELDS) if e_gpu[i] > bound[i]}
+
+
+def test_rk4_ten_steps_single_puncture_128_full_box():
+    """The headline workload itself: the 128^3 single-puncture box at dx = M/8
+    with frozen ghosts, 10 RK4 steps on the GPU against the oracle's 10 steps
+    of the whole box, every cell: within 1e-10 relative per field."""
+    print("case: 10 RK4 steps single puncture 128^3 (oracle ~1-2 min on the host)", flush=True)
+    p = I.default_params()
+    dx = 1.0 / 8.0
+    u = I.single_puncture(128, dx)
+    ut = torch.from_numpy(u).to(DEV)
+    st = G.Stepper(G.make_params(p), G.box_of(ut, dx), ut, 0.25 * dx)
+    for _ in range(10):
+        st.step()
+    code, bits = st.status()
+    assert code == 0, bits
+    g = st.u.cpu().numpy()
+    del st, ut
+    o, fo = O.rk4(I.params_vector(p), u, dx, 0.25 * dx, 10, periodic=False)
+    assert fo == 0
     e = rel_err_per_field(g, o, interior=False)
-    print(f"10-step max rel err {e.max():.3e}, one-ulp input floor {floor:.3e}", flush=True)
-    assert e.max() <= max(1e-10, floor), (e.max(), floor, dict(zip(I.FIELDS, e)))
+    print(f"128^3, 10 steps: max rel err {e.max():.3e}", flush=True)
+    assert e.max() <= 1e-10, dict(zip(I.FIELDS, e))
 
 
 def test_rk4_ten_steps_puncture_strict():
@@ -205,13 +220,13 @@ def test_rk4_ten_steps_puncture_strict():
     print("case: 10 RK4 steps 24^3 puncture", flush=True)
     p = I.default_params()
     u = I.single_puncture(24, 0.25)
-    o, floor = _ulp_floor(p, u, 0.25, 0.0625, 10, False, seeds=(0,))
+    o, _ = O.rk4(I.params_vector(p), u, 0.25, 0.0625, 10, periodic=False)
     ut = torch.from_numpy(u).to(DEV)
     st = G.Stepper(G.make_params(p), G.box_of(ut, 0.25), ut, 0.0625)
     for _ in range(10):
         st.step()
     e = rel_err_per_field(st.u.cpu().numpy(), o, interior=False)
-    print(f"10-step max rel err {e.max():.3e}, one-ulp input floor {floor:.3e}", flush=True)
+    print(f"10-step max rel err {e.max():.3e}", flush=True)
     assert e.max() <= 1e-10, dict(zip(I.FIELDS, e))
 
 
