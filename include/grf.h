@@ -131,11 +131,17 @@ typedef struct {
 size_t grf_workspace_bytes(const grf_box* box);
 
 /* Right-hand side d_t u (including Kreiss-Oliger) at interior cells of u,
- * written to the interior cells of rhs (state layout; ghosts of rhs untouched). */
+ * written to the interior cells of rhs (state layout; ghosts of rhs untouched).
+ * The operation: the CCZ4 equations in the modified puncture gauge coupled to
+ * the scalar with the four-derivative scalar-tensor terms (Summary; Key
+ * features, "Stable gauge evolution" and "Modified gravity theories"),
+ * discretised with the finite differences of Key features, "Accuracy". */
 grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u, double* rhs,
                         void* workspace, size_t workspace_bytes, hipStream_t stream);
 
-/* One classic RK4 stage (c = 1/2, 1/2, 1; weights 1, 2, 2, 1 over 6), stage in 1..4.
+/* One classic RK4 stage (c = 1/2, 1/2, 1; weights 1, 2, 2, 1 over 6), stage in 1..4:
+ * the method-of-lines time integration of the right-hand side above (Key
+ * features, "Accuracy").
  * Reads u0 (state at the start of the step) and us (the stage state; us == u0 at
  * stage 1), computes k = RHS(us) and, on interior cells,
  *   stage 1: acc  = k;             unext = u0 + (dt/2) k
@@ -249,7 +255,9 @@ grf_status grf_rk4_stage_bc(const grf_params* p, const grf_box* box, const grf_b
                             const double* u0, const double* us, double* unext, double* acc, double* gacc,
                             void* workspace, size_t workspace_bytes, hipStream_t stream);
 
-/* Vector-Jacobian product of the right-hand side: with w a cotangent of
+/* Vector-Jacobian product of the right-hand side (the adjoint of the
+ * operation of grf_rhs_eval, for gradients of observables with respect to the
+ * couplings and the initial data): with w a cotangent of
  * grf_rhs_eval's output (state layout, interior cells read),
  *   u_bar     += (d RHS / d u)^T w      over all cells of u, ghosts included,
  *   theta_bar += (d RHS / d (lambda_gb, g2))^T w   (2 doubles, device memory),
@@ -325,22 +333,27 @@ grf_status grf_energy_densities(const grf_params* p, const grf_box* box, const d
 grf_status grf_coupling_diagnostics(const grf_params* p, const grf_box* box, const double* u, double* out,
                                     void* workspace, size_t workspace_bytes, hipStream_t stream);
 
-/* ---- Batched boxes (uneven sizes and refinement levels, frozen ghosts).
- * One RK4 step of the batch is four stages; each stage is one persistent
- * stencil launch per stencil variant in use and one pointwise launch,
- * covering every box (work lists of (box, tile or column chunk) entries,
- * fixed assignment to workgroups, and (box, 64-cell wave) entries, one per
- * workgroup; no atomics).
+/* ---- Batched boxes (uneven sizes and refinement levels, frozen ghosts): the
+ * many boxes per refinement level of the paper's adaptive-mesh runs (Key
+ * features, "Adaptive Mesh Refinement") advanced together on one GPU.
+ * One RK4 stage of the batch is one persistent stencil launch per stencil
+ * variant in use and one pointwise launch, covering every box (work lists of
+ * (box, tile or column chunk) entries, fixed assignment to workgroups, and
+ * (box, 64-cell wave) entries, one per workgroup; no atomics); one RK4 step is
+ * the four stages in order.
  * Per cell the device code is the one of grf_rk4_stage, so results are
  * bitwise identical to per-box launches (grf_batch_step_perbox runs that
  * reference form on the same buffers).  Boxes use stencil variant 8 (the
  * z-marching 16x16x32 form) until grf_batch_autotune chooses.
- *   u[b]      state of box b (device, caller-owned); after an even number of
- *             steps the current state is back in u[b], after an odd number it
- *             is in the batch's second buffer (grf_batch_state gives it);
+ *   u[b]      state of box b (device, caller-owned); every step writes the new
+ *             state back into u[b] (stage 1 u -> A, 2 A -> B, 3 B -> A,
+ *             4 A -> u over the step's start state, which is safe because a
+ *             cell's new value reads the start state only at that cell);
+ *             between the stages of a step u[b] holds the step's start state;
  *   dts[b]    time step of box b (host array, copied);
- *   scratch   caller-owned device memory of grf_batch_scratch_bytes: two
- *             stage states, the accumulator and the derivative records per box.
+ *   scratch   caller-owned device memory of grf_batch_scratch_bytes: the two
+ *             stage states A and B, the accumulator and the derivative
+ *             records per box.
  * The batch object (host) owns its device descriptor and work-list arrays
  * (allocated by grf_batch_create / grf_batch_autotune, freed by
  * grf_batch_destroy) and a status word (grf_batch_status_fetch). */
@@ -348,11 +361,16 @@ typedef struct grf_batch grf_batch;
 size_t grf_batch_scratch_bytes(const grf_box* boxes, int nboxes);
 grf_status grf_batch_create(const grf_params* p, const grf_box* boxes, int nboxes, double* const* u,
                             const double* dts, void* scratch, size_t scratch_bytes, grf_batch** out);
+/* One RK4 stage (1..4, GRF_EINVAL otherwise) of every box of the batch, the
+ * stage formulas of grf_rk4_stage; stages must run in the order 1, 2, 3, 4
+ * (a multi-GPU caller would exchange halos between them). */
+grf_status grf_batch_rk4_stage(grf_batch* batch, int stage, hipStream_t stream);
+/* One RK4 step: grf_batch_rk4_stage for stages 1 to 4. */
 grf_status grf_batch_step(grf_batch* batch, hipStream_t stream);
 grf_status grf_batch_step_perbox(grf_batch* batch, hipStream_t stream);
-/* Captures two batched RK4 steps (so that buffer roles are the same before
- * and after every replay) on a non-null stream into an executable graph. */
-grf_status grf_batch_capture(grf_batch* batch, hipStream_t stream, hipGraphExec_t* exec);
+/* Captures one batched RK4 step (its four stages) on a non-null stream into
+ * an executable graph; every replay advances the batch by one step. */
+grf_status grf_batch_capture_step(grf_batch* batch, hipStream_t stream, hipGraphExec_t* exec);
 /* Chooses a stencil variant per box-shape class among those the batch can
  * run (tiled 0..4, z-marching 5, 6 and 8; see grf_set_tile_variant): each variant is
  * timed on one box of each class alone, giving a per-class mix; then the mix
@@ -362,6 +380,7 @@ grf_status grf_batch_capture(grf_batch* batch, hipStream_t stream, hipGraphExec_
  * cached per shape class for the life of the process; classes already cached
  * keep their variant in later batches. */
 grf_status grf_batch_autotune(grf_batch* batch, hipStream_t stream);
+/* The buffer holding box `box`'s current state: always u[box]. */
 grf_status grf_batch_state(const grf_batch* batch, int box, double** current);
 grf_status grf_batch_tile_variant(const grf_batch* batch, int box, int* variant);
 /* Sets the stencil variant of one box (0..6 or 8; GRF_EINVAL otherwise) and
@@ -371,7 +390,7 @@ grf_status grf_batch_tile_variant(const grf_batch* batch, int box, int* variant)
 grf_status grf_batch_set_tile_variant(grf_batch* batch, int box, int variant);
 grf_status grf_batch_status_fetch(const grf_batch* batch, hipStream_t stream, uint32_t* bits);
 void grf_batch_destroy(grf_batch* batch);
-/* Launch / destroy an executable graph made by grf_batch_capture. */
+/* Launch / destroy an executable graph made by grf_batch_capture_step. */
 grf_status grf_graph_launch(hipGraphExec_t exec, hipStream_t stream);
 grf_status grf_graph_destroy(hipGraphExec_t exec);
 

@@ -11,8 +11,8 @@ namespace grf {
 
 struct BatchBoxDev {
   BoxDev bd;
-  double* u;    // state buffer A (the state after an even number of steps)
-  double* ub;   // state buffer B (after an odd number of steps; stage scratch otherwise)
+  double* u;    // the state (caller's buffer; each step writes its new state here)
+  double* ub;   // stage scratch
   double* ua;   // stage scratch
   double* acc;  // compact accumulator
   double* D;    // derivative records
@@ -29,25 +29,26 @@ struct CellEntry {  // 64 cells c0 .. c0 + 63 of a box (fewer at its end)
   int64_t c0;
 };
 
-// Buffer roles of RK4 stage s (1..4) for step parity p: base state, stage input,
-// stage output.  Parity 0 steps u -> ub, parity 1 steps ub -> u.
-__device__ __forceinline__ void stage_roles(const BatchBoxDev& B, int stage, int parity, const double*& base,
+// Buffer roles of RK4 stage s (1..4): base state, stage input, stage output.
+// Every step maps u to u: stage 1 u -> ua, 2 ua -> ub, 3 ub -> ua, 4 ua -> u.
+// The last stage writes the new state over its base; that is safe because a
+// cell's new value depends on the base only at that cell, and each lane reads
+// a cell's base values before it writes them (the stencils of stage 4 read ua).
+__device__ __forceinline__ void stage_roles(const BatchBoxDev& B, int stage, const double*& base,
                                             const double*& in, double*& out) {
-  double* b0 = parity ? B.ub : B.u;
-  double* fin = parity ? B.u : B.ub;
-  base = b0;
+  base = B.u;
   switch (stage) {
-    case 1: in = b0; out = B.ua; break;
-    case 2: in = B.ua; out = fin; break;
-    case 3: in = fin; out = B.ua; break;
-    default: in = B.ua; out = fin; break;
+    case 1: in = B.u; out = B.ua; break;
+    case 2: in = B.ua; out = B.ub; break;
+    case 3: in = B.ub; out = B.ua; break;
+    default: in = B.ua; out = B.u; break;
   }
 }
 
 template <int TX, int TY, int TZ>
 __global__ __launch_bounds__(TX* TY* TZ) void k_deriv_batch(const BatchBoxDev* __restrict__ boxes,
                                                             const TileEntry* __restrict__ entries, int nentries,
-                                                            int stage, int parity, double ko_sigma, int shift_adv) {
+                                                            int stage, double ko_sigma, int shift_adv) {
   __shared__ double t[(TZ + 6) * (TY + 6) * (TX + 6)];
   const int64_t total = (int64_t)nentries * NF;
   for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_deriv_batch(const BatchBoxDev* _
     const BatchBoxDev B = boxes[en.box];
     const double *base, *in;
     double* out;
-    stage_roles(B, stage, parity, base, in, out);
+    stage_roles(B, stage, base, in, out);
     deriv_tile<TX, TY, TZ>(B.bd, en.tile, f, in, B.D, ko_sigma, shift_adv, nullptr, t);
   }
 }
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_deriv_batch(const BatchBoxDev* _
 template <int TX, int TY, int ZC>
 __global__ __launch_bounds__(TX* TY) void k_deriv_batch_zm(const BatchBoxDev* __restrict__ boxes,
                                                            const TileEntry* __restrict__ entries, int nentries,
-                                                           int stage, int parity, double ko_sigma, int shift_adv) {
+                                                           int stage, double ko_sigma, int shift_adv) {
   __shared__ double t[8 * (TX + 6) * (TY + 6)];
   const int64_t total = (int64_t)nentries * NF;
   for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(TX* TY) void k_deriv_batch_zm(const BatchBoxDev* __
     const BatchBoxDev B = boxes[en.box];
     const double *base, *in;
     double* out;
-    stage_roles(B, stage, parity, base, in, out);
+    stage_roles(B, stage, base, in, out);
     zm_column<TX, TY, ZC>(B.bd, en.tile, f, in, B.D, ko_sigma, shift_adv, nullptr, t);
   }
 }
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(TX* TY) void k_deriv_batch_zm(const BatchBoxDev* __
 template <int MODE, int SHIFTADV>
 __global__ __launch_bounds__(kStagedThreads) void k_point_batch(const BatchBoxDev* __restrict__ boxes,
                                                                 const CellEntry* __restrict__ entries, int nentries,
-                                                                int stage, int parity, grf_point_params P,
+                                                                int stage, grf_point_params P,
                                                                 unsigned* __restrict__ status) {
   __shared__ double lbuf0_[GRF_STAGE_SLOTS * 64];
   __shared__ double lbuf1_[GRF_STAGE_SLOTS * 64];
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(kStagedThreads) void k_point_batch(const BatchBoxDe
   const BatchBoxDev B = boxes[en.box];
   const double *base, *in;
   double* out;
-  stage_roles(B, stage, parity, base, in, out);
+  stage_roles(B, stage, base, in, out);
   StageCoef sc;
   sc.cnext = stage == 4 ? B.dt / 6.0 : (stage == 3 ? 1.0 * B.dt : 0.5 * B.dt);
   staged_wave<MODE, SHIFTADV>(B.bd, en.c0, P, in, B.D, base, out, B.acc, sc, status, (grf_lds_double*)lbuf0_,

@@ -28,7 +28,7 @@ hipError_t launch_deriv6(const BoxDev& bd, const double* u, double* D, double si
                          hipStream_t st);
 // batched stencil stage: tiled variants 0..4 and the z-marching variant 8
 hipError_t launch_deriv_batch(int variant, int grid, const BatchBoxDev* boxes, const TileEntry* tiles, int ntiles,
-                              int stage, int parity, double sigma, int sa, hipStream_t st);
+                              int stage, double sigma, int sa, hipStream_t st);
 int grid_deriv_batch(int variant, int64_t work);
 hipError_t launch_periodic(const BoxDev& bd, double* u, hipStream_t st);
 hipError_t launch_status_clear(unsigned* s, hipStream_t st);
@@ -75,12 +75,12 @@ template <> hipError_t launch_point_m<4>(int, const BoxDev&, const grf_point_par
 // batched pointwise stage (stage 1 -> mode 1, stages 2-3 -> mode 2, stage 4 -> mode 4)
 template <int MODE>
 hipError_t launch_point_batch_m(int sa, int grid, const BatchBoxDev* boxes, const CellEntry* cells, int ncells,
-                                int stage, int parity, const grf_point_params& pp, unsigned* status, hipStream_t st);
-template <> hipError_t launch_point_batch_m<1>(int, int, const BatchBoxDev*, const CellEntry*, int, int, int,
+                                int stage, const grf_point_params& pp, unsigned* status, hipStream_t st);
+template <> hipError_t launch_point_batch_m<1>(int, int, const BatchBoxDev*, const CellEntry*, int, int,
                                                const grf_point_params&, unsigned*, hipStream_t);
-template <> hipError_t launch_point_batch_m<2>(int, int, const BatchBoxDev*, const CellEntry*, int, int, int,
+template <> hipError_t launch_point_batch_m<2>(int, int, const BatchBoxDev*, const CellEntry*, int, int,
                                                const grf_point_params&, unsigned*, hipStream_t);
-template <> hipError_t launch_point_batch_m<4>(int, int, const BatchBoxDev*, const CellEntry*, int, int, int,
+template <> hipError_t launch_point_batch_m<4>(int, int, const BatchBoxDev*, const CellEntry*, int, int,
                                                const grf_point_params&, unsigned*, hipStream_t);
 template <int MODE>
 int grid_point_batch_m(int sa, int64_t work);

@@ -237,12 +237,12 @@ hipError_t launch_pointwise(int path, int mode, int sa, const BoxDev& bd, const 
 }
 
 hipError_t launch_point_batch(int mode, int sa, int grid, const BatchBoxDev* boxes, const CellEntry* cells,
-                              int ncells, int stage, int parity, const grf_point_params& pp, unsigned* status,
+                              int ncells, int stage, const grf_point_params& pp, unsigned* status,
                               hipStream_t st) {
   switch (mode) {
-    case 1: return launch_point_batch_m<1>(sa, grid, boxes, cells, ncells, stage, parity, pp, status, st);
-    case 2: return launch_point_batch_m<2>(sa, grid, boxes, cells, ncells, stage, parity, pp, status, st);
-    default: return launch_point_batch_m<4>(sa, grid, boxes, cells, ncells, stage, parity, pp, status, st);
+    case 1: return launch_point_batch_m<1>(sa, grid, boxes, cells, ncells, stage, pp, status, st);
+    case 2: return launch_point_batch_m<2>(sa, grid, boxes, cells, ncells, stage, pp, status, st);
+    default: return launch_point_batch_m<4>(sa, grid, boxes, cells, ncells, stage, pp, status, st);
   }
 }
 
@@ -818,7 +818,6 @@ struct grf_batch {
   grf::CellEntry* cells = nullptr;
   int ncells = 0;
   unsigned* status = nullptr;
-  int parity = 0;
   int grid_deriv[grf::kTileVariantsMax] = {};
   int grid_point = 0;
 };
@@ -850,7 +849,7 @@ grf_status batch_stage(grf_batch* B, int stage, hipStream_t st) {
   for (int v : kBatchVariants) {
     if (!B->ntiles[v]) continue;
     prof_mark(0, st);
-    GRF_HIP_CHECK(launch_deriv_batch(v, B->grid_deriv[v], B->dev, B->tiles[v], B->ntiles[v], stage, B->parity,
+    GRF_HIP_CHECK(launch_deriv_batch(v, B->grid_deriv[v], B->dev, B->tiles[v], B->ntiles[v], stage,
                                      B->params.ko_sigma, B->params.shift_advec != 0.0, st));
     prof_mark(0, st);
   }
@@ -858,7 +857,7 @@ grf_status batch_stage(grf_batch* B, int stage, hipStream_t st) {
   prof_mark(1, st);
   const int mode = stage == 1 ? 1 : (stage == 4 ? 4 : 2);
   GRF_HIP_CHECK(launch_point_batch(mode, B->params.shift_advec != 0.0, B->grid_point, B->dev, B->cells, B->ncells,
-                                   stage, B->parity, pp, B->status, st));
+                                   stage, pp, B->status, st));
   prof_mark(1, st);
   return GRF_OK;
 }
@@ -955,12 +954,17 @@ void grf_batch_destroy(grf_batch* B) {
   delete B;
 }
 
+grf_status grf_batch_rk4_stage(grf_batch* B, int stage, hipStream_t stream) {
+  if (!B) return fail(GRF_EINVAL, "batch is null");
+  if (stage < 1 || stage > 4) return fail(GRF_EINVAL, "stage must be 1..4 (got %d)", stage);
+  return batch_stage(B, stage, stream);
+}
+
 grf_status grf_batch_step(grf_batch* B, hipStream_t stream) {
   if (!B) return fail(GRF_EINVAL, "batch is null");
   grf_status s;
   for (int stage = 1; stage <= 4; ++stage)
-    if ((s = batch_stage(B, stage, stream)) != GRF_OK) return s;
-  B->parity ^= 1;
+    if ((s = grf_batch_rk4_stage(B, stage, stream)) != GRF_OK) return s;
   return GRF_OK;
 }
 
@@ -972,30 +976,27 @@ grf_status grf_batch_step_perbox(grf_batch* B, hipStream_t stream) {
     const int mode = stage == 1 ? 1 : (stage == 4 ? 4 : 2);
     for (size_t b = 0; b < B->host.size(); ++b) {
       const BatchBoxDev& d = B->host[b];
-      double* b0 = B->parity ? d.ub : d.u;
-      double* fin = B->parity ? d.u : d.ub;
-      const double* in = stage == 1 ? b0 : (stage == 3 ? fin : d.ua);
-      double* o = (stage == 1 || stage == 3) ? d.ua : fin;
+      // the buffer roles of stage_roles: u -> ua -> ub -> ua -> u
+      const double* in = stage == 1 ? d.u : (stage == 3 ? d.ub : d.ua);
+      double* o = stage == 2 ? d.ub : (stage == 4 ? d.u : d.ua);
       const StageCoef sc{stage == 4 ? d.dt / 6.0 : (stage == 3 ? 1.0 * d.dt : 0.5 * d.dt)};
       prof_mark(0, stream);
       GRF_HIP_CHECK(launch_deriv(B->variant[b], d.bd, in, d.D, B->params.ko_sigma, sa, nullptr, stream));
       prof_mark(0, stream);
       prof_mark(1, stream);
-      GRF_HIP_CHECK(launch_staged(mode, sa, d.bd, pp, in, d.D, b0, o, d.acc, sc, B->status, stream));
+      GRF_HIP_CHECK(launch_staged(mode, sa, d.bd, pp, in, d.D, d.u, o, d.acc, sc, B->status, stream));
       prof_mark(1, stream);
     }
   }
-  B->parity ^= 1;
   return GRF_OK;
 }
 
-grf_status grf_batch_capture(grf_batch* B, hipStream_t stream, hipGraphExec_t* exec) {
+grf_status grf_batch_capture_step(grf_batch* B, hipStream_t stream, hipGraphExec_t* exec) {
   if (!B || !exec) return fail(GRF_EINVAL, "null argument");
   if (stream == 0) return fail(GRF_EINVAL, "capture needs a non-null stream");
   hipGraph_t graph;
   GRF_HIP_CHECK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-  grf_status s = GRF_OK;
-  for (int k = 0; k < 2 && s == GRF_OK; ++k) s = grf_batch_step(B, stream);
+  grf_status s = grf_batch_step(B, stream);
   hipError_t e = hipStreamEndCapture(stream, &graph);
   if (s != GRF_OK) return s;
   if (e != hipSuccess) return fail(GRF_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
@@ -1075,7 +1076,7 @@ grf_status grf_batch_autotune(grf_batch* B, hipStream_t stream) {
           [&]() -> grf_status {
             for (int v : kBatchVariants) {
               if (!B->ntiles[v]) continue;
-              GRF_HIP_CHECK(launch_deriv_batch(v, B->grid_deriv[v], B->dev, B->tiles[v], B->ntiles[v], 1, B->parity,
+              GRF_HIP_CHECK(launch_deriv_batch(v, B->grid_deriv[v], B->dev, B->tiles[v], B->ntiles[v], 1,
                                                B->params.ko_sigma, sa, stream));
             }
             return GRF_OK;
@@ -1098,7 +1099,7 @@ grf_status grf_batch_autotune(grf_batch* B, hipStream_t stream) {
 
 grf_status grf_batch_state(const grf_batch* B, int box, double** current) {
   if (!B || !current || box < 0 || box >= (int)B->host.size()) return fail(GRF_EINVAL, "bad argument");
-  *current = B->parity ? B->host[box].ub : B->host[box].u;
+  *current = B->host[box].u;
   return GRF_OK;
 }
 

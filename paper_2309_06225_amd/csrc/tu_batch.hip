@@ -7,14 +7,14 @@ namespace grf {
 
 template <>
 hipError_t launch_point_batch_m<GRF_TU_MODE>(int sa, int grid, const BatchBoxDev* boxes, const CellEntry* cells,
-                                             int ncells, int stage, int parity, const grf_point_params& pp,
+                                             int ncells, int stage, const grf_point_params& pp,
                                              unsigned* status, hipStream_t st) {
   if (sa)
     hipLaunchKernelGGL((k_point_batch<GRF_TU_MODE, 1>), dim3(grid), dim3(kStagedThreads), 0, st, boxes, cells, ncells,
-                       stage, parity, pp, status);
+                       stage, pp, status);
   else
     hipLaunchKernelGGL((k_point_batch<GRF_TU_MODE, 0>), dim3(grid), dim3(kStagedThreads), 0, st, boxes, cells, ncells,
-                       stage, parity, pp, status);
+                       stage, pp, status);
   return hipGetLastError();
 }
 

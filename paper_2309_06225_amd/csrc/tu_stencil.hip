@@ -256,32 +256,32 @@ int grid_deriv_batch(int variant, int64_t work) {
 
 template <int TX, int TY, int TZ>
 hipError_t launch_deriv_batch_t(int grid, const BatchBoxDev* boxes, const TileEntry* tiles, int ntiles, int stage,
-                                int parity, double sigma, int sa, hipStream_t st) {
+                                double sigma, int sa, hipStream_t st) {
   hipLaunchKernelGGL((k_deriv_batch<TX, TY, TZ>), dim3(grid), dim3(TX * TY * TZ), 0, st, boxes, tiles, ntiles, stage,
-                     parity, sigma, sa);
+                     sigma, sa);
   return hipGetLastError();
 }
 
 hipError_t launch_deriv_batch(int variant, int grid, const BatchBoxDev* boxes, const TileEntry* tiles, int ntiles,
-                              int stage, int parity, double sigma, int sa, hipStream_t st) {
+                              int stage, double sigma, int sa, hipStream_t st) {
   switch (variant) {
     case 5:
       hipLaunchKernelGGL((k_deriv_batch_zm<16, 8, 32>), dim3(grid), dim3(128), 0, st, boxes, tiles, ntiles, stage,
-                         parity, sigma, sa);
+                         sigma, sa);
       return hipGetLastError();
     case 6:
       hipLaunchKernelGGL((k_deriv_batch_zm<32, 8, 32>), dim3(grid), dim3(256), 0, st, boxes, tiles, ntiles, stage,
-                         parity, sigma, sa);
+                         sigma, sa);
       return hipGetLastError();
     case 8:
       hipLaunchKernelGGL((k_deriv_batch_zm<16, 16, 32>), dim3(grid), dim3(256), 0, st, boxes, tiles, ntiles, stage,
-                         parity, sigma, sa);
+                         sigma, sa);
       return hipGetLastError();
-    case 1: return launch_deriv_batch_t<32, 4, 4>(grid, boxes, tiles, ntiles, stage, parity, sigma, sa, st);
-    case 2: return launch_deriv_batch_t<8, 8, 8>(grid, boxes, tiles, ntiles, stage, parity, sigma, sa, st);
-    case 3: return launch_deriv_batch_t<16, 16, 2>(grid, boxes, tiles, ntiles, stage, parity, sigma, sa, st);
-    case 4: return launch_deriv_batch_t<64, 4, 2>(grid, boxes, tiles, ntiles, stage, parity, sigma, sa, st);
-    default: return launch_deriv_batch_t<16, 8, 4>(grid, boxes, tiles, ntiles, stage, parity, sigma, sa, st);
+    case 1: return launch_deriv_batch_t<32, 4, 4>(grid, boxes, tiles, ntiles, stage, sigma, sa, st);
+    case 2: return launch_deriv_batch_t<8, 8, 8>(grid, boxes, tiles, ntiles, stage, sigma, sa, st);
+    case 3: return launch_deriv_batch_t<16, 16, 2>(grid, boxes, tiles, ntiles, stage, sigma, sa, st);
+    case 4: return launch_deriv_batch_t<64, 4, 2>(grid, boxes, tiles, ntiles, stage, sigma, sa, st);
+    default: return launch_deriv_batch_t<16, 8, 4>(grid, boxes, tiles, ntiles, stage, sigma, sa, st);
   }
 }
 

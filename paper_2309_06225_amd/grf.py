@@ -92,7 +92,8 @@ def lib():
                                        ctypes.c_size_t, ctypes.POINTER(_vp)]
         for name in ("grf_batch_step", "grf_batch_step_perbox", "grf_batch_autotune"):
             getattr(L, name).argtypes = [_vp, _vp]
-        L.grf_batch_capture.argtypes = [_vp, _vp, ctypes.POINTER(_vp)]
+        L.grf_batch_capture_step.argtypes = [_vp, _vp, ctypes.POINTER(_vp)]
+        L.grf_batch_rk4_stage.argtypes = [_vp, ctypes.c_int, _vp]
         L.grf_batch_state.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_vp)]
         L.grf_batch_tile_variant.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.grf_batch_set_tile_variant.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
@@ -119,7 +120,7 @@ def lib():
                      "grf_status_clear", "grf_set_tile_variant", "grf_set_stage_path", "grf_set_slab_planes", "grf_rk4_stage_static",
                      "grf_prof_begin", "grf_prof_end",
                      "grf_rk4_step_vjp", "grf_enforce", "grf_batch_create", "grf_batch_step", "grf_batch_step_perbox",
-                     "grf_batch_autotune", "grf_batch_capture", "grf_batch_state", "grf_batch_tile_variant",
+                     "grf_batch_autotune", "grf_batch_capture_step", "grf_batch_rk4_stage", "grf_batch_state", "grf_batch_tile_variant",
                      "grf_batch_set_tile_variant",
                      "grf_batch_status_fetch", "grf_graph_launch", "grf_graph_destroy"):
             getattr(L, name).restype = ctypes.c_int
@@ -414,8 +415,8 @@ class Batch:
     """Boxes of uneven sizes and levels advanced together (frozen ghosts).
 
     states: list of device tensors (state layout, one per box), advanced in
-    place: after an even number of steps each box's state is back in its
-    tensor; `state(b)` returns the current state of box b at any time."""
+    place: after every step each box's new state is in its tensor (the stage
+    states live in the batch's scratch); `state(b)` returns that tensor."""
 
     def __init__(self, params: Params, boxes, states, dts):
         self.params = params
@@ -437,6 +438,10 @@ class Batch:
     def step(self, stream=None):
         _check(lib().grf_batch_step(self.h, _stream(stream)))
 
+    def rk4_stage(self, stage, stream=None):
+        """One RK4 stage (1..4) of every box; four in order make one step."""
+        _check(lib().grf_batch_rk4_stage(self.h, int(stage), _stream(stream)))
+
     def step_perbox(self, stream=None):
         _check(lib().grf_batch_step_perbox(self.h, _stream(stream)))
 
@@ -452,9 +457,10 @@ class Batch:
         _check(lib().grf_batch_set_tile_variant(self.h, int(b), int(v)))
 
     def capture(self, stream):
-        """Executable graph of two batched steps, captured on `stream` (non-default)."""
+        """Executable graph of one batched RK4 step (four stages), captured on
+        `stream` (non-default); every replay advances the batch one step."""
         g = _vp()
-        _check(lib().grf_batch_capture(self.h, _stream(stream), ctypes.byref(g)))
+        _check(lib().grf_batch_capture_step(self.h, _stream(stream), ctypes.byref(g)))
         self.graphs.append(g)
         return g
 
@@ -464,11 +470,8 @@ class Batch:
     def state(self, b):
         p = _vp()
         _check(lib().grf_batch_state(self.h, int(b), ctypes.byref(p)))
-        if p.value == self.states[b].data_ptr():
-            return self.states[b]
-        off = (p.value - self.scratch.data_ptr()) // 8
-        n = self.states[b].numel()
-        return self.scratch[off:off + n].view(self.states[b].shape)
+        assert p.value == self.states[b].data_ptr()
+        return self.states[b]
 
     def status(self, stream=None):
         bits = ctypes.c_uint32(0)

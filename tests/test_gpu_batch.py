@@ -48,11 +48,32 @@ def test_batched_equals_per_box_bitwise(shift_advec):
     for b in range(len(boxes)):
         assert torch.equal(A.state(b), B.state(b)), b
     assert A.status() == (0, 0)
-    # one step each more: odd count, the state lives in the second buffer
-    A.step()
+    # one step each more, the batched one as four per-stage calls
+    for stage in (1, 2, 3, 4):
+        A.rk4_stage(stage)
     B.step_perbox()
     for b in range(len(boxes)):
         assert torch.equal(A.state(b), B.state(b)), b
+    A.close()
+    B.close()
+
+
+def test_per_stage_calls_equal_step_bitwise():
+    """grf_batch_step is four grf_batch_rk4_stage calls: the same bits, and
+    every step's state is back in the caller's tensor; a stage outside 1..4
+    is refused."""
+    p, boxes, states, dts = _make(SMALL, 1.0)
+    A = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
+    B = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
+    for _ in range(3):
+        A.step()
+        for stage in (1, 2, 3, 4):
+            B.rk4_stage(stage)
+    for b in range(len(boxes)):
+        assert A.state(b) is A.states[b]
+        assert torch.equal(A.state(b), B.state(b)), b
+    with pytest.raises(G.GrfError):
+        A.rk4_stage(5)
     A.close()
     B.close()
 
@@ -92,8 +113,8 @@ def test_batched_matches_oracle():
 
 
 def test_graph_replays_match_eager():
-    """Each replay is two steps; eager work and synchronisations in between;
-    every replay is checked against an eager batch."""
+    """Each replay is one step (four stages); eager work and synchronisations
+    in between; every replay is checked against an eager batch."""
     print("case: hipGraph replays", flush=True)
     p, boxes, states, dts = _make(SMALL)
     stream = torch.cuda.Stream()
@@ -102,9 +123,8 @@ def test_graph_replays_match_eager():
         E = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
         torch.cuda.synchronize()
         graph = A.capture(stream)
-        for rep in range(3):
+        for rep in range(4):
             A.replay(graph, stream)
-            E.step(stream)
             E.step(stream)
             stream.synchronize()
             junk = torch.randn(1000, device=DEV).sum()  # unrelated eager work
@@ -133,6 +153,35 @@ def test_autotune_is_cached_and_result_independent():
         assert torch.equal(A.state(b), C.state(b))
     for x in (A, B, C):
         x.close()
+
+
+def test_amr_workload_boxes_match_oracle():
+    """The 96-box workload after one batched step (autotuned, graph-free): the
+    two largest boxes and the largest box of the coarsest and of the finest
+    level against the oracle's step of the same box, within 1e-10 relative
+    per field (R12: every cell of the box, frozen ghosts included)."""
+    print("case: 96 AMR boxes, 4 boxes against the oracle", flush=True)
+    spec = I.amr_boxes()
+    p, boxes, states, dts = _make(spec)
+    A = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
+    A.autotune()
+    A.step()
+    torch.cuda.synchronize()
+    assert A.status()[0] == 0
+    size = [int(np.prod(b["dims"])) for b in spec]
+    order = sorted(range(len(spec)), key=lambda b: -size[b])
+    pick = order[:2]
+    for lev in (min(b["level"] for b in spec), max(b["level"] for b in spec)):
+        on = [b for b in order if spec[b]["level"] == lev and b not in pick]
+        if on:
+            pick.append(on[0])
+    for b in pick:
+        o, fo = O.rk4(I.params_vector(p), states[b], spec[b]["dx"], dts[b], 1, periodic=False)
+        assert fo == 0
+        e = rel_err_per_field(A.state(b).cpu().numpy(), o, interior=False)
+        print(f"box {b} dims {spec[b]['dims']} level {spec[b]['level']}: max rel err {e.max():.3e}", flush=True)
+        assert e.max() <= 1e-10, (b, dict(zip(I.FIELDS, e)))
+    A.close()
 
 
 def test_amr_workload_batched_equals_per_box():
