@@ -152,7 +152,10 @@ def _dec_flops():
 
 
 def vjp_code(shift_advec: bool, decoupled: bool = False):
-    b = M.build(shift_advec, decoupled=decoupled)
+    """Reverse of the pointwise algebra with the quadratic coupling alone (the
+    adjoint takes gradients with respect to lambda_gb and g2; the general
+    coupling's nodes would only lengthen the tape)."""
+    b = M.build(shift_advec, decoupled=decoupled, general_coupling=False)
     g = b["graph"]
     w = [g.input(f"w{f}") for f in range(M.NF)]
     leaves = [n for n in g.nodes if n.op == "in" and not n.name.startswith("w")]

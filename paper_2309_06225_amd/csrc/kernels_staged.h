@@ -49,7 +49,7 @@ __device__ __forceinline__ void stage_item(const double* p0, const double* p1, i
 }
 
 // RK4 stage update of one field from staged values (the order and rounding of
-// stage_one).
+// stage_one), stored non-temporally.
 #pragma clang fp contract(off)
 template <int MODE>
 __device__ __forceinline__ void stage_one_st(int f, double rhs_f, double ko_f, double u0_f, double acc_f,
@@ -59,17 +59,19 @@ __device__ __forceinline__ void stage_one_st(int f, double rhs_f, double ko_f, d
   if (!isfinite(kf)) flags |= 1u;
   const int64_t q = (int64_t)f * b.fs + s;
   const int64_t qa = (int64_t)f * b.as + c;
+#define GRF_ST(p, v) __builtin_nontemporal_store((v), &(p))
   if constexpr (MODE == 0) {
-    out[q] = kf;
+    GRF_ST(out[q], kf);
   } else if constexpr (MODE == 1) {
-    acc[qa] = kf;
-    out[q] = u0_f + sc.cnext * kf;
+    GRF_ST(acc[qa], kf);
+    GRF_ST(out[q], u0_f + sc.cnext * kf);
   } else if constexpr (MODE == 2) {
-    acc[qa] = acc_f + 2.0 * kf;
-    out[q] = u0_f + sc.cnext * kf;
+    GRF_ST(acc[qa], acc_f + 2.0 * kf);
+    GRF_ST(out[q], u0_f + sc.cnext * kf);
   } else {
-    out[q] = u0_f + sc.cnext * (acc_f + kf);
+    GRF_ST(out[q], u0_f + sc.cnext * (acc_f + kf));
   }
+#undef GRF_ST
 }
 #pragma clang fp contract(fast)
 
@@ -100,17 +102,19 @@ __device__ __forceinline__ void staged_wave(const BoxDev& b, int64_t c0, const g
 #define GRF_STAGE_D(bb, slot, cc) \
   stage_item<2>(D + (int64_t)(cc) * nc + vc0, D + (int64_t)(cc) * nc + vc1, wb, &GRF_BUF(bb)[(slot) * 64])
 #define GRF_STAGE_KO(bb, slot, f) GRF_STAGE_D(bb, slot, GRF_OFF_KO + (f))
+// every input and output of the kernel is read or written once: all of it
+// streams past the caches (non-temporal), leaving them to the register spills
 #define GRF_STAGE_U(bb, slot, f) \
-  stage_item(us + (int64_t)(f) * b.fs + vs0, us + (int64_t)(f) * b.fs + vs1, wb, &GRF_BUF(bb)[(slot) * 64])
+  stage_item<2>(us + (int64_t)(f) * b.fs + vs0, us + (int64_t)(f) * b.fs + vs1, wb, &GRF_BUF(bb)[(slot) * 64])
 #define GRF_STAGE_U0(bb, slot, f)                                                                              \
   do {                                                                                                         \
     if constexpr (MODE != 0)                                                                                   \
-      stage_item(u0 + (int64_t)(f) * b.fs + vs0, u0 + (int64_t)(f) * b.fs + vs1, wb, &GRF_BUF(bb)[(slot) * 64]); \
+      stage_item<2>(u0 + (int64_t)(f) * b.fs + vs0, u0 + (int64_t)(f) * b.fs + vs1, wb, &GRF_BUF(bb)[(slot) * 64]); \
   } while (0)
 #define GRF_STAGE_ACC(bb, slot, f)                                                                         \
   do {                                                                                                     \
     if constexpr (MODE == 2 || MODE == 4)                                                                  \
-      stage_item(acc + (int64_t)(f) * b.as + vc0, acc + (int64_t)(f) * b.as + vc1, wb, &GRF_BUF(bb)[(slot) * 64]); \
+      stage_item<2>(acc + (int64_t)(f) * b.as + vc0, acc + (int64_t)(f) * b.as + vc1, wb, &GRF_BUF(bb)[(slot) * 64]); \
   } while (0)
 #define GRF_PHASE_SYNC()                        \
   do {                                          \

@@ -719,6 +719,8 @@ grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u,
   if (!u || !w || !u_bar || !theta_bar || !workspace) return fail(GRF_EINVAL, "null pointer");
   if (box->ng == 4 && p->fd_order != 6) return fail(GRF_EUNSUPPORTED, "four ghost layers only with fd_order 6");
   if (u_bar == u || u_bar == w) return fail(GRF_EINVAL, "u_bar must not alias u or w");
+  if (p->lambda_lin != 0.0 || p->beta != 0.0)
+    return fail(GRF_EUNSUPPORTED, "the adjoint takes the quadratic coupling (lambda_lin = beta = 0)");
   const VjpLayout L = vjp_layout(box);
   if (workspace_bytes < L.total) return fail(GRF_ENOMEM, "workspace %zu bytes < %zu", workspace_bytes, L.total);
   BoxDev bd = make_boxdev(box);
@@ -763,6 +765,8 @@ grf_status grf_rk4_step_vjp(const grf_params* p, const grf_box* box, double dt, 
   if (box->bc != GRF_BC_FROZEN) return fail(GRF_EUNSUPPORTED, "the step adjoint is implemented for frozen ghosts");
   if (box->ng == 4 && p->fd_order != 6) return fail(GRF_EUNSUPPORTED, "four ghost layers only with fd_order 6");
   if (p->enforce) return fail(GRF_EUNSUPPORTED, "the step adjoint does not differentiate the enforcement");
+  if (p->lambda_lin != 0.0 || p->beta != 0.0)
+    return fail(GRF_EUNSUPPORTED, "the adjoint takes the quadratic coupling (lambda_lin = beta = 0)");
   if (!u || !u2 || !u3 || !u4 || !ubar_new || !ubar || !theta_bar || !workspace) return fail(GRF_EINVAL, "null pointer");
   if (ubar == ubar_new || ubar == u || ubar == u2 || ubar == u3 || ubar == u4)
     return fail(GRF_EINVAL, "ubar must not alias an input");
