@@ -325,7 +325,7 @@ grf_status grf_energy_densities(const grf_params* p, const grf_box* box, const d
  * |2 g2 X| (the X^2 term against the X term); the paper does not define the
  * conditions, these two ratios are this library's reading.  Fourth, the
  * determinant of the per-cell 7x7 system (the product of its elimination
- * pivots): it vanishes where the mixed time derivatives can no longer be
+ * pivots, signed by the row exchanges): it vanishes where the mixed time derivatives can no longer be
  * solved for, this library's on-path stand-in for the effective-metric
  * determinant the paper plots.  Same stencils, arguments, workspace and
  * errors as grf_constraints;

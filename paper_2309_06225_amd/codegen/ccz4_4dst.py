@@ -300,12 +300,25 @@ def build(shift_advec: bool = False, decoupled: bool = False, general_coupling: 
     srest = FX * (D2phi + K * Pi + adphi) - 2.0 * g2 * (KDD - 2.0 * Pi * PiV - Pi * Pi * adphi)
     bvec.append(srest + dlam * (8.0 * M2 - 4.0 * B2))
 
-    # Gaussian elimination without row exchanges (the matrix is identity plus
-    # O(lambda', g2) in the weak-coupling regime); pivots are reported.
+    # Gaussian elimination with partial pivoting; pivots are reported.  Before
+    # column kk is eliminated, rows kk+1..6 are compared in turn with row kk,
+    # and a row whose entry in column kk is strictly larger in magnitude is
+    # exchanged with it (branch-free selects), so that row kk ends with the
+    # first largest entry of the column.  In the weak-coupling regime the
+    # matrix is identity plus O(lambda', g2) and no exchange is taken.
     M = [row[:] for row in Amat]
     rhs7 = bvec[:]
     pivots = []
+    swaps = []  # exchange conditions, for the sign of the determinant
     for kk in range(7):
+        for ii in range(kk + 1, 7):
+            cnd = g.gtabs(M[ii][kk], M[kk][kk])
+            if cnd.op == "c" and cnd.val == 0.0:
+                continue
+            swaps.append(cnd)
+            for jj in range(kk, 7):
+                M[kk][jj], M[ii][jj] = g.sel(cnd, M[ii][jj], M[kk][jj]), g.sel(cnd, M[kk][jj], M[ii][jj])
+            rhs7[kk], rhs7[ii] = g.sel(cnd, rhs7[ii], rhs7[kk]), g.sel(cnd, rhs7[kk], rhs7[ii])
         piv = M[kk][kk]
         pivots.append(piv)
         ipiv = 1.0 / piv
@@ -388,7 +401,7 @@ def build(shift_advec: bool = False, decoupled: bool = False, general_coupling: 
     # (with the pure Ricci scalar) and momentum M_i - 8 pi S_i
     # in the decoupling limit the metric constraints carry no scalar sources
     constraints = [Hg - 2.0 * rho8m] + [Mi[i] - S8im[i] for i in R3]
-    return dict(graph=g, rhs=rhs, pivots=pivots, pivot_check=pivot_check, inputs=inputs, params=P,
+    return dict(graph=g, rhs=rhs, pivots=pivots, pivot_check=pivot_check, swaps=swaps, inputs=inputs, params=P,
                 theta=[P["lambda_gb"], P["g2"]], solution=x, constraints=constraints,
                 scalar_parts=dict(X=X, Pi=Pi, GW=GW, g2=g2, Gcu=Gcu, Cs=Cs, M2=M2, B2=B2, dlam=dlam))
 
@@ -405,7 +418,9 @@ def coupling(b):
     lgb = 8.0 * gc + 8.0 * q["M2"] - 4.0 * q["B2"]
     det = b["pivots"][0]
     for pv in b["pivots"][1:]:
-        det = det * pv  # the elimination has no row exchanges: det = product of the pivots
+        det = det * pv
+    for cnd in b["swaps"]:  # each exchange taken flips the sign
+        det = g.sel(cnd, -det, det)
     return [lgb, g.fabs(q["dlam"]) * g.sqrt(g.fabs(lgb)), g.fabs(2.0 * q["g2"] * q["X"]), det]
 
 

@@ -17,12 +17,13 @@ class Graph:
         self.nodes: list[Node] = []
         self.table: dict = {}
 
-    def _new(self, op, a=None, b=None, val=None, name=None):
-        key = (op, a.idx if a is not None else None, b.idx if b is not None else None, val, name)
+    def _new(self, op, a=None, b=None, val=None, name=None, c=None):
+        key = (op, a.idx if a is not None else None, b.idx if b is not None else None, val, name,
+               c.idx if c is not None else None)
         hit = self.table.get(key)
         if hit is not None:
             return hit
-        n = Node(self, op, a, b, val, name, len(self.nodes))
+        n = Node(self, op, a, b, val, name, len(self.nodes), c)
         self.nodes.append(n)
         self.table[key] = n
         return n
@@ -134,6 +135,24 @@ class Graph:
             a = a.a
         return self._new("abs", a)
 
+    def gtabs(self, a, b):
+        """Condition |a| > |b| (a boolean: only `sel` reads it)."""
+        a, b = self.lift(a), self.lift(b)
+        if a.op == "c" and b.op == "c":
+            return self.const(1.0 if abs(a.val) > abs(b.val) else 0.0)
+        if a.is_const(0.0):
+            return self.const(0.0)
+        return self._new("gt", a, b)
+
+    def sel(self, cond, x, y):
+        """x where cond holds, else y (cond: a `gtabs` node or a constant)."""
+        x, y = self.lift(x), self.lift(y)
+        if cond.op == "c":
+            return x if cond.val != 0.0 else y
+        if x is y:
+            return x
+        return self._new("sel", x, y, c=cond)
+
     def lift(self, x):
         if isinstance(x, Node):
             return x
@@ -147,10 +166,14 @@ class Graph:
 
 
 class Node:
-    __slots__ = ("g", "op", "a", "b", "val", "name", "idx")
+    __slots__ = ("g", "op", "a", "b", "val", "name", "idx", "c")
 
-    def __init__(self, g, op, a, b, val, name, idx):
+    def __init__(self, g, op, a, b, val, name, idx, c=None):
         self.g, self.op, self.a, self.b, self.val, self.name, self.idx = g, op, a, b, val, name, idx
+        self.c = c  # third operand: the condition of a select
+
+    def kids(self):
+        return [k for k in (self.a, self.b, self.c) if k is not None]
 
     def is_const(self, v):
         return self.op == "c" and self.val == v
@@ -195,10 +218,7 @@ def reachable(outputs):
         if n.idx in seen:
             continue
         seen.add(n.idx)
-        if n.a is not None:
-            stack.append(n.a)
-        if n.b is not None:
-            stack.append(n.b)
+        stack.extend(n.kids())
     return seen
 
 
@@ -211,7 +231,7 @@ def vjp(g: Graph, outputs, cotangents, wrt):
     for n in g.nodes:
         if n.idx not in need:
             continue
-        if n.idx in wrt_idx or (n.a is not None and n.a.idx in varied) or (n.b is not None and n.b.idx in varied):
+        if n.idx in wrt_idx or any(k.idx in varied for k in n.kids()):
             varied.add(n.idx)
     adj: dict[int, Node] = {}
 
@@ -242,6 +262,11 @@ def vjp(g: Graph, outputs, cotangents, wrt):
             acc(n.a, g.neg(g.mul(a, g.mul(n, n))))
         elif n.op == "exp":  # d exp(x) = exp(x)
             acc(n.a, g.mul(a, n))
+        elif n.op == "sel":  # the adjoint goes to the operand taken
+            acc(n.a, g.sel(n.c, a, 0.0))
+            acc(n.b, g.sel(n.c, 0.0, a))
+        elif n.op == "gt":  # piecewise constant
+            continue
         else:
             raise ValueError(n.op)
     return [adj.get(w.idx, g.const(0.0)) for w in wrt]
@@ -258,7 +283,7 @@ def _lit(v: float) -> str:
 
 def count_flops(g: Graph, outputs):
     """Count of add, sub, mul, reciprocal, square-root and exponential nodes
-    (1 flop each); negation and absolute value are free."""
+    (1 flop each); negation, absolute value, comparisons and selects are free."""
     need = reachable(outputs)
     c = {"+": 0, "-": 0, "*": 0, "rcp": 0, "neg": 0}
     for i in need:
@@ -280,7 +305,7 @@ def register_need(outputs):
             if x.idx in need:
                 stack.pop()
                 continue
-            chs = [c for c in (x.a, x.b) if c is not None]
+            chs = x.kids()
             pend = [c for c in chs if c.idx not in need]
             if pend:
                 stack.extend(pend)
@@ -314,7 +339,7 @@ def dfs_order(outputs, heavy_first=False):
                 order.append(n.idx)
                 continue
             stack.append((n, True))
-            chs = [ch for ch in (n.a, n.b) if ch is not None and ch.idx not in seen]
+            chs = [ch for ch in n.kids() if ch.idx not in seen]
             if heavy_first:
                 chs.sort(key=lambda c: need.get(c.idx, 0), reverse=True)
             for ch in reversed(chs):
@@ -337,10 +362,10 @@ def greedy_order(outputs, prio_order):
         if x.idx in nodes:
             continue
         nodes[x.idx] = x
-        for c in (x.a, x.b):
-            if c is not None and c.idx not in nodes:
+        for c in x.kids():
+            if c.idx not in nodes:
                 stack.append(c)
-    ops_of = {i: {c.idx for c in (x.a, x.b) if c is not None} for i, x in nodes.items()}
+    ops_of = {i: {c.idx for c in x.kids()} for i, x in nodes.items()}
     users = {i: [] for i in nodes}
     for i in nodes:
         for c in ops_of[i]:
@@ -401,7 +426,7 @@ def fusion_plan(g: Graph, seq, outputs):
                     k_fused = k
                     plan[i] = (ch.idx, k)
                     break
-        for k, ch in enumerate((n.a, n.b)):
+        for k, ch in enumerate((n.a, n.b, n.c)):
             if ch is not None and k != k_fused:
                 other_use.add(ch.idx)
     skipped = {m for m, _ in plan.values() if m not in other_use and m not in outs}
@@ -436,7 +461,15 @@ def _node_expr(g, n, name_of, plan):
         return f"exp({name_of(n.a)})"
     if n.op == "abs":
         return f"fabs({name_of(n.a)})"
+    if n.op == "gt":
+        return f"fabs({name_of(n.a)}) > fabs({name_of(n.b)})"
+    if n.op == "sel":
+        return f"{name_of(n.c)} ? {name_of(n.a)} : {name_of(n.b)}"
     raise ValueError(n.op)
+
+
+def _ctype(n) -> str:
+    return "bool" if n.op == "gt" else "double"
 
 
 def emit(g: Graph, outputs, out_names, input_expr, param_expr, indent="  ", prefix="t", order="dfs"):
@@ -481,7 +514,7 @@ def emit(g: Graph, outputs, out_names, input_expr, param_expr, indent="  ", pref
                 expr = _node_expr(g, n, name_of, plan)
             nm = f"{prefix}{i}"
             names[i] = nm
-            lines.append(f"{indent}const double {nm} = {expr};")
+            lines.append(f"{indent}const {_ctype(n)} {nm} = {expr};")
         for o, tmpl in after.get(k, []):
             lines.append(indent + tmpl.format(names[o.idx]) + ";")
     return "\n".join(lines)
@@ -578,7 +611,7 @@ def emit_staged(g: Graph, outputs, out_stmts, input_key, param_expr, slots, inde
                     expr = _node_expr(g, n, name_of, plan)
                 nm = f"{prefix}{i}"
                 names[i] = nm
-                lines.append(f"{indent}const double {nm} = {expr};")
+                lines.append(f"{indent}const {_ctype(n)} {nm} = {expr};")
             else:
                 _, o, tmpl, keys = st
                 fmt = {"v": names[o.idx], "b": str(buf)}

@@ -8,7 +8,7 @@ pytestmark = pytest.mark.gpu
 from oracle import oracle as O
 from paper_2309_06225_amd import grf as G
 from paper_2309_06225_amd import inputs as I
-from parity_util import rel_err_per_field
+from parity_util import exchange_state, no_exchange_pivots, quadratic_box, rel_err_per_field
 
 DEV = "cuda"
 
@@ -79,6 +79,31 @@ def test_rhs_parity_puncture_ragged():
         for variant in range(18):  # every stencil variant
             g, code, bits = gpu_rhs(p, u, dx, G.BC_FROZEN, variant, path=path)
             assert np.array_equal(g, g0), ("stencil variant / stage path changed the arithmetic", path, variant)
+
+
+def test_rhs_row_exchange_cell():
+    """The per-cell solve pivots on the GPU: a 9^3 box holds a quadratic state
+    whose central cell has the pointwise inputs of a system with a vanishing
+    first diagonal entry and condition number 4 (elimination without row
+    exchanges meets a zero pivot there).  Every stage path matches the
+    oracle's partial-pivoting solve on every interior cell, with no flag."""
+    print("case: 9^3 quadratic box, per-cell system with a zero first pivot", flush=True)
+    u0, d1, d2, lg = exchange_state()
+    p = I.default_params(lambda_gb=lg, g2=0.1)
+    dims, dx = (9, 9, 9), 0.05
+    u = quadratic_box(u0, d1, d2, dims, dx)
+    _, ex, _ = O.rhs_point(I.params_vector(p), u0, d1, d2, d1)
+    assert abs(no_exchange_pivots(ex["A"])[0]) < 1e-14 and np.linalg.cond(ex["A"]) < 10.0
+    o, fo = O.rhs(I.params_vector(p), u, dx)
+    assert fo == 0
+    res = []
+    for path in (2, 0, 1):
+        g, code, bits = gpu_rhs(p, u, dx, G.BC_FROZEN, path=path)
+        assert code == 0 and bits == 0, ("flagged", path)
+        e = rel_err_per_field(g, o)
+        assert e.max() <= 1e-11, (path, dict(zip(I.FIELDS, e)))
+        res.append(g)
+    assert np.array_equal(res[0], res[1]) and np.array_equal(res[0], res[2])
 
 
 def test_stencil_variants_bitwise_multi_chunk():
