@@ -385,7 +385,7 @@ def main():
     fl = load_flops("full_theory_shift_advection" if params["shift_advec"] != 0.0 else "full_theory")
     stage_flops = fl["rk4_step"] / 4.0
     point_flops = stage_flops - fl["stencils"]
-    kname = {0: "k_point", 1: "k_stage_fused", 2: "k_point_staged"}[G.get_stage_path()]
+    kname = {0: "k_point", 2: "k_point_staged"}[G.get_stage_path()]
     dom = roofline_point(point_flops, BYTES_STAGE, ncell, avg_point)
     stage = roofline_point(stage_flops, BYTES_STAGE, ncell, avg_stage)
     traffic = load_traffic(kname, f"single_puncture_{n}")

@@ -407,17 +407,18 @@ grf_status grf_graph_destroy(hipGraphExec_t exec);
 grf_status grf_set_tile_variant(int variant);
 int grf_get_tile_variant(void);
 
-/* Stage path of grf_rhs_eval / grf_rk4_stage:
- * 0 = a stencil kernel writing the derivative records of the whole box, then a
- *     pointwise kernel reading them;
- * 1 = one fused kernel per stage (each workgroup stages the 27 fields of an
- *     8x8x4 tile in LDS, keeps the records in a small per-workgroup scratch,
- *     then runs the pointwise algebra on the same cells);
- * 2 (default) = as 0, but the pointwise kernel copies its inputs (record
- *     components, state, u0, accumulator) phase by phase into LDS with
- *     LDS-direct loads, one phase ahead of the arithmetic.
- * On a 128^3 box one stage takes about 3.4 ms (0), 9.4 ms (1) and 2.3 ms (2).
- * Results are bitwise identical.  GRF_EINVAL outside 0..2. */
+/* Stage path of grf_rhs_eval / grf_rk4_stage, both a stencil kernel writing
+ * the derivative records of the whole box, then a pointwise kernel reading
+ * them:
+ * 0 = the plain pointwise kernel (one thread per cell, inputs loaded where
+ *     the algebra uses them);
+ * 2 (default) = the pointwise kernel copies its inputs (record components,
+ *     state, u0, accumulator) phase by phase into LDS with LDS-direct loads,
+ *     one phase ahead of the arithmetic.
+ * On a 128^3 box one stage takes about 3.4 ms (0) and 2.3 ms (2).  Results
+ * are bitwise identical.  GRF_EINVAL for any other value (1 named a fused
+ * per-tile kernel, 9.4 ms per stage, no longer provided); the decoupling
+ * limit runs on path 2 only (GRF_EUNSUPPORTED on 0). */
 grf_status grf_set_stage_path(int path);
 int grf_get_stage_path(void);
 

@@ -25,7 +25,6 @@ UNITS = [("libgrf.hip", "api", []), ("tu_stencil.hip", "stencil", []), ("tu_vjp.
          ("tu_constraints.hip", "constraints", []), ("tu_bc.hip", "bc", [])]
 UNITS += [("tu_point.hip", f"point_m{m}", [f"-DGRF_TU_MODE={m}"]) for m in (0, 1, 2, 4)]
 UNITS += [("tu_batch.hip", f"batch_m{m}", [f"-DGRF_TU_MODE={m}"]) for m in (1, 2, 4)]
-UNITS += [("tu_fused.hip", f"fused_m{m}", [f"-DGRF_TU_MODE={m}"]) for m in (0, 1, 2, 4)]
 UNITS += [("tu_staged.hip", f"staged_m{m}", [f"-DGRF_TU_MODE={m}"]) for m in (0, 1, 2, 4)]
 
 

@@ -166,16 +166,9 @@ __device__ __forceinline__ void tile_origin(const BoxDev& b, int tile, int TX, i
   tz0 = (tile / nty) * TZ;
 }
 
-// Store of one record component.  Streamed (non-temporal) where the record of
-// a whole box goes to memory and is read back by a later kernel; plain where
-// the record is a small per-workgroup slice meant to stay in cache.
-template <bool STREAM>
-__device__ __forceinline__ void rec_store(double* p, double v) {
-  if constexpr (STREAM)
-    __builtin_nontemporal_store(v, p);
-  else
-    *p = v;
-}
+// Store of one record component: streamed (non-temporal), the record of a
+// whole box goes to memory and is read back by a later kernel.
+__device__ __forceinline__ void rec_store(double* p, double v) { __builtin_nontemporal_store(v, p); }
 
 // Derivative record of field f for one cell (interior i, j, k) from staged
 // values.  The staged neighbourhood is addressed as t[pb[dz + 3] + cxy + dy*LX + dx]
@@ -184,7 +177,7 @@ __device__ __forceinline__ void rec_store(double* p, double v) {
 // component q of the cell lives at Dc[q * nc].
 // H: the staged halo (3, or 4 for the sixth-order scheme with four ghost
 // layers: sixth-order advection and eighth-difference dissipation).
-template <int LX, bool STREAM = true, int ORD = 4, int H = 3>
+template <int LX, int ORD = 4, int H = 3>
 __device__ __forceinline__ void compute_cell(const BoxDev& b, int i, int j, int k, int f, const double* __restrict__ u,
                                              double* __restrict__ Dc, int64_t nc, int64_t cell, double ko_sigma,
                                              int shift_adv, double* __restrict__ UP, const double* t, const int* pb,
@@ -205,7 +198,7 @@ __device__ __forceinline__ void compute_cell(const BoxDev& b, int i, int j, int 
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double v = ORD == 6 ? sten6_d1(l7[d]) * b.i60h[d] : sten_d1(l7[d]) * b.i12h[d];
-      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D1 + 3 * s1 + d) * nc], v);
+      rec_store(&Dc[(int64_t)(GRF_OFF_D1 + 3 * s1 + d) * nc], v);
     }
   }
   const int s2 = grf_d2_slot[f];
@@ -214,17 +207,17 @@ __device__ __forceinline__ void compute_cell(const BoxDev& b, int i, int j, int 
     if constexpr (ORD == 6) {
 #pragma unroll
       for (int d = 0; d < 3; ++d)
-        rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc], sten6_d2(l7[d]) * b.i180h2[d]);
-      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 1) * nc], sten6_mixed<LX, 0, H>(t, pb, cxy) * b.i3600[0]);
-      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 2) * nc], sten6_mixed<LX, 1, H>(t, pb, cxy) * b.i3600[1]);
-      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 4) * nc], sten6_mixed<LX, 2, H>(t, pb, cxy) * b.i3600[2]);
+        rec_store(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc], sten6_d2(l7[d]) * b.i180h2[d]);
+      rec_store(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 1) * nc], sten6_mixed<LX, 0, H>(t, pb, cxy) * b.i3600[0]);
+      rec_store(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 2) * nc], sten6_mixed<LX, 1, H>(t, pb, cxy) * b.i3600[1]);
+      rec_store(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 4) * nc], sten6_mixed<LX, 2, H>(t, pb, cxy) * b.i3600[2]);
     } else {
 #pragma unroll
       for (int d = 0; d < 3; ++d)
-        rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc], sten_d2(l7[d]) * b.i12h2[d]);
-      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 1) * nc], sten_mixed<LX, 0>(t, pb, cxy) * b.i144[0]);
-      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 2) * nc], sten_mixed<LX, 1>(t, pb, cxy) * b.i144[1]);
-      rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 4) * nc], sten_mixed<LX, 2>(t, pb, cxy) * b.i144[2]);
+        rec_store(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc], sten_d2(l7[d]) * b.i12h2[d]);
+      rec_store(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 1) * nc], sten_mixed<LX, 0>(t, pb, cxy) * b.i144[0]);
+      rec_store(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 2) * nc], sten_mixed<LX, 1>(t, pb, cxy) * b.i144[1]);
+      rec_store(&Dc[(int64_t)(GRF_OFF_D2 + 6 * s2 + 4) * nc], sten_mixed<LX, 2>(t, pb, cxy) * b.i144[2]);
     }
   }
 #undef GRF_AT
@@ -248,7 +241,7 @@ __device__ __forceinline__ void compute_cell(const BoxDev& b, int i, int j, int 
   double adv = 0.0;
   if (advected(f, shift_adv)) {
     adv = beta[0] * up[0] + beta[1] * up[1] + beta[2] * up[2];
-    if (!merged) rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_ADV + f) * nc], adv);
+    if (!merged) rec_store(&Dc[(int64_t)(GRF_OFF_ADV + f) * nc], adv);
   }
   double ko = 0.0;
 #pragma unroll
@@ -258,14 +251,13 @@ __device__ __forceinline__ void compute_cell(const BoxDev& b, int i, int j, int 
     else
       ko += sten_ko(l7[d]) * b.i64h[d];
   }
-  rec_store<STREAM>(&Dc[(int64_t)(GRF_OFF_KO + f) * nc], merged ? adv + ko_sigma * ko : ko_sigma * ko);
+  rec_store(&Dc[(int64_t)(GRF_OFF_KO + f) * nc], merged ? adv + ko_sigma * ko : ko_sigma * ko);
 }
 
-// Derivative record of field f for this thread's cell of a staged 3-D tile.
-// Record layout: D[q * dstride + dcell] with dcell the interior cell index
-// (whole-box record, dstride = ncell) or the thread's index within the tile
-// (per-workgroup record, dstride = tile size).  Threads outside the box do nothing.
-template <int TX, int TY, int TZ, bool LOCAL_RECORD>
+// Derivative record of field f for this thread's cell of a staged 3-D tile
+// (D[q * ncell + cell], cell the interior cell index).  Threads outside the box
+// do nothing.
+template <int TX, int TY, int TZ>
 __device__ __forceinline__ void compute_tile(const BoxDev& b, int tx0, int ty0, int tz0, int f,
                                              const double* __restrict__ u, double* __restrict__ D, double ko_sigma,
                                              int shift_adv, double* __restrict__ UP, const double* t) {
@@ -280,12 +272,10 @@ __device__ __forceinline__ void compute_tile(const BoxDev& b, int tx0, int ty0, 
 #pragma unroll
   for (int o = 0; o < 7; ++o) pb[o] = (iz + o) * LX * LY;
   const int cxy = (iy + 3) * LX + (ix + 3);
-  double* __restrict__ Dc = D + (LOCAL_RECORD ? (int64_t)threadIdx.x : cell);
-  const int64_t nc = LOCAL_RECORD ? (int64_t)(TX * TY * TZ) : b.ncell;
-  compute_cell<LX, !LOCAL_RECORD>(b, i, j, k, f, u, Dc, nc, cell, ko_sigma, shift_adv, UP, t, pb, cxy);
+  compute_cell<LX>(b, i, j, k, f, u, D + cell, b.ncell, cell, ko_sigma, shift_adv, UP, t, pb, cxy);
 }
 
-template <int TX, int TY, int TZ, bool LOCAL_RECORD = false>
+template <int TX, int TY, int TZ>
 __device__ __forceinline__ void deriv_tile(const BoxDev& b, int tile, int f, const double* __restrict__ u,
                                            double* __restrict__ D, double ko_sigma, int shift_adv,
                                            double* __restrict__ UP, double* t) {
@@ -294,7 +284,7 @@ __device__ __forceinline__ void deriv_tile(const BoxDev& b, int tile, int f, con
   __syncthreads();  // the previous work item of this workgroup is done with t
   stage_tile<TX, TY, TZ, TX * TY * TZ>(b, tx0, ty0, tz0, u + (int64_t)f * b.fs, t);
   __syncthreads();
-  compute_tile<TX, TY, TZ, LOCAL_RECORD>(b, tx0, ty0, tz0, f, u, D, ko_sigma, shift_adv, UP, t);
+  compute_tile<TX, TY, TZ>(b, tx0, ty0, tz0, f, u, D, ko_sigma, shift_adv, UP, t);
 }
 
 template <int TX, int TY, int TZ>
@@ -389,7 +379,7 @@ __device__ __forceinline__ void zm_column(const BoxDev& b, int item, int f, cons
 #pragma unroll
       for (int o = 0; o < 2 * H + 1; ++o) pb[o] = ((unsigned)(k + o) % R) * PL;
       const int64_t cell = ((int64_t)k * b.ny + j) * b.nx + i;
-      compute_cell<LX, true, ORD, H>(b, i, j, k, f, u, D + cell, b.ncell, cell, ko_sigma, shift_adv, UP, t, pb,
+      compute_cell<LX, ORD, H>(b, i, j, k, f, u, D + cell, b.ncell, cell, ko_sigma, shift_adv, UP, t, pb,
                                      cxy);
     }
   }
@@ -495,64 +485,6 @@ __global__ __launch_bounds__(kPointThreads) void k_point(BoxDev b, grf_point_par
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= b.ncell) return;
   point_cell<MODE, SHIFTADV>(b, c, P, us, D, b.ncell, c, u0, out, acc, sc, status);
-}
-
-// ---------------------------------------------------------------------------
-// Fused RK4 stage.  A persistent workgroup takes 8x8x4 tiles (tile = blockIdx.x,
-// blockIdx.x + gridDim.x, ...).  For each tile it stages the 27 fields three at
-// a time into LDS, writes the derivative records of its 256 cells into its own
-// slice of Dwg (kept small so that it stays cache-resident between the two
-// phases), then runs the pointwise right-hand side and the stage update on the
-// same cells.  Per cell the arithmetic is the one of k_deriv + k_point.
-constexpr int kFusedTX = 8, kFusedTY = 8, kFusedTZ = 4;
-constexpr int kFusedNT = kFusedTX * kFusedTY * kFusedTZ;
-constexpr int kFusedFB = 3;  // fields staged per LDS round (27 = 9 x 3)
-constexpr int kFusedLSZ = (kFusedTX + 6) * (kFusedTY + 6) * (kFusedTZ + 6);
-
-__host__ __device__ inline int fused_tiles(const BoxDev& b) {
-  return ((b.nx + kFusedTX - 1) / kFusedTX) * ((b.ny + kFusedTY - 1) / kFusedTY) * ((b.nz + kFusedTZ - 1) / kFusedTZ);
-}
-
-template <int MODE, int SHIFTADV>
-__device__ __forceinline__ void fused_tile(const BoxDev& b, int tile, const grf_point_params& P,
-                                           const double* __restrict__ us, const double* __restrict__ u0,
-                                           double* __restrict__ out, double* __restrict__ acc, StageCoef sc,
-                                           double* __restrict__ D, double ko_sigma, unsigned* __restrict__ status,
-                                           double* t) {
-  int tx0, ty0, tz0;
-  tile_origin(b, tile, kFusedTX, kFusedTY, kFusedTZ, tx0, ty0, tz0);
-  for (int f0 = 0; f0 < NF; f0 += kFusedFB) {
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kFusedFB; ++q)
-      stage_tile<kFusedTX, kFusedTY, kFusedTZ, kFusedNT>(b, tx0, ty0, tz0, us + (int64_t)(f0 + q) * b.fs,
-                                                        t + q * kFusedLSZ);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kFusedFB; ++q)
-      compute_tile<kFusedTX, kFusedTY, kFusedTZ, true>(b, tx0, ty0, tz0, f0 + q, us, D, ko_sigma, SHIFTADV, nullptr,
-                                                       t + q * kFusedLSZ);
-  }
-  const int ix = threadIdx.x % kFusedTX, iy = (threadIdx.x / kFusedTX) % kFusedTY;
-  const int iz = threadIdx.x / (kFusedTX * kFusedTY);
-  const int i = tx0 + ix, j = ty0 + iy, k = tz0 + iz;
-  if (i < b.nx && j < b.ny && k < b.nz) {
-    const int64_t c = ((int64_t)k * b.ny + j) * b.nx + i;
-    point_cell<MODE, SHIFTADV>(b, c, P, us, D, kFusedNT, threadIdx.x, u0, out, acc, sc, status);
-  }
-}
-
-template <int MODE, int SHIFTADV>
-__global__ __launch_bounds__(kFusedNT) void k_stage_fused(BoxDev b, grf_point_params P, const double* __restrict__ us,
-                                                          const double* __restrict__ u0, double* __restrict__ out,
-                                                          double* __restrict__ acc, StageCoef sc,
-                                                          double* __restrict__ Dwg, double ko_sigma,
-                                                          unsigned* __restrict__ status) {
-  __shared__ double t[kFusedFB * kFusedLSZ];
-  double* __restrict__ D = Dwg + (int64_t)blockIdx.x * GRF_NCOMP * kFusedNT;
-  const int ntiles = fused_tiles(b);
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-    fused_tile<MODE, SHIFTADV>(b, tile, P, us, u0, out, acc, sc, D, ko_sigma, status, t);
 }
 
 }  // namespace grf

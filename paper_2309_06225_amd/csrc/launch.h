@@ -104,30 +104,6 @@ GRF_DECL_STAGED(2)
 GRF_DECL_STAGED(4)
 #undef GRF_DECL_STAGED
 
-// fused stage (stencil records in a per-workgroup slice of Dwg, then pointwise + stage update)
-template <int MODE>
-hipError_t launch_fused_m(int sa, int grid, const BoxDev& bd, const grf_point_params& pp, const double* us,
-                          const double* u0, double* out, double* acc, const StageCoef& sc, double* Dwg, double sigma,
-                          unsigned* status, hipStream_t st);
-template <> hipError_t launch_fused_m<0>(int, int, const BoxDev&, const grf_point_params&, const double*,
-                                         const double*, double*, double*, const StageCoef&, double*, double, unsigned*,
-                                         hipStream_t);
-template <> hipError_t launch_fused_m<1>(int, int, const BoxDev&, const grf_point_params&, const double*,
-                                         const double*, double*, double*, const StageCoef&, double*, double, unsigned*,
-                                         hipStream_t);
-template <> hipError_t launch_fused_m<2>(int, int, const BoxDev&, const grf_point_params&, const double*,
-                                         const double*, double*, double*, const StageCoef&, double*, double, unsigned*,
-                                         hipStream_t);
-template <> hipError_t launch_fused_m<4>(int, int, const BoxDev&, const grf_point_params&, const double*,
-                                         const double*, double*, double*, const StageCoef&, double*, double, unsigned*,
-                                         hipStream_t);
-template <int MODE>
-int fused_blocks_per_cu_m(int sa);
-template <> int fused_blocks_per_cu_m<0>(int);
-template <> int fused_blocks_per_cu_m<1>(int);
-template <> int fused_blocks_per_cu_m<2>(int);
-template <> int fused_blocks_per_cu_m<4>(int);
-
 // VJP pieces
 hipError_t launch_vjp_point(int sa, const BoxDev& bd, const grf_point_params& pp, const double* u, const double* D,
                             const double* UP, const double* w, double* ubar, double* Dbar, double* TH,

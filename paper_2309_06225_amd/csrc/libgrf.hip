@@ -140,30 +140,16 @@ grf_point_params make_pp(const grf_params* p) {
   return q;
 }
 
-// Stage path of the single-box calls: 0 = stencil kernel + pointwise kernel
-// (record of the whole box through HBM), 1 = fused per-tile kernel.
-int g_stage_path = 2;  // split, pointwise inputs staged through LDS
-
-// Persistent grid of the fused kernel (workgroups resident at once) and the
-// size of its per-workgroup record scratch.
-int fused_grid_max() {
-  static int g = 0;
-  if (g == 0) {
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-      hipDeviceProp_t prop;
-      if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-    }
-    g = fused_blocks_per_cu_m<2>(0) * cus;
-    if (g < 1) g = 1;
-  }
-  return g;
-}
+// Stage path of the single-box calls, both a stencil kernel writing the
+// record of the whole box and a pointwise kernel reading it: 0 = the plain
+// pointwise kernel, 2 = the pointwise kernel with its inputs staged through
+// LDS (the default).  The plain kernel carries the same algebra in another
+// emission of the generated code (depth-first order, the general coupling),
+// so the two check each other bit for bit.
+int g_stage_path = 2;
 
 size_t deriv_bytes(const grf_box* b) {
-  const size_t whole = (size_t)GRF_NCOMP * (size_t)b->nx * b->ny * b->nz * sizeof(double);
-  const size_t fused = (size_t)fused_grid_max() * GRF_NCOMP * kFusedNT * sizeof(double);
-  return whole > fused ? whole : fused;
+  return (size_t)GRF_NCOMP * (size_t)b->nx * b->ny * b->nz * sizeof(double);
 }
 
 constexpr int kTileVariantsMax = kDerivVariants;
@@ -198,20 +184,6 @@ hipError_t launch_point(int mode, int sa, const BoxDev& bd, const grf_point_para
     case 2: return launch_point_m<2>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
     case 4: return launch_point_m<4>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
     default: return launch_point_m<0>(sa, bd, pp, us, D, u0, out, acc, sc, status, st);
-  }
-}
-
-hipError_t launch_fused(int mode, int sa, const BoxDev& bd, const grf_point_params& pp, const double* us,
-                        const double* u0, double* out, double* acc, StageCoef sc, double* Dwg, double sigma,
-                        unsigned* status, hipStream_t st) {
-  int grid = fused_grid_max();
-  const int nt = fused_tiles(bd);
-  if (grid > nt) grid = nt;
-  switch (mode) {
-    case 1: return launch_fused_m<1>(sa, grid, bd, pp, us, u0, out, acc, sc, Dwg, sigma, status, st);
-    case 2: return launch_fused_m<2>(sa, grid, bd, pp, us, u0, out, acc, sc, Dwg, sigma, status, st);
-    case 4: return launch_fused_m<4>(sa, grid, bd, pp, us, u0, out, acc, sc, Dwg, sigma, status, st);
-    default: return launch_fused_m<0>(sa, grid, bd, pp, us, u0, out, acc, sc, Dwg, sigma, status, st);
   }
 }
 
@@ -377,20 +349,10 @@ grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u
   if (!u || !rhs) return fail(GRF_EINVAL, "u/rhs is null");
   if (u == rhs) return fail(GRF_EINVAL, "rhs must not alias u");
   BoxDev bd = make_boxdev(box);
-  grf_point_params pp = make_pp(p);
   unsigned* status = (unsigned*)workspace;
   double* D = (double*)((char*)workspace + kStatusBytes);
-  const int sa = p->shift_advec != 0.0;
   if (p->decoupled && g_stage_path != 2)
     return fail(GRF_EUNSUPPORTED, "the decoupling limit runs on stage path 2 only");
-  if (p->fd_order == 6 && g_stage_path == 1)
-    return fail(GRF_EUNSUPPORTED, "sixth-order stencils run on stage paths 0 and 2");
-  if (g_stage_path == 1) {
-    prof_mark(1, stream);
-    GRF_HIP_CHECK(launch_fused(0, sa, bd, pp, u, nullptr, rhs, nullptr, StageCoef{0.0}, D, p->ko_sigma, status, stream));
-    prof_mark(1, stream);
-    return GRF_OK;
-  }
   GRF_HIP_CHECK(split_stage(p, bd, g_slab_planes, 0, StageCoef{0.0}, u, nullptr, rhs, nullptr, D, status, stream));
   return GRF_OK;
 }
@@ -416,14 +378,10 @@ static grf_status rk4_stage_impl(const grf_params* p, const grf_box* box, int st
   if (unext == us || unext == u0) return fail(GRF_EINVAL, "unext must not alias us or u0");
   if (!std::isfinite(dt)) return fail(GRF_EINVAL, "dt not finite");
   BoxDev bd = make_boxdev(box);
-  grf_point_params pp = make_pp(p);
   unsigned* status = (unsigned*)workspace;
   double* D = (double*)((char*)workspace + kStatusBytes);
-  const int sa = p->shift_advec != 0.0;
   if (p->decoupled && g_stage_path != 2)
     return fail(GRF_EUNSUPPORTED, "the decoupling limit runs on stage path 2 only");
-  if (p->fd_order == 6 && g_stage_path == 1)
-    return fail(GRF_EUNSUPPORTED, "sixth-order stencils run on stage paths 0 and 2");
   StageCoef sc;
   int mode;
   switch (stage) {
@@ -432,13 +390,7 @@ static grf_status rk4_stage_impl(const grf_params* p, const grf_box* box, int st
     case 3: mode = 2; sc = StageCoef{1.0 * dt}; break;
     default: mode = 4; sc = StageCoef{dt / 6.0}; break;
   }
-  if (g_stage_path == 1) {
-    prof_mark(1, stream);
-    GRF_HIP_CHECK(launch_fused(mode, sa, bd, pp, us, u0, unext, acc, sc, D, p->ko_sigma, status, stream));
-    prof_mark(1, stream);
-  } else {
-    GRF_HIP_CHECK(split_stage(p, bd, g_slab_planes, mode, sc, us, u0, unext, acc, D, status, stream));
-  }
+  GRF_HIP_CHECK(split_stage(p, bd, g_slab_planes, mode, sc, us, u0, unext, acc, D, status, stream));
   if (p->enforce)
     GRF_HIP_CHECK(launch_enforce(bd, unext + interior_shift(bd), p->chi_min, p->lapse_min, stream));
   if (box_ghosts && box->bc == GRF_BC_PERIODIC) GRF_HIP_CHECK(launch_periodic(bd, unext, stream));
@@ -1216,10 +1168,10 @@ grf_status grf_prof_end(double* ms, int* count) {
   return GRF_OK;
 }
 
-// Select the stage path of the single-box calls: 0 split, 1 fused per tile,
-// 2 split with the pointwise kernel's inputs staged through LDS.
+// Select the stage path of the single-box calls: 0 the plain pointwise
+// kernel, 2 the pointwise kernel with its inputs staged through LDS.
 grf_status grf_set_stage_path(int path) {
-  if (path < 0 || path > 2) return fail(GRF_EINVAL, "stage path must be 0, 1 or 2");
+  if (path != 0 && path != 2) return fail(GRF_EINVAL, "stage path must be 0 or 2");
   g_stage_path = path;
   return GRF_OK;
 }

@@ -315,8 +315,8 @@ def set_tile_variant(v: int):
 
 
 def set_stage_path(path: int):
-    """0: stencil kernel + pointwise kernel; 1: fused per-tile stage kernel;
-    2 (default): stencil kernel + pointwise kernel with LDS-staged inputs."""
+    """0: stencil kernel + plain pointwise kernel; 2 (default): stencil kernel
+    + pointwise kernel with LDS-staged inputs."""
     _check(lib().grf_set_stage_path(int(path)))
 
 

@@ -158,12 +158,5 @@ def test_unsupported_paths_are_refused():
     box = G.box_of(u, 0.25)
     ws = G.alloc_workspace(G.workspace_bytes(box))
     out = torch.zeros_like(u)
-    p0 = G.get_stage_path()
-    try:
-        G.set_stage_path(1)
-        with pytest.raises(G.GrfError):
-            G.rhs_eval(p, box, u, out, ws)
-    finally:
-        G.set_stage_path(p0)
     with pytest.raises(G.GrfError):
         G.Batch(p, [box], [u], [0.01])

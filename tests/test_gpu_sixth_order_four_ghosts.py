@@ -370,13 +370,6 @@ def test_four_ghost_layers_refused_elsewhere():
         G.rhs_eval(G.make_params(I.default_params()), box, u, out, ws)
     assert e.value.code == 7
     p = G.make_params(_p6())
-    p0 = G.get_stage_path()
-    try:
-        G.set_stage_path(1)
-        with pytest.raises(G.GrfError):
-            G.rhs_eval(p, box, u, out, ws)
-    finally:
-        G.set_stage_path(p0)
     with pytest.raises((G.GrfError, ValueError)):
         G.Batch(p, [box], [u], [0.01])
     # the adjoint of the fourth-order scheme
