@@ -92,8 +92,8 @@ enum { GRF_FLAG_NONFINITE = 1, GRF_FLAG_HYPERBOLIC = 2, GRF_FLAG_NONPOSITIVE = 4
  * keeps order 6 with dissipation on.  Order 6 runs the z-marching 32x8x32
  * stencil kernel whatever grf_set_tile_variant chose, on stage paths 0 and 2,
  * in grf_rhs_eval, grf_rk4_stage, grf_rk4_stage_bc, the diagnostics and the
- * adjoint (the transposes of the same stencils); the fused path and the
- * batched form return GRF_EUNSUPPORTED. */
+ * adjoint (the transposes of the same stencils); the batched form returns
+ * GRF_EUNSUPPORTED. */
 typedef struct {
   double lambda_gb;
   int32_t lambda_kind;
@@ -398,12 +398,11 @@ grf_status grf_graph_destroy(hipGraphExec_t exec);
  * field of an LDS tile plus halo): 0: 16x8x4, 1: 32x4x4, 2: 8x8x8, 3: 16x16x2,
  * 4: 64x4x2.  z-marching (a workgroup per field of an x-y column of cells
  * walking a chunk of z-planes through a ring of LDS planes), column x chunk:
- * 5: 16x8x32, 6: 32x8x32, 7: 32x4x32, 8: 16x16x32, 9: 32x8x16,
- * 10: 64x4x32, 11: 32x8x32 with fields as the slowest work index, 12: 32x8x64,
- * 13: 32x16x32, 14: 64x8x32, 15: 64x8x64, 16: 64x16x32, 17: 128x8x32
- * (default: on a 128^3 box 0.99 ms per launch against 1.12 ms for 6, the
- * wider column re-reading fewer halo cells).
- * Results do not depend on it.  GRF_EINVAL outside 0..17. */
+ * 5: 16x8x32, 6: 32x8x32, 7: 32x4x32, 8: 16x16x32, 9: 128x8x32 (default: on
+ * a 128^3 box 0.99 ms per launch against 1.12 ms for 6, the wider column
+ * re-reading fewer halo cells; 32x8 with 16- and 64-plane chunks, 64x4,
+ * 32x16, 64x8 and 64x16 columns were measured between the two and dropped).
+ * Results do not depend on it.  GRF_EINVAL outside 0..9. */
 grf_status grf_set_tile_variant(int variant);
 int grf_get_tile_variant(void);
 

@@ -17,9 +17,9 @@ struct TileEntry;
 struct CellEntry;
 
 constexpr int kTileVariants = 5;      // tiled stencil shapes (single-box and batched calls)
-constexpr int kDerivVariants = 18;    // plus z-marching shapes 5..17 (single-box calls)
+constexpr int kDerivVariants = 10;    // plus z-marching shapes 5..9 (single-box calls)
 
-// stencil stage (variant 0..17), optionally storing the upwinded derivatives
+// stencil stage (variant 0..9), optionally storing the upwinded derivatives
 hipError_t launch_deriv(int variant, const BoxDev& bd, const double* u, double* D, double sigma, int sa, double* UP,
                         hipStream_t st);
 int tiles_of_variant(int variant, const BoxDev& bd);

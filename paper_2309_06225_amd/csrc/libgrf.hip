@@ -155,7 +155,7 @@ size_t deriv_bytes(const grf_box* b) {
 constexpr int kTileVariantsMax = kDerivVariants;
 // stencil variants the batched form can run (tiled shapes, z-marching 16x8x32, 32x8x32, 16x16x32)
 constexpr int kBatchVariants[] = {0, 1, 2, 3, 4, 5, 6, 8};
-int g_tile_variant = 17;  // z-marching 128x8 columns, 32-plane chunks
+int g_tile_variant = 9;  // z-marching 128x8 columns, 32-plane chunks
 
 // Optional per-kernel timing with HIP events recorded on the launch stream
 // around each stencil-stage and pointwise launch (enabled by grf_prof_begin).
@@ -1179,7 +1179,7 @@ grf_status grf_set_stage_path(int path) {
 int grf_get_stage_path(void) { return g_stage_path; }
 int grf_get_tile_variant(void) { return g_tile_variant; }
 
-// Select the stencil variant (0..12) used by the single-box calls.
+// Select the stencil variant (0..9) used by the single-box calls.
 grf_status grf_set_tile_variant(int variant) {
   if (variant < 0 || variant >= kDerivVariants) return fail(GRF_EINVAL, "tile variant out of range");
   g_tile_variant = variant;

@@ -196,15 +196,7 @@ hipError_t launch_deriv(int variant, const BoxDev& bd, const double* u, double* 
     case 6: return launch_deriv_zm_t<32, 8, 32, true>(bd, u, D, sigma, sa, UP, st);
     case 7: return launch_deriv_zm_t<32, 4, 32, true>(bd, u, D, sigma, sa, UP, st);
     case 8: return launch_deriv_zm_t<16, 16, 32, true>(bd, u, D, sigma, sa, UP, st);
-    case 9: return launch_deriv_zm_t<32, 8, 16, true>(bd, u, D, sigma, sa, UP, st);
-    case 10: return launch_deriv_zm_t<64, 4, 32, true>(bd, u, D, sigma, sa, UP, st);
-    case 11: return launch_deriv_zm_t<32, 8, 32, false>(bd, u, D, sigma, sa, UP, st);
-    case 12: return launch_deriv_zm_t<32, 8, 64, true>(bd, u, D, sigma, sa, UP, st);
-    case 13: return launch_deriv_zm_t<32, 16, 32, true>(bd, u, D, sigma, sa, UP, st);
-    case 14: return launch_deriv_zm_t<64, 8, 32, true>(bd, u, D, sigma, sa, UP, st);
-    case 15: return launch_deriv_zm_t<64, 8, 64, true>(bd, u, D, sigma, sa, UP, st);
-    case 16: return launch_deriv_zm_t<64, 16, 32, true>(bd, u, D, sigma, sa, UP, st);
-    case 17: return launch_deriv_zm_t<128, 8, 32, true>(bd, u, D, sigma, sa, UP, st);
+    case 9: return launch_deriv_zm_t<128, 8, 32, true>(bd, u, D, sigma, sa, UP, st);
     case 1: return launch_deriv_t<32, 4, 4>(bd, u, D, sigma, sa, UP, st);
     case 2: return launch_deriv_t<8, 8, 8>(bd, u, D, sigma, sa, UP, st);
     case 3: return launch_deriv_t<16, 16, 2>(bd, u, D, sigma, sa, UP, st);
