@@ -313,13 +313,13 @@ static int g_slab_planes = 0;
 // ghosts at the ends), its record in D is compact over the slab, and the
 // accumulator keeps the whole box's field stride.  Per cell the arithmetic is
 // that of the whole-box launches, so results are bitwise identical.
-static hipError_t split_stage(const grf_params* p, const BoxDev& bd, int planes, int mode, StageCoef sc,
+// path: the stage path (0 or 2), read once by the caller.
+static hipError_t split_stage(const grf_params* p, const BoxDev& bd, int path, int planes, int mode, StageCoef sc,
                               const double* us, const double* u0, double* out, double* acc, double* D,
                               unsigned* status, hipStream_t stream) {
   const grf_point_params pp = make_pp(p);
   const int sa = p->shift_advec != 0.0;
   const int var = staged_variant(p, sa);
-  const int path = g_stage_path == 0 ? 0 : 2;
   const int64_t sh = interior_shift(bd);
   const int64_t plane = (int64_t)bd.nx * bd.ny;
   if (planes <= 0 || planes > bd.nz) planes = bd.nz;
@@ -351,9 +351,11 @@ grf_status grf_rhs_eval(const grf_params* p, const grf_box* box, const double* u
   BoxDev bd = make_boxdev(box);
   unsigned* status = (unsigned*)workspace;
   double* D = (double*)((char*)workspace + kStatusBytes);
-  if (p->decoupled && g_stage_path != 2)
+  const int path = g_stage_path;
+  if (p->decoupled && path != 2)
     return fail(GRF_EUNSUPPORTED, "the decoupling limit runs on stage path 2 only");
-  GRF_HIP_CHECK(split_stage(p, bd, g_slab_planes, 0, StageCoef{0.0}, u, nullptr, rhs, nullptr, D, status, stream));
+  GRF_HIP_CHECK(split_stage(p, bd, path, g_slab_planes, 0, StageCoef{0.0}, u, nullptr, rhs, nullptr, D, status,
+                            stream));
   return GRF_OK;
 }
 
@@ -380,7 +382,8 @@ static grf_status rk4_stage_impl(const grf_params* p, const grf_box* box, int st
   BoxDev bd = make_boxdev(box);
   unsigned* status = (unsigned*)workspace;
   double* D = (double*)((char*)workspace + kStatusBytes);
-  if (p->decoupled && g_stage_path != 2)
+  const int path = g_stage_path;
+  if (p->decoupled && path != 2)
     return fail(GRF_EUNSUPPORTED, "the decoupling limit runs on stage path 2 only");
   StageCoef sc;
   int mode;
@@ -390,7 +393,7 @@ static grf_status rk4_stage_impl(const grf_params* p, const grf_box* box, int st
     case 3: mode = 2; sc = StageCoef{1.0 * dt}; break;
     default: mode = 4; sc = StageCoef{dt / 6.0}; break;
   }
-  GRF_HIP_CHECK(split_stage(p, bd, g_slab_planes, mode, sc, us, u0, unext, acc, D, status, stream));
+  GRF_HIP_CHECK(split_stage(p, bd, path, g_slab_planes, mode, sc, us, u0, unext, acc, D, status, stream));
   if (p->enforce)
     GRF_HIP_CHECK(launch_enforce(bd, unext + interior_shift(bd), p->chi_min, p->lapse_min, stream));
   if (box_ghosts && box->bc == GRF_BC_PERIODIC) GRF_HIP_CHECK(launch_periodic(bd, unext, stream));
@@ -458,10 +461,8 @@ extern "C" grf_status grf_rk4_stage_static(const grf_params* p, const grf_box* b
     case 3: mode = 2; sc = StageCoef{1.0 * dt}; break;
     default: mode = 4; sc = StageCoef{dt / 6.0}; break;
   }
-  const int keep = g_stage_path;
-  g_stage_path = 2;  // the split path with staged pointwise inputs
-  const hipError_t e = split_stage(p, bd, planes, mode, sc, us, u0, unext, acc, D, (unsigned*)status, stream);
-  g_stage_path = keep;
+  // the split path with staged pointwise inputs, whatever grf_set_stage_path chose
+  const hipError_t e = split_stage(p, bd, 2, planes, mode, sc, us, u0, unext, acc, D, (unsigned*)status, stream);
   if (e != hipSuccess) return fail(GRF_EHIP, "grf_rk4_stage_static: %s", hipGetErrorString(e));
   if (p->enforce)
     GRF_HIP_CHECK(launch_enforce(bd, unext + interior_shift(bd), p->chi_min, p->lapse_min, stream));
