@@ -154,13 +154,15 @@ def adjoint_ratio(torch, G, I):
 
 def large_box(torch, G, I, steps=3):
     """256^3 two-puncture box, dx = M/16, lambda_gb = 0.2, g2 = 0.02: forward
-    cell-updates/s of full RK4 steps (one warm-up step)."""
+    cell-updates/s of full RK4 steps (one warm-up step), and the pointwise
+    kernel against its roofline as on the headline box."""
     n, dx = 256, 1.0 / 16.0
     p = I.default_params(lambda_gb=0.2, g2=0.02)
     u = torch.from_numpy(I.two_punctures(n, dx)).to("cuda")
     st = G.Stepper(G.make_params(p), G.box_of(u, dx, G.BC_FROZEN), u, 0.25 * dx)
     st.step()
     torch.cuda.synchronize()
+    G.prof_begin(4 * steps)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
@@ -168,11 +170,18 @@ def large_box(torch, G, I, steps=3):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    prof = G.prof_end()
     code, _ = st.status()
     del st, u
     torch.cuda.empty_cache()
+    point_ms, point_n = prof["point"]
+    fl = load_flops("full_theory")
+    dom = roofline_point(fl["rk4_step"] / 4.0 - fl["stencils"], BYTES_STAGE, n ** 3, point_ms / max(point_n, 1))
     return {"workload": "two_punctures_256", "cells": n ** 3, "ms_per_step": ms,
-            "cell_updates_per_s": n ** 3 / (ms * 1e-3), "steps": steps, "status": code}
+            "cell_updates_per_s": n ** 3 / (ms * 1e-3), "steps": steps, "status": code,
+            "dominant_kernel_roofline": {"kernel": "k_point_staged", "avg_launch_ms": dom["ms"],
+                                         "achieved": dom["achieved"], "peak": dom["peak"], "unit": dom["unit"],
+                                         "frac": dom["frac"]}}
 
 
 def batched_speedup(torch, G, I, steps=4):
