@@ -10,6 +10,7 @@ from oracle import oracle as O
 from paper_2309_06225_amd import adjoint as A
 from paper_2309_06225_amd import grf as G
 from paper_2309_06225_amd import inputs as I
+from parity_util import exchange_state, no_exchange_pivots, quadratic_box
 
 DEV = "cuda"
 H_CS = 1e-30
@@ -36,6 +37,35 @@ def _interior_mask(shape):
     m = np.zeros(shape, bool)
     m[:, 3:-3, 3:-3, 3:-3] = True
     return m
+
+
+def test_rhs_vjp_through_row_exchanges():
+    """The reverse of the pivoting solve on the GPU: on the 9^3 quadratic box
+    whose central cell's per-cell system has a vanishing first diagonal entry
+    (so the solve exchanges rows there), <w, J v + J_theta dth> from the
+    oracle's complex-step tangent equals <VJP(w), (v, dth)>."""
+    print("case: RHS VJP 9^3 quadratic box, per-cell system with a zero first pivot", flush=True)
+    u0, d1, d2, lg = exchange_state()
+    p = I.default_params(lambda_gb=lg, g2=0.1)
+    _, ex, _ = O.rhs_point(I.params_vector(p), u0, d1, d2, d1)
+    assert abs(no_exchange_pivots(ex["A"])[0]) < 1e-14
+    dims, dx = (9, 9, 9), 0.05
+    u = quadratic_box(u0, d1, d2, dims, dx)
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(u.shape)
+    dth = np.array([0.7, -0.4])
+    w = rng.standard_normal(u.shape) * _interior_mask(u.shape)
+    _, jim = O.rhs_cs(I.params_vector(p), H_CS * dth, u, H_CS * v, dx)
+    lhs = np.sum(w * jim / H_CS * _interior_mask(u.shape))
+    ut = torch.from_numpy(u).to(DEV)
+    wt = torch.from_numpy(w).to(DEV)
+    ubar = torch.zeros_like(ut)
+    tbar = torch.zeros(2, dtype=torch.float64, device=DEV)
+    box = G.box_of(ut, dx)
+    ws = G.alloc_workspace(G.vjp_workspace_bytes(box))
+    G.rhs_vjp(G.make_params(p), box, ut, wt, ubar, tbar, ws)
+    rhs = float(np.sum(ubar.cpu().numpy() * v) + tbar.cpu().numpy() @ dth)
+    assert abs(lhs - rhs) <= 1e-11 * max(abs(lhs), 1.0), (lhs, rhs)
 
 
 @pytest.mark.parametrize("fd_order", [4.0, 6.0])
