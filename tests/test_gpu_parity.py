@@ -273,6 +273,60 @@ def test_rk4_frozen_puncture_steps_and_ghosts():
     assert np.array_equal(g[:, ghost], u[:, ghost])
 
 
+@pytest.mark.parametrize("dims", [(1, 1, 1), (1, 4, 2), (2, 1, 5), (5, 3, 1), (1, 1, 9)])
+@pytest.mark.parametrize("bc", ["frozen", "periodic"])
+def test_degenerate_boxes(dims, bc):
+    """Boxes one or two cells thick along some axes (a single cell at the
+    extreme), frozen ghosts or periodic ones wrapping the few interior cells
+    many times: one right-hand side within 1e-12 and three RK4 steps within
+    1e-10 per field, with a shift of both signs.  The steps are compared, as
+    for the small periodic workload, with the oracle run in long double: a
+    periodic axis of one or two cells makes the differences cancel their
+    O(1) values exactly or nearly (the double oracle itself is off by up to
+    ~3e-10 there), so each field must be within max(1e-10, 1.5 x the double
+    oracle's own error).  A periodic single cell is homogeneous space, where
+    the trace-free fields stay zero up to rounding (the oracle's residue
+    1e-18, the generated code's 1e-14): a field whose reference values all
+    lie below the tolerance times the largest field is compared at that
+    largest field's scale, as a field of exact zeros is."""
+    print("case: degenerate box", dims, bc, flush=True)
+    p = I.default_params(shift_advec=1.0)
+    dx = 0.3
+    u = I.puncture(dims, dx, centre=(0.4, -0.2, 0.1), phi_fn=I.shell_pulse(0.1, 2.0))
+    rng = np.random.default_rng(7)
+    u[I.IDX["shift1"]:I.IDX["shift3"] + 1] += 0.05 * rng.standard_normal(u[19:22].shape)
+    periodic = bc == "periodic"
+    if periodic:
+        u = I.wrap_ghosts(u)
+    gbc = G.BC_PERIODIC if periodic else G.BC_FROZEN
+    o, fo = O.rhs(I.params_vector(p), u, dx)
+    g, code, bits = gpu_rhs(p, u, dx, gbc)
+    assert code == 0 and bits == 0 and fo == 0
+    e = rel_err_per_field(g, o)
+    assert e.max() <= 1e-12, dict(zip(I.FIELDS, e))
+    dt = 0.25 * dx
+    pv = I.params_vector(p)
+    o3, _ = O.rk4(pv, u, dx, dt, 3, periodic=periodic)
+    ref, _ = O.rk4_ld(pv, u, dx, dt, 3, periodic=periodic)
+    ut = torch.from_numpy(u).to(DEV)
+    st = G.Stepper(G.make_params(p), G.box_of(ut, dx, gbc), ut, dt)
+    for _ in range(3):
+        st.step()
+    assert G.status_fetch(st.ws) == (0, 0)
+    g3 = st.u.cpu().numpy()
+    if not periodic:
+        g3, o3, ref = (a[:, 3:-3, 3:-3, 3:-3] for a in (g3, o3, ref))
+    den = np.abs(ref).reshape(27, -1).max(axis=1)
+    den = np.where(den > 1e-10 * den.max(), den, den.max())
+
+    def err(a):
+        return np.abs(a - ref).reshape(27, -1).max(axis=1) / den
+
+    e_gpu, e_orc = err(g3), err(o3)
+    bound = np.maximum(1e-10, 1.5 * e_orc)
+    assert np.all(e_gpu <= bound), {f: (e_gpu[i], bound[i]) for i, f in enumerate(I.FIELDS) if e_gpu[i] > bound[i]}
+
+
 def test_periodic_fill_gpu_matches_wrap():
     rng = np.random.default_rng(2)
     u = rng.standard_normal((27, 7 + 6, 5 + 6, 2 + 6))
