@@ -39,6 +39,33 @@ def _interior_mask(shape):
     return m
 
 
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 3, 1), (5, 1, 4), (70, 2, 2)])
+def test_rhs_vjp_degenerate_boxes(dims):
+    """The reverse on boxes of a single cell, one or two cells thick, or with
+    a row longer than a wave: <w, J v + J_theta dth> from the oracle's
+    complex-step tangent equals <VJP(w), (v, dth)> (frozen ghosts, so the
+    transposed stencils reach into the ghost layers from every side)."""
+    print("case: RHS VJP degenerate box", dims, flush=True)
+    p = I.default_params(shift_advec=1.0, lambda_gb=0.3, g2=0.05)
+    dx = 0.4
+    u = _state(dims, dx, 4)
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(u.shape)
+    dth = np.array([0.7, -0.4])
+    w = rng.standard_normal(u.shape) * _interior_mask(u.shape)
+    _, jim = O.rhs_cs(I.params_vector(p), H_CS * dth, u, H_CS * v, dx)
+    lhs = np.sum(w * jim / H_CS * _interior_mask(u.shape))
+    ut = torch.from_numpy(u).to(DEV)
+    wt = torch.from_numpy(w).to(DEV)
+    ubar = torch.zeros_like(ut)
+    tbar = torch.zeros(2, dtype=torch.float64, device=DEV)
+    box = G.box_of(ut, dx)
+    ws = G.alloc_workspace(G.vjp_workspace_bytes(box))
+    G.rhs_vjp(G.make_params(p), box, ut, wt, ubar, tbar, ws)
+    rhs = float(np.sum(ubar.cpu().numpy() * v) + tbar.cpu().numpy() @ dth)
+    assert abs(lhs - rhs) <= 1e-11 * max(abs(lhs), 1.0), (lhs, rhs)
+
+
 def test_rhs_vjp_through_row_exchanges():
     """The reverse of the pivoting solve on the GPU: on the 9^3 quadratic box
     whose central cell's per-cell system has a vanishing first diagonal entry
