@@ -39,10 +39,15 @@ def gpu_energy(p, u, dx, bc=G.BC_FROZEN):
 
 
 def _case(case):
+    """noise32: the plain small periodic workload; puncture_ragged: a frozen
+    puncture box whose extents are not multiples of any tile; thin and row:
+    degenerate frozen boxes (one or two cells thick; a row longer than a
+    wave of cells), with the same perturbations."""
     if case == "noise32":
         return I.flat_noise_pulse(32, 0.25, seed=0), 0.25, G.BC_PERIODIC
     dx, bc = 0.3, G.BC_FROZEN
-    u = I.puncture((21, 17, 13), dx, centre=(0.4, -0.2, 0.1), phi_fn=I.shell_pulse(0.1, 2.0))
+    dims = {"puncture_ragged": (21, 17, 13), "thin": (1, 4, 2), "row": (70, 2, 3)}[case]
+    u = I.puncture(dims, dx, centre=(0.4, -0.2, 0.1), phi_fn=I.shell_pulse(0.1, 2.0))
     rng = np.random.default_rng(4)
     u[I.IDX["K"]] += 0.01 * rng.standard_normal(u[7].shape)
     u[I.IDX["A11"]:I.IDX["A33"] + 1] += 0.01 * rng.standard_normal(u[8:14].shape)
@@ -60,7 +65,7 @@ def test_flat_space_constraints_exactly_zero():
     assert np.all(ham == 0.0) and np.all(mom == 0.0)
 
 
-@pytest.mark.parametrize("case", ["noise32", "puncture_ragged"])
+@pytest.mark.parametrize("case", ["noise32", "puncture_ragged", "thin", "row"])
 def test_constraints_match_oracle(case):
     print("case: constraints", case, flush=True)
     p = I.default_params(lambda_gb=0.3, g2=0.05)
@@ -107,7 +112,7 @@ def test_flat_space_energy_densities_exactly_zero():
     assert np.all(rho == 0.0)
 
 
-@pytest.mark.parametrize("case", ["noise32", "puncture_ragged"])
+@pytest.mark.parametrize("case", ["noise32", "puncture_ragged", "thin", "row"])
 def test_energy_densities_match_oracle(case):
     print("case: energy densities", case, flush=True)
     p = I.default_params(lambda_gb=0.3, g2=0.05)
@@ -126,7 +131,7 @@ def gpu_coupling(p, u, dx, bc=G.BC_FROZEN):
     return G.coupling_diagnostics(G.make_params(p), box, ut, ws).cpu().numpy()
 
 
-@pytest.mark.parametrize("case", ["noise32", "puncture_ragged"])
+@pytest.mark.parametrize("case", ["noise32", "puncture_ragged", "thin", "row"])
 def test_coupling_diagnostics_match_oracle(case):
     print("case: Gauss-Bonnet invariant and weak-coupling indicators", case, flush=True)
     p = I.default_params(lambda_gb=0.3, g2=0.05)
