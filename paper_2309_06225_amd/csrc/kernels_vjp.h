@@ -80,18 +80,33 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 // contiguous row read); sources outside the interior contribute nothing.
 // u_bar[f] += sum over the field's stencils of their transposes applied to the
 // cotangent record (the upwind split by the sign of the shift at the source
-// cell) and the Kreiss-Oliger transpose applied to w.  (An LDS-tiled form of
-// the same sums measured 1.30 against 1.10 ms at 64^3.)  ORD 6: the transposes
+// cell) and the Kreiss-Oliger transpose applied to w.  Every load is issued
+// unconditionally (see src_at), so a thread's loads of one stencil group are
+// in flight together; with a bounds branch around each load they were issued
+// and waited for one at a time (1.06 ms at 64^3 against 0.55).  (An LDS-tiled
+// form of the same sums measured 1.30 ms.)  ORD 6: the transposes
 // of the sixth-order stencils of the three-ghost box (centred derivatives on
 // seven points, the fifth-order biased advection stencils), the same
 // Kreiss-Oliger operator; with H = 4 (four ghost layers) the sixth-order
 // biased stencils on seven points and the eighth difference.
 // (X, Y, Z: state coordinates on a box with H ghost layers)
+// The load is unconditional, from the source clamped into the interior (always
+// in bounds), and the value is dropped afterwards when the source lies
+// outside: no branch per load, so a thread issues all its loads before it
+// waits for any.
+__device__ __forceinline__ int clamp_to(int v, int n) { return min(max(v, 0), n - 1); }
+
+// (bitwise ands: no short-circuit branches for the compiler to sink the loads into)
+__device__ __forceinline__ bool inside(const BoxDev& b, int ix, int iy, int iz) {
+  return (ix >= 0) & (ix < b.nx) & (iy >= 0) & (iy < b.ny) & (iz >= 0) & (iz < b.nz);
+}
+
 template <int H = 3>
 __device__ __forceinline__ double src_at(const BoxDev& b, const double* __restrict__ comp, int X, int Y, int Z) {
   const int ix = X - H, iy = Y - H, iz = Z - H;
-  if (ix < 0 || ix >= b.nx || iy < 0 || iy >= b.ny || iz < 0 || iz >= b.nz) return 0.0;
-  return comp[((int64_t)iz * b.ny + iy) * b.nx + ix];
+  const double v =
+      comp[((int64_t)clamp_to(iz, b.nz) * b.ny + clamp_to(iy, b.ny)) * b.nx + clamp_to(ix, b.nx)];
+  return inside(b, ix, iy, iz) ? v : 0.0;
 }
 
 constexpr int kGatherThreads = 256;
@@ -120,6 +135,7 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
     const double w1[7] = {-1.0, 9.0, -45.0, 0.0, 45.0, -9.0, 1.0};
     const double w2[7] = {2.0, -27.0, 270.0, -490.0, 270.0, -27.0, 2.0};
     if (s1 >= 0) {
+#pragma unroll
       for (int d = 0; d < 3; ++d) {
         const double* comp = Dbar + (int64_t)(GRF_OFF_D1 + 3 * s1 + d) * nc;
         double s = 0.0;
@@ -131,6 +147,7 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
     }
     if (s2 >= 0) {
       const int pure[3] = {0, 3, 5};
+#pragma unroll
       for (int d = 0; d < 3; ++d) {
         const double* comp = Dbar + (int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc;
         double s = 0.0;
@@ -139,6 +156,7 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
         acc += s * b.i180h2[d];
       }
       const int pd[3] = {0, 0, 1}, pe[3] = {1, 2, 2}, pq[3] = {1, 2, 4};
+#pragma unroll
       for (int m = 0; m < 3; ++m) {
         const double* comp = Dbar + (int64_t)(GRF_OFF_D2 + 6 * s2 + pq[m]) * nc;
         double s = 0.0;
@@ -158,6 +176,7 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
   } else {
   if (s1 >= 0) {
     const double w1[5] = {1.0, -8.0, 0.0, 8.0, -1.0};
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double* comp = Dbar + (int64_t)(GRF_OFF_D1 + 3 * s1 + d) * nc;
       double s = 0.0;
@@ -171,6 +190,7 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
     const double w1[5] = {1.0, -8.0, 0.0, 8.0, -1.0};
     const double w2[5] = {-1.0, 16.0, -30.0, 16.0, -1.0};
     const int pure[3] = {0, 3, 5};
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double* comp = Dbar + (int64_t)(GRF_OFF_D2 + 6 * s2 + pure[d]) * nc;
       double s = 0.0;
@@ -179,6 +199,7 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
       acc += s * b.i12h2[d];
     }
     const int pd[3] = {0, 0, 1}, pe[3] = {1, 2, 2}, pq[3] = {1, 2, 4};
+#pragma unroll
     for (int m = 0; m < 3; ++m) {
       const double* comp = Dbar + (int64_t)(GRF_OFF_D2 + 6 * s2 + pq[m]) * nc;
       double s = 0.0;
@@ -223,18 +244,15 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
       double s = 0.0;
 #pragma unroll
       for (int o = -H; o <= H; ++o) {
-        const int sx = X - (d == 0 ? o : 0), sy = Y - (d == 1 ? o : 0), sz = Z - (d == 2 ? o : 0);
-        double vp = 0.0, vm = 0.0;
-        const int ix = sx - H, iy = sy - H, iz = sz - H;
-        if (ix >= 0 && ix < b.nx && iy >= 0 && iy < b.ny && iz >= 0 && iz < b.nz) {
-          const double a = merged ? wf_adv[(int64_t)sz * b.sz + (int64_t)sy * b.sy + sx]
-                                  : comp[((int64_t)iz * b.ny + iy) * b.nx + ix];
-          const double bd = beta[(int64_t)sz * b.sz + (int64_t)sy * b.sy + sx];
-          if (bd >= 0.0)
-            vp = a * bd;
-          else
-            vm = a * bd;
-        }
+        const int ix = X - (d == 0 ? o : 0) - H, iy = Y - (d == 1 ? o : 0) - H, iz = Z - (d == 2 ? o : 0) - H;
+        const bool in = inside(b, ix, iy, iz);
+        const int cx = clamp_to(ix, b.nx), cy = clamp_to(iy, b.ny), cz = clamp_to(iz, b.nz);
+        const int64_t st = (int64_t)(cz + H) * b.sz + (int64_t)(cy + H) * b.sy + (cx + H);
+        const double a = merged ? wf_adv[st] : comp[((int64_t)cz * b.ny + cy) * b.nx + cx];
+        const double bd = beta[st];
+        const double ab = a * bd;
+        const double vp = (in & (bd >= 0.0)) ? ab : 0.0;
+        const double vm = (in & !(bd >= 0.0)) ? ab : 0.0;
         s += wp[o + H] * vp + wm[o + H] * vm;
       }
       acc += s * (ORD == 6 ? b.i60h[d] : b.i12h[d]);
@@ -257,12 +275,10 @@ __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __res
       double sd = 0.0;
 #pragma unroll
       for (int o = -H; o <= H; ++o) {
-        const int sx = X - (d == 0 ? o : 0), sy = Y - (d == 1 ? o : 0), sz = Z - (d == 2 ? o : 0);
-        const int ix = sx - H, iy = sy - H, iz = sz - H;
-        double v = 0.0;
-        if (ix >= 0 && ix < b.nx && iy >= 0 && iy < b.ny && iz >= 0 && iz < b.nz)
-          v = wf[(int64_t)sz * b.sz + (int64_t)sy * b.sy + sx];
-        sd += wk[o + H] * v;
+        const int ix = X - (d == 0 ? o : 0) - H, iy = Y - (d == 1 ? o : 0) - H, iz = Z - (d == 2 ? o : 0) - H;
+        const double v = wf[(int64_t)(clamp_to(iz, b.nz) + H) * b.sz + (int64_t)(clamp_to(iy, b.ny) + H) * b.sy +
+                            (clamp_to(ix, b.nx) + H)];
+        sd += wk[o + H] * (inside(b, ix, iy, iz) ? v : 0.0);
       }
       s += sd * (H == 4 ? -b.i256h[d] : b.i64h[d]);
     }
