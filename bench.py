@@ -217,10 +217,32 @@ def batched_speedup(torch, G, I, steps=4):
         for b in range(len(spec)):
             B.set_tile_variant(b, 0)
         per_box_tiled = timed(lambda: B.step_perbox(st), steps)
+        # and with every box on the stencil variant fastest for its own shape:
+        # one RK4 step of a lone box of that shape timed with each variant a
+        # batch box can take (grf_batch_set_tile_variant: 0..6 and 8)
+        accepted = (0, 1, 2, 3, 4, 5, 6, 8)
+        first = {}
+        for b, bx in enumerate(spec):
+            first.setdefault(tuple(bx["dims"]), b)
+        v_single = G.get_tile_variant()
+        best_v = {}
+        for shp, b in first.items():
+            S = G.Stepper(G.make_params(p), boxes[b], torch.from_numpy(states[b]).to("cuda"), dts[b])
+            tv = {}
+            for v in accepted:
+                G.set_tile_variant(v)
+                tv[v] = timed(lambda: S.step(st), 3)
+            best_v[shp] = min(tv, key=tv.get)
+        G.set_tile_variant(v_single)
+        for b, bx in enumerate(spec):
+            B.set_tile_variant(b, best_v[tuple(bx["dims"])])
+        per_box_own = timed(lambda: B.step_perbox(st), steps)
         B.close()
     ncell = sum(int(b["dims"][0] * b["dims"][1] * b["dims"][2]) for b in spec)
-    best_per_box = min(per_box, per_box_tiled)
+    best_per_box = min(per_box, per_box_tiled, per_box_own)
     return {"per_box_ms_per_step": per_box, "per_box_tiled_ms_per_step": per_box_tiled,
+            "per_box_own_variant_ms_per_step": per_box_own,
+            "per_box_own_variants": sorted(set(best_v.values())),
             "batched_graph_ms_per_step": graph, "speedup": best_per_box / graph,
             "speedup_vs_same_variant_per_box": per_box / graph, "batched_cell_updates_per_s": ncell / (graph * 1e-3),
             "stencil_variants": sorted(set(chosen)), "cells": ncell, "boxes": len(spec), "status": code}
