@@ -358,7 +358,7 @@ def main():
         print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (the box-per-GPU "
+        print("bench.py measures one GPU only: libgrf has no multi-GPU path (the box-per-GPU "
               "sharding with halo exchange is a design, not code); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
