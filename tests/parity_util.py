@@ -89,3 +89,25 @@ def quadratic_box(u, d1, d2, dims, dx, ng=NG):
         out[f] = (u[f] + d1[f, 0] * X + d1[f, 1] * Y + d1[f, 2] * Z
                   + 0.5 * (xx * X * X + yy * Y * Y + zz * Z * Z) + xy * X * Y + xz * X * Z + yz * Y * Z)
     return out
+
+
+def oracle_region_rk4(oracle, pv, u, dx, dt, nsteps, r0, w, ng=NG):
+    """The oracle's state after nsteps RK4 steps with frozen ghosts, on the
+    interior cells r0[a] .. r0[a] + w - 1 along each axis (x, y, z) of the
+    ghost-inclusive state u, computed on a sub-box cut from u.
+
+    A cell's value after n steps depends only on cells within 3 (4n - 1) of it:
+    the first stage reads the initial state, and each of the 4n - 1 later stages
+    reads at most three cells further.  So a sub-box that reaches that far
+    beyond the region inside the box (and to the box's own ghosts where the
+    region is closer to a face: those are frozen in both runs) gives the region
+    the whole box's values.  Returns the region, shape (27, w, w, w)."""
+    m = 3 * (4 * nsteps - 1)
+    n = [u.shape[3] - 2 * ng, u.shape[2] - 2 * ng, u.shape[1] - 2 * ng]
+    lo = [max(0, r0[a] - m) for a in range(3)]
+    hi = [min(n[a], r0[a] + w + m) for a in range(3)]
+    sub = np.ascontiguousarray(u[:, lo[2]:hi[2] + 2 * ng, lo[1]:hi[1] + 2 * ng, lo[0]:hi[0] + 2 * ng])
+    o, flags = oracle.rk4(pv, sub, dx, dt, nsteps, periodic=False)
+    assert flags == 0, flags
+    s = [r0[a] - lo[a] + ng for a in range(3)]
+    return o[:, s[2]:s[2] + w, s[1]:s[1] + w, s[0]:s[0] + w]

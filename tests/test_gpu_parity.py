@@ -8,7 +8,7 @@ pytestmark = pytest.mark.gpu
 from oracle import oracle as O
 from paper_2309_06225_amd import grf as G
 from paper_2309_06225_amd import inputs as I
-from parity_util import exchange_state, no_exchange_pivots, quadratic_box, rel_err_per_field
+from parity_util import exchange_state, no_exchange_pivots, oracle_region_rk4, quadratic_box, rel_err_per_field
 
 DEV = "cuda"
 
@@ -237,6 +237,38 @@ def test_rk4_ten_steps_single_puncture_128_full_box():
     e = rel_err_per_field(g, o, interior=False)
     print(f"128^3, 10 steps: max rel err {e.max():.3e}", flush=True)
     assert e.max() <= 1e-10, dict(zip(I.FIELDS, e))
+
+
+def test_rk4_steps_two_punctures_256_regions():
+    """The large single-box workload (256^3 two punctures, dx = M/16,
+    lambda_gb = 0.2, g2 = 0.02, frozen ghosts): three RK4 steps of the whole
+    box on the GPU, compared on four 16^3 regions (both punctures' cells, the
+    scalar pulse's centre between them, a box corner) with the oracle's three
+    steps of sub-boxes reaching 33 cells beyond each region (the method is
+    checked against whole-box oracle runs in test_subbox_method.py): within
+    1e-10 relative per field."""
+    print("case: 3 RK4 steps two punctures 256^3, four regions against oracle sub-boxes", flush=True)
+    p = I.default_params(lambda_gb=0.2, g2=0.02)
+    n, dx, nsteps, w = 256, 1.0 / 16.0, 3, 16
+    dt = 0.25 * dx
+    u = I.two_punctures(n, dx)
+    ut = torch.from_numpy(u).to(DEV)
+    st = G.Stepper(G.make_params(p), G.box_of(ut, dx), ut, dt)
+    for _ in range(nsteps):
+        st.step()
+    code, bits = st.status()
+    assert code == 0, bits
+    del ut
+    pv = I.params_vector(p)
+    # punctures at x = +-3: cells 79/80 and 175/176 (x_i = -8 + (i + 1/2)/16)
+    regions = {"puncture +": (168, 120, 120), "puncture -": (72, 120, 120), "pulse centre": (120, 120, 120),
+               "corner": (240, 0, 240)}
+    for name, r0 in regions.items():
+        o = oracle_region_rk4(O, pv, u, dx, dt, nsteps, r0, w)
+        g = st.u[:, r0[2] + 3:r0[2] + 3 + w, r0[1] + 3:r0[1] + 3 + w, r0[0] + 3:r0[0] + 3 + w].cpu().numpy()
+        e = rel_err_per_field(g, o, interior=False)
+        print(f"{name}: max rel err {e.max():.3e}", flush=True)
+        assert e.max() <= 1e-10, (name, dict(zip(I.FIELDS, e)))
 
 
 def test_rk4_ten_steps_puncture_strict():
