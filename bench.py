@@ -148,8 +148,26 @@ def adjoint_ratio(torch, G, I):
         t2 = time.perf_counter()
         times.append((t1 - t0, t2 - t1))
     f, b = times[-1]
+    # one more backward, not timed, with the kernels of each right-hand-side
+    # VJP timed by HIP events: the whole VJP and its reverse pointwise kernel
+    theta.grad = None
+    x = u0.clone().requires_grad_(True)
+    J = A.shell_phi2(A.Evolve.apply(theta, x, traj), mask)
+    G.prof_begin(4 * nsteps)
+    J.backward()
+    torch.cuda.synchronize()
+    prof = G.prof_end()
+    vjp_ms, vjp_n = prof["vjp"]
+    pt_ms, pt_n = prof["vjp_point"]
+    pt_avg = pt_ms / max(pt_n, 1)
+    flops = G.flops_per_cell(2)
+    tflops = flops * n ** 3 / (pt_avg * 1e-3) / 1e12
     return {"ratio": b / f, "forward_s": f, "backward_s": b, "workload": "single_puncture_64_dx0.25_50steps_ckpt10",
-            "dJ_dlambda_gb": float(theta.grad[0]), "dJ_dg2": float(theta.grad[1])}
+            "dJ_dlambda_gb": float(theta.grad[0]), "dJ_dg2": float(theta.grad[1]),
+            "rhs_vjp_avg_ms": vjp_ms / max(vjp_n, 1), "rhs_vjps": vjp_n,
+            "reverse_pointwise_kernel": {"kernel": "k_vjp_point", "avg_launch_ms": pt_avg, "launches": pt_n,
+                                         "executed_flops_per_cell": flops, "achieved": tflops, "peak": PEAK_FP64,
+                                         "unit": "TFLOP/s", "frac": tflops / PEAK_FP64}}
 
 
 def large_box(torch, G, I, steps=3):

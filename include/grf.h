@@ -433,7 +433,8 @@ int grf_get_slab_planes(void);
 /* Kernel timing with HIP events recorded on the launch stream around each
  * launch, for up to max_launches launches per kernel class; grf_prof_end waits
  * for the events and returns per class (0 stencil stage, 1 pointwise + RK4,
- * 2 VJP kernels) the summed milliseconds and launch counts (arrays of 3).
+ * 2 VJP kernels (a whole grf_rhs_vjp), 3 the reverse pointwise kernel alone)
+ * the summed milliseconds and launch counts (arrays of 4).
  * Host-side state, not thread-safe; intended for benchmarks. */
 /* Measured peaks of the device, for roofline fractions next to the datasheet
  * ones: an FP64 FMA-chain kernel (TFLOP/s, fused multiply-add = 2 flops) and a

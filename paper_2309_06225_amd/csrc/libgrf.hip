@@ -166,7 +166,7 @@ struct ProfClass {
 struct Prof {
   bool on = false;
   int cap = 0;
-  ProfClass cls[3];  // 0 stencil stage, 1 pointwise/RK4, 2 VJP kernels
+  ProfClass cls[4];  // 0 stencil stage, 1 pointwise/RK4, 2 VJP kernels, 3 the reverse pointwise kernel
 } g_prof;
 
 void prof_mark(int which, hipStream_t st) {
@@ -695,7 +695,11 @@ grf_status grf_rhs_vjp(const grf_params* p, const grf_box* box, const double* u,
   if (p->decoupled)
     GRF_HIP_CHECK(launch_vjp_point_dec(sa, bd, pp, u + sh, D, UP, w + sh, u_bar + sh, Dbar, TH, stream));
   else
+  {
+    prof_mark(3, stream);
     GRF_HIP_CHECK(launch_vjp_point(sa, bd, pp, u + sh, D, UP, w + sh, u_bar + sh, Dbar, TH, stream));
+    prof_mark(3, stream);
+  }
   GRF_HIP_CHECK(launch_vjp_transpose(bd, u, w, Dbar, p->ko_sigma, sa, order, u_bar, stream));
   GRF_HIP_CHECK(launch_reduce(TH, bd.ncell, kRedChunk, L.nparts, part, theta_bar, stream));
   prof_mark(2, stream);
@@ -1149,11 +1153,12 @@ grf_status grf_prof_begin(int max_launches) {
   return GRF_OK;
 }
 
-// Stop recording; for each kernel class (0 stencil, 1 pointwise, 2 VJP) return
-// the summed kernel time in ms and the number of timed launches (waits for them).
+// Stop recording; for each kernel class (0 stencil, 1 pointwise, 2 VJP, 3 the
+// reverse pointwise kernel) return the summed kernel time in ms and the number
+// of timed launches (waits for them).
 grf_status grf_prof_end(double* ms, int* count) {
   g_prof.on = false;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 4; ++k) {
     ProfClass& c = g_prof.cls[k];
     double tot = 0.0;
     for (int q = 0; q + 1 < c.used; q += 2) {

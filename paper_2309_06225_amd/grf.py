@@ -351,11 +351,13 @@ def prof_begin(max_launches: int):
 
 
 def prof_end():
-    """-> {'deriv': (ms, n), 'point': (ms, n), 'vjp': (ms, n)} from HIP events."""
-    ms = (ctypes.c_double * 3)()
-    cnt = (ctypes.c_int * 3)()
+    """-> {'deriv': (ms, n), 'point': (ms, n), 'vjp': (ms, n), 'vjp_point': (ms, n)}
+    from HIP events ('vjp': whole right-hand-side VJPs, 'vjp_point': their
+    reverse pointwise kernel)."""
+    ms = (ctypes.c_double * 4)()
+    cnt = (ctypes.c_int * 4)()
     _check(lib().grf_prof_end(ms, cnt))
-    return {k: (ms[i], cnt[i]) for i, k in enumerate(("deriv", "point", "vjp"))}
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(("deriv", "point", "vjp", "vjp_point"))}
 
 
 def flops_per_cell(which=0) -> int:
