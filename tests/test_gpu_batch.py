@@ -192,11 +192,17 @@ def test_autotune_is_cached_and_result_independent():
 
 
 def test_amr_workload_boxes_match_oracle():
-    """The 96-box workload after one batched step (autotuned, graph-free): the
-    two largest boxes and the largest box of the coarsest and of the finest
-    level against the oracle's step of the same box, within 1e-10 relative
-    per field (R12: every cell of the box, frozen ghosts included)."""
-    print("case: 96 AMR boxes, 4 boxes against the oracle", flush=True)
+    """The 96-box workload after one batched step (autotuned, graph-free):
+    every box against the oracle's step of the same box (about 20 s of oracle
+    time on the host), every cell of the box, frozen ghosts included, within
+    1e-10 relative per field (R12).  Boxes far from the puncture are
+    ill-conditioned as the noise box is (R20): there K, A_ij and Theta are
+    about 1e-6 after one step, formed from cancelling O(1) terms, and the
+    double-precision oracle itself is off by up to ~1e-9 relative.  A box that
+    misses 1e-10 against the double oracle is therefore held, field by field,
+    to max(1e-10, 1.5 x the double oracle's own error) against the oracle run
+    in long double."""
+    print("case: 96 AMR boxes, every box against the oracle", flush=True)
     spec = I.amr_boxes()
     p, boxes, states, dts = _make(spec)
     A = G.Batch(G.make_params(p), boxes, [torch.from_numpy(s).to(DEV) for s in states], dts)
@@ -204,19 +210,28 @@ def test_amr_workload_boxes_match_oracle():
     A.step()
     torch.cuda.synchronize()
     assert A.status()[0] == 0
-    size = [int(np.prod(b["dims"])) for b in spec]
-    order = sorted(range(len(spec)), key=lambda b: -size[b])
-    pick = order[:2]
-    for lev in (min(b["level"] for b in spec), max(b["level"] for b in spec)):
-        on = [b for b in order if spec[b]["level"] == lev and b not in pick]
-        if on:
-            pick.append(on[0])
-    for b in pick:
-        o, fo = O.rk4(I.params_vector(p), states[b], spec[b]["dx"], dts[b], 1, periodic=False)
+    pv = I.params_vector(p)
+    worst, ill = {}, []
+    for b in range(len(spec)):
+        o, fo = O.rk4(pv, states[b], spec[b]["dx"], dts[b], 1, periodic=False)
         assert fo == 0
-        e = rel_err_per_field(A.state(b).cpu().numpy(), o, interior=False)
-        print(f"box {b} dims {spec[b]['dims']} level {spec[b]['level']}: max rel err {e.max():.3e}", flush=True)
-        assert e.max() <= 1e-10, (b, dict(zip(I.FIELDS, e)))
+        g = A.state(b).cpu().numpy()
+        e = rel_err_per_field(g, o, interior=False)
+        lev = spec[b]["level"]
+        worst[lev] = max(worst.get(lev, 0.0), float(e.max()))
+        if e.max() <= 1e-10:
+            continue
+        ref, fl = O.rk4_ld(pv, states[b], spec[b]["dx"], dts[b], 1, periodic=False)
+        assert fl == 0
+        e_gpu = rel_err_per_field(g, ref, interior=False)
+        e_orc = rel_err_per_field(o, ref, interior=False)
+        bound = np.maximum(1e-10, 1.5 * e_orc)
+        ill.append((b, f"{e_gpu.max():.2e}", f"{e_orc.max():.2e}"))
+        assert np.all(e_gpu <= bound), (b, spec[b]["dims"], lev, {f: (e_gpu[i], bound[i]) for i, f in
+                                                                  enumerate(I.FIELDS) if e_gpu[i] > bound[i]})
+    print("largest relative error against the double oracle, per level:",
+          {k: f"{v:.2e}" for k, v in sorted(worst.items())}, flush=True)
+    print("boxes held against the long-double oracle (box, GPU error, double oracle's error):", ill, flush=True)
     A.close()
 
 
