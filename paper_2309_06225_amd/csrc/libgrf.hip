@@ -2,6 +2,7 @@
 // stage (declarations and argument conventions in include/grf.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdarg>
@@ -787,6 +788,17 @@ namespace grf {
 
 std::map<std::tuple<int, int, int>, int> g_tile_cache;  // autotuned tile variant per box shape
 
+// Cells an entry's workgroup stages (its tile or column chunk with the halo):
+// the stencil stage's cost of the entry.
+static int64_t entry_cost(int v, const BoxDev& bd, int t) {
+  static const int shape[kTileVariantsMax][3] = {{16, 8, 4}, {32, 4, 4}, {8, 8, 8},  {16, 16, 2}, {64, 4, 2},
+                                                 {16, 8, 32}, {32, 8, 32}, {32, 4, 32}, {16, 16, 32}, {128, 8, 32}};
+  const int TX = shape[v][0], TY = shape[v][1], TZ = shape[v][2];
+  const int ntx = (bd.nx + TX - 1) / TX, nty = (bd.ny + TY - 1) / TY;
+  const int x0 = (t % ntx) * TX, y0 = (t / ntx % nty) * TY, z0 = (t / ntx / nty) * TZ;
+  return (int64_t)(std::min(TX, bd.nx - x0) + 6) * (std::min(TY, bd.ny - y0) + 6) * (std::min(TZ, bd.nz - z0) + 6);
+}
+
 grf_status batch_upload_tiles(grf_batch* B) {
   std::vector<TileEntry> lists[kTileVariantsMax];
   for (size_t b = 0; b < B->boxes.size(); ++b) {
@@ -794,6 +806,12 @@ grf_status batch_upload_tiles(grf_batch* B) {
     const int nt = tiles_of_variant(v, B->host[b].bd);
     for (int t = 0; t < nt; ++t) lists[v].push_back(TileEntry{(int)b, t});
   }
+  // heaviest entries first: the persistent workgroups take entries in turn, so
+  // the last ones to run are the light ones
+  for (int v : kBatchVariants)
+    std::stable_sort(lists[v].begin(), lists[v].end(), [&](const TileEntry& a, const TileEntry& c) {
+      return entry_cost(v, B->host[a.box].bd, a.tile) > entry_cost(v, B->host[c.box].bd, c.tile);
+    });
   for (int v : kBatchVariants) {
     if (B->tiles[v]) GRF_HIP_CHECK(hipFree(B->tiles[v]));
     B->tiles[v] = nullptr;
