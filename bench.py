@@ -204,7 +204,7 @@ def large_box(torch, G, I, steps=3):
 
 def batched_speedup(torch, G, I, steps=4):
     """96 uneven boxes (levels 0-5): one-launch-per-box RK4 steps vs the batched
-    persistent form replayed from a hipGraph (one step per replay)."""
+    form replayed from a hipGraph (one step per replay)."""
     spec = I.amr_boxes()
     states, dts = I.amr_states(spec)
     p = I.default_params()

@@ -336,11 +336,11 @@ grf_status grf_coupling_diagnostics(const grf_params* p, const grf_box* box, con
 /* ---- Batched boxes (uneven sizes and refinement levels, frozen ghosts): the
  * many boxes per refinement level of the paper's adaptive-mesh runs (Key
  * features, "Adaptive Mesh Refinement") advanced together on one GPU.
- * One RK4 stage of the batch is one persistent stencil launch per stencil
- * variant in use and one pointwise launch, covering every box (work lists of
- * (box, tile or column chunk) entries, fixed assignment to workgroups, and
- * (box, 64-cell wave) entries, one per workgroup; no atomics); one RK4 step is
- * the four stages in order.
+ * One RK4 stage of the batch is one stencil launch per stencil variant in
+ * use and one pointwise launch, covering every box (work lists of (box, tile
+ * or column chunk) entries, heaviest first, and (box, 64-cell wave) entries,
+ * one workgroup per entry; no atomics); one RK4 step is the four stages in
+ * order.
  * Per cell the device code is the one of grf_rk4_stage, so results are
  * bitwise identical to per-box launches (grf_batch_step_perbox runs that
  * reference form on the same buffers).  Boxes use stencil variant 8 (the

@@ -1,7 +1,8 @@
-// Batched persistent kernels: one launch per RK4 stage phase covers every box
-// of a batch.  Work lists are static (box, tile) and (box, cell block) entries;
-// workgroup w takes entries w, w + G, w + 2G, ... so no atomics are involved and
-// every cell is computed by exactly the same device code as in the per-box
+// Batched kernels: one launch per RK4 stage phase covers every box of a batch.
+// Work lists are static (box, tile) and (box, cell block) entries; workgroup w
+// takes entries w, w + G, w + 2G, ... (G the grid: one workgroup per entry as
+// launched, a persistent grid works the same way), so no atomics are involved
+// and every cell is computed by exactly the same device code as in the per-box
 // launches (results are bitwise identical).
 #pragma once
 #include "kernels_fwd.h"

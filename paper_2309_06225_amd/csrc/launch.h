@@ -120,6 +120,5 @@ hipError_t launch_axpby(int64_t n, double a, const double* x, double b, const do
                         hipStream_t st);
 hipError_t launch_fill(int64_t n, double v, double* out, hipStream_t st);
 
-int persistent_grid_from(int per_cu, int64_t work);
 
 }  // namespace grf

@@ -806,8 +806,8 @@ grf_status batch_upload_tiles(grf_batch* B) {
     const int nt = tiles_of_variant(v, B->host[b].bd);
     for (int t = 0; t < nt; ++t) lists[v].push_back(TileEntry{(int)b, t});
   }
-  // heaviest entries first: the persistent workgroups take entries in turn, so
-  // the last ones to run are the light ones
+  // heaviest entries first: workgroups are dispatched in list order, so the
+  // last ones to run are the light ones
   for (int v : kBatchVariants)
     std::stable_sort(lists[v].begin(), lists[v].end(), [&](const TileEntry& a, const TileEntry& c) {
       return entry_cost(v, B->host[a.box].bd, a.tile) > entry_cost(v, B->host[c.box].bd, c.tile);
@@ -1035,7 +1035,7 @@ grf_status grf_batch_autotune(grf_batch* B, hipStream_t stream) {
     }
     // (2) whole assignments timed as the batched stencil stage runs them: the
     // per-class mix, then every variant for all boxes; boxes of one class run
-    // concurrently with all others in one persistent launch, so a variant that
+    // concurrently with all others in one launch, so a variant that
     // loses on a box alone can win in the batch
     std::vector<std::vector<int>> cands;
     {
