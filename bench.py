@@ -148,6 +148,25 @@ def adjoint_ratio(torch, G, I):
         t2 = time.perf_counter()
         times.append((t1 - t0, t2 - t1))
     f, b = times[-1]
+    # the same with every stencil stage on the 128-wide column (the single-box
+    # default for this 64-wide box before narrow boxes got the 16x16 column):
+    # a slower forward, so a lower ratio at a higher cost
+    v0 = G.get_tile_variant()
+    G.set_tile_variant(9)
+    try:
+        theta.grad = None
+        x = u0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = A.shell_phi2(A.Evolve.apply(theta, x, traj), mask)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+    finally:
+        G.set_tile_variant(v0)
+    wide = {"forward_s": t1 - t0, "backward_s": t2 - t1, "ratio": (t2 - t1) / (t1 - t0)}
     # one more backward, not timed, with the kernels of each right-hand-side
     # VJP timed by HIP events: the whole VJP and its reverse pointwise kernel
     theta.grad = None
@@ -165,6 +184,7 @@ def adjoint_ratio(torch, G, I):
     return {"ratio": b / f, "forward_s": f, "backward_s": b, "workload": "single_puncture_64_dx0.25_50steps_ckpt10",
             "dJ_dlambda_gb": float(theta.grad[0]), "dJ_dg2": float(theta.grad[1]),
             "rhs_vjp_avg_ms": vjp_ms / max(vjp_n, 1), "rhs_vjps": vjp_n,
+            "with_128_wide_stencil_column": wide,
             "reverse_pointwise_kernel": {"kernel": "k_vjp_point", "avg_launch_ms": pt_avg, "launches": pt_n,
                                          "executed_flops_per_cell": flops, "achieved": tflops, "peak": PEAK_FP64,
                                          "unit": "TFLOP/s", "frac": tflops / PEAK_FP64}}

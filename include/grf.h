@@ -398,11 +398,13 @@ grf_status grf_graph_destroy(hipGraphExec_t exec);
  * field of an LDS tile plus halo): 0: 16x8x4, 1: 32x4x4, 2: 8x8x8, 3: 16x16x2,
  * 4: 64x4x2.  z-marching (a workgroup per field of an x-y column of cells
  * walking a chunk of z-planes through a ring of LDS planes), column x chunk:
- * 5: 16x8x32, 6: 32x8x32, 7: 32x4x32, 8: 16x16x32, 9: 128x8x32 (default: on
- * a 128^3 box 0.99 ms per launch against 1.12 ms for 6, the wider column
- * re-reading fewer halo cells; 32x8 with 16- and 64-plane chunks, 64x4,
- * 32x16, 64x8 and 64x16 columns were measured between the two and dropped).
- * Results do not depend on it.  GRF_EINVAL outside 0..9. */
+ * 5: 16x8x32, 6: 32x8x32, 7: 32x4x32, 8: 16x16x32, 9: 128x8x32.  -1 (the
+ * default): chosen per box, 9 for boxes at least 128 cells wide (on a 128^3
+ * box 0.99 ms per launch against 1.12 ms for 6, the wider column re-reading
+ * fewer halo cells; 32x8 with 16- and 64-plane chunks, 64x4, 32x16, 64x8 and
+ * 64x16 columns were measured between the two and dropped), 8 for narrower
+ * ones (on a 64^3 box 0.148 ms against 0.207 ms for 9).  Results do not
+ * depend on it.  GRF_EINVAL outside -1..9. */
 grf_status grf_set_tile_variant(int variant);
 int grf_get_tile_variant(void);
 
