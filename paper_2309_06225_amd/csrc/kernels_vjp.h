@@ -109,7 +109,7 @@ __device__ __forceinline__ double src_at(const BoxDev& b, const double* __restri
   return inside(b, ix, iy, iz) ? v : 0.0;
 }
 
-constexpr int kGatherThreads = 256;
+constexpr int kGatherThreads = 512;  // 0.50 ms per 64^3 gather against 0.56 with 128 or 256 and 0.55 with 1024
 
 template <int NT, int ORD = 4, int H = 3>
 __global__ __launch_bounds__(NT) void k_vjp_gather(BoxDev b, const double* __restrict__ u,
