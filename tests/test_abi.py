@@ -92,3 +92,19 @@ def test_static_stage_refuses_oversized_planes_on_the_host():
     code = L.grf_rk4_stage_static(ctypes.byref(p), ctypes.byref(box), 1, 0.1, ptr[0], ptr[1], ptr[2], ptr[3],
                                   None, None)
     assert code == 1
+
+
+def test_tile_variant_setting_on_the_host():
+    """The single-box stencil variant: -1 (chosen per box, the default) or
+    0..9; anything else is refused with GRF_EINVAL and leaves the setting."""
+    from paper_2309_06225_amd import grf as G
+    L = G.lib()
+    v0 = L.grf_get_tile_variant()
+    assert v0 == -1
+    try:
+        assert L.grf_set_tile_variant(9) == 0 and L.grf_get_tile_variant() == 9
+        assert L.grf_set_tile_variant(10) == 1 and L.grf_get_tile_variant() == 9
+        assert L.grf_set_tile_variant(-2) == 1 and L.grf_get_tile_variant() == 9
+        assert L.grf_set_tile_variant(-1) == 0 and L.grf_get_tile_variant() == -1
+    finally:
+        L.grf_set_tile_variant(v0)
